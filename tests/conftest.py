@@ -1,0 +1,21 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (runs through the HIP library)")
+    config.addinivalue_line("markers", "slow: long CPU test (physics pins over many steps)")
+
+
+@pytest.fixture(scope="session")
+def orc():
+    """The FP64 oracle (built on first use)."""
+    from oracle import oracle
+    oracle.lib()
+    return oracle
