@@ -1,0 +1,206 @@
+"""Benchmark of the SRD step on one MI355X.
+
+Default workload: one periodic box of 256^3 unit cells with 10 particles per
+cell (167,772,160 particles), dt = 0.1, alpha = 130 deg, seed 3, positions
+uniform and velocities Maxwellian at kT = 1 drawn on the device (the paper's
+benchmark system, Sec. 4, at its L = 256 size).  A "step" is one SRD update of
+the whole box (stream, shift, bin, cell sums, rotation, diagnostics).
+
+Prints ONE JSON line with particle-steps/s, the roofline of the dominant
+kernel (algorithmic bytes per launch / its average HIP-event duration on the
+library stream) and the FP64 oracle timed on a bounded sample on the host.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (L, particles per cell, dt, alpha_deg, seed)
+    "srd_256cube_10ppc": ((256, 256, 256), 10, 0.1, 130.0, 3),
+    "srd_100cube_10ppc": ((100, 100, 100), 10, 0.1, 130.0, 2),
+}
+DEFAULT_WORKLOAD = "srd_256cube_10ppc"
+
+# Algorithmic bytes each kernel's function has to move, per particle (P) and
+# per cell (C), independent of how the kernel is written:
+#   stream_bin : read x, v (24 B), write x (12 B)                    -> 36 P
+#   rotate     : read v, write v                                      -> 24 P
+#   finalize   : read the cell sums (3 x 4 B + count 4 B), write
+#                u_c and the axis (6 x 4 B)                           -> 40 C
+#   cell_rotate: read v, write v                                      -> 24 P
+#   scatter    : read x, v, id (28 B), write them (28 B)              -> 56 P
+#   count      : read x (12 B), write the key (4 B)                   -> 16 P
+ALGO_BYTES = {
+    "stream_bin": (36, 0),
+    "rotate": (24, 0),
+    "finalize": (0, 40),
+    "cell_rotate": (24, 0),
+    "scatter": (56, 0),
+    "count": (16, 0),
+}
+# the whole step: every particle's x and v read once and written once
+STEP_ALGO_BYTES_PER_PARTICLE = 48
+
+
+def context_options():
+    """Launch configuration the benchmark times (also used by the full-size
+    parity test)."""
+    from paper_2212_11878_amd import mpcd
+    return dict(binning=mpcd.MPCD_BIN_AUTO, use_graph=True)
+
+
+def kernel_sources_sha():
+    h = hashlib.sha256()
+    for f in ("mpcd_dev.h", "mpcd_kernels.hip"):
+        with open(os.path.join(ROOT, "paper_2212_11878_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel, workload):
+    """HBM bytes per dispatch from the committed rocprofv3 counter summary,
+    or None when missing or taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.txt" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_sources_sha") != kernel_sources_sha():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_dispatch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(workload):
+    """The FP64 oracle, single-threaded, on a bounded sample of the workload:
+    a 128^3-cell box of the same density and parameters, 3 steps."""
+    from oracle import oracle as orc
+    from paper_2212_11878_amd import inputs
+    L, ppc, dt, alpha, seed = WORKLOADS[workload]
+    Ls = tuple(min(128, l) for l in L)
+    n = ppc * Ls[0] * Ls[1] * Ls[2]
+    steps = 3
+    pos, vel = inputs.thermal_state(Ls, n, seed)
+    st = orc.State(pos, vel)
+    del pos, vel
+    box = orc.make_box(Ls, dt=dt, alpha_deg=alpha, seed=seed)
+    t0 = time.perf_counter()
+    orc.run(box, 0, steps, st)
+    t = time.perf_counter() - t0
+    return {"value": n * steps / t, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": "%dx%dx%d cells x %d particles/cell (%d particles), %d steps, FP64, %.1f s"
+                      % (Ls[0], Ls[1], Ls[2], ppc, n, steps, t)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
+    ap.add_argument("--binning", default="auto", choices=["auto", "atomic", "sort"])
+    ap.add_argument("--resort-period", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the SRD box runs on a single device here "
+              "(multi-GPU halo decomposition is not part of this build); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2212_11878_amd import mpcd
+
+    L, ppc, dt, alpha, seed = WORKLOADS[args.workload]
+    n = ppc * L[0] * L[1] * L[2]
+    ncell = L[0] * L[1] * L[2]
+    opts = context_options()
+    if args.binning != "auto":
+        opts["binning"] = mpcd.MPCD_BIN_ATOMIC if args.binning == "atomic" else mpcd.MPCD_BIN_SORT
+    opts["resort_period"] = args.resort_period
+
+    print("[bench] workload %s: %d particles, admitting" % (args.workload, n), file=sys.stderr,
+          flush=True)
+    ctx = mpcd.Context(**opts)
+    slot = ctx.admit(mpcd.make_desc(L, n, dt=dt, alpha_deg=alpha, seed=seed, init="maxwell"))
+    ctx.step(args.warmup)
+    ctx.synchronize()
+    print("[bench] warmup done, timing %d steps" % args.steps, file=sys.stderr, flush=True)
+    # timed region: per-kernel HIP events on the library stream
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(args.steps)
+    ctx.synchronize()
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    stats = ctx.kernel_stats()
+    ctx.profile(False)
+    obs = ctx.observe(slot)
+    ctx.close()
+    if obs["status"] != 0 or obs["step"] != args.warmup + args.steps:
+        print("[bench] box state invalid: %r" % obs, file=sys.stderr)
+        sys.exit(1)
+
+    value = n * args.steps / t
+    ms_per_step = 1000.0 * t / args.steps
+
+    # dominant kernel by total time
+    dom = max(stats.items(), key=lambda kv: kv[1][1])
+    kname, (launches, total_ms) = dom
+    avg_ms = total_ms / max(1, launches)
+    per_p, per_c = ALGO_BYTES.get(kname, (0, 0))
+    algo = per_p * n + per_c * ncell
+    achieved = algo / (avg_ms * 1e-3) / 1e9
+    traffic = load_traffic(kname, args.workload)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": kname, "kernel_avg_ms": round(avg_ms, 4),
+                "algorithmic_bytes_per_launch": algo}
+    kern = {k: {"launches": v[0], "avg_ms": round(v[1] / max(1, v[0]), 4)} for k, v in stats.items()}
+
+    out = {
+        "metric": "particle-steps/s",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "cells": list(L), "particles": n, "dt": dt,
+                   "alpha_deg": alpha, "seed": seed, "binning": obs["binning"],
+                   "resort_period": obs["resort_period"]},
+        "useful_hbm_frac": round(value * STEP_ALGO_BYTES_PER_PARTICLE / 1e9 / HBM_PEAK_GBS, 4),
+        "roofline": roofline,
+        "kernels": kern,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(args.workload)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

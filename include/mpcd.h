@@ -1,0 +1,194 @@
+/*
+ * mpcd.h -- C ABI of the MI355X Stochastic Rotation Dynamics (SRD/MPCD)
+ * library libmpcd.so.
+ *
+ * The library advances periodic boxes of point particles with the SRD step
+ * of Halver, Junghans, Sutmann, "Kokkos-Based Implementation of MPCD on
+ * Heterogeneous Nodes" (arXiv 2212.11878), Sec. 2: every step it
+ *   1. streams every particle, x <- x + v dt, folded into the periodic box
+ *      (the paper's benchmark boundary conditions, Sec. 4);
+ *   2. draws a random grid shift s in [-a/2, a/2)^3 (Sec. 2, Fig. 1) and puts
+ *      each particle into the cell floor((x - s)/a) of the displaced grid
+ *      (Sec. 3.1, Listing 1);
+ *   3. reduces each cell's centre-of-mass velocity u_c = sum(m v)/sum(m)
+ *      (Sec. 3.3, Listing 4);
+ *   4. rotates each relative velocity v - u_c by the fixed angle alpha about
+ *      a random unit axis drawn per cell (Sec. 2, parts (ii)-(iii)).
+ * Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by the box seed;
+ * the shift of step k uses counter (k_lo, 0, k_hi, 0), the axis of canonical
+ * cell c = ix + Lx (iy + Ly iz) uses counter (k_lo, c, k_hi, 1).  Results
+ * therefore depend only on (seed, step, state), never on storage order or on
+ * which other boxes share the device.
+ *
+ * Precision: positions and velocities are FP32.  Per-cell momentum sums are
+ * exact two's-complement 64-bit fixed point (velocity quantum 2^-32), so the
+ * sum is independent of summation order; global momentum / energy
+ * diagnostics are accumulated in FP64.
+ *
+ * General conventions
+ *   - Every call returns an mpcd_status; a failing call leaves the context
+ *     unchanged (admission is all-or-nothing).
+ *   - A context is not thread safe: use it from one host thread.
+ *   - Device work is queued on the context's HIP stream; only mpcd_observe,
+ *     mpcd_get_state, mpcd_set_state, mpcd_admit, mpcd_release and
+ *     mpcd_kernel_stats synchronise with it.
+ *   - Pointers marked "host" are ordinary host memory owned by the caller
+ *     and only read or written during the call.
+ */
+#ifndef MPCD_H
+#define MPCD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPCD_ABI_VERSION 1
+
+typedef enum {
+    MPCD_OK = 0,
+    MPCD_EINVAL = -1,   /* invalid argument or descriptor                  */
+    MPCD_ENOMEM = -2,   /* over the context's device-memory budget, or the
+                           allocator refused                                */
+    MPCD_EDEVICE = -3,  /* a HIP runtime call failed                        */
+    MPCD_EBUSY = -4,    /* no free slot                                     */
+    MPCD_ESTATE = -5,   /* NaN/Inf detected in a box's diagnostics          */
+    MPCD_ENOTFOUND = -6 /* slot not live                                    */
+} mpcd_status;
+
+/* mpcd_box_desc.flags */
+#define MPCD_INIT_MAXWELL 0x1u   /* draw uniform positions and Maxwellian
+                                    velocities on the device (zero momentum,
+                                    temperature exactly kT)                 */
+#define MPCD_INIT_EXTERNAL 0x2u  /* caller supplies the state with
+                                    mpcd_set_state before the first step    */
+#define MPCD_TRACK_VACF 0x4u     /* record the velocity autocorrelation     */
+
+/* mpcd_options.binning */
+#define MPCD_BIN_AUTO 0    /* autotuner chooses per box-shape class         */
+#define MPCD_BIN_ATOMIC 1  /* accumulate cell sums with atomics on
+                              near-sorted particles (re-sorted periodically) */
+#define MPCD_BIN_SORT 2    /* counting-sort particles by collision cell every
+                              step, then reduce each cell's contiguous run   */
+
+/* One periodic box (a "slot" once admitted). */
+typedef struct {
+    int32_t L[3];          /* cells per edge, each in [1, 4096]; L0*L1*L2 < 2^31 */
+    double a;              /* cell edge, > 0                                 */
+    int64_t n_particles;   /* >= 0                                           */
+    double dt;             /* streaming time step, > 0                       */
+    double alpha;          /* rotation angle in radians, finite              */
+    double kT;             /* initial temperature (MPCD_INIT_MAXWELL), > 0   */
+    double mass;           /* particle mass, > 0 (all particles equal)       */
+    uint64_t seed;         /* Philox key                                     */
+    int64_t n_steps;       /* steps this box runs, then idles; 0 = unbounded */
+    uint32_t flags;        /* MPCD_INIT_* | MPCD_TRACK_VACF                   */
+    int32_t vacf_stride;   /* steps between VACF samples, >= 1 when tracked  */
+    int32_t vacf_capacity; /* max VACF samples kept; 0 = n_steps/stride + 1
+                              (1024 if n_steps == 0)                        */
+} mpcd_box_desc;
+
+/* Device allocator supplied by the caller (e.g. backed by PyTorch).  Must
+ * return device memory aligned to >= 256 bytes, or NULL. */
+typedef void* (*mpcd_alloc_fn)(size_t bytes, void* user);
+typedef void (*mpcd_free_fn)(void* ptr, void* user);
+
+typedef struct {
+    int32_t binning;        /* MPCD_BIN_*                                    */
+    int32_t resort_period;  /* steps between re-sorts (ATOMIC); 0 = auto     */
+    int32_t block;          /* threads per workgroup: 0 (auto), 256, 512, 1024 */
+    int32_t use_graph;      /* 1: replay steps from a captured hipGraph      */
+    int64_t hbm_budget;     /* bytes all boxes may occupy; 0 = unlimited     */
+    void* stream;           /* hipStream_t; NULL = the library creates one   */
+    mpcd_alloc_fn alloc;    /* NULL = hipMalloc                              */
+    mpcd_free_fn free;      /* NULL = hipFree                                */
+    void* user;             /* passed to alloc/free                          */
+    int32_t device;         /* HIP device ordinal                            */
+    int32_t max_slots;      /* 0 = 4096                                      */
+} mpcd_options;
+
+typedef struct {
+    int64_t step;           /* steps completed                               */
+    double P[3];            /* total momentum (FP64 sum of FP32 data)        */
+    double E_kin;           /* kinetic energy                                */
+    double T;               /* sum m |v - V|^2 / (3 (N - 1)), k_B = 1        */
+    double mass_total;
+    int32_t status;         /* MPCD_OK or MPCD_ESTATE                        */
+    int32_t vacf_len;       /* number of VACF samples                        */
+    const double* vacf;     /* host; valid until the next call on the ctx;
+                               sample j = (1/N) sum_i v_i(j stride) . v_i(0) */
+    int64_t n_particles;
+    int32_t binning;        /* binning mode in use for this box              */
+    int32_t resort_period;
+} mpcd_observables;
+
+/* Per-kernel timing collected while profiling is on. */
+typedef struct {
+    const char* name;       /* static string                                 */
+    int64_t launches;
+    double total_ms;        /* sum of HIP-event durations on the ctx stream  */
+} mpcd_kernel_stat;
+
+typedef struct mpcd_ctx mpcd_ctx;   /* opaque, owned by the library */
+
+/* Create a context on options->device (options may be NULL: defaults).
+ * *out receives the handle.  EINVAL for bad options, EDEVICE if the device
+ * cannot be used. */
+int mpcd_create(const mpcd_options* options, mpcd_ctx** out);
+
+/* Admit one box (Sec. 4 workload: cubic periodic box of unit cells holding
+ * on average n_particles / (L0 L1 L2) particles).  Allocates its device
+ * state through the context allocator and, with MPCD_INIT_MAXWELL, draws the
+ * initial state on the device (Philox counter (i_lo, i_hi, 0, 2) for
+ * positions, (i_lo, i_hi, 0, 3) for Box-Muller velocities).  The box starts
+ * at step 0.  *slot receives its index.
+ * ENOMEM over budget, EBUSY no free slot, EINVAL bad descriptor. */
+int mpcd_admit(mpcd_ctx* ctx, const mpcd_box_desc* desc, int32_t* slot);
+
+/* Queue n_steps SRD steps (Sec. 2) for every live box whose step budget is
+ * not exhausted; boxes that reach desc.n_steps stop advancing.  Asynchronous
+ * on the context stream. */
+int mpcd_step(mpcd_ctx* ctx, int32_t n_steps);
+
+/* Synchronise and read a box's diagnostics.  out->vacf stays valid until the
+ * next call on ctx.  Returns MPCD_ESTATE (and fills *out) if the box's
+ * energy became NaN or Inf. */
+int mpcd_observe(mpcd_ctx* ctx, int32_t slot, mpcd_observables* out);
+
+/* Copy a box's state to host memory xyzv (6 N floats, SoA: x[N], y[N], z[N],
+ * vx[N], vy[N], vz[N]) in the particle order given at admission / the last
+ * mpcd_set_state; *step receives the steps completed.  Synchronises. */
+int mpcd_get_state(mpcd_ctx* ctx, int32_t slot, float* xyzv, int64_t* step);
+
+/* Replace a box's state with host xyzv (layout as mpcd_get_state; positions
+ * must lie in [0, L_d a)) and set its step counter; the velocities become
+ * the VACF reference v(0).  EINVAL if a position is out of range or not
+ * finite (state unchanged).  Synchronises. */
+int mpcd_set_state(mpcd_ctx* ctx, int32_t slot, const float* xyzv, int64_t step);
+
+/* Free a box's device state; the slot number may be reused.  Synchronises. */
+int mpcd_release(mpcd_ctx* ctx, int32_t slot);
+
+/* Turn per-kernel HIP-event timing on (1) or off (0); turning it on clears
+ * the statistics. */
+int mpcd_profile(mpcd_ctx* ctx, int32_t enable);
+
+/* Synchronise and copy up to max entries of per-kernel timing into out;
+ * *count receives the number of kernels with statistics. */
+int mpcd_kernel_stats(mpcd_ctx* ctx, mpcd_kernel_stat* out, int32_t max, int32_t* count);
+
+/* Release every box and the context itself.  NULL is ignored. */
+void mpcd_destroy(mpcd_ctx* ctx);
+
+/* Static description of a status code. */
+const char* mpcd_strerror(int status);
+
+/* MPCD_ABI_VERSION of the loaded library. */
+int mpcd_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -140,6 +140,13 @@ int64_t oracle_cell_of(const oracle_box* b, const double s[3], double x, double 
     return idx[0] + (int64_t)b->L[0] * (idx[1] + (int64_t)b->L[1] * idx[2]);
 }
 
+void oracle_cells(const oracle_box* b, const double s[3], int64_t N,
+                  const double* x, const double* y, const double* z, int64_t* out)
+{
+    for (int64_t i = 0; i < N; ++i)
+        out[i] = oracle_cell_of(b, s, x[i], y[i], z[i]);
+}
+
 static int64_t n_cells(const oracle_box* b)
 {
     return (int64_t)b->L[0] * b->L[1] * b->L[2];

@@ -72,6 +72,10 @@ void oracle_stream(const oracle_box* b, int64_t N, double* x, double* y, double*
 /* Canonical shifted-cell index of a position inside the box. */
 int64_t oracle_cell_of(const oracle_box* b, const double s[3], double x, double y, double z);
 
+/* oracle_cell_of for every particle: out[i] = cell of particle i. */
+void oracle_cells(const oracle_box* b, const double s[3], int64_t N,
+                  const double* x, const double* y, const double* z, int64_t* out);
+
 /* Per-cell sums for shift s: count[c], P[3c+d] = sum m v_d, M[c] = sum m
  * (m == NULL means unit masses).  Arrays have L0*L1*L2 entries; they are
  * overwritten. */

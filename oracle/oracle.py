@@ -60,6 +60,8 @@ def lib():
         L.oracle_stream.restype = None
         L.oracle_cell_of.argtypes = [bp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.oracle_cell_of.restype = ctypes.c_int64
+        L.oracle_cells.argtypes = [bp, _dp, ctypes.c_int64] + [_dp] * 3 + [_i64p]
+        L.oracle_cells.restype = None
         L.oracle_cell_sums.argtypes = [bp, _dp, ctypes.c_int64] + [_dp] * 7 + [_i64p, _dp, _dp]
         L.oracle_cell_sums.restype = None
         L.oracle_collide.argtypes = [bp, ctypes.c_uint64, ctypes.c_int64] + [_dp] * 7 + [_i64p]
@@ -149,6 +151,15 @@ def stream(box, st: State):
 def cell_of(box, s, x, y, z):
     s = _f64(s)
     return int(lib().oracle_cell_of(ctypes.byref(box), _ptr(s), float(x), float(y), float(z)))
+
+
+def cells(box, s, st: State):
+    out = np.zeros(st.n, dtype=np.int64)
+    s = _f64(s)
+    p = st.pos
+    lib().oracle_cells(ctypes.byref(box), _ptr(s), st.n, p[0].ctypes.data_as(_dp),
+                       p[1].ctypes.data_as(_dp), p[2].ctypes.data_as(_dp), out.ctypes.data_as(_i64p))
+    return out
 
 
 def n_cells(box):

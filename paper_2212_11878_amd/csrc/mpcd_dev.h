@@ -1,0 +1,213 @@
+// mpcd_dev.h -- records shared by the HIP kernels and the host engine of
+// libmpcd.so, plus the device-side helpers of the SRD step (Philox, cell
+// index, fixed-point sums, rotation).  Internal: not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mpcd {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;          // threads per workgroup of the particle kernels
+constexpr int kPartTile = 4096;      // particles per particle tile (16 per thread)
+constexpr int kCellTile = 2048;      // cells per cell tile
+constexpr int kNumDiag = 5;          // per-tile FP64 partials: sum v (3), sum v^2, sum v.v0
+
+// Per-cell accumulator: exact 64-bit fixed-point momentum sums (quantum
+// 2^-32 velocity units) and the particle count.  32 bytes, one sector.
+struct alignas(32) CellAcc {
+    unsigned long long sx, sy, sz;
+    unsigned int n;
+    unsigned int pad;
+};
+
+// Per-cell collision data: centre-of-mass velocity and rotation axis.
+struct alignas(32) CellUN {
+    float ux, uy, uz, nx, ny, nz, pad0, pad1;
+};
+
+// Read-only description of one box, resident in device memory.  Particle
+// arrays come in two buffers (ping-pong for the out-of-place sort); the
+// buffer in use is BoxState::parity.
+struct BoxDev {
+    float* p[2][6];        // x, y, z, vx, vy, vz
+    float* v0[2][3];       // VACF reference velocities (null if untracked)
+    int32_t* pid[2];       // particle identity (admission order)
+    uint32_t* cell;        // collision cell of each particle, this step
+    uint32_t* rank;        // rank of each particle inside its key (sort)
+    CellAcc* acc;          // per cell
+    CellUN* un;            // per cell
+    uint32_t* cstart;      // per cell: counts, then exclusive starts (C + 1)
+    double* vacf;          // VACF samples
+    int64_t n;             // particles
+    int64_t ncell;
+    int32_t L[3];
+    int32_t vacf_stride;   // 0 = untracked
+    int32_t vacf_cap;
+    int32_t binning;       // MPCD_BIN_ATOMIC or MPCD_BIN_SORT
+    int32_t resort_period; // ATOMIC: re-sort by logical cell when k % period == 0
+    int32_t ptile0, ptile1;   // particle tiles [ptile0, ptile1)
+    int32_t ctile0, ctile1;   // cell tiles [ctile0, ctile1)
+    float len[3];          // L_d * a
+    float a, inv_a, dt;
+    float ca, sa, omc;     // cos(alpha), sin(alpha), 1 - cos(alpha) rounded from FP64
+    float mass;
+    uint32_t key0, key1;   // Philox key = seed
+    int32_t pad;
+};
+
+// Mutable per-box state, resident in device memory and advanced by the last
+// kernel of every step, so a captured step replays unchanged.
+struct BoxState {
+    long long k;           // steps completed
+    long long remaining;   // steps left; < 0 = unbounded
+    long long vacf_origin; // step at which v0 was taken
+    int parity;            // particle buffer in use
+    int vacf_len;
+    int status;            // 0 or MPCD_ESTATE
+    int sorted_now;        // set when this step re-sorted (diagnostic)
+    double diag[4];        // sum v (3), sum v^2 after the last step
+};
+
+// A contiguous range of one box's particles or cells.
+struct Tile {
+    int32_t box;
+    int32_t pad;
+    int64_t begin, end;
+};
+
+// ----------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64-bit
+// products whose halves are exchanged with the odd words and the round key;
+// the key advances by the Weyl increments after every round.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 ctr, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t a = ctr.x, b = ctr.z;
+        const uint32_t lo_a = a * 0xD2511F53u, hi_a = __umulhi(a, 0xD2511F53u);
+        const uint32_t lo_b = b * 0xCD9E8D57u, hi_b = __umulhi(b, 0xCD9E8D57u);
+        ctr = make_uint4(hi_b ^ ctr.y ^ k0, lo_b, hi_a ^ ctr.w ^ k1, lo_a);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return ctr;
+}
+
+// top 24 bits as a float in [0, 1); exact
+__device__ __forceinline__ float unit24(uint32_t r)
+{
+    return (float)(r >> 8) * 5.9604644775390625e-8f;   // 2^-24
+}
+
+// Grid shift of step k: s_d = a (u_d - 1/2), stream 0.
+__device__ __forceinline__ float3 grid_shift(const BoxDev& b, long long k)
+{
+    const uint4 r = philox4x32_10(
+        make_uint4((uint32_t)k, 0u, (uint32_t)((unsigned long long)k >> 32), 0u), b.key0, b.key1);
+    return make_float3(b.a * (unit24(r.x) - 0.5f), b.a * (unit24(r.y) - 0.5f),
+                       b.a * (unit24(r.z) - 0.5f));
+}
+
+// Rotation axis of canonical cell c at step k, uniform on the sphere
+// (z uniform in [-1, 1), azimuth uniform), stream 1.
+__device__ __forceinline__ float3 cell_axis(const BoxDev& b, long long k, uint32_t c)
+{
+    const uint4 q = philox4x32_10(
+        make_uint4((uint32_t)k, c, (uint32_t)((unsigned long long)k >> 32), 1u), b.key0, b.key1);
+    const float z = 2.0f * unit24(q.x) - 1.0f;
+    const float phi = 6.2831853071795864769f * unit24(q.y);
+    float sp, cp;
+    sincosf(phi, &sp, &cp);
+    const float rho = sqrtf(fmaxf(0.0f, 1.0f - z * z));
+    return make_float3(rho * cp, rho * sp, z);
+}
+
+// Periodic fold of a streamed coordinate into [0, len).
+__device__ __forceinline__ float fold(float x, float len)
+{
+    if (x < 0.0f || x >= len) {
+        if (x < -len || x >= 2.0f * len) x -= len * floorf(x / len);
+        if (x < 0.0f) x += len;
+        if (x >= len) x -= len;
+        if (x < 0.0f || x >= len) x = 0.0f;   // rounding landed on an edge
+    }
+    return x;
+}
+
+// Cell index along one axis of the grid displaced by s (floor((x - s)/a)),
+// folded periodically; clamped so it can never leave [0, L).
+__device__ __forceinline__ int axis_cell(float x, float s, float inv_a, int L)
+{
+    int i = (int)floorf((x - s) * inv_a);
+    if (i < 0) i += L;
+    if (i >= L) i -= L;
+    return min(max(i, 0), L - 1);
+}
+
+__device__ __forceinline__ uint32_t collision_cell(const BoxDev& b, float x, float y, float z,
+                                                   float3 s)
+{
+    const int ix = axis_cell(x, s.x, b.inv_a, b.L[0]);
+    const int iy = axis_cell(y, s.y, b.inv_a, b.L[1]);
+    const int iz = axis_cell(z, s.z, b.inv_a, b.L[2]);
+    return (uint32_t)ix + (uint32_t)b.L[0] * ((uint32_t)iy + (uint32_t)b.L[1] * (uint32_t)iz);
+}
+
+// Unshifted (logical) cell, used as the re-sort key.
+__device__ __forceinline__ uint32_t logical_cell(const BoxDev& b, float x, float y, float z)
+{
+    return collision_cell(b, x, y, z, make_float3(0.0f, 0.0f, 0.0f));
+}
+
+// Velocity in 64-bit fixed point with quantum 2^-32 (exact for |v| >= 2^-9,
+// nearest multiple of 2^-32 below that).  Saturates far outside the valid
+// range |v| < 2^30 (such a box is flagged by the rotation's range check).
+__device__ __forceinline__ unsigned long long to_fixed(float v)
+{
+    const float t = fminf(fmaxf(v * 4294967296.0f, -4.0e18f), 4.0e18f);
+    return (unsigned long long)(long long)rintf(t);
+}
+
+// Largest speed component the fixed-point cell sums accept.
+constexpr float kVelocityLimit = 1073741824.0f;   // 2^30
+
+// Adds +inf to an energy partial when a velocity leaves the valid range or
+// is not finite, so the box's diagnostics flag it.
+__device__ __forceinline__ void range_check(float3 v, double& energy)
+{
+    const float m = fmaxf(fabsf(v.x), fmaxf(fabsf(v.y), fabsf(v.z)));
+    if (!(m < kVelocityLimit)) energy = __builtin_inf();
+}
+
+__device__ __forceinline__ float fixed_mean(unsigned long long s, unsigned int n)
+{
+    return ((float)(long long)s * 2.3283064365386963e-10f) / (float)n;   // 2^-32
+}
+
+// v' = u + w cos(a) + (n x w) sin(a) + n (n.w)(1 - cos(a)), w = v - u
+__device__ __forceinline__ float3 rotate_about(const CellUN& c, float vx, float vy, float vz,
+                                               float ca, float sa, float omc)
+{
+    const float wx = vx - c.ux, wy = vy - c.uy, wz = vz - c.uz;
+    const float cx = c.ny * wz - c.nz * wy;
+    const float cy = c.nz * wx - c.nx * wz;
+    const float cz = c.nx * wy - c.ny * wx;
+    const float f = (c.nx * wx + c.ny * wy + c.nz * wz) * omc;
+    return make_float3(c.ux + fmaf(wx, ca, fmaf(cx, sa, c.nx * f)),
+                       c.uy + fmaf(wy, ca, fmaf(cy, sa, c.ny * f)),
+                       c.uz + fmaf(wz, ca, fmaf(cz, sa, c.nz * f)));
+}
+
+// Blocks are dealt round-robin to the 8 XCDs; renumber so that each XCD
+// works on one contiguous run of tiles (neighbouring tiles share boundary
+// cells, which then stay in one L2).
+__device__ __forceinline__ int xcd_tile(int bid, int nblocks)
+{
+    const int q = nblocks >> 3, r = nblocks & 7;
+    const int x = bid & 7, i = bid >> 3;
+    return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+}  // namespace mpcd

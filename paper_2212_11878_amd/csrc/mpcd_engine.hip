@@ -1,0 +1,778 @@
+// mpcd_engine.hip -- host runtime of libmpcd.so: contexts, box slots,
+// device tables, the per-step launch sequence (eager or replayed from a
+// captured hipGraph), per-kernel timing, and the C ABI of include/mpcd.h.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <map>
+#include <vector>
+
+#include "mpcd.h"
+#include "mpcd_dev.h"
+#include "mpcd_launch.h"
+
+using namespace mpcd;
+
+#define HIPCHK(expr)                                                        \
+    do {                                                                    \
+        hipError_t e_ = (expr);                                             \
+        if (e_ != hipSuccess) {                                             \
+            fprintf(stderr, "libmpcd: %s failed: %s (%s:%d)\n", #expr,      \
+                    hipGetErrorString(e_), __FILE__, __LINE__);             \
+            return MPCD_EDEVICE;                                            \
+        }                                                                   \
+    } while (0)
+
+namespace {
+
+enum Kern {
+    K_ZERO, K_COUNT, K_SCAN, K_SCATTER, K_FLIP, K_STREAM_BIN, K_FINALIZE, K_ROTATE,
+    K_CELL_ROTATE, K_BOX_FINISH, K_NUM
+};
+const char* const kKernName[K_NUM] = {
+    "zero_counts", "count", "scan", "scatter", "flip", "stream_bin", "finalize", "rotate",
+    "cell_rotate", "box_finish"};
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct Slot {
+    bool live = false;
+    mpcd_box_desc desc{};
+    void* mem = nullptr;
+    size_t bytes = 0;
+    BoxDev dev{};
+    int64_t ptiles = 0, ctiles = 0;
+    int32_t part_tile = kPartTile;   // particles per tile
+};
+
+}  // namespace
+
+struct mpcd_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    mpcd_alloc_fn alloc = nullptr;
+    mpcd_free_fn free = nullptr;
+    void* user = nullptr;
+    int64_t budget = 0, used = 0;
+    int32_t binning = MPCD_BIN_AUTO;
+    int32_t resort_period = 0;
+    int32_t block = 0;
+    bool use_graph = false;
+    int max_slots = 4096;
+    std::vector<Slot> slots;
+
+    // device tables
+    Tables T;
+    void* tab_mem = nullptr;         // boxes + state (fixed size, max_slots)
+    void* tile_mem = nullptr;        // tiles, active, partials, tilesum
+    size_t tile_cap = 0;
+    bool dirty = true;
+    bool any_atomic = false, any_sort = false;
+
+    // graph of one step
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+
+    // profiling
+    bool profiling = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    double prof_ms[K_NUM] = {};
+    int64_t prof_n[K_NUM] = {};
+
+    // host copies handed out by mpcd_observe
+    std::vector<double> vacf_host;
+    std::vector<float> stage;
+    std::vector<int32_t> stage_pid;
+};
+
+namespace {
+
+void* ctx_alloc(mpcd_ctx* c, size_t bytes)
+{
+    if (bytes == 0) bytes = 256;
+    if (c->alloc) return c->alloc(bytes, c->user);
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    return p;
+}
+
+void ctx_free(mpcd_ctx* c, void* p)
+{
+    if (!p) return;
+    if (c->free)
+        c->free(p, c->user);
+    else
+        (void)hipFree(p);
+}
+
+void drop_graph(mpcd_ctx* c)
+{
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+}
+
+// Layout of one box's device allocation.
+struct Layout {
+    size_t off_p[2][6], off_v0[2][3], off_pid[2], off_cell, off_rank, off_acc, off_un,
+        off_cstart, off_vacf, total;
+};
+
+Layout box_layout(int64_t n, int64_t ncell, bool vacf, int vacf_cap)
+{
+    Layout L{};
+    size_t o = 0;
+    const size_t pf = align256((size_t)n * 4);
+    for (int b = 0; b < 2; ++b)
+        for (int d = 0; d < 6; ++d) { L.off_p[b][d] = o; o += pf; }
+    for (int b = 0; b < 2; ++b)
+        for (int d = 0; d < 3; ++d) {
+            L.off_v0[b][d] = o;
+            if (vacf) o += pf;
+        }
+    for (int b = 0; b < 2; ++b) { L.off_pid[b] = o; o += pf; }
+    L.off_cell = o; o += pf;
+    L.off_rank = o; o += pf;
+    L.off_acc = o; o += align256((size_t)ncell * sizeof(CellAcc));
+    L.off_un = o; o += align256((size_t)ncell * sizeof(CellUN));
+    L.off_cstart = o; o += align256((size_t)(ncell + 1) * 4);
+    L.off_vacf = o; o += align256((size_t)std::max(vacf_cap, 1) * 8);
+    L.total = o;
+    return L;
+}
+
+int validate_desc(const mpcd_box_desc* d)
+{
+    if (!d) return MPCD_EINVAL;
+    int64_t C = 1;
+    for (int i = 0; i < 3; ++i) {
+        if (d->L[i] < 1 || d->L[i] > 4096) return MPCD_EINVAL;
+        C *= d->L[i];
+    }
+    if (C >= ((int64_t)1 << 31)) return MPCD_EINVAL;
+    if (!(d->a > 0.0) || !isfinite(d->a)) return MPCD_EINVAL;
+    if (d->n_particles < 0 || d->n_particles >= ((int64_t)1 << 31)) return MPCD_EINVAL;
+    if (!(d->dt > 0.0) || !isfinite(d->dt)) return MPCD_EINVAL;
+    if (!isfinite(d->alpha)) return MPCD_EINVAL;
+    if (!(d->mass > 0.0) || !isfinite(d->mass)) return MPCD_EINVAL;
+    if (d->n_steps < 0) return MPCD_EINVAL;
+    if (d->flags & ~(MPCD_INIT_MAXWELL | MPCD_INIT_EXTERNAL | MPCD_TRACK_VACF)) return MPCD_EINVAL;
+    const uint32_t init = d->flags & (MPCD_INIT_MAXWELL | MPCD_INIT_EXTERNAL);
+    if (init != MPCD_INIT_MAXWELL && init != MPCD_INIT_EXTERNAL) return MPCD_EINVAL;
+    if ((d->flags & MPCD_INIT_MAXWELL) && (!(d->kT > 0.0) || !isfinite(d->kT))) return MPCD_EINVAL;
+    if ((d->flags & MPCD_TRACK_VACF) && d->vacf_stride < 1) return MPCD_EINVAL;
+    if (d->vacf_capacity < 0) return MPCD_EINVAL;
+    for (int i = 0; i < 3; ++i)
+        if ((double)d->L[i] * d->a > 1e7) return MPCD_EINVAL;
+    return MPCD_OK;
+}
+
+int vacf_capacity(const mpcd_box_desc* d)
+{
+    if (!(d->flags & MPCD_TRACK_VACF)) return 1;
+    if (d->vacf_capacity > 0) return d->vacf_capacity;
+    if (d->n_steps > 0) return (int)std::min<int64_t>(d->n_steps / d->vacf_stride + 1, 1 << 24);
+    return 1024;
+}
+
+// Rebuild the device tables (tiles, active list, descriptors) for the live
+// slots.  Synchronises the stream first (old tables may still be in use).
+int rebuild_tables(mpcd_ctx* c)
+{
+    HIPCHK(hipStreamSynchronize(c->stream));
+    drop_graph(c);
+    std::vector<Tile> pt, ct;
+    std::vector<int32_t> active;
+    c->any_atomic = c->any_sort = false;
+    for (int s = 0; s < (int)c->slots.size(); ++s) {
+        Slot& sl = c->slots[s];
+        if (!sl.live) continue;
+        active.push_back(s);
+        BoxDev& b = sl.dev;
+        b.ptile0 = (int32_t)pt.size();
+        for (int64_t i = 0; i < b.n; i += sl.part_tile)
+            pt.push_back(Tile{s, 0, i, std::min<int64_t>(b.n, i + sl.part_tile)});
+        b.ptile1 = (int32_t)pt.size();
+        b.ctile0 = (int32_t)ct.size();
+        for (int64_t i = 0; i < b.ncell; i += kCellTile)
+            ct.push_back(Tile{s, 0, i, std::min<int64_t>(b.ncell, i + kCellTile)});
+        b.ctile1 = (int32_t)ct.size();
+        if (b.binning == MPCD_BIN_SORT)
+            c->any_sort = true;
+        else
+            c->any_atomic = true;
+    }
+    const size_t need = align256(pt.size() * sizeof(Tile) + 256) + align256(ct.size() * sizeof(Tile) + 256) +
+                        align256(active.size() * 4 + 256) + align256(pt.size() * kNumDiag * 8 + 256) +
+                        align256(ct.size() * kNumDiag * 8 + 256) + align256(ct.size() * 4 + 256);
+    if (need > c->tile_cap) {
+        void* m = ctx_alloc(c, need * 5 / 4);
+        if (!m) return MPCD_ENOMEM;
+        ctx_free(c, c->tile_mem);
+        c->tile_mem = m;
+        c->tile_cap = need * 5 / 4;
+    }
+    char* base = (char*)c->tile_mem;
+    size_t o = 0;
+    c->T.ptiles = (Tile*)(base + o); o += align256(pt.size() * sizeof(Tile) + 256);
+    c->T.ctiles = (Tile*)(base + o); o += align256(ct.size() * sizeof(Tile) + 256);
+    c->T.active = (int32_t*)(base + o); o += align256(active.size() * 4 + 256);
+    c->T.partials = (double*)(base + o); o += align256(pt.size() * kNumDiag * 8 + 256);
+    c->T.partials_c = (double*)(base + o); o += align256(ct.size() * kNumDiag * 8 + 256);
+    c->T.tilesum = (uint32_t*)(base + o);
+    c->T.nptiles = (int)pt.size();
+    c->T.nctiles = (int)ct.size();
+    c->T.nactive = (int)active.size();
+    if (!pt.empty()) HIPCHK(hipMemcpy(c->T.ptiles, pt.data(), pt.size() * sizeof(Tile), hipMemcpyHostToDevice));
+    if (!ct.empty()) HIPCHK(hipMemcpy(c->T.ctiles, ct.data(), ct.size() * sizeof(Tile), hipMemcpyHostToDevice));
+    if (!active.empty())
+        HIPCHK(hipMemcpy(c->T.active, active.data(), active.size() * 4, hipMemcpyHostToDevice));
+    for (int32_t s : active)
+        HIPCHK(hipMemcpy(&c->T.boxes[s], &c->slots[s].dev, sizeof(BoxDev), hipMemcpyHostToDevice));
+    c->dirty = false;
+    return MPCD_OK;
+}
+
+hipEvent_t get_event(mpcd_ctx* c)
+{
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+int harvest(mpcd_ctx* c)
+{
+    if (c->pending.empty()) return MPCD_OK;
+    HIPCHK(hipEventSynchronize(c->pending.back().second.second));
+    for (auto& p : c->pending) {
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, p.second.first, p.second.second));
+        c->prof_ms[p.first] += ms;
+        c->prof_n[p.first] += 1;
+        c->ev_pool.push_back(p.second.first);
+        c->ev_pool.push_back(p.second.second);
+    }
+    c->pending.clear();
+    return MPCD_OK;
+}
+
+template <class F>
+int timed(mpcd_ctx* c, int k, F&& launch)
+{
+    if (!c->profiling) {
+        launch();
+        return MPCD_OK;
+    }
+    hipEvent_t a = get_event(c), b = get_event(c);
+    if (!a || !b) return MPCD_EDEVICE;
+    HIPCHK(hipEventRecord(a, c->stream));
+    launch();
+    HIPCHK(hipEventRecord(b, c->stream));
+    c->pending.push_back({k, {a, b}});
+    return MPCD_OK;
+}
+
+// The launch sequence of one step for every live box.
+int enqueue_step(mpcd_ctx* c)
+{
+    const Tables& T = c->T;
+    hipStream_t s = c->stream;
+    int rc = MPCD_OK;
+#define STEP_K(id, call)                                       \
+    do {                                                       \
+        rc = timed(c, id, [&] { call; });                      \
+        if (rc) return rc;                                     \
+    } while (0)
+    // counting sort: every step for SORT boxes, every resort_period steps for ATOMIC boxes
+    STEP_K(K_ZERO, launch_zero_counts(T, s));
+    STEP_K(K_COUNT, launch_count(T, s));
+    STEP_K(K_SCAN, launch_scan(T, s));
+    STEP_K(K_SCATTER, launch_scatter(T, s));
+    STEP_K(K_FLIP, launch_flip(T, s));
+    if (c->any_atomic) {
+        STEP_K(K_STREAM_BIN, launch_stream_bin(T, s));
+        STEP_K(K_FINALIZE, launch_finalize(T, s));
+        STEP_K(K_ROTATE, launch_rotate(T, s));
+    }
+    if (c->any_sort) STEP_K(K_CELL_ROTATE, launch_cell_rotate(T, s));
+    STEP_K(K_BOX_FINISH, launch_box_finish(T, s));
+#undef STEP_K
+    HIPCHK(hipGetLastError());
+    return MPCD_OK;
+}
+
+int capture_graph(mpcd_ctx* c)
+{
+    drop_graph(c);
+    HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    int rc = enqueue_step(c);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->stream, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    HIPCHK(e);
+    c->graph = g;
+    HIPCHK(hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0));
+    return MPCD_OK;
+}
+
+Slot* live_slot(mpcd_ctx* c, int32_t slot)
+{
+    if (!c || slot < 0 || slot >= (int)c->slots.size() || !c->slots[slot].live) return nullptr;
+    return &c->slots[slot];
+}
+
+// FP64 sums of kNumDiag partials over one box's particle tiles (host side,
+// after a synchronising copy).
+int read_box_partials(mpcd_ctx* c, const Slot& sl, double out[kNumDiag])
+{
+    const int n = sl.dev.ptile1 - sl.dev.ptile0;
+    std::vector<double> h((size_t)n * kNumDiag);
+    if (n > 0)
+        HIPCHK(hipMemcpyAsync(h.data(), c->T.partials + (size_t)sl.dev.ptile0 * kNumDiag,
+                              h.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int j = 0; j < kNumDiag; ++j) out[j] = 0.0;
+    for (int t = 0; t < n; ++t)
+        for (int j = 0; j < kNumDiag; ++j) out[j] += h[(size_t)t * kNumDiag + j];
+    return MPCD_OK;
+}
+
+// Write a fresh BoxState for slot s.
+int reset_state(mpcd_ctx* c, int32_t s, int64_t step, int parity)
+{
+    Slot& sl = c->slots[s];
+    BoxState st{};
+    st.k = step;
+    st.remaining = sl.desc.n_steps > 0 ? std::max<int64_t>(sl.desc.n_steps - step, 0) : -1;
+    st.vacf_origin = step;
+    st.parity = parity;
+    st.vacf_len = 0;
+    st.status = 0;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpy(&c->T.state[s], &st, sizeof(BoxState), hipMemcpyHostToDevice));
+    return MPCD_OK;
+}
+
+// v0 <- v (if tracked), record VACF sample 0 and the diagnostics of the
+// current state.
+int take_snapshot(mpcd_ctx* c, int32_t s)
+{
+    Slot& sl = c->slots[s];
+    const Tile* tiles = c->T.ptiles + sl.dev.ptile0;
+    launch_snapshot(tiles, sl.dev.ptile1 - sl.dev.ptile0, c->T, 1, c->stream);
+    HIPCHK(hipGetLastError());
+    double d[kNumDiag];
+    int rc = read_box_partials(c, sl, d);
+    if (rc) return rc;
+    BoxState st;
+    HIPCHK(hipMemcpy(&st, &c->T.state[s], sizeof(BoxState), hipMemcpyDeviceToHost));
+    st.diag[0] = d[0];
+    st.diag[1] = d[1];
+    st.diag[2] = d[2];
+    st.diag[3] = d[3];
+    st.vacf_len = 0;
+    if (sl.dev.vacf_stride > 0 && sl.dev.n > 0) {
+        const double c0 = d[4] / (double)sl.dev.n;
+        HIPCHK(hipMemcpy(sl.dev.vacf, &c0, 8, hipMemcpyHostToDevice));
+        st.vacf_len = 1;
+    }
+    st.status = (d[3] < 1e300 && d[3] >= 0.0) ? 0 : MPCD_ESTATE;
+    HIPCHK(hipMemcpy(&c->T.state[s], &st, sizeof(BoxState), hipMemcpyHostToDevice));
+    return MPCD_OK;
+}
+
+int init_maxwell(mpcd_ctx* c, int32_t s)
+{
+    Slot& sl = c->slots[s];
+    const int64_t n = sl.dev.n;
+    const Tile* tiles = c->T.ptiles + sl.dev.ptile0;
+    const int nt = sl.dev.ptile1 - sl.dev.ptile0;
+    const double vs = sqrt(sl.desc.kT / sl.desc.mass);
+    launch_init_maxwell(tiles, nt, c->T, (float)vs, c->stream);
+    HIPCHK(hipGetLastError());
+    double d[kNumDiag];
+    int rc = read_box_partials(c, sl, d);
+    if (rc) return rc;
+    if (n > 1) {
+        const double mx = d[0] / n, my = d[1] / n, mz = d[2] / n;
+        // centre, then measure
+        launch_init_adjust(tiles, nt, c->T, (float)mx, (float)my, (float)mz, 1.0f, c->stream);
+        HIPCHK(hipGetLastError());
+        rc = read_box_partials(c, sl, d);
+        if (rc) return rc;
+        const double m = sl.desc.mass;
+        const double P2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        const double T = m * (d[3] - P2 / n) / (3.0 * (n - 1));
+        const double scale = T > 0 ? sqrt(sl.desc.kT / T) : 1.0;
+        launch_init_adjust(tiles, nt, c->T, 0.0f, 0.0f, 0.0f, (float)scale, c->stream);
+        HIPCHK(hipGetLastError());
+    }
+    return MPCD_OK;
+}
+
+}  // namespace
+
+// ==========================================================================
+// C ABI
+
+extern "C" {
+
+int mpcd_abi_version(void) { return MPCD_ABI_VERSION; }
+
+const char* mpcd_strerror(int status)
+{
+    switch (status) {
+        case MPCD_OK: return "ok";
+        case MPCD_EINVAL: return "invalid argument";
+        case MPCD_ENOMEM: return "device memory budget exceeded or allocation failed";
+        case MPCD_EDEVICE: return "HIP runtime error";
+        case MPCD_EBUSY: return "no free slot";
+        case MPCD_ESTATE: return "non-finite state detected";
+        case MPCD_ENOTFOUND: return "slot not live";
+        default: return "unknown status";
+    }
+}
+
+int mpcd_create(const mpcd_options* opt, mpcd_ctx** out)
+{
+    if (!out) return MPCD_EINVAL;
+    *out = nullptr;
+    mpcd_options o{};
+    if (opt) o = *opt;
+    if (o.binning < 0 || o.binning > 2 || o.resort_period < 0 || o.hbm_budget < 0 || o.max_slots < 0)
+        return MPCD_EINVAL;
+    if (o.block != 0 && o.block != 256 && o.block != 512 && o.block != 1024) return MPCD_EINVAL;
+    if ((o.alloc == nullptr) != (o.free == nullptr)) return MPCD_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return MPCD_EDEVICE;
+    if (o.device < 0 || o.device >= ndev) return MPCD_EINVAL;
+    HIPCHK(hipSetDevice(o.device));
+    mpcd_ctx* c = new mpcd_ctx();
+    c->device = o.device;
+    c->alloc = o.alloc;
+    c->free = o.free;
+    c->user = o.user;
+    c->budget = o.hbm_budget;
+    c->binning = o.binning;
+    c->resort_period = o.resort_period;
+    c->block = o.block;
+    c->use_graph = o.use_graph != 0;
+    c->max_slots = o.max_slots > 0 ? o.max_slots : 4096;
+    if (o.stream) {
+        c->stream = (hipStream_t)o.stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return MPCD_EDEVICE;
+        }
+        c->own_stream = true;
+    }
+    const size_t tab = align256(sizeof(BoxDev) * c->max_slots) + align256(sizeof(BoxState) * c->max_slots);
+    c->tab_mem = ctx_alloc(c, tab);
+    if (!c->tab_mem) {
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
+        delete c;
+        return MPCD_ENOMEM;
+    }
+    c->T.boxes = (BoxDev*)c->tab_mem;
+    c->T.state = (BoxState*)((char*)c->tab_mem + align256(sizeof(BoxDev) * c->max_slots));
+    *out = c;
+    return MPCD_OK;
+}
+
+int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
+{
+    if (!c || !slot) return MPCD_EINVAL;
+    int rc = validate_desc(d);
+    if (rc) return rc;
+    int s = -1;
+    for (int i = 0; i < (int)c->slots.size(); ++i)
+        if (!c->slots[i].live) { s = i; break; }
+    if (s < 0) {
+        if ((int)c->slots.size() >= c->max_slots) return MPCD_EBUSY;
+        s = (int)c->slots.size();
+    }
+    const bool vacf = (d->flags & MPCD_TRACK_VACF) != 0;
+    const int64_t ncell = (int64_t)d->L[0] * d->L[1] * d->L[2];
+    const int cap = vacf_capacity(d);
+    const Layout L = box_layout(d->n_particles, ncell, vacf, cap);
+    if (c->budget > 0 && c->used + (int64_t)L.total > c->budget) return MPCD_ENOMEM;
+    HIPCHK(hipSetDevice(c->device));
+    void* mem = ctx_alloc(c, L.total);
+    if (!mem) return MPCD_ENOMEM;
+
+    Slot sl;
+    sl.live = true;
+    sl.desc = *d;
+    sl.mem = mem;
+    sl.bytes = L.total;
+    BoxDev& b = sl.dev;
+    char* m = (char*)mem;
+    for (int p = 0; p < 2; ++p) {
+        for (int k = 0; k < 6; ++k) b.p[p][k] = (float*)(m + L.off_p[p][k]);
+        for (int k = 0; k < 3; ++k) b.v0[p][k] = vacf ? (float*)(m + L.off_v0[p][k]) : nullptr;
+        b.pid[p] = (int32_t*)(m + L.off_pid[p]);
+    }
+    b.cell = (uint32_t*)(m + L.off_cell);
+    b.rank = (uint32_t*)(m + L.off_rank);
+    b.acc = (CellAcc*)(m + L.off_acc);
+    b.un = (CellUN*)(m + L.off_un);
+    b.cstart = (uint32_t*)(m + L.off_cstart);
+    b.vacf = (double*)(m + L.off_vacf);
+    b.n = d->n_particles;
+    b.ncell = ncell;
+    for (int k = 0; k < 3; ++k) {
+        b.L[k] = d->L[k];
+        b.len[k] = (float)(d->L[k] * d->a);
+    }
+    b.vacf_stride = vacf ? d->vacf_stride : 0;
+    b.vacf_cap = cap;
+    b.binning = c->binning == MPCD_BIN_SORT ? MPCD_BIN_SORT : MPCD_BIN_ATOMIC;
+    b.resort_period = c->resort_period > 0 ? c->resort_period : 20;
+    b.a = (float)d->a;
+    b.inv_a = (float)(1.0 / d->a);
+    b.dt = (float)d->dt;
+    b.ca = (float)cos(d->alpha);
+    b.sa = (float)sin(d->alpha);
+    b.omc = (float)(1.0 - cos(d->alpha));
+    b.mass = (float)d->mass;
+    b.key0 = (uint32_t)(d->seed & 0xffffffffu);
+    b.key1 = (uint32_t)(d->seed >> 32);
+    if (s == (int)c->slots.size())
+        c->slots.push_back(sl);
+    else
+        c->slots[s] = sl;
+
+    auto undo = [&](int code) {
+        c->slots[s].live = false;
+        ctx_free(c, mem);
+        c->dirty = true;
+        (void)rebuild_tables(c);
+        return code;
+    };
+    rc = rebuild_tables(c);
+    if (rc) return undo(rc);
+    // zeroed cell accumulators and a defined particle state
+    Slot& S = c->slots[s];
+    if (hipMemsetAsync(S.dev.acc, 0, ncell * sizeof(CellAcc), c->stream) != hipSuccess) return undo(MPCD_EDEVICE);
+    if (hipMemsetAsync(S.dev.un, 0, ncell * sizeof(CellUN), c->stream) != hipSuccess) return undo(MPCD_EDEVICE);
+    rc = reset_state(c, s, 0, 0);
+    if (rc) return undo(rc);
+    if (d->flags & MPCD_INIT_MAXWELL) {
+        rc = init_maxwell(c, s);
+    } else {
+        for (int k = 0; k < 6; ++k)
+            if (hipMemsetAsync(S.dev.p[0][k], 0, (size_t)S.dev.n * 4, c->stream) != hipSuccess)
+                return undo(MPCD_EDEVICE);
+        launch_fill_iota(S.dev.pid[0], S.dev.n, c->stream);
+    }
+    if (rc) return undo(rc);
+    rc = take_snapshot(c, s);
+    if (rc) return undo(rc);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return undo(MPCD_EDEVICE);
+    c->used += (int64_t)L.total;
+    *slot = s;
+    return MPCD_OK;
+}
+
+int mpcd_step(mpcd_ctx* c, int32_t n)
+{
+    if (!c || n < 0) return MPCD_EINVAL;
+    if (n == 0 || c->T.nactive == 0) return MPCD_OK;
+    HIPCHK(hipSetDevice(c->device));
+    if (c->dirty) {
+        int rc = rebuild_tables(c);
+        if (rc) return rc;
+    }
+    const bool graph = c->use_graph && !c->profiling;
+    if (graph && !c->graph_exec) {
+        int rc = capture_graph(c);
+        if (rc) return rc;
+    }
+    for (int i = 0; i < n; ++i) {
+        if (graph) {
+            HIPCHK(hipGraphLaunch(c->graph_exec, c->stream));
+        } else {
+            int rc = enqueue_step(c);
+            if (rc) return rc;
+            if (c->pending.size() > 4096) {
+                rc = harvest(c);
+                if (rc) return rc;
+            }
+        }
+    }
+    return MPCD_OK;
+}
+
+int mpcd_observe(mpcd_ctx* c, int32_t slot, mpcd_observables* out)
+{
+    if (!c || !out) return MPCD_EINVAL;
+    Slot* sl = live_slot(c, slot);
+    if (!sl) return MPCD_ENOTFOUND;
+    HIPCHK(hipSetDevice(c->device));
+    BoxState st;
+    HIPCHK(hipMemcpyAsync(&st, &c->T.state[slot], sizeof(BoxState), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->vacf_host.assign((size_t)std::max(st.vacf_len, 0), 0.0);
+    if (st.vacf_len > 0)
+        HIPCHK(hipMemcpy(c->vacf_host.data(), sl->dev.vacf, (size_t)st.vacf_len * 8, hipMemcpyDeviceToHost));
+    const double m = sl->desc.mass;
+    const int64_t n = sl->dev.n;
+    memset(out, 0, sizeof(*out));
+    out->step = st.k;
+    for (int d = 0; d < 3; ++d) out->P[d] = m * st.diag[d];
+    out->E_kin = 0.5 * m * st.diag[3];
+    out->mass_total = m * (double)n;
+    if (n > 1) {
+        const double P2 = st.diag[0] * st.diag[0] + st.diag[1] * st.diag[1] + st.diag[2] * st.diag[2];
+        out->T = m * (st.diag[3] - P2 / (double)n) / (3.0 * (double)(n - 1));
+    }
+    out->status = st.status ? MPCD_ESTATE : MPCD_OK;
+    out->vacf_len = st.vacf_len;
+    out->vacf = c->vacf_host.empty() ? nullptr : c->vacf_host.data();
+    out->n_particles = n;
+    out->binning = sl->dev.binning;
+    out->resort_period = sl->dev.resort_period;
+    return out->status;
+}
+
+int mpcd_get_state(mpcd_ctx* c, int32_t slot, float* xyzv, int64_t* step)
+{
+    Slot* sl = live_slot(c, slot);
+    if (!c || !xyzv) return MPCD_EINVAL;
+    if (!sl) return MPCD_ENOTFOUND;
+    HIPCHK(hipSetDevice(c->device));
+    BoxState st;
+    HIPCHK(hipMemcpyAsync(&st, &c->T.state[slot], sizeof(BoxState), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const int64_t n = sl->dev.n;
+    c->stage.resize((size_t)n);
+    c->stage_pid.resize((size_t)n);
+    if (n > 0) {
+        HIPCHK(hipMemcpy(c->stage_pid.data(), sl->dev.pid[st.parity], (size_t)n * 4, hipMemcpyDeviceToHost));
+        for (int d = 0; d < 6; ++d) {
+            HIPCHK(hipMemcpy(c->stage.data(), sl->dev.p[st.parity][d], (size_t)n * 4, hipMemcpyDeviceToHost));
+            float* dst = xyzv + (size_t)d * n;
+            for (int64_t i = 0; i < n; ++i) {
+                const int32_t id = c->stage_pid[i];
+                if (id < 0 || id >= n) return MPCD_ESTATE;
+                dst[id] = c->stage[i];
+            }
+        }
+    }
+    if (step) *step = st.k;
+    return MPCD_OK;
+}
+
+int mpcd_set_state(mpcd_ctx* c, int32_t slot, const float* xyzv, int64_t step)
+{
+    Slot* sl = live_slot(c, slot);
+    if (!c || !xyzv || step < 0) return MPCD_EINVAL;
+    if (!sl) return MPCD_ENOTFOUND;
+    const int64_t n = sl->dev.n;
+    for (int d = 0; d < 3; ++d) {
+        const float len = sl->dev.len[d];
+        const float* p = xyzv + (size_t)d * n;
+        for (int64_t i = 0; i < n; ++i)
+            if (!(p[i] >= 0.0f && p[i] < len)) return MPCD_EINVAL;
+    }
+    for (int64_t i = 3 * n; i < 6 * n; ++i)
+        if (!isfinite(xyzv[i])) return MPCD_EINVAL;
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (n > 0) {
+        for (int d = 0; d < 6; ++d)
+            HIPCHK(hipMemcpy(sl->dev.p[0][d], xyzv + (size_t)d * n, (size_t)n * 4, hipMemcpyHostToDevice));
+        launch_fill_iota(sl->dev.pid[0], n, c->stream);
+        HIPCHK(hipGetLastError());
+    }
+    int rc = reset_state(c, slot, step, 0);
+    if (rc) return rc;
+    rc = take_snapshot(c, slot);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return MPCD_OK;
+}
+
+int mpcd_release(mpcd_ctx* c, int32_t slot)
+{
+    Slot* sl = live_slot(c, slot);
+    if (!c) return MPCD_EINVAL;
+    if (!sl) return MPCD_ENOTFOUND;
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    ctx_free(c, sl->mem);
+    c->used -= (int64_t)sl->bytes;
+    sl->live = false;
+    sl->mem = nullptr;
+    c->dirty = true;
+    return rebuild_tables(c);
+}
+
+int mpcd_profile(mpcd_ctx* c, int32_t enable)
+{
+    if (!c) return MPCD_EINVAL;
+    HIPCHK(hipSetDevice(c->device));
+    int rc = harvest(c);
+    if (rc) return rc;
+    if (enable) {
+        for (int k = 0; k < K_NUM; ++k) {
+            c->prof_ms[k] = 0.0;
+            c->prof_n[k] = 0;
+        }
+    }
+    c->profiling = enable != 0;
+    return MPCD_OK;
+}
+
+int mpcd_kernel_stats(mpcd_ctx* c, mpcd_kernel_stat* out, int32_t max, int32_t* count)
+{
+    if (!c || !count || max < 0 || (max > 0 && !out)) return MPCD_EINVAL;
+    HIPCHK(hipSetDevice(c->device));
+    int rc = harvest(c);
+    if (rc) return rc;
+    int n = 0;
+    for (int k = 0; k < K_NUM; ++k) {
+        if (c->prof_n[k] == 0) continue;
+        if (n < max) {
+            out[n].name = kKernName[k];
+            out[n].launches = c->prof_n[k];
+            out[n].total_ms = c->prof_ms[k];
+        }
+        ++n;
+    }
+    *count = n;
+    return MPCD_OK;
+}
+
+void mpcd_destroy(mpcd_ctx* c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    (void)harvest(c);
+    drop_graph(c);
+    for (auto& sl : c->slots)
+        if (sl.live) ctx_free(c, sl.mem);
+    ctx_free(c, c->tile_mem);
+    ctx_free(c, c->tab_mem);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+}  // extern "C"

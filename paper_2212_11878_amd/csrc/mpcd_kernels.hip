@@ -1,0 +1,647 @@
+// mpcd_kernels.hip -- HIP kernels of the SRD step for gfx950 (MI355X).
+//
+// One step of a box (paper Sec. 2; shifted grid of Sec. 3.1, Listing 1;
+// mass-weighted cell velocity of Sec. 3.3, Listing 4) runs as:
+//
+//   ATOMIC binning (particles kept near cell order by a periodic re-sort)
+//     [re-sort by logical cell when k % period == 0: zero, count, scan, scatter, flip]
+//     k_stream_bin   x <- fold(x + v dt); c = cell of (x - s); acc[c] += (v, 1)
+//     k_finalize     u_c = sum v / n, axis n_c from Philox; zero acc
+//     k_rotate       v <- u_c + R(n_c, alpha)(v - u_c); FP64 partial diagnostics
+//     k_box_finish   per box: reduce partials, VACF sample, k++
+//
+//   SORT binning (counting sort by collision cell every step)
+//     zero, k_count (streamed collision cell + rank), scan, k_scatter (streams
+//     while moving), flip, k_cell_rotate (one thread per cell over its
+//     contiguous run), k_box_finish
+//
+// Both paths sum the momentum of a cell exactly (64-bit fixed point), so
+// they produce bit-identical velocities whatever the order of the atomics.
+// All kernels grid over "tiles" (contiguous particle or cell ranges of one
+// box), which lets one launch advance many boxes of different sizes.
+#include "mpcd_dev.h"
+#include "mpcd_launch.h"
+
+namespace mpcd {
+
+// --------------------------------------------------------------------------
+// small helpers
+
+__device__ __forceinline__ bool box_idle(const BoxState& s) { return s.remaining == 0; }
+
+__device__ __forceinline__ bool sort_due(const BoxDev& b, const BoxState& s)
+{
+    if (b.binning == 2) return true;
+    return b.resort_period > 0 && (s.k % b.resort_period) == 0;
+}
+
+__device__ __forceinline__ bool vacf_due(const BoxDev& b, const BoxState& s)
+{
+    return b.vacf_stride > 0 && ((s.k + 1 - s.vacf_origin) % b.vacf_stride) == 0;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Deterministic block sum of kNumDiag doubles; thread 0 writes out[0..].
+__device__ __forceinline__ void block_diag(double (&d)[kNumDiag], double* out)
+{
+    __shared__ double red[kBlock / kWave][kNumDiag];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+#pragma unroll
+    for (int j = 0; j < kNumDiag; ++j) {
+        const double v = wave_sum(d[j]);
+        if (lane == 0) red[w][j] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kNumDiag) {
+        double v = 0.0;
+        for (int i = 0; i < kBlock / kWave; ++i) v += red[i][threadIdx.x];
+        out[threadIdx.x] = v;
+    }
+}
+
+// Block-wide exclusive scan of one uint32 per thread; returns the prefix and
+// the block total in *total.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* total)
+{
+    __shared__ uint32_t wsum[kBlock / kWave];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    uint32_t incl = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t t = __shfl_up(incl, o, kWave);
+        if (lane >= o) incl += t;
+    }
+    if (lane == kWave - 1) wsum[w] = incl;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < kBlock / kWave; ++i) {
+        const uint32_t s = wsum[i];
+        if (i < w) base += s;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return base + incl - v;
+}
+
+// --------------------------------------------------------------------------
+// ATOMIC path
+
+__global__ __launch_bounds__(kBlock) void k_stream_bin(const Tile* __restrict__ tiles,
+                                                        const BoxDev* __restrict__ boxes,
+                                                        const BoxState* __restrict__ st)
+{
+    const Tile tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    const BoxState s = st[tl.box];
+    const BoxDev& b = boxes[tl.box];
+    if (box_idle(s) || b.binning != 1) return;
+    float* __restrict__ x = b.p[s.parity][0];
+    float* __restrict__ y = b.p[s.parity][1];
+    float* __restrict__ z = b.p[s.parity][2];
+    const float* __restrict__ vx = b.p[s.parity][3];
+    const float* __restrict__ vy = b.p[s.parity][4];
+    const float* __restrict__ vz = b.p[s.parity][5];
+    uint32_t* __restrict__ cell = b.cell;
+    CellAcc* __restrict__ acc = b.acc;
+    const float3 sh = grid_shift(b, s.k);
+    const float dt = b.dt, l0 = b.len[0], l1 = b.len[1], l2 = b.len[2];
+    for (int64_t i = tl.begin + threadIdx.x; i < tl.end; i += kBlock) {
+        const float ux = vx[i], uy = vy[i], uz = vz[i];
+        const float px = fold(fmaf(ux, dt, x[i]), l0);
+        const float py = fold(fmaf(uy, dt, y[i]), l1);
+        const float pz = fold(fmaf(uz, dt, z[i]), l2);
+        x[i] = px;
+        y[i] = py;
+        z[i] = pz;
+        const uint32_t c = collision_cell(b, px, py, pz, sh);
+        cell[i] = c;
+        atomicAdd(&acc[c].sx, to_fixed(ux));
+        atomicAdd(&acc[c].sy, to_fixed(uy));
+        atomicAdd(&acc[c].sz, to_fixed(uz));
+        atomicAdd(&acc[c].n, 1u);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_finalize(const Tile* __restrict__ tiles,
+                                                      const BoxDev* __restrict__ boxes,
+                                                      const BoxState* __restrict__ st)
+{
+    const Tile tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    const BoxState s = st[tl.box];
+    const BoxDev& b = boxes[tl.box];
+    if (box_idle(s) || b.binning != 1) return;
+    CellAcc* __restrict__ acc = b.acc;
+    CellUN* __restrict__ un = b.un;
+    for (int64_t c = tl.begin + threadIdx.x; c < tl.end; c += kBlock) {
+        const CellAcc a = acc[c];
+        if (a.n == 0) continue;
+        CellUN u;
+        u.ux = fixed_mean(a.sx, a.n);
+        u.uy = fixed_mean(a.sy, a.n);
+        u.uz = fixed_mean(a.sz, a.n);
+        const float3 ax = cell_axis(b, s.k, (uint32_t)c);
+        u.nx = ax.x;
+        u.ny = ax.y;
+        u.nz = ax.z;
+        u.pad0 = 0.0f;
+        u.pad1 = 0.0f;
+        un[c] = u;
+        CellAcc zero = {0ull, 0ull, 0ull, 0u, 0u};
+        acc[c] = zero;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_rotate(const Tile* __restrict__ tiles,
+                                                    const BoxDev* __restrict__ boxes,
+                                                    const BoxState* __restrict__ st,
+                                                    double* __restrict__ partials)
+{
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const Tile tl = tiles[t];
+    const BoxState s = st[tl.box];
+    const BoxDev& b = boxes[tl.box];
+    if (box_idle(s) || b.binning != 1) return;
+    float* __restrict__ vx = b.p[s.parity][3];
+    float* __restrict__ vy = b.p[s.parity][4];
+    float* __restrict__ vz = b.p[s.parity][5];
+    const uint32_t* __restrict__ cell = b.cell;
+    const CellUN* __restrict__ un = b.un;
+    const bool vacf = vacf_due(b, s);
+    const float* __restrict__ w0x = b.v0[s.parity][0];
+    const float* __restrict__ w0y = b.v0[s.parity][1];
+    const float* __restrict__ w0z = b.v0[s.parity][2];
+    const float ca = b.ca, sa = b.sa, omc = b.omc;
+    double d[kNumDiag] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = tl.begin + threadIdx.x; i < tl.end; i += kBlock) {
+        const CellUN u = un[cell[i]];
+        const float3 v = rotate_about(u, vx[i], vy[i], vz[i], ca, sa, omc);
+        vx[i] = v.x;
+        vy[i] = v.y;
+        vz[i] = v.z;
+        d[0] += (double)v.x;
+        d[1] += (double)v.y;
+        d[2] += (double)v.z;
+        d[3] += (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z;
+        if (vacf) d[4] += (double)v.x * w0x[i] + (double)v.y * w0y[i] + (double)v.z * w0z[i];
+        range_check(v, d[3]);
+    }
+    block_diag(d, partials + (size_t)t * kNumDiag);
+}
+
+// --------------------------------------------------------------------------
+// counting sort (re-sort by logical cell for ATOMIC; by collision cell for SORT)
+
+__global__ __launch_bounds__(kBlock) void k_zero_counts(const Tile* __restrict__ tiles,
+                                                         const BoxDev* __restrict__ boxes,
+                                                         const BoxState* __restrict__ st)
+{
+    const Tile tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    const BoxState s = st[tl.box];
+    const BoxDev& b = boxes[tl.box];
+    if (box_idle(s) || !sort_due(b, s)) return;
+    for (int64_t c = tl.begin + threadIdx.x; c < tl.end; c += kBlock) b.cstart[c] = 0u;
+    if (tl.end == b.ncell && threadIdx.x == 0) b.cstart[b.ncell] = 0u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_count(const Tile* __restrict__ tiles,
+                                                   const BoxDev* __restrict__ boxes,
+                                                   const BoxState* __restrict__ st)
+{
+    const Tile tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    const BoxState s = st[tl.box];
+    const BoxDev& b = boxes[tl.box];
+    if (box_idle(s) || !sort_due(b, s)) return;
+    const float* __restrict__ x = b.p[s.parity][0];
+    const float* __restrict__ y = b.p[s.parity][1];
+    const float* __restrict__ z = b.p[s.parity][2];
+    const float* __restrict__ vx = b.p[s.parity][3];
+    const float* __restrict__ vy = b.p[s.parity][4];
+    const float* __restrict__ vz = b.p[s.parity][5];
+    const bool collide_key = (b.binning == 2);
+    const float3 sh = collide_key ? grid_shift(b, s.k) : make_float3(0.0f, 0.0f, 0.0f);
+    const float dt = b.dt;
+    for (int64_t i = tl.begin + threadIdx.x; i < tl.end; i += kBlock) {
+        float px = x[i], py = y[i], pz = z[i];
+        if (collide_key) {
+            px = fold(fmaf(vx[i], dt, px), b.len[0]);
+            py = fold(fmaf(vy[i], dt, py), b.len[1]);
+            pz = fold(fmaf(vz[i], dt, pz), b.len[2]);
+        }
+        const uint32_t key = collision_cell(b, px, py, pz, sh);
+        b.cell[i] = key;
+        b.rank[i] = atomicAdd(&b.cstart[key], 1u);
+    }
+}
+
+// per cell tile: total count
+__global__ __launch_bounds__(kBlock) void k_scan_tilesum(const Tile* __restrict__ tiles,
+                                                          const BoxDev* __restrict__ boxes,
+                                                          const BoxState* __restrict__ st,
+                                                          uint32_t* __restrict__ tilesum)
+{
+    const int t = blockIdx.x;
+    const Tile tl = tiles[t];
+    const BoxState s = st[tl.box];
+    const BoxDev& b = boxes[tl.box];
+    if (box_idle(s) || !sort_due(b, s)) return;
+    uint32_t v = 0;
+    for (int64_t c = tl.begin + threadIdx.x; c < tl.end; c += kBlock) v += b.cstart[c];
+    uint32_t total;
+    block_exclusive_scan(v, &total);
+    if (threadIdx.x == 0) tilesum[t] = total;
+}
+
+// per box: exclusive scan of its tiles' totals (in place)
+__global__ __launch_bounds__(kBlock) void k_scan_box(const int32_t* __restrict__ active,
+                                                      const BoxDev* __restrict__ boxes,
+                                                      const BoxState* __restrict__ st,
+                                                      uint32_t* __restrict__ tilesum)
+{
+    const int bx = active[blockIdx.x];
+    const BoxState s = st[bx];
+    const BoxDev& b = boxes[bx];
+    if (box_idle(s) || !sort_due(b, s)) return;
+    const int t0 = b.ctile0, nt = b.ctile1 - b.ctile0;
+    const int per = (nt + kBlock - 1) / kBlock;
+    const int lo = t0 + min(nt, (int)threadIdx.x * per), hi = t0 + min(nt, ((int)threadIdx.x + 1) * per);
+    uint32_t v = 0;
+    for (int t = lo; t < hi; ++t) v += tilesum[t];
+    uint32_t total;
+    uint32_t run = block_exclusive_scan(v, &total);
+    for (int t = lo; t < hi; ++t) {
+        const uint32_t c = tilesum[t];
+        tilesum[t] = run;
+        run += c;
+    }
+}
+
+// per cell tile: exclusive scan of counts into starts
+__global__ __launch_bounds__(kBlock) void k_scan_apply(const Tile* __restrict__ tiles,
+                                                        const BoxDev* __restrict__ boxes,
+                                                        const BoxState* __restrict__ st,
+                                                        const uint32_t* __restrict__ tilesum)
+{
+    constexpr int kPer = kCellTile / kBlock;
+    const int t = blockIdx.x;
+    const Tile tl = tiles[t];
+    const BoxState s = st[tl.box];
+    const BoxDev& b = boxes[tl.box];
+    if (box_idle(s) || !sort_due(b, s)) return;
+    const int64_t c0 = tl.begin + (int64_t)threadIdx.x * kPer;
+    uint32_t loc[kPer];
+    uint32_t v = 0;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        loc[j] = (c0 + j < tl.end) ? b.cstart[c0 + j] : 0u;
+        v += loc[j];
+    }
+    uint32_t total;
+    uint32_t run = tilesum[t] + block_exclusive_scan(v, &total);
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        if (c0 + j < tl.end) b.cstart[c0 + j] = run;
+        run += loc[j];
+    }
+    if (tl.end == b.ncell && threadIdx.x == 0) b.cstart[b.ncell] = (uint32_t)b.n;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter(const Tile* __restrict__ tiles,
+                                                     const BoxDev* __restrict__ boxes,
+                                                     const BoxState* __restrict__ st)
+{
+    const Tile tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    const BoxState s = st[tl.box];
+    const BoxDev& b = boxes[tl.box];
+    if (box_idle(s) || !sort_due(b, s)) return;
+    const int src = s.parity, dst = s.parity ^ 1;
+    const bool stream = (b.binning == 2);
+    const bool vacf = b.vacf_stride > 0;
+    const float dt = b.dt;
+    for (int64_t i = tl.begin + threadIdx.x; i < tl.end; i += kBlock) {
+        const int64_t j = (int64_t)b.cstart[b.cell[i]] + b.rank[i];
+        const float vx = b.p[src][3][i], vy = b.p[src][4][i], vz = b.p[src][5][i];
+        float px = b.p[src][0][i], py = b.p[src][1][i], pz = b.p[src][2][i];
+        if (stream) {
+            px = fold(fmaf(vx, dt, px), b.len[0]);
+            py = fold(fmaf(vy, dt, py), b.len[1]);
+            pz = fold(fmaf(vz, dt, pz), b.len[2]);
+        }
+        b.p[dst][0][j] = px;
+        b.p[dst][1][j] = py;
+        b.p[dst][2][j] = pz;
+        b.p[dst][3][j] = vx;
+        b.p[dst][4][j] = vy;
+        b.p[dst][5][j] = vz;
+        b.pid[dst][j] = b.pid[src][i];
+        if (vacf) {
+            b.v0[dst][0][j] = b.v0[src][0][i];
+            b.v0[dst][1][j] = b.v0[src][1][i];
+            b.v0[dst][2][j] = b.v0[src][2][i];
+        }
+    }
+}
+
+__global__ void k_flip(const int32_t* __restrict__ active, int nactive,
+                       const BoxDev* __restrict__ boxes, BoxState* __restrict__ st)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nactive) return;
+    const int bx = active[i];
+    BoxState& s = st[bx];
+    const bool due = !box_idle(s) && sort_due(boxes[bx], s);
+    s.sorted_now = due ? 1 : 0;
+    if (due) s.parity ^= 1;
+}
+
+// SORT path: particles of cell c occupy [cstart[c], cstart[c+1]) in the
+// current buffer, already streamed.  One thread per cell.
+__global__ __launch_bounds__(kBlock) void k_cell_rotate(const Tile* __restrict__ tiles,
+                                                         const BoxDev* __restrict__ boxes,
+                                                         const BoxState* __restrict__ st,
+                                                         double* __restrict__ partials)
+{
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const Tile tl = tiles[t];
+    const BoxState s = st[tl.box];
+    const BoxDev& b = boxes[tl.box];
+    if (box_idle(s) || b.binning != 2) return;
+    float* __restrict__ vx = b.p[s.parity][3];
+    float* __restrict__ vy = b.p[s.parity][4];
+    float* __restrict__ vz = b.p[s.parity][5];
+    const bool vacf = vacf_due(b, s);
+    const float* __restrict__ w0x = b.v0[s.parity][0];
+    const float* __restrict__ w0y = b.v0[s.parity][1];
+    const float* __restrict__ w0z = b.v0[s.parity][2];
+    const float ca = b.ca, sa = b.sa, omc = b.omc;
+    double d[kNumDiag] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t c = tl.begin + threadIdx.x; c < tl.end; c += kBlock) {
+        const uint32_t beg = b.cstart[c], end = b.cstart[c + 1];
+        if (beg == end) continue;
+        unsigned long long sx = 0, sy = 0, sz = 0;
+        for (uint32_t j = beg; j < end; ++j) {
+            sx += to_fixed(vx[j]);
+            sy += to_fixed(vy[j]);
+            sz += to_fixed(vz[j]);
+        }
+        const unsigned int n = end - beg;
+        CellUN u;
+        u.ux = fixed_mean(sx, n);
+        u.uy = fixed_mean(sy, n);
+        u.uz = fixed_mean(sz, n);
+        const float3 ax = cell_axis(b, s.k, (uint32_t)c);
+        u.nx = ax.x;
+        u.ny = ax.y;
+        u.nz = ax.z;
+        for (uint32_t j = beg; j < end; ++j) {
+            const float3 v = rotate_about(u, vx[j], vy[j], vz[j], ca, sa, omc);
+            vx[j] = v.x;
+            vy[j] = v.y;
+            vz[j] = v.z;
+            d[0] += (double)v.x;
+            d[1] += (double)v.y;
+            d[2] += (double)v.z;
+            d[3] += (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z;
+            if (vacf) d[4] += (double)v.x * w0x[j] + (double)v.y * w0y[j] + (double)v.z * w0z[j];
+            range_check(v, d[3]);
+        }
+    }
+    block_diag(d, partials + (size_t)t * kNumDiag);
+}
+
+// --------------------------------------------------------------------------
+// end of step: per-box reduction of the partials in a fixed order
+
+__global__ __launch_bounds__(kBlock) void k_box_finish(const int32_t* __restrict__ active,
+                                                        const BoxDev* __restrict__ boxes,
+                                                        BoxState* __restrict__ st,
+                                                        const double* __restrict__ partials_p,
+                                                        const double* __restrict__ partials_c)
+{
+    const int bx = active[blockIdx.x];
+    BoxState* sp = &st[bx];
+    if (box_idle(*sp)) return;
+    const BoxDev& b = boxes[bx];
+    const bool by_cell = (b.binning == 2);
+    const int t0 = by_cell ? b.ctile0 : b.ptile0;
+    const int t1 = by_cell ? b.ctile1 : b.ptile1;
+    const double* __restrict__ partials = by_cell ? partials_c : partials_p;
+    double d[kNumDiag] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int t = t0 + (int)threadIdx.x; t < t1; t += kBlock) {
+#pragma unroll
+        for (int j = 0; j < kNumDiag; ++j) d[j] += partials[(size_t)t * kNumDiag + j];
+    }
+    __shared__ double tot[kNumDiag];
+    block_diag(d, tot);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const bool vac = vacf_due(b, *sp);
+        sp->diag[0] = tot[0];
+        sp->diag[1] = tot[1];
+        sp->diag[2] = tot[2];
+        sp->diag[3] = tot[3];
+        if (!(tot[3] < 1e300 && tot[3] >= 0.0)) sp->status = -5;   // NaN or Inf
+        if (vac && sp->vacf_len < b.vacf_cap && b.n > 0)
+            b.vacf[sp->vacf_len++] = tot[4] / (double)b.n;
+        sp->k += 1;
+        if (sp->remaining > 0) sp->remaining -= 1;
+    }
+}
+
+// --------------------------------------------------------------------------
+// initial state on the device (not part of the step)
+
+__global__ __launch_bounds__(kBlock) void k_init_maxwell(const Tile* __restrict__ tiles,
+                                                          const BoxDev* __restrict__ boxes,
+                                                          const BoxState* __restrict__ st,
+                                                          float vscale, double* __restrict__ partials)
+{
+    const int t = blockIdx.x;
+    const Tile tl = tiles[t];
+    const BoxDev& b = boxes[tl.box];
+    const int par = st[tl.box].parity;
+    double d[kNumDiag] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = tl.begin + threadIdx.x; i < tl.end; i += kBlock) {
+        const uint32_t lo = (uint32_t)i, hi = (uint32_t)((uint64_t)i >> 32);
+        const uint4 r = philox4x32_10(make_uint4(lo, hi, 0u, 2u), b.key0, b.key1);
+        b.p[par][0][i] = fold(b.len[0] * unit24(r.x), b.len[0]);
+        b.p[par][1][i] = fold(b.len[1] * unit24(r.y), b.len[1]);
+        b.p[par][2][i] = fold(b.len[2] * unit24(r.z), b.len[2]);
+        const uint4 q = philox4x32_10(make_uint4(lo, hi, 0u, 3u), b.key0, b.key1);
+        const float r1 = sqrtf(-2.0f * logf(1.0f - unit24(q.x)));
+        const float r2 = sqrtf(-2.0f * logf(1.0f - unit24(q.z)));
+        float s1, c1, s2, c2;
+        sincosf(6.2831853071795864769f * unit24(q.y), &s1, &c1);
+        sincosf(6.2831853071795864769f * unit24(q.w), &s2, &c2);
+        const float vx = vscale * r1 * c1, vy = vscale * r1 * s1, vz = vscale * r2 * c2;
+        b.p[par][3][i] = vx;
+        b.p[par][4][i] = vy;
+        b.p[par][5][i] = vz;
+        b.pid[par][i] = (int32_t)i;
+        d[0] += vx;
+        d[1] += vy;
+        d[2] += vz;
+    }
+    block_diag(d, partials + (size_t)t * kNumDiag);
+}
+
+// v <- (v - V) * scale; partial sums of v^2 before scaling and of v after
+__global__ __launch_bounds__(kBlock) void k_init_adjust(const Tile* __restrict__ tiles,
+                                                         const BoxDev* __restrict__ boxes,
+                                                         const BoxState* __restrict__ st,
+                                                         float mx, float my, float mz, float scale,
+                                                         double* __restrict__ partials)
+{
+    const int t = blockIdx.x;
+    const Tile tl = tiles[t];
+    const BoxDev& b = boxes[tl.box];
+    const int par = st[tl.box].parity;
+    double d[kNumDiag] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = tl.begin + threadIdx.x; i < tl.end; i += kBlock) {
+        const float vx = (b.p[par][3][i] - mx) * scale;
+        const float vy = (b.p[par][4][i] - my) * scale;
+        const float vz = (b.p[par][5][i] - mz) * scale;
+        b.p[par][3][i] = vx;
+        b.p[par][4][i] = vy;
+        b.p[par][5][i] = vz;
+        d[0] += vx;
+        d[1] += vy;
+        d[2] += vz;
+        d[3] += (double)vx * vx + (double)vy * vy + (double)vz * vz;
+    }
+    block_diag(d, partials + (size_t)t * kNumDiag);
+}
+
+// v0 <- v, and the FP64 partials of the current state (sum v, sum v^2, sum v.v0)
+__global__ __launch_bounds__(kBlock) void k_snapshot(const Tile* __restrict__ tiles,
+                                                      const BoxDev* __restrict__ boxes,
+                                                      const BoxState* __restrict__ st,
+                                                      int set_v0, double* __restrict__ partials)
+{
+    const int t = blockIdx.x;
+    const Tile tl = tiles[t];
+    const BoxDev& b = boxes[tl.box];
+    const int par = st[tl.box].parity;
+    const bool has_v0 = b.vacf_stride > 0;
+    double d[kNumDiag] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = tl.begin + threadIdx.x; i < tl.end; i += kBlock) {
+        const float vx = b.p[par][3][i], vy = b.p[par][4][i], vz = b.p[par][5][i];
+        if (has_v0 && set_v0) {
+            b.v0[par][0][i] = vx;
+            b.v0[par][1][i] = vy;
+            b.v0[par][2][i] = vz;
+        }
+        d[0] += vx;
+        d[1] += vy;
+        d[2] += vz;
+        d[3] += (double)vx * vx + (double)vy * vy + (double)vz * vz;
+        if (has_v0)
+            d[4] += (double)vx * b.v0[par][0][i] + (double)vy * b.v0[par][1][i] +
+                    (double)vz * b.v0[par][2][i];
+    }
+    block_diag(d, partials + (size_t)t * kNumDiag);
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_iota(int32_t* __restrict__ p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        p[i] = (int32_t)i;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_zero_u32(uint32_t* __restrict__ p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        p[i] = 0u;
+}
+
+// --------------------------------------------------------------------------
+// host launchers
+
+#define MPCD_LAUNCH(kern, grid, block, stream, ...)                              \
+    do {                                                                          \
+        if ((grid) > 0) hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, stream, __VA_ARGS__); \
+    } while (0)
+
+void launch_stream_bin(const Tables& T, hipStream_t s)
+{
+    MPCD_LAUNCH(k_stream_bin, T.nptiles, kBlock, s, T.ptiles, T.boxes, T.state);
+}
+void launch_finalize(const Tables& T, hipStream_t s)
+{
+    MPCD_LAUNCH(k_finalize, T.nctiles, kBlock, s, T.ctiles, T.boxes, T.state);
+}
+void launch_rotate(const Tables& T, hipStream_t s)
+{
+    MPCD_LAUNCH(k_rotate, T.nptiles, kBlock, s, T.ptiles, T.boxes, T.state, T.partials);
+}
+void launch_box_finish(const Tables& T, hipStream_t s)
+{
+    MPCD_LAUNCH(k_box_finish, T.nactive, kBlock, s, T.active, T.boxes, T.state, T.partials,
+                T.partials_c);
+}
+void launch_zero_counts(const Tables& T, hipStream_t s)
+{
+    MPCD_LAUNCH(k_zero_counts, T.nctiles, kBlock, s, T.ctiles, T.boxes, T.state);
+}
+void launch_count(const Tables& T, hipStream_t s)
+{
+    MPCD_LAUNCH(k_count, T.nptiles, kBlock, s, T.ptiles, T.boxes, T.state);
+}
+void launch_scan(const Tables& T, hipStream_t s)
+{
+    MPCD_LAUNCH(k_scan_tilesum, T.nctiles, kBlock, s, T.ctiles, T.boxes, T.state, T.tilesum);
+    MPCD_LAUNCH(k_scan_box, T.nactive, kBlock, s, T.active, T.boxes, T.state, T.tilesum);
+    MPCD_LAUNCH(k_scan_apply, T.nctiles, kBlock, s, T.ctiles, T.boxes, T.state, T.tilesum);
+}
+void launch_scatter(const Tables& T, hipStream_t s)
+{
+    MPCD_LAUNCH(k_scatter, T.nptiles, kBlock, s, T.ptiles, T.boxes, T.state);
+}
+void launch_flip(const Tables& T, hipStream_t s)
+{
+    MPCD_LAUNCH(k_flip, (T.nactive + kBlock - 1) / kBlock, kBlock, s, T.active, T.nactive, T.boxes,
+                T.state);
+}
+void launch_cell_rotate(const Tables& T, hipStream_t s)
+{
+    MPCD_LAUNCH(k_cell_rotate, T.nctiles, kBlock, s, T.ctiles, T.boxes, T.state, T.partials_c);
+}
+
+// The init/snapshot launchers take a sub-range of T.ptiles (one box); their
+// partials land at the same tile indices as the step's.
+static double* partials_at(const Tile* tiles, const Tables& T)
+{
+    return T.partials + (size_t)(tiles - T.ptiles) * kNumDiag;
+}
+void launch_init_maxwell(const Tile* tiles, int ntiles, const Tables& T, float vscale, hipStream_t s)
+{
+    MPCD_LAUNCH(k_init_maxwell, ntiles, kBlock, s, tiles, T.boxes, T.state, vscale, partials_at(tiles, T));
+}
+void launch_init_adjust(const Tile* tiles, int ntiles, const Tables& T, float mx, float my, float mz,
+                        float scale, hipStream_t s)
+{
+    MPCD_LAUNCH(k_init_adjust, ntiles, kBlock, s, tiles, T.boxes, T.state, mx, my, mz, scale,
+                partials_at(tiles, T));
+}
+void launch_snapshot(const Tile* tiles, int ntiles, const Tables& T, int set_v0, hipStream_t s)
+{
+    MPCD_LAUNCH(k_snapshot, ntiles, kBlock, s, tiles, T.boxes, T.state, set_v0, partials_at(tiles, T));
+}
+void launch_fill_iota(int32_t* p, int64_t n, hipStream_t s)
+{
+    const int64_t g = (n + kBlock - 1) / kBlock;
+    MPCD_LAUNCH(k_fill_iota, (int)(g < 65536 ? g : 65536), kBlock, s, p, n);
+}
+void launch_fill_zero_u32(uint32_t* p, int64_t n, hipStream_t s)
+{
+    const int64_t g = (n + kBlock - 1) / kBlock;
+    MPCD_LAUNCH(k_fill_zero_u32, (int)(g < 65536 ? g : 65536), kBlock, s, p, n);
+}
+
+}  // namespace mpcd

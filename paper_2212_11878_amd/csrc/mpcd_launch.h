@@ -1,0 +1,44 @@
+// mpcd_launch.h -- host-side launchers of the SRD kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mpcd_dev.h"
+
+namespace mpcd {
+
+// Device tables describing the live boxes; every kernel reads its box's
+// descriptor and step counter from here, so a captured graph stays valid
+// until the tables are rebuilt.
+struct Tables {
+    BoxDev* boxes = nullptr;     // indexed by slot
+    BoxState* state = nullptr;   // indexed by slot
+    Tile* ptiles = nullptr;      // particle tiles of all live boxes
+    Tile* ctiles = nullptr;      // cell tiles of all live boxes
+    int32_t* active = nullptr;   // live slots
+    double* partials = nullptr;  // kNumDiag per particle tile
+    double* partials_c = nullptr;  // kNumDiag per cell tile
+    uint32_t* tilesum = nullptr; // per cell tile
+    int nptiles = 0, nctiles = 0, nactive = 0;
+};
+
+void launch_stream_bin(const Tables& T, hipStream_t s);
+void launch_finalize(const Tables& T, hipStream_t s);
+void launch_rotate(const Tables& T, hipStream_t s);
+void launch_box_finish(const Tables& T, hipStream_t s);
+void launch_zero_counts(const Tables& T, hipStream_t s);
+void launch_count(const Tables& T, hipStream_t s);
+void launch_scan(const Tables& T, hipStream_t s);
+void launch_scatter(const Tables& T, hipStream_t s);
+void launch_flip(const Tables& T, hipStream_t s);
+void launch_cell_rotate(const Tables& T, hipStream_t s);
+
+void launch_init_maxwell(const Tile* tiles, int ntiles, const Tables& T, float vscale, hipStream_t s);
+void launch_init_adjust(const Tile* tiles, int ntiles, const Tables& T, float mx, float my, float mz,
+                        float scale, hipStream_t s);
+void launch_snapshot(const Tile* tiles, int ntiles, const Tables& T, int set_v0, hipStream_t s);
+void launch_fill_iota(int32_t* p, int64_t n, hipStream_t s);
+void launch_fill_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
+
+}  // namespace mpcd

@@ -1,0 +1,358 @@
+"""ctypes binding of libmpcd.so (C ABI in include/mpcd.h).
+
+The functions below carry the C names and only marshal arguments; every step
+of the SRD update runs in the library's HIP kernels.  PyTorch supplies device
+memory (through the allocator callback) and the HIP stream.  Importing this
+module fails loudly if the library has not been built.
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmpcd.so")
+
+MPCD_OK = 0
+MPCD_EINVAL = -1
+MPCD_ENOMEM = -2
+MPCD_EDEVICE = -3
+MPCD_EBUSY = -4
+MPCD_ESTATE = -5
+MPCD_ENOTFOUND = -6
+
+MPCD_INIT_MAXWELL = 0x1
+MPCD_INIT_EXTERNAL = 0x2
+MPCD_TRACK_VACF = 0x4
+
+MPCD_BIN_AUTO = 0
+MPCD_BIN_ATOMIC = 1
+MPCD_BIN_SORT = 2
+
+
+class mpcd_box_desc(ctypes.Structure):
+    _fields_ = [
+        ("L", ctypes.c_int32 * 3),
+        ("a", ctypes.c_double),
+        ("n_particles", ctypes.c_int64),
+        ("dt", ctypes.c_double),
+        ("alpha", ctypes.c_double),
+        ("kT", ctypes.c_double),
+        ("mass", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("n_steps", ctypes.c_int64),
+        ("flags", ctypes.c_uint32),
+        ("vacf_stride", ctypes.c_int32),
+        ("vacf_capacity", ctypes.c_int32),
+    ]
+
+
+mpcd_alloc_fn = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+mpcd_free_fn = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class mpcd_options(ctypes.Structure):
+    _fields_ = [
+        ("binning", ctypes.c_int32),
+        ("resort_period", ctypes.c_int32),
+        ("block", ctypes.c_int32),
+        ("use_graph", ctypes.c_int32),
+        ("hbm_budget", ctypes.c_int64),
+        ("stream", ctypes.c_void_p),
+        ("alloc", mpcd_alloc_fn),
+        ("free", mpcd_free_fn),
+        ("user", ctypes.c_void_p),
+        ("device", ctypes.c_int32),
+        ("max_slots", ctypes.c_int32),
+    ]
+
+
+class mpcd_observables(ctypes.Structure):
+    _fields_ = [
+        ("step", ctypes.c_int64),
+        ("P", ctypes.c_double * 3),
+        ("E_kin", ctypes.c_double),
+        ("T", ctypes.c_double),
+        ("mass_total", ctypes.c_double),
+        ("status", ctypes.c_int32),
+        ("vacf_len", ctypes.c_int32),
+        ("vacf", ctypes.POINTER(ctypes.c_double)),
+        ("n_particles", ctypes.c_int64),
+        ("binning", ctypes.c_int32),
+        ("resort_period", ctypes.c_int32),
+    ]
+
+
+class mpcd_kernel_stat(ctypes.Structure):
+    _fields_ = [
+        ("name", ctypes.c_char_p),
+        ("launches", ctypes.c_int64),
+        ("total_ms", ctypes.c_double),
+    ]
+
+
+# every function the header declares, with its C signature
+_SIGNATURES = {
+    "mpcd_create": (ctypes.c_int, [ctypes.POINTER(mpcd_options), ctypes.POINTER(ctypes.c_void_p)]),
+    "mpcd_admit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(mpcd_box_desc),
+                                  ctypes.POINTER(ctypes.c_int32)]),
+    "mpcd_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "mpcd_observe": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(mpcd_observables)]),
+    "mpcd_get_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_float),
+                                      ctypes.POINTER(ctypes.c_int64)]),
+    "mpcd_set_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_float),
+                                      ctypes.c_int64]),
+    "mpcd_release": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "mpcd_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "mpcd_kernel_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(mpcd_kernel_stat), ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_int32)]),
+    "mpcd_destroy": (None, [ctypes.c_void_p]),
+    "mpcd_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "mpcd_abi_version": (ctypes.c_int, []),
+}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libmpcd.so is not built (%s); run `python -m paper_2212_11878_amd.csrc.build`"
+                      % LIB_PATH)
+_lib = ctypes.CDLL(LIB_PATH)
+for _name, (_res, _args) in _SIGNATURES.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class MPCDError(RuntimeError):
+    def __init__(self, status, what=""):
+        self.status = status
+        super().__init__("%s: %s (%d)" % (what, mpcd_strerror(status), status))
+
+
+def _check(rc, what):
+    if rc != MPCD_OK:
+        raise MPCDError(rc, what)
+    return rc
+
+
+# ---------------------------------------------------------------------------
+# the C functions, same names, argument marshalling only
+
+def mpcd_abi_version():
+    return _lib.mpcd_abi_version()
+
+
+def mpcd_strerror(status):
+    return _lib.mpcd_strerror(int(status)).decode()
+
+
+def mpcd_create(options):
+    h = ctypes.c_void_p()
+    rc = _lib.mpcd_create(ctypes.byref(options) if options is not None else None, ctypes.byref(h))
+    return rc, h
+
+
+def mpcd_admit(ctx, desc):
+    slot = ctypes.c_int32(-1)
+    rc = _lib.mpcd_admit(ctx, ctypes.byref(desc), ctypes.byref(slot))
+    return rc, slot.value
+
+
+def mpcd_step(ctx, n_steps):
+    return _lib.mpcd_step(ctx, int(n_steps))
+
+
+def mpcd_observe(ctx, slot):
+    obs = mpcd_observables()
+    rc = _lib.mpcd_observe(ctx, int(slot), ctypes.byref(obs))
+    return rc, obs
+
+
+def mpcd_get_state(ctx, slot, n):
+    buf = np.empty(6 * int(n), dtype=np.float32)
+    step = ctypes.c_int64(0)
+    rc = _lib.mpcd_get_state(ctx, int(slot), buf.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                             ctypes.byref(step))
+    return rc, buf.reshape(6, -1), step.value
+
+
+def mpcd_set_state(ctx, slot, xyzv, step):
+    buf = np.ascontiguousarray(xyzv, dtype=np.float32).reshape(-1)
+    return _lib.mpcd_set_state(ctx, int(slot), buf.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                               int(step))
+
+
+def mpcd_release(ctx, slot):
+    return _lib.mpcd_release(ctx, int(slot))
+
+
+def mpcd_profile(ctx, enable):
+    return _lib.mpcd_profile(ctx, 1 if enable else 0)
+
+
+def mpcd_kernel_stats(ctx, max_entries=32):
+    arr = (mpcd_kernel_stat * max_entries)()
+    count = ctypes.c_int32(0)
+    rc = _lib.mpcd_kernel_stats(ctx, arr, max_entries, ctypes.byref(count))
+    out = {}
+    for i in range(min(count.value, max_entries)):
+        out[arr[i].name.decode()] = (int(arr[i].launches), float(arr[i].total_ms))
+    return rc, out
+
+
+def mpcd_destroy(ctx):
+    _lib.mpcd_destroy(ctx)
+
+
+# ---------------------------------------------------------------------------
+# convenience wrapper: torch memory and stream, exceptions on errors
+
+class _TorchAllocator:
+    """Device memory for the library from PyTorch's caching allocator."""
+
+    def __init__(self, device):
+        import torch
+        self._torch = torch
+        self.device = device
+        self.blocks = {}
+        self.c_alloc = mpcd_alloc_fn(self._alloc)
+        self.c_free = mpcd_free_fn(self._free)
+
+    def _alloc(self, nbytes, user):
+        try:
+            t = self._torch.empty(int(nbytes), dtype=self._torch.uint8, device=self.device)
+        except Exception:
+            return None
+        p = t.data_ptr()
+        self.blocks[p] = t
+        return p
+
+    def _free(self, ptr, user):
+        self.blocks.pop(ptr, None)
+
+    def bytes_held(self):
+        return sum(t.numel() for t in self.blocks.values())
+
+
+def make_desc(L, n_particles, dt=0.1, alpha_deg=130.0, seed=1, a=1.0, kT=1.0, mass=1.0,
+              n_steps=0, init="maxwell", vacf_stride=0, vacf_capacity=0, alpha_rad=None):
+    d = mpcd_box_desc()
+    if isinstance(L, int):
+        L = (L, L, L)
+    for i in range(3):
+        d.L[i] = int(L[i])
+    d.a = float(a)
+    d.n_particles = int(n_particles)
+    d.dt = float(dt)
+    d.alpha = float(alpha_rad) if alpha_rad is not None else math.radians(alpha_deg)
+    d.kT = float(kT)
+    d.mass = float(mass)
+    d.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+    d.n_steps = int(n_steps)
+    d.flags = MPCD_INIT_MAXWELL if init == "maxwell" else MPCD_INIT_EXTERNAL
+    if vacf_stride:
+        d.flags |= MPCD_TRACK_VACF
+        d.vacf_stride = int(vacf_stride)
+        d.vacf_capacity = int(vacf_capacity)
+    return d
+
+
+class Context:
+    """One library context on a torch-owned HIP stream."""
+
+    def __init__(self, device=0, binning=MPCD_BIN_AUTO, resort_period=0, use_graph=True,
+                 hbm_budget=0, max_slots=0, block=0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible to PyTorch; libmpcd needs a HIP device")
+        self.device = torch.device("cuda", device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        self.allocator = _TorchAllocator(self.device)
+        opt = mpcd_options()
+        opt.binning = binning
+        opt.resort_period = resort_period
+        opt.block = block
+        opt.use_graph = 1 if use_graph else 0
+        opt.hbm_budget = int(hbm_budget)
+        opt.stream = ctypes.c_void_p(self.stream.cuda_stream)
+        opt.alloc = self.allocator.c_alloc
+        opt.free = self.allocator.c_free
+        opt.user = None
+        opt.device = device
+        opt.max_slots = max_slots
+        self._opt = opt
+        rc, h = mpcd_create(opt)
+        _check(rc, "mpcd_create")
+        self.handle = h
+        self.n = {}
+
+    def admit(self, desc, state=None, step=0):
+        rc, slot = mpcd_admit(self.handle, desc)
+        _check(rc, "mpcd_admit")
+        self.n[slot] = int(desc.n_particles)
+        if state is not None:
+            self.set_state(slot, state, step)
+        return slot
+
+    def try_admit(self, desc):
+        rc, slot = mpcd_admit(self.handle, desc)
+        if rc == MPCD_OK:
+            self.n[slot] = int(desc.n_particles)
+            return slot
+        if rc in (MPCD_ENOMEM, MPCD_EBUSY):
+            return None
+        raise MPCDError(rc, "mpcd_admit")
+
+    def set_state(self, slot, state, step=0):
+        pos, vel = state
+        xyzv = np.concatenate([np.asarray(pos, np.float32).reshape(3, -1),
+                               np.asarray(vel, np.float32).reshape(3, -1)])
+        _check(mpcd_set_state(self.handle, slot, xyzv, step), "mpcd_set_state")
+
+    def get_state(self, slot):
+        rc, buf, step = mpcd_get_state(self.handle, slot, self.n[slot])
+        _check(rc, "mpcd_get_state")
+        return buf[:3].copy(), buf[3:].copy(), step
+
+    def step(self, n=1):
+        _check(mpcd_step(self.handle, n), "mpcd_step")
+
+    def observe(self, slot):
+        rc, obs = mpcd_observe(self.handle, slot)
+        if rc not in (MPCD_OK, MPCD_ESTATE):
+            raise MPCDError(rc, "mpcd_observe")
+        vacf = [obs.vacf[i] for i in range(obs.vacf_len)] if obs.vacf_len > 0 else []
+        return dict(step=obs.step, P=np.array(obs.P[:]), E=obs.E_kin, T=obs.T, M=obs.mass_total,
+                    status=obs.status, vacf=np.array(vacf), binning=obs.binning,
+                    resort_period=obs.resort_period, n=obs.n_particles)
+
+    def release(self, slot):
+        _check(mpcd_release(self.handle, slot), "mpcd_release")
+        self.n.pop(slot, None)
+
+    def profile(self, enable):
+        _check(mpcd_profile(self.handle, enable), "mpcd_profile")
+
+    def kernel_stats(self):
+        rc, out = mpcd_kernel_stats(self.handle)
+        _check(rc, "mpcd_kernel_stats")
+        return out
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            mpcd_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

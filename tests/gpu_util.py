@@ -1,0 +1,99 @@
+"""Helpers for the GPU parity tests: run the FP64 oracle on the same FP32
+input the HIP path gets and compare element by element.
+
+Tolerances (what the FP32 path can and must reach against FP64):
+  * positions: torus distance <= 1 ulp_FP32 of the box edge (one FP32
+    rounding of x + v dt, one of the periodic fold);
+  * collision cells: bit-exact, except particles whose FP64 (x - s)/a lies
+    within a face band of 4 ulp_FP32(edge) of a cell face, where the FP32
+    position may round onto the other side;
+  * velocities: |v_gpu - v_oracle|_inf <= 1e-5 max(|v_oracle|_inf, sqrt(kT/m))
+    per particle, outside the (at most two) cells each face-band particle
+    may belong to.
+"""
+import math
+
+import numpy as np
+
+from oracle import oracle as orc
+
+
+def ulp_top(length):
+    """Spacing of float32 numbers just below `length`."""
+    return float(np.spacing(np.float32(np.nextafter(np.float32(length), np.float32(0)))))
+
+
+def f32_state(pos, vel, L, a=1.0):
+    """Round an FP64 state to FP32 keeping positions inside [0, L a)."""
+    pos32 = np.asarray(pos, dtype=np.float32).copy()
+    for d in range(3):
+        edge = np.float32(L[d] * a)
+        pos32[d][pos32[d] >= edge] = np.float32(0.0)
+        pos32[d][pos32[d] < 0] = np.float32(0.0)
+    return pos32, np.asarray(vel, dtype=np.float32).copy()
+
+
+def oracle_one_step(pos32, vel32, box, k):
+    """One oracle step (stream + collide at step k) from the FP32 state."""
+    st = orc.State(pos32.astype(np.float64), vel32.astype(np.float64))
+    orc.stream(box, st)
+    s = orc.shift(box.seed, k, box.a)
+    cells = orc.cells(box, s, st)
+    orc.collide(box, k, st)
+    return st, s, cells
+
+
+def face_band_mask(pos64, s, box):
+    """Particles whose (x - s)/a is within the face band of a cell face."""
+    L = [int(box.L[d]) for d in range(3)]
+    delta = 4.0 * max(ulp_top(L[d] * box.a) for d in range(3)) / box.a
+    near = np.zeros(pos64.shape[1], dtype=bool)
+    for d in range(3):
+        q = (pos64[d] - s[d]) / box.a
+        near |= np.abs(q - np.round(q)) < delta
+    return near
+
+
+def neighbour_cells(cells, pos64, s, box):
+    """For face-band particles: the cells on both sides of the nearby faces."""
+    L = [int(box.L[d]) for d in range(3)]
+    out = set()
+    for i in range(len(cells)):
+        idx = []
+        for d in range(3):
+            q = (pos64[d, i] - s[d]) / box.a
+            base = int(math.floor(q))
+            cand = {base % L[d], (base - 1) % L[d], (base + 1) % L[d]}
+            idx.append(sorted(cand))
+        for ix in idx[0]:
+            for iy in idx[1]:
+                for iz in idx[2]:
+                    out.add(ix + L[0] * (iy + L[1] * iz))
+    return out
+
+
+def check_against(ref, s, cells, box, gpu_pos, gpu_vel, kT=1.0, mass=1.0):
+    """Compare a GPU result with the oracle's FP64 result `ref` (an
+    oracle.State after stream + collide); `cells` are the oracle's collision
+    cells of the streamed positions under shift s."""
+    L = np.array([int(box.L[d]) for d in range(3)], dtype=np.float64) * box.a
+    dpos = gpu_pos.astype(np.float64) - ref.pos
+    dpos -= np.round(dpos / L[:, None]) * L[:, None]
+    ptol = max(ulp_top(x) for x in L)
+    assert np.max(np.abs(dpos)) <= ptol, ("position", np.max(np.abs(dpos)), ptol)
+    band = face_band_mask(ref.pos, s, box)
+    exempt_cells = neighbour_cells(cells[band], ref.pos[:, band], s, box) if band.any() else set()
+    keep = ~np.isin(cells, np.fromiter(exempt_cells, dtype=np.int64, count=len(exempt_cells)))
+    scale = np.maximum(np.max(np.abs(ref.vel), axis=0), math.sqrt(kT / mass))
+    err = np.max(np.abs(gpu_vel.astype(np.float64) - ref.vel), axis=0) / scale
+    bad = keep & (err > 1e-5)
+    assert not bad.any(), ("velocity", int(bad.sum()), float(err[keep].max()))
+    assert keep.sum() >= len(keep) - 64 * max(1, int(band.sum())), "too many exemptions"
+    return int(band.sum()), float(err[keep].max()) if keep.any() else 0.0
+
+
+def compare_step(pos32, vel32, gpu_pos, gpu_vel, box, k, kT=1.0, mass=1.0):
+    """Assert the GPU's one-step result matches the oracle's; returns the
+    number of face-band particles and the largest kept velocity error."""
+    st, s, cells = oracle_one_step(pos32, vel32, box, k)
+    return check_against(st, s, cells, box, gpu_pos, gpu_vel, kT, mass)

@@ -1,0 +1,85 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function include/mpcd.h declares, its structs have the same layout in
+C and in the binding, and calls that cannot reach a device fail cleanly."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mpcd.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:int|void|const char\*)\s+(mpcd_\w+)\s*\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def m():
+    from paper_2212_11878_amd import mpcd
+    return mpcd
+
+
+def test_exports_every_declared_function(m):
+    names = _declared_functions()
+    assert len(names) >= 12
+    lib = ctypes.CDLL(m.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(m._SIGNATURES), set(names) ^ set(m._SIGNATURES)
+
+
+def test_struct_layout_matches_header(m, tmp_path):
+    structs = {
+        "mpcd_box_desc": m.mpcd_box_desc,
+        "mpcd_options": m.mpcd_options,
+        "mpcd_observables": m.mpcd_observables,
+        "mpcd_kernel_stat": m.mpcd_kernel_stat,
+    }
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mpcd.h"', "int main(void){"]
+    for sname, cls in structs.items():
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (sname, sname))
+        for fname, _ in cls._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (sname, fname, sname, fname))
+    lines.append("return 0;}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                 check=True).stdout.splitlines())
+    for sname, cls in structs.items():
+        assert int(out[sname]) == ctypes.sizeof(cls), sname
+        for fname, _ in cls._fields_:
+            assert int(out["%s.%s" % (sname, fname)]) == getattr(cls, fname).offset, (sname, fname)
+
+
+def test_status_strings_and_version(m):
+    assert m.mpcd_abi_version() == 1
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert m.mpcd_strerror(code) and m.mpcd_strerror(code) != "unknown status"
+    assert m.mpcd_strerror(12345) == "unknown status"
+
+
+def test_null_arguments_rejected(m):
+    lib = m._lib
+    assert lib.mpcd_create(None, None) == m.MPCD_EINVAL
+    assert lib.mpcd_step(None, 1) == m.MPCD_EINVAL
+    assert lib.mpcd_release(None, 0) == m.MPCD_EINVAL
+    assert lib.mpcd_observe(None, 0, None) == m.MPCD_EINVAL
+    lib.mpcd_destroy(None)
+
+
+def test_create_without_device_fails_cleanly(m):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    opt = m.mpcd_options()
+    rc, h = m.mpcd_create(opt)
+    assert rc == m.MPCD_EDEVICE
+    assert not h.value
+    opt.binning = 7
+    assert m.mpcd_create(opt)[0] == m.MPCD_EINVAL

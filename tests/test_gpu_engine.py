@@ -1,0 +1,224 @@
+"""GPU tests of the engine behaviour around the step: binning modes, graph
+replay, batching, device-side initial state, diagnostics, VACF, errors."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2212_11878_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2212_11878_amd import mpcd
+    return mpcd
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _run(mp, boxes, steps, binning, use_graph=True, chunks=1, resort=0):
+    """Admit (L, n, seed, alpha) boxes with a shared-input state, run, return states."""
+    out = []
+    with mp.Context(binning=binning, use_graph=use_graph, resort_period=resort) as ctx:
+        slots = []
+        for (L, n, seed, alpha) in boxes:
+            pos, vel = inputs.thermal_state(L, n, seed)
+            s = ctx.admit(mp.make_desc(L, n, alpha_deg=alpha, seed=seed, init="external"))
+            ctx.set_state(s, (pos, vel))
+            slots.append(s)
+        for _ in range(chunks):
+            ctx.step(steps)
+        for s in slots:
+            out.append(ctx.get_state(s))
+    return out
+
+
+def test_binning_modes_bit_identical(mp):
+    """Cell sums are exact integers, so atomic and sort binning (any re-sort
+    period) give the same bits for every particle."""
+    _say("modes")
+    boxes = [((12, 12, 12), 17280, 4, 130.0)]
+    a = _run(mp, boxes, 25, mp.MPCD_BIN_ATOMIC, resort=7)[0]
+    b = _run(mp, boxes, 25, mp.MPCD_BIN_SORT)[0]
+    c = _run(mp, boxes, 25, mp.MPCD_BIN_ATOMIC, resort=1)[0]
+    for x, y in ((a, b), (a, c)):
+        assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])
+
+
+def test_graph_replay_matches_eager(mp):
+    """Every replay of the captured step equals the eager sequence, with
+    host synchronisations between replays."""
+    _say("graph")
+    boxes = [((10, 10, 10), 10000, 6, 120.0)]
+    eager = _run(mp, boxes, 5, mp.MPCD_BIN_ATOMIC, use_graph=False, chunks=4)[0]
+    graph = _run(mp, boxes, 5, mp.MPCD_BIN_ATOMIC, use_graph=True, chunks=4)[0]
+    assert np.array_equal(eager[0], graph[0]) and np.array_equal(eager[1], graph[1])
+
+
+def test_box_alone_equals_box_in_mix(mp):
+    """Results depend only on (seed, step, state): a box advanced alone and
+    advanced in a batch of uneven boxes ends in the same bits."""
+    _say("mix")
+    mix = [((8, 8, 8), 5120, 11, 90.0), ((20, 20, 20), 160000, 12, 130.0),
+           ((9, 13, 5), 4000, 13, 120.0), ((3, 3, 3), 0, 14, 130.0), ((16, 16, 16), 61440, 15, 150.0)]
+    for binning in (mp.MPCD_BIN_ATOMIC, mp.MPCD_BIN_SORT):
+        together = _run(mp, mix, 30, binning)
+        for i, box in enumerate(mix):
+            alone = _run(mp, [box], 30, binning)[0]
+            assert np.array_equal(alone[0], together[i][0])
+            assert np.array_equal(alone[1], together[i][1])
+            assert alone[2] == together[i][2] == 30
+
+
+def test_device_maxwell_initial_state(mp):
+    _say("init")
+    L, n = (30, 30, 30), 270000
+    with mp.Context() as ctx:
+        s = ctx.admit(mp.make_desc(L, n, seed=77, kT=1.7, mass=1.0))
+        o = ctx.observe(s)
+        pos, vel, step = ctx.get_state(s)
+    assert step == 0 and o["step"] == 0
+    assert abs(o["T"] - 1.7) < 1e-5
+    assert np.all(np.abs(o["P"]) < 1e-2)
+    assert pos.min() >= 0 and pos.max() < 30
+    # uniform positions: occupancy of 1000 coarse bins
+    h, _ = np.histogramdd(pos.T, bins=(10, 10, 10), range=[(0, 30)] * 3)
+    assert abs(h.mean() - 270) < 1e-9 and h.std() < 4 * math.sqrt(270)
+    # Gaussian components
+    x = vel.reshape(-1).astype(np.float64) / math.sqrt(1.7)
+    assert abs(np.mean(x ** 2) - 1) < 0.01 and abs(np.mean(x ** 4) - 3) < 0.05
+
+
+def test_conservation_over_many_steps(mp):
+    """FP32 state, exact cell sums: momentum and energy drift stay at FP32
+    rounding level over 500 steps of a 10^6-particle box."""
+    _say("conservation")
+    L, n = (50, 50, 40), 1000000
+    with mp.Context() as ctx:
+        s = ctx.admit(mp.make_desc(L, n, seed=3))
+        o0 = ctx.observe(s)
+        ctx.step(500)
+        o1 = ctx.observe(s)
+    assert o1["step"] == 500 and o1["status"] == 0
+    assert abs(o1["E"] - o0["E"]) / o0["E"] < 1e-5, (o0["E"], o1["E"])
+    assert np.all(np.abs(o1["P"] - o0["P"]) < 1e-3 * math.sqrt(n)), (o0["P"], o1["P"])
+
+
+def test_diagnostics_match_oracle(mp):
+    _say("diag")
+    L, n = (10, 10, 10), 10000
+    pos, vel = inputs.thermal_state(L, n, 21)
+    with mp.Context() as ctx:
+        s = ctx.admit(mp.make_desc(L, n, seed=21, init="external"))
+        ctx.set_state(s, (pos, vel))
+        ctx.step(10)
+        o = ctx.observe(s)
+        gp, gv, _ = ctx.get_state(s)
+    P, E, T, M = orc.diagnostics(orc.State(gp, gv))
+    assert np.allclose(o["P"], P, rtol=0, atol=1e-9)
+    assert abs(o["E"] - E) < 1e-9 * E and abs(o["T"] - T) < 1e-9 * T and o["M"] == M
+
+
+def test_vacf_samples(mp):
+    """VACF sample j = (1/N) sum v(j stride) . v(0), recorded on the device."""
+    _say("vacf")
+    L, n = (12, 12, 12), 17280
+    pos, vel = inputs.thermal_state(L, n, 8)
+    with mp.Context() as ctx:
+        s = ctx.admit(mp.make_desc(L, n, seed=8, init="external", vacf_stride=3, n_steps=12))
+        ctx.set_state(s, (pos, vel))
+        ctx.step(20)                       # stops at n_steps
+        o = ctx.observe(s)
+        gp, gv, step = ctx.get_state(s)
+    assert step == 12 and o["step"] == 12
+    assert len(o["vacf"]) == 5
+    v0 = vel.astype(np.float64)
+    assert abs(o["vacf"][0] - np.sum(v0 * v0) / n) < 1e-9
+    assert abs(o["vacf"][-1] - np.sum(gv.astype(np.float64) * v0) / n) < 1e-9
+
+
+def test_one_step_vacf_closed_form_gpu(mp):
+    """Same statistical pin as the oracle's, on the GPU path at 1.6e6 particles."""
+    _say("vacf-closed-form")
+    L, n = 54, 10 * 54 ** 3
+    alpha = math.radians(130.0)
+    inv_n = L ** 3 / n * (1 - (1 - 1 / L ** 3) ** n)
+    want = 1 - (2 / 3) * (1 - math.cos(alpha)) * (1 - inv_n)
+    with mp.Context() as ctx:
+        s = ctx.admit(mp.make_desc(L, n, seed=31, vacf_stride=1, n_steps=1))
+        ctx.step(1)
+        v = ctx.observe(s)["vacf"]
+    got = v[1] / v[0]
+    assert abs(got - want) < 5 * math.sqrt(3.0 / n), (got, want)
+
+
+def test_stop_after_n_steps_and_release(mp):
+    _say("lifecycle")
+    with mp.Context() as ctx:
+        a = ctx.admit(mp.make_desc(8, 5120, seed=1, n_steps=5))
+        b = ctx.admit(mp.make_desc(8, 5120, seed=2, n_steps=0))
+        ctx.step(8)
+        assert ctx.observe(a)["step"] == 5
+        assert ctx.observe(b)["step"] == 8
+        ctx.release(a)
+        with pytest.raises(mp.MPCDError) as e:
+            ctx.observe(a)
+        assert e.value.status == mp.MPCD_ENOTFOUND
+        c = ctx.admit(mp.make_desc(6, 2160, seed=3))
+        assert c == a                        # slot reused
+        ctx.step(2)
+        assert ctx.observe(b)["step"] == 10 and ctx.observe(c)["step"] == 2
+
+
+def test_admission_errors_leave_context_unchanged(mp):
+    _say("errors")
+    with mp.Context(hbm_budget=64 << 20, max_slots=2) as ctx:
+        bad = mp.make_desc(8, 100)
+        bad.L[1] = 0
+        assert mp.mpcd_admit(ctx.handle, bad)[0] == mp.MPCD_EINVAL
+        bad = mp.make_desc(8, 100, dt=-1.0)
+        assert mp.mpcd_admit(ctx.handle, bad)[0] == mp.MPCD_EINVAL
+        bad = mp.make_desc(8, 100)
+        bad.flags = mp.MPCD_INIT_MAXWELL | mp.MPCD_INIT_EXTERNAL
+        assert mp.mpcd_admit(ctx.handle, bad)[0] == mp.MPCD_EINVAL
+        # over the 64 MiB budget
+        assert ctx.try_admit(mp.make_desc(100, 10 ** 6)) is None
+        s0 = ctx.admit(mp.make_desc(8, 5120, seed=1))
+        s1 = ctx.admit(mp.make_desc(8, 5120, seed=2))
+        assert mp.mpcd_admit(ctx.handle, mp.make_desc(8, 10))[0] == mp.MPCD_EBUSY
+        ctx.step(3)
+        assert ctx.observe(s0)["step"] == 3 and ctx.observe(s1)["step"] == 3
+        # set_state rejects positions outside the box and non-finite values
+        pos, vel = inputs.thermal_state(8, 5120, 1)
+        p2 = pos.copy()
+        p2[0, 5] = 8.0
+        assert mp.mpcd_set_state(ctx.handle, s0, np.concatenate([p2, vel]), 0) == mp.MPCD_EINVAL
+        v2 = vel.copy()
+        v2[1, 7] = np.nan
+        assert mp.mpcd_set_state(ctx.handle, s0, np.concatenate([pos, v2]), 0) == mp.MPCD_EINVAL
+        assert ctx.observe(s0)["step"] == 3
+
+
+def test_nonfinite_velocity_flags_only_its_box(mp):
+    """A huge velocity overflows that box's energy to Inf; the other box in the
+    batch stays healthy."""
+    _say("nan-guard")
+    with mp.Context() as ctx:
+        a = ctx.admit(mp.make_desc(8, 5120, seed=1, init="external"))
+        b = ctx.admit(mp.make_desc(8, 5120, seed=2))
+        pos, vel = inputs.thermal_state(8, 5120, 1)
+        vel[0, 10] = np.float32(3e38)
+        ctx.set_state(a, (pos, vel))
+        ctx.step(2)
+        oa = ctx.observe(a)
+        ob = ctx.observe(b)
+    assert oa["status"] == mp.MPCD_ESTATE
+    assert ob["status"] == mp.MPCD_OK and ob["step"] == 2
