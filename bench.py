@@ -33,19 +33,21 @@ DEFAULT_WORKLOAD = "srd_256cube_10ppc"
 
 # Algorithmic bytes each kernel's function has to move, per particle (P) and
 # per cell (C), independent of how the kernel is written:
-#   stream_bin : read x, v (24 B), write x (12 B)                    -> 36 P
-#   rotate     : read v, write v                                      -> 24 P
-#   finalize   : read the cell sums (3 x 4 B + count 4 B), write
-#                u_c and the axis (6 x 4 B)                           -> 40 C
+#   brick_accumulate: read x, v (24 B); write the cell sums
+#                (3 x 4 B + a 4 B count per cell)                     -> 24 P + 16 C
+#   brick_finalize: read the cell sums (16 B), write u_c and the
+#                axis (6 x 4 B)                                       -> 40 C
+#   brick_rotate: read x, v (24 B) and u_c, axis (24 B per cell),
+#                write x, v (24 B)                                    -> 48 P + 24 C
 #   cell_rotate: read v, write v                                      -> 24 P
-#   scatter    : read x, v, id (28 B), write them (28 B)              -> 56 P
+#   scatter    : read x, v (24 B), write them (24 B)                  -> 48 P
 #   count      : read x (12 B), write the key (4 B)                   -> 16 P
 ALGO_BYTES = {
-    "stream_bin": (36, 0),
-    "rotate": (24, 0),
-    "finalize": (0, 40),
+    "brick_accumulate": (24, 16),
+    "brick_finalize": (0, 40),
+    "brick_rotate": (48, 24),
     "cell_rotate": (24, 0),
-    "scatter": (56, 0),
+    "scatter": (48, 0),
     "count": (16, 0),
 }
 # the whole step: every particle's x and v read once and written once
@@ -115,7 +117,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
     ap.add_argument("--binning", default="auto", choices=["auto", "atomic", "sort"])
-    ap.add_argument("--resort-period", type=int, default=0)
+    ap.add_argument("--brick", type=int, nargs=3, default=[0, 0, 0])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
 
@@ -134,7 +136,7 @@ def main():
     opts = context_options()
     if args.binning != "auto":
         opts["binning"] = mpcd.MPCD_BIN_ATOMIC if args.binning == "atomic" else mpcd.MPCD_BIN_SORT
-    opts["resort_period"] = args.resort_period
+    opts["brick"] = tuple(args.brick)
 
     print("[bench] workload %s: %d particles, admitting" % (args.workload, n), file=sys.stderr,
           flush=True)
@@ -191,7 +193,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "cells": list(L), "particles": n, "dt": dt,
                    "alpha_deg": alpha, "seed": seed, "binning": obs["binning"],
-                   "resort_period": obs["resort_period"]},
+                   "brick": list(obs["brick"])},
         "useful_hbm_frac": round(value * STEP_ALGO_BYTES_PER_PARTICLE / 1e9 / HBM_PEAK_GBS, 4),
         "roofline": roofline,
         "kernels": kern,

@@ -68,8 +68,10 @@ typedef enum {
 
 /* mpcd_options.binning */
 #define MPCD_BIN_AUTO 0    /* autotuner chooses per box-shape class         */
-#define MPCD_BIN_ATOMIC 1  /* accumulate cell sums with atomics on
-                              near-sorted particles (re-sorted periodically) */
+#define MPCD_BIN_ATOMIC 1  /* particles kept in buckets by brick of cells
+                              (re-bucketed every step while rotating); cell
+                              sums accumulated with LDS atomics per brick
+                              window, partial windows added per cell       */
 #define MPCD_BIN_SORT 2    /* counting-sort particles by collision cell every
                               step, then reduce each cell's contiguous run   */
 
@@ -97,8 +99,9 @@ typedef void (*mpcd_free_fn)(void* ptr, void* user);
 
 typedef struct {
     int32_t binning;        /* MPCD_BIN_*                                    */
-    int32_t resort_period;  /* steps between re-sorts (ATOMIC); 0 = auto     */
-    int32_t block;          /* threads per workgroup: 0 (auto), 256, 512, 1024 */
+    int32_t brick[3];       /* ATOMIC: brick edge in cells per dimension,
+                               each 0 (auto) or in [2, 64]                   */
+    int32_t block;          /* reserved, must be 0                           */
     int32_t use_graph;      /* 1: replay steps from a captured hipGraph      */
     int64_t hbm_budget;     /* bytes all boxes may occupy; 0 = unlimited     */
     void* stream;           /* hipStream_t; NULL = the library creates one   */
@@ -121,7 +124,7 @@ typedef struct {
                                sample j = (1/N) sum_i v_i(j stride) . v_i(0) */
     int64_t n_particles;
     int32_t binning;        /* binning mode in use for this box              */
-    int32_t resort_period;
+    int32_t brick[3];       /* ATOMIC: brick edges in use (largest brick)    */
 } mpcd_observables;
 
 /* Per-kernel timing collected while profiling is on. */

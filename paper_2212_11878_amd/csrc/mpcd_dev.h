@@ -12,6 +12,7 @@ constexpr int kWave = 64;
 constexpr int kBlock = 256;          // threads per workgroup of the particle kernels
 constexpr int kPartTile = 4096;      // particles per particle tile (16 per thread)
 constexpr int kCellTile = 2048;      // cells per cell tile
+constexpr int kItems = 8;            // particles per thread per chunk (brick rotation)
 constexpr int kNumDiag = 5;          // per-tile FP64 partials: sum v (3), sum v^2, sum v.v0
 
 // Per-cell accumulator: exact 64-bit fixed-point momentum sums (quantum
@@ -28,33 +29,53 @@ struct alignas(32) CellUN {
 };
 
 // Read-only description of one box, resident in device memory.  Particle
-// arrays come in two buffers (ping-pong for the out-of-place sort); the
-// buffer in use is BoxState::parity.
+// arrays come in two buffers (ping-pong); the buffer in use is
+// BoxState::parity.
+//
+// Brick binning (MPCD_BIN_ATOMIC): the L0 x L1 x L2 cells are split into
+// nb0 x nb1 x nb2 bricks of nearly equal size; the particles of a buffer are
+// stored bucket by bucket, bucket b holding the particles whose position lies
+// in brick b.  A particle of brick b streams at most a few tenths of a cell,
+// so its collision cell lies in the brick's "window": the brick grown by
+// `margin` cells on every side.  Cell sums are accumulated per window in LDS
+// and written as partial records; a cell's total is the sum of the records of
+// every window that contains it, plus the escape record of particles that
+// left their window (rare).
 struct BoxDev {
     float* p[2][6];        // x, y, z, vx, vy, vz
     float* v0[2][3];       // VACF reference velocities (null if untracked)
     int32_t* pid[2];       // particle identity (admission order)
-    uint32_t* cell;        // collision cell of each particle, this step
+    uint32_t* cell;        // sort key of each particle
     uint32_t* rank;        // rank of each particle inside its key (sort)
-    CellAcc* acc;          // per cell
-    CellUN* un;            // per cell
-    uint32_t* cstart;      // per cell: counts, then exclusive starts (C + 1)
+    uint32_t* cstart;      // counts, then exclusive starts, per key (C + 1)
+    CellUN* un;            // per cell: u_c and axis of this step (brick mode)
+    CellAcc* part;         // brick mode: nbrick x wsize window partial sums
+    CellAcc* esc;          // brick mode: per cell, sums of escaped particles
+    uint32_t* eflag;       // brick mode: per brick, k+1 when esc holds data for it
+    uint32_t* bstart[2];   // brick mode: bucket starts of each buffer (nbrick + 1)
+    uint32_t* bcount;      // brick mode: particles bound for each bucket next step
+    uint32_t* bcursor;     // brick mode: write cursors of the next buckets
     double* vacf;          // VACF samples
     int64_t n;             // particles
     int64_t ncell;
     int32_t L[3];
+    int32_t nb[3];         // bricks per dimension
+    int32_t bmax[3];       // largest brick extent per dimension
+    int32_t wdim[3];       // window extents: bmax + 2 margin
+    int32_t margin;
+    int32_t wsize;         // wdim0 * wdim1 * wdim2
+    int32_t nbrick;
     int32_t vacf_stride;   // 0 = untracked
     int32_t vacf_cap;
-    int32_t binning;       // MPCD_BIN_ATOMIC or MPCD_BIN_SORT
-    int32_t resort_period; // ATOMIC: re-sort by logical cell when k % period == 0
+    int32_t binning;       // MPCD_BIN_ATOMIC (bricks) or MPCD_BIN_SORT
     int32_t ptile0, ptile1;   // particle tiles [ptile0, ptile1)
     int32_t ctile0, ctile1;   // cell tiles [ctile0, ctile1)
+    int32_t btile0, btile1;   // brick tiles [btile0, btile1)
     float len[3];          // L_d * a
     float a, inv_a, dt;
     float ca, sa, omc;     // cos(alpha), sin(alpha), 1 - cos(alpha) rounded from FP64
     float mass;
     uint32_t key0, key1;   // Philox key = seed
-    int32_t pad;
 };
 
 // Mutable per-box state, resident in device memory and advanced by the last
@@ -66,7 +87,7 @@ struct BoxState {
     int parity;            // particle buffer in use
     int vacf_len;
     int status;            // 0 or MPCD_ESTATE
-    int sorted_now;        // set when this step re-sorted (diagnostic)
+    int rebucket;          // brick mode: particles not yet in brick buckets
     double diag[4];        // sum v (3), sum v^2 after the last step
 };
 
@@ -155,10 +176,31 @@ __device__ __forceinline__ uint32_t collision_cell(const BoxDev& b, float x, flo
     return (uint32_t)ix + (uint32_t)b.L[0] * ((uint32_t)iy + (uint32_t)b.L[1] * (uint32_t)iz);
 }
 
-// Unshifted (logical) cell, used as the re-sort key.
-__device__ __forceinline__ uint32_t logical_cell(const BoxDev& b, float x, float y, float z)
+// Brick geometry: brick i of a dimension with L cells split into nb bricks
+// covers cells [floor(i L / nb), floor((i+1) L / nb)).
+__device__ __forceinline__ int brick_lo(int i, int L, int nb) { return (int)(((long long)i * L) / nb); }
+__device__ __forceinline__ int brick_of(int c, int L, int nb)
 {
-    return collision_cell(b, x, y, z, make_float3(0.0f, 0.0f, 0.0f));
+    return (int)((((long long)c + 1) * nb - 1) / L);
+}
+
+// Brick that holds a position (unshifted grid), per dimension.
+__device__ __forceinline__ int3 brick_of_pos(const BoxDev& b, float x, float y, float z)
+{
+    const int cx = axis_cell(x, 0.0f, b.inv_a, b.L[0]);
+    const int cy = axis_cell(y, 0.0f, b.inv_a, b.L[1]);
+    const int cz = axis_cell(z, 0.0f, b.inv_a, b.L[2]);
+    return make_int3(brick_of(cx, b.L[0], b.nb[0]), brick_of(cy, b.L[1], b.nb[1]),
+                     brick_of(cz, b.L[2], b.nb[2]));
+}
+
+// Offset (-1, 0, 1) of brick `to` from brick `from` along a dimension with nb
+// bricks (periodic); 2 when it is farther.
+__device__ __forceinline__ int brick_rel(int from, int to, int nb)
+{
+    if (nb <= 2) return to - from;
+    const int r = ((to - from + nb + 1) % nb) - 1;
+    return r <= 1 ? r : 2;
 }
 
 // Velocity in 64-bit fixed point with quantum 2^-32 (exact for |v| >= 2^-9,
@@ -181,9 +223,14 @@ __device__ __forceinline__ void range_check(float3 v, double& energy)
     if (!(m < kVelocityLimit)) energy = __builtin_inf();
 }
 
+// Mean velocity of a cell from its exact fixed-point sum, rounded once to
+// FP32 (the 64-bit sum is split into exact 32-bit halves, combined and
+// divided in FP64).
 __device__ __forceinline__ float fixed_mean(unsigned long long s, unsigned int n)
 {
-    return ((float)(long long)s * 2.3283064365386963e-10f) / (float)n;   // 2^-32
+    const double hi = (double)(int)(unsigned)(s >> 32);
+    const double lo = (double)(unsigned)(s & 0xffffffffu);
+    return (float)((hi + lo * 2.3283064365386963e-10) / (double)n);   // (hi 2^32 + lo) 2^-32 / n
 }
 
 // v' = u + w cos(a) + (n x w) sin(a) + n (n.w)(1 - cos(a)), w = v - u

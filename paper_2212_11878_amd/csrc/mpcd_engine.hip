@@ -29,12 +29,12 @@ using namespace mpcd;
 namespace {
 
 enum Kern {
-    K_ZERO, K_COUNT, K_SCAN, K_SCATTER, K_FLIP, K_STREAM_BIN, K_FINALIZE, K_ROTATE,
-    K_CELL_ROTATE, K_BOX_FINISH, K_NUM
+    K_ZERO, K_COUNT, K_SCAN, K_SCATTER, K_FLIP, K_BRICK_ACC, K_BRICK_SCAN, K_BRICK_FIN,
+    K_BRICK_ROT, K_CELL_ROTATE, K_BOX_FINISH, K_NUM
 };
 const char* const kKernName[K_NUM] = {
-    "zero_counts", "count", "scan", "scatter", "flip", "stream_bin", "finalize", "rotate",
-    "cell_rotate", "box_finish"};
+    "zero_counts", "count", "scan", "scatter", "flip", "brick_accumulate", "brick_scan",
+    "brick_finalize", "brick_rotate", "cell_rotate", "box_finish"};
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -59,8 +59,8 @@ struct mpcd_ctx {
     void* user = nullptr;
     int64_t budget = 0, used = 0;
     int32_t binning = MPCD_BIN_AUTO;
-    int32_t resort_period = 0;
-    int32_t block = 0;
+    int32_t brick[3] = {0, 0, 0};
+    bool pending_rebucket = false;
     bool use_graph = false;
     int max_slots = 4096;
     std::vector<Slot> slots;
@@ -71,7 +71,7 @@ struct mpcd_ctx {
     void* tile_mem = nullptr;        // tiles, active, partials, tilesum
     size_t tile_cap = 0;
     bool dirty = true;
-    bool any_atomic = false, any_sort = false;
+    bool any_brick = false, any_sort = false;
 
     // graph of one step
     hipGraph_t graph = nullptr;
@@ -118,13 +118,35 @@ void drop_graph(mpcd_ctx* c)
     c->graph = nullptr;
 }
 
-// Layout of one box's device allocation.
-struct Layout {
-    size_t off_p[2][6], off_v0[2][3], off_pid[2], off_cell, off_rank, off_acc, off_un,
-        off_cstart, off_vacf, total;
+// Brick decomposition of one box (brick binning).
+struct BrickGeom {
+    int nb[3], bmax[3], wdim[3], margin, wsize, nbrick;
 };
 
-Layout box_layout(int64_t n, int64_t ncell, bool vacf, int vacf_cap)
+BrickGeom brick_geometry(const int32_t L[3], const int32_t want[3])
+{
+    BrickGeom g{};
+    g.margin = 1;
+    g.nbrick = 1;
+    g.wsize = 1;
+    for (int d = 0; d < 3; ++d) {
+        const int B = want[d] > 0 ? want[d] : 8;
+        g.nb[d] = std::max(1, (L[d] + B - 1) / B);
+        g.bmax[d] = (L[d] + g.nb[d] - 1) / g.nb[d];
+        g.wdim[d] = g.bmax[d] + 2 * g.margin;
+        g.nbrick *= g.nb[d];
+        g.wsize *= g.wdim[d];
+    }
+    return g;
+}
+
+// Layout of one box's device allocation.
+struct Layout {
+    size_t off_p[2][6], off_v0[2][3], off_pid[2], off_cell, off_rank, off_cstart, off_un, off_part,
+        off_esc, off_eflag, off_bstart[2], off_bcount, off_bcursor, off_vacf, total;
+};
+
+Layout box_layout(int64_t n, int64_t ncell, bool vacf, int vacf_cap, bool brick, const BrickGeom& g)
 {
     Layout L{};
     size_t o = 0;
@@ -139,9 +161,15 @@ Layout box_layout(int64_t n, int64_t ncell, bool vacf, int vacf_cap)
     for (int b = 0; b < 2; ++b) { L.off_pid[b] = o; o += pf; }
     L.off_cell = o; o += pf;
     L.off_rank = o; o += pf;
-    L.off_acc = o; o += align256((size_t)ncell * sizeof(CellAcc));
-    L.off_un = o; o += align256((size_t)ncell * sizeof(CellUN));
     L.off_cstart = o; o += align256((size_t)(ncell + 1) * 4);
+    const size_t nbk = brick ? (size_t)g.nbrick : 0;
+    L.off_un = o; o += brick ? align256((size_t)ncell * sizeof(CellUN)) : 0;
+    L.off_part = o; o += align256(nbk * g.wsize * sizeof(CellAcc));
+    L.off_esc = o; o += brick ? align256((size_t)ncell * sizeof(CellAcc)) : 0;
+    L.off_eflag = o; o += align256(nbk * 4);
+    for (int b = 0; b < 2; ++b) { L.off_bstart[b] = o; o += align256((nbk + 1) * 4); }
+    L.off_bcount = o; o += align256(nbk * 4);
+    L.off_bcursor = o; o += align256(nbk * 4);
     L.off_vacf = o; o += align256((size_t)std::max(vacf_cap, 1) * 8);
     L.total = o;
     return L;
@@ -187,9 +215,10 @@ int rebuild_tables(mpcd_ctx* c)
 {
     HIPCHK(hipStreamSynchronize(c->stream));
     drop_graph(c);
-    std::vector<Tile> pt, ct;
+    std::vector<Tile> pt, ct, bt;
     std::vector<int32_t> active;
-    c->any_atomic = c->any_sort = false;
+    c->any_brick = c->any_sort = false;
+    int max_wsize = 0;
     for (int s = 0; s < (int)c->slots.size(); ++s) {
         Slot& sl = c->slots[s];
         if (!sl.live) continue;
@@ -203,14 +232,21 @@ int rebuild_tables(mpcd_ctx* c)
         for (int64_t i = 0; i < b.ncell; i += kCellTile)
             ct.push_back(Tile{s, 0, i, std::min<int64_t>(b.ncell, i + kCellTile)});
         b.ctile1 = (int32_t)ct.size();
-        if (b.binning == MPCD_BIN_SORT)
+        b.btile0 = (int32_t)bt.size();
+        if (b.binning == MPCD_BIN_ATOMIC)
+            for (int64_t i = 0; i < b.nbrick; ++i) bt.push_back(Tile{s, 0, i, i + 1});
+        b.btile1 = (int32_t)bt.size();
+        if (b.binning == MPCD_BIN_SORT) {
             c->any_sort = true;
-        else
-            c->any_atomic = true;
+        } else {
+            c->any_brick = true;
+            max_wsize = std::max(max_wsize, b.wsize);
+        }
     }
     const size_t need = align256(pt.size() * sizeof(Tile) + 256) + align256(ct.size() * sizeof(Tile) + 256) +
-                        align256(active.size() * 4 + 256) + align256(pt.size() * kNumDiag * 8 + 256) +
-                        align256(ct.size() * kNumDiag * 8 + 256) + align256(ct.size() * 4 + 256);
+                        align256(bt.size() * sizeof(Tile) + 256) + align256(active.size() * 4 + 256) +
+                        align256(pt.size() * kNumDiag * 8 + 256) + align256(ct.size() * kNumDiag * 8 + 256) +
+                        align256(bt.size() * kNumDiag * 8 + 256) + align256(ct.size() * 4 + 256);
     if (need > c->tile_cap) {
         void* m = ctx_alloc(c, need * 5 / 4);
         if (!m) return MPCD_ENOMEM;
@@ -222,15 +258,20 @@ int rebuild_tables(mpcd_ctx* c)
     size_t o = 0;
     c->T.ptiles = (Tile*)(base + o); o += align256(pt.size() * sizeof(Tile) + 256);
     c->T.ctiles = (Tile*)(base + o); o += align256(ct.size() * sizeof(Tile) + 256);
+    c->T.btiles = (Tile*)(base + o); o += align256(bt.size() * sizeof(Tile) + 256);
     c->T.active = (int32_t*)(base + o); o += align256(active.size() * 4 + 256);
     c->T.partials = (double*)(base + o); o += align256(pt.size() * kNumDiag * 8 + 256);
     c->T.partials_c = (double*)(base + o); o += align256(ct.size() * kNumDiag * 8 + 256);
+    c->T.partials_b = (double*)(base + o); o += align256(bt.size() * kNumDiag * 8 + 256);
     c->T.tilesum = (uint32_t*)(base + o);
     c->T.nptiles = (int)pt.size();
     c->T.nctiles = (int)ct.size();
+    c->T.nbtiles = (int)bt.size();
     c->T.nactive = (int)active.size();
+    c->T.max_wsize = max_wsize;
     if (!pt.empty()) HIPCHK(hipMemcpy(c->T.ptiles, pt.data(), pt.size() * sizeof(Tile), hipMemcpyHostToDevice));
     if (!ct.empty()) HIPCHK(hipMemcpy(c->T.ctiles, ct.data(), ct.size() * sizeof(Tile), hipMemcpyHostToDevice));
+    if (!bt.empty()) HIPCHK(hipMemcpy(c->T.btiles, bt.data(), bt.size() * sizeof(Tile), hipMemcpyHostToDevice));
     if (!active.empty())
         HIPCHK(hipMemcpy(c->T.active, active.data(), active.size() * 4, hipMemcpyHostToDevice));
     for (int32_t s : active)
@@ -283,8 +324,9 @@ int timed(mpcd_ctx* c, int k, F&& launch)
     return MPCD_OK;
 }
 
-// The launch sequence of one step for every live box.
-int enqueue_step(mpcd_ctx* c)
+// The launch sequence of one step for every live box.  with_sort adds the
+// counting sort that buckets freshly admitted / reset brick boxes.
+int enqueue_step(mpcd_ctx* c, bool with_sort)
 {
     const Tables& T = c->T;
     hipStream_t s = c->stream;
@@ -294,16 +336,18 @@ int enqueue_step(mpcd_ctx* c)
         rc = timed(c, id, [&] { call; });                      \
         if (rc) return rc;                                     \
     } while (0)
-    // counting sort: every step for SORT boxes, every resort_period steps for ATOMIC boxes
-    STEP_K(K_ZERO, launch_zero_counts(T, s));
-    STEP_K(K_COUNT, launch_count(T, s));
-    STEP_K(K_SCAN, launch_scan(T, s));
-    STEP_K(K_SCATTER, launch_scatter(T, s));
-    STEP_K(K_FLIP, launch_flip(T, s));
-    if (c->any_atomic) {
-        STEP_K(K_STREAM_BIN, launch_stream_bin(T, s));
-        STEP_K(K_FINALIZE, launch_finalize(T, s));
-        STEP_K(K_ROTATE, launch_rotate(T, s));
+    if (c->any_sort || with_sort) {
+        STEP_K(K_ZERO, launch_zero_counts(T, s));
+        STEP_K(K_COUNT, launch_count(T, s));
+        STEP_K(K_SCAN, launch_scan(T, s));
+        STEP_K(K_SCATTER, launch_scatter(T, s));
+        STEP_K(K_FLIP, launch_flip(T, s));
+    }
+    if (c->any_brick) {
+        STEP_K(K_BRICK_ACC, launch_brick_accumulate(T, s));
+        STEP_K(K_BRICK_SCAN, launch_brick_scan(T, s));
+        STEP_K(K_BRICK_FIN, launch_brick_finalize(T, s));
+        STEP_K(K_BRICK_ROT, launch_brick_rotate(T, s));
     }
     if (c->any_sort) STEP_K(K_CELL_ROTATE, launch_cell_rotate(T, s));
     STEP_K(K_BOX_FINISH, launch_box_finish(T, s));
@@ -316,7 +360,7 @@ int capture_graph(mpcd_ctx* c)
 {
     drop_graph(c);
     HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-    int rc = enqueue_step(c);
+    int rc = enqueue_step(c, false);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(c->stream, &g);
     if (rc) {
@@ -362,6 +406,8 @@ int reset_state(mpcd_ctx* c, int32_t s, int64_t step, int parity)
     st.parity = parity;
     st.vacf_len = 0;
     st.status = 0;
+    st.rebucket = (sl.dev.binning == MPCD_BIN_ATOMIC) ? 1 : 0;
+    if (st.rebucket) c->pending_rebucket = true;
     HIPCHK(hipStreamSynchronize(c->stream));
     HIPCHK(hipMemcpy(&c->T.state[s], &st, sizeof(BoxState), hipMemcpyHostToDevice));
     return MPCD_OK;
@@ -453,9 +499,10 @@ int mpcd_create(const mpcd_options* opt, mpcd_ctx** out)
     *out = nullptr;
     mpcd_options o{};
     if (opt) o = *opt;
-    if (o.binning < 0 || o.binning > 2 || o.resort_period < 0 || o.hbm_budget < 0 || o.max_slots < 0)
-        return MPCD_EINVAL;
-    if (o.block != 0 && o.block != 256 && o.block != 512 && o.block != 1024) return MPCD_EINVAL;
+    if (o.binning < 0 || o.binning > 2 || o.hbm_budget < 0 || o.max_slots < 0) return MPCD_EINVAL;
+    for (int d = 0; d < 3; ++d)
+        if (o.brick[d] != 0 && (o.brick[d] < 2 || o.brick[d] > 64)) return MPCD_EINVAL;
+    if (o.block != 0) return MPCD_EINVAL;
     if ((o.alloc == nullptr) != (o.free == nullptr)) return MPCD_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return MPCD_EDEVICE;
@@ -468,8 +515,7 @@ int mpcd_create(const mpcd_options* opt, mpcd_ctx** out)
     c->user = o.user;
     c->budget = o.hbm_budget;
     c->binning = o.binning;
-    c->resort_period = o.resort_period;
-    c->block = o.block;
+    for (int d = 0; d < 3; ++d) c->brick[d] = o.brick[d];
     c->use_graph = o.use_graph != 0;
     c->max_slots = o.max_slots > 0 ? o.max_slots : 4096;
     if (o.stream) {
@@ -509,7 +555,11 @@ int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
     const bool vacf = (d->flags & MPCD_TRACK_VACF) != 0;
     const int64_t ncell = (int64_t)d->L[0] * d->L[1] * d->L[2];
     const int cap = vacf_capacity(d);
-    const Layout L = box_layout(d->n_particles, ncell, vacf, cap);
+    const int32_t binning = c->binning == MPCD_BIN_SORT ? MPCD_BIN_SORT : MPCD_BIN_ATOMIC;
+    const bool brick = binning == MPCD_BIN_ATOMIC;
+    const BrickGeom g = brick_geometry(d->L, c->brick);
+    if (brick && g.wsize > max_window_records()) return MPCD_EINVAL;
+    const Layout L = box_layout(d->n_particles, ncell, vacf, cap, brick, g);
     if (c->budget > 0 && c->used + (int64_t)L.total > c->budget) return MPCD_ENOMEM;
     HIPCHK(hipSetDevice(c->device));
     void* mem = ctx_alloc(c, L.total);
@@ -529,9 +579,22 @@ int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
     }
     b.cell = (uint32_t*)(m + L.off_cell);
     b.rank = (uint32_t*)(m + L.off_rank);
-    b.acc = (CellAcc*)(m + L.off_acc);
-    b.un = (CellUN*)(m + L.off_un);
     b.cstart = (uint32_t*)(m + L.off_cstart);
+    b.un = brick ? (CellUN*)(m + L.off_un) : nullptr;
+    b.part = brick ? (CellAcc*)(m + L.off_part) : nullptr;
+    b.esc = brick ? (CellAcc*)(m + L.off_esc) : nullptr;
+    b.eflag = brick ? (uint32_t*)(m + L.off_eflag) : nullptr;
+    for (int p = 0; p < 2; ++p) b.bstart[p] = brick ? (uint32_t*)(m + L.off_bstart[p]) : nullptr;
+    b.bcount = brick ? (uint32_t*)(m + L.off_bcount) : nullptr;
+    b.bcursor = brick ? (uint32_t*)(m + L.off_bcursor) : nullptr;
+    for (int k = 0; k < 3; ++k) {
+        b.nb[k] = brick ? g.nb[k] : 1;
+        b.bmax[k] = brick ? g.bmax[k] : d->L[k];
+        b.wdim[k] = brick ? g.wdim[k] : 0;
+    }
+    b.margin = g.margin;
+    b.wsize = brick ? g.wsize : 0;
+    b.nbrick = brick ? g.nbrick : 0;
     b.vacf = (double*)(m + L.off_vacf);
     b.n = d->n_particles;
     b.ncell = ncell;
@@ -541,8 +604,7 @@ int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
     }
     b.vacf_stride = vacf ? d->vacf_stride : 0;
     b.vacf_cap = cap;
-    b.binning = c->binning == MPCD_BIN_SORT ? MPCD_BIN_SORT : MPCD_BIN_ATOMIC;
-    b.resort_period = c->resort_period > 0 ? c->resort_period : 20;
+    b.binning = binning;
     b.a = (float)d->a;
     b.inv_a = (float)(1.0 / d->a);
     b.dt = (float)d->dt;
@@ -568,8 +630,16 @@ int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
     if (rc) return undo(rc);
     // zeroed cell accumulators and a defined particle state
     Slot& S = c->slots[s];
-    if (hipMemsetAsync(S.dev.acc, 0, ncell * sizeof(CellAcc), c->stream) != hipSuccess) return undo(MPCD_EDEVICE);
-    if (hipMemsetAsync(S.dev.un, 0, ncell * sizeof(CellUN), c->stream) != hipSuccess) return undo(MPCD_EDEVICE);
+    if (brick) {
+        const size_t nbk = (size_t)S.dev.nbrick;
+        if (hipMemsetAsync(S.dev.un, 0, ncell * sizeof(CellUN), c->stream) != hipSuccess ||
+            hipMemsetAsync(S.dev.esc, 0, ncell * sizeof(CellAcc), c->stream) != hipSuccess ||
+            hipMemsetAsync(S.dev.eflag, 0, nbk * 4, c->stream) != hipSuccess ||
+            hipMemsetAsync(S.dev.bcount, 0, nbk * 4, c->stream) != hipSuccess ||
+            hipMemsetAsync(S.dev.bstart[0], 0, (nbk + 1) * 4, c->stream) != hipSuccess ||
+            hipMemsetAsync(S.dev.bstart[1], 0, (nbk + 1) * 4, c->stream) != hipSuccess)
+            return undo(MPCD_EDEVICE);
+    }
     rc = reset_state(c, s, 0, 0);
     if (rc) return undo(rc);
     if (d->flags & MPCD_INIT_MAXWELL) {
@@ -598,6 +668,12 @@ int mpcd_step(mpcd_ctx* c, int32_t n)
         int rc = rebuild_tables(c);
         if (rc) return rc;
     }
+    if (c->pending_rebucket) {   // bucket fresh brick boxes, then one eager step
+        int rc = enqueue_step(c, true);
+        if (rc) return rc;
+        c->pending_rebucket = false;
+        if (--n == 0) return MPCD_OK;
+    }
     const bool graph = c->use_graph && !c->profiling;
     if (graph && !c->graph_exec) {
         int rc = capture_graph(c);
@@ -607,7 +683,7 @@ int mpcd_step(mpcd_ctx* c, int32_t n)
         if (graph) {
             HIPCHK(hipGraphLaunch(c->graph_exec, c->stream));
         } else {
-            int rc = enqueue_step(c);
+            int rc = enqueue_step(c, false);
             if (rc) return rc;
             if (c->pending.size() > 4096) {
                 rc = harvest(c);
@@ -646,7 +722,7 @@ int mpcd_observe(mpcd_ctx* c, int32_t slot, mpcd_observables* out)
     out->vacf = c->vacf_host.empty() ? nullptr : c->vacf_host.data();
     out->n_particles = n;
     out->binning = sl->dev.binning;
-    out->resort_period = sl->dev.resort_period;
+    for (int d = 0; d < 3; ++d) out->brick[d] = sl->dev.binning == MPCD_BIN_ATOMIC ? sl->dev.bmax[d] : 0;
     return out->status;
 }
 

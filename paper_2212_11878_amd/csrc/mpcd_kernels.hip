@@ -3,12 +3,17 @@
 // One step of a box (paper Sec. 2; shifted grid of Sec. 3.1, Listing 1;
 // mass-weighted cell velocity of Sec. 3.3, Listing 4) runs as:
 //
-//   ATOMIC binning (particles kept near cell order by a periodic re-sort)
-//     [re-sort by logical cell when k % period == 0: zero, count, scan, scatter, flip]
-//     k_stream_bin   x <- fold(x + v dt); c = cell of (x - s); acc[c] += (v, 1)
-//     k_finalize     u_c = sum v / n, axis n_c from Philox; zero acc
-//     k_rotate       v <- u_c + R(n_c, alpha)(v - u_c); FP64 partial diagnostics
-//     k_box_finish   per box: reduce partials, VACF sample, k++
+//   ATOMIC binning (particles bucketed by brick of cells)
+//     k_brick_accumulate  per brick: stream, bin into the brick's window,
+//                         LDS-atomic exact cell sums, write window partials,
+//                         count next-step buckets
+//     k_brick_scan        per box: next bucket starts
+//     k_brick_finalize    per cell: add the window partials (and escapes),
+//                         u_c = sum v / n, axis n_c from Philox
+//     k_brick_rotate      per brick: stream again (same arithmetic), rotate
+//                         v <- u_c + R(n_c, alpha)(v - u_c), write the
+//                         particle into its next bucket; FP64 diagnostics
+//     k_box_finish        per box: reduce diagnostics, VACF sample, k++
 //
 //   SORT binning (counting sort by collision cell every step)
 //     zero, k_count (streamed collision cell + rank), scan, k_scatter (streams
@@ -17,8 +22,8 @@
 //
 // Both paths sum the momentum of a cell exactly (64-bit fixed point), so
 // they produce bit-identical velocities whatever the order of the atomics.
-// All kernels grid over "tiles" (contiguous particle or cell ranges of one
-// box), which lets one launch advance many boxes of different sizes.
+// All kernels grid over "tiles" (contiguous particle, cell or brick ranges of
+// one box), which lets one launch advance many boxes of different sizes.
 #include "mpcd_dev.h"
 #include "mpcd_launch.h"
 
@@ -29,10 +34,11 @@ namespace mpcd {
 
 __device__ __forceinline__ bool box_idle(const BoxState& s) { return s.remaining == 0; }
 
+// The counting sort runs every step for SORT boxes, and once for brick
+// boxes whose particles are not bucketed yet (after admission / set_state).
 __device__ __forceinline__ bool sort_due(const BoxDev& b, const BoxState& s)
 {
-    if (b.binning == 2) return true;
-    return b.resort_period > 0 && (s.k % b.resort_period) == 0;
+    return b.binning == 2 || s.rebucket != 0;
 }
 
 __device__ __forceinline__ bool vacf_due(const BoxDev& b, const BoxState& s)
@@ -92,111 +98,306 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* t
 }
 
 // --------------------------------------------------------------------------
-// ATOMIC path
+// ATOMIC (brick) path
 
-__global__ __launch_bounds__(kBlock) void k_stream_bin(const Tile* __restrict__ tiles,
-                                                        const BoxDev* __restrict__ boxes,
-                                                        const BoxState* __restrict__ st)
+__global__ __launch_bounds__(kBlock) void k_brick_accumulate(const Tile* __restrict__ tiles,
+                                                              const BoxDev* __restrict__ boxes,
+                                                              const BoxState* __restrict__ st)
 {
+    extern __shared__ CellAcc win[];
+    __shared__ uint32_t cnt[27];
     const Tile tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     const BoxState s = st[tl.box];
     const BoxDev& b = boxes[tl.box];
     if (box_idle(s) || b.binning != 1) return;
-    float* __restrict__ x = b.p[s.parity][0];
-    float* __restrict__ y = b.p[s.parity][1];
-    float* __restrict__ z = b.p[s.parity][2];
-    const float* __restrict__ vx = b.p[s.parity][3];
-    const float* __restrict__ vy = b.p[s.parity][4];
-    const float* __restrict__ vz = b.p[s.parity][5];
-    uint32_t* __restrict__ cell = b.cell;
-    CellAcc* __restrict__ acc = b.acc;
+    const int brick = (int)tl.begin;
+    const int bx = brick % b.nb[0], by = (brick / b.nb[0]) % b.nb[1], bz = brick / (b.nb[0] * b.nb[1]);
+    const int m = b.margin;
+    const int lox = brick_lo(bx, b.L[0], b.nb[0]), loy = brick_lo(by, b.L[1], b.nb[1]),
+              loz = brick_lo(bz, b.L[2], b.nb[2]);
+    const int ex = brick_lo(bx + 1, b.L[0], b.nb[0]) - lox + 2 * m;   // window extents
+    const int ey = brick_lo(by + 1, b.L[1], b.nb[1]) - loy + 2 * m;
+    const int ez = brick_lo(bz + 1, b.L[2], b.nb[2]) - loz + 2 * m;
+    const int wx = b.wdim[0], wy = b.wdim[1];
+    for (int i = threadIdx.x; i < b.wsize; i += kBlock) {
+        CellAcc z = {0ull, 0ull, 0ull, 0u, 0u};
+        win[i] = z;
+    }
+    if (threadIdx.x < 27) cnt[threadIdx.x] = 0u;
+    __syncthreads();
+
+    const int par = s.parity;
+    const float* __restrict__ x = b.p[par][0];
+    const float* __restrict__ y = b.p[par][1];
+    const float* __restrict__ z = b.p[par][2];
+    const float* __restrict__ vx = b.p[par][3];
+    const float* __restrict__ vy = b.p[par][4];
+    const float* __restrict__ vz = b.p[par][5];
     const float3 sh = grid_shift(b, s.k);
-    const float dt = b.dt, l0 = b.len[0], l1 = b.len[1], l2 = b.len[2];
-    for (int64_t i = tl.begin + threadIdx.x; i < tl.end; i += kBlock) {
+    const float dt = b.dt;
+    const uint32_t stamp = (uint32_t)(s.k + 1);
+    const int64_t beg = b.bstart[par][brick], end = b.bstart[par][brick + 1];
+    for (int64_t i = beg + threadIdx.x; i < end; i += kBlock) {
         const float ux = vx[i], uy = vy[i], uz = vz[i];
-        const float px = fold(fmaf(ux, dt, x[i]), l0);
-        const float py = fold(fmaf(uy, dt, y[i]), l1);
-        const float pz = fold(fmaf(uz, dt, z[i]), l2);
-        x[i] = px;
-        y[i] = py;
-        z[i] = pz;
-        const uint32_t c = collision_cell(b, px, py, pz, sh);
-        cell[i] = c;
-        atomicAdd(&acc[c].sx, to_fixed(ux));
-        atomicAdd(&acc[c].sy, to_fixed(uy));
-        atomicAdd(&acc[c].sz, to_fixed(uz));
-        atomicAdd(&acc[c].n, 1u);
+        const float px = fold(fmaf(ux, dt, x[i]), b.len[0]);
+        const float py = fold(fmaf(uy, dt, y[i]), b.len[1]);
+        const float pz = fold(fmaf(uz, dt, z[i]), b.len[2]);
+        const int cx = axis_cell(px, sh.x, b.inv_a, b.L[0]);
+        const int cy = axis_cell(py, sh.y, b.inv_a, b.L[1]);
+        const int cz = axis_cell(pz, sh.z, b.inv_a, b.L[2]);
+        int lx = cx - lox + m, ly = cy - loy + m, lz = cz - loz + m;
+        lx += (lx < 0) ? b.L[0] : 0; lx -= (lx >= b.L[0]) ? b.L[0] : 0;
+        ly += (ly < 0) ? b.L[1] : 0; ly -= (ly >= b.L[1]) ? b.L[1] : 0;
+        lz += (lz < 0) ? b.L[2] : 0; lz -= (lz >= b.L[2]) ? b.L[2] : 0;
+        const unsigned long long fx = to_fixed(ux), fy = to_fixed(uy), fz = to_fixed(uz);
+        if (lx < ex && ly < ey && lz < ez) {
+            CellAcc* w = &win[lx + wx * (ly + wy * lz)];
+            atomicAdd(&w->sx, fx);
+            atomicAdd(&w->sy, fy);
+            atomicAdd(&w->sz, fz);
+            atomicAdd(&w->n, 1u);
+        } else {   // left the window: exact global sums, flag the owner brick
+            const uint32_t c = (uint32_t)cx + (uint32_t)b.L[0] * ((uint32_t)cy + (uint32_t)b.L[1] * (uint32_t)cz);
+            atomicAdd(&b.esc[c].sx, fx);
+            atomicAdd(&b.esc[c].sy, fy);
+            atomicAdd(&b.esc[c].sz, fz);
+            atomicAdd(&b.esc[c].n, 1u);
+            const int ob = brick_of(cx, b.L[0], b.nb[0]) +
+                           b.nb[0] * (brick_of(cy, b.L[1], b.nb[1]) + b.nb[1] * brick_of(cz, b.L[2], b.nb[2]));
+            b.eflag[ob] = stamp;
+        }
+        // bucket of the streamed position for the next step
+        const int3 d = brick_of_pos(b, px, py, pz);
+        const int rx = brick_rel(bx, d.x, b.nb[0]), ry = brick_rel(by, d.y, b.nb[1]),
+                  rz = brick_rel(bz, d.z, b.nb[2]);
+        if (rx <= 1 && ry <= 1 && rz <= 1)
+            atomicAdd(&cnt[(rx + 1) + 3 * ((ry + 1) + 3 * (rz + 1))], 1u);
+        else
+            atomicAdd(&b.bcount[d.x + b.nb[0] * (d.y + b.nb[1] * d.z)], 1u);
+    }
+    __syncthreads();
+    CellAcc* __restrict__ out = b.part + (size_t)brick * b.wsize;
+    for (int i = threadIdx.x; i < b.wsize; i += kBlock) out[i] = win[i];
+    if (threadIdx.x < 27 && cnt[threadIdx.x] != 0u) {
+        const int r = threadIdx.x;
+        const int dx = (bx + (r % 3) - 1 + b.nb[0]) % b.nb[0];
+        const int dy = (by + (r / 3) % 3 - 1 + b.nb[1]) % b.nb[1];
+        const int dz = (bz + r / 9 - 1 + b.nb[2]) % b.nb[2];
+        atomicAdd(&b.bcount[dx + b.nb[0] * (dy + b.nb[1] * dz)], cnt[r]);
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_finalize(const Tile* __restrict__ tiles,
-                                                      const BoxDev* __restrict__ boxes,
-                                                      const BoxState* __restrict__ st)
+// per box: bucket starts of the next buffer from the counts, cursors, reset
+__global__ __launch_bounds__(kBlock) void k_brick_scan(const int32_t* __restrict__ active,
+                                                        const BoxDev* __restrict__ boxes,
+                                                        const BoxState* __restrict__ st)
+{
+    const int bx = active[blockIdx.x];
+    const BoxState s = st[bx];
+    const BoxDev& b = boxes[bx];
+    if (box_idle(s) || b.binning != 1) return;
+    const int nb = b.nbrick;
+    const int per = (nb + kBlock - 1) / kBlock;
+    const int lo = min(nb, (int)threadIdx.x * per), hi = min(nb, ((int)threadIdx.x + 1) * per);
+    uint32_t v = 0;
+    for (int i = lo; i < hi; ++i) v += b.bcount[i];
+    uint32_t total;
+    uint32_t run = block_exclusive_scan(v, &total);
+    uint32_t* __restrict__ next = b.bstart[s.parity ^ 1];
+    for (int i = lo; i < hi; ++i) {
+        const uint32_t c = b.bcount[i];
+        next[i] = run;
+        b.bcursor[i] = run;
+        b.bcount[i] = 0u;
+        run += c;
+    }
+    if (threadIdx.x == 0) next[nb] = total;
+}
+
+// windows of bricks along one dimension that contain cell c: (brick, offset)
+__device__ __forceinline__ int windows_of(int c, int L, int nb, int m, int* bi, int* li)
+{
+    const int own = brick_of(c, L, nb);
+    int n = 0;
+    for (int k = -1; k <= 1; ++k) {
+        int i = own + k;
+        i += (i < 0) ? nb : 0;
+        i -= (i >= nb) ? nb : 0;
+        bool dup = false;
+        for (int j = 0; j < n; ++j) dup |= (bi[j] == i);
+        if (dup) continue;
+        const int lo = brick_lo(i, L, nb), ext = brick_lo(i + 1, L, nb) - lo + 2 * m;
+        int l = c - lo + m;
+        l += (l < 0) ? L : 0;
+        l -= (l >= L) ? L : 0;
+        if (l < ext) {
+            bi[n] = i;
+            li[n] = l;
+            ++n;
+        }
+    }
+    return n;
+}
+
+__global__ __launch_bounds__(kBlock) void k_brick_finalize(const Tile* __restrict__ tiles,
+                                                            const BoxDev* __restrict__ boxes,
+                                                            const BoxState* __restrict__ st)
 {
     const Tile tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     const BoxState s = st[tl.box];
     const BoxDev& b = boxes[tl.box];
     if (box_idle(s) || b.binning != 1) return;
-    CellAcc* __restrict__ acc = b.acc;
-    CellUN* __restrict__ un = b.un;
+    const int m = b.margin;
+    const uint32_t stamp = (uint32_t)(s.k + 1);
     for (int64_t c = tl.begin + threadIdx.x; c < tl.end; c += kBlock) {
-        const CellAcc a = acc[c];
-        if (a.n == 0) continue;
+        const int cx = (int)(c % b.L[0]);
+        const int cy = (int)((c / b.L[0]) % b.L[1]);
+        const int cz = (int)(c / ((int64_t)b.L[0] * b.L[1]));
+        int bxs[3], lxs[3], bys[3], lys[3], bzs[3], lzs[3];
+        const int nx = windows_of(cx, b.L[0], b.nb[0], m, bxs, lxs);
+        const int ny = windows_of(cy, b.L[1], b.nb[1], m, bys, lys);
+        const int nz = windows_of(cz, b.L[2], b.nb[2], m, bzs, lzs);
+        unsigned long long sx = 0, sy = 0, sz = 0;
+        unsigned int n = 0;
+        for (int iz = 0; iz < nz; ++iz)
+            for (int iy = 0; iy < ny; ++iy)
+                for (int ix = 0; ix < nx; ++ix) {
+                    const int br = bxs[ix] + b.nb[0] * (bys[iy] + b.nb[1] * bzs[iz]);
+                    const int sl = lxs[ix] + b.wdim[0] * (lys[iy] + b.wdim[1] * lzs[iz]);
+                    const CellAcc r = b.part[(size_t)br * b.wsize + sl];
+                    sx += r.sx;
+                    sy += r.sy;
+                    sz += r.sz;
+                    n += r.n;
+                }
+        const int ob = brick_of(cx, b.L[0], b.nb[0]) +
+                       b.nb[0] * (brick_of(cy, b.L[1], b.nb[1]) + b.nb[1] * brick_of(cz, b.L[2], b.nb[2]));
+        if (b.eflag[ob] == stamp) {
+            const CellAcc e = b.esc[c];
+            if (e.n) {
+                sx += e.sx;
+                sy += e.sy;
+                sz += e.sz;
+                n += e.n;
+                CellAcc zero = {0ull, 0ull, 0ull, 0u, 0u};
+                b.esc[c] = zero;
+            }
+        }
+        if (n == 0) continue;
         CellUN u;
-        u.ux = fixed_mean(a.sx, a.n);
-        u.uy = fixed_mean(a.sy, a.n);
-        u.uz = fixed_mean(a.sz, a.n);
+        u.ux = fixed_mean(sx, n);
+        u.uy = fixed_mean(sy, n);
+        u.uz = fixed_mean(sz, n);
         const float3 ax = cell_axis(b, s.k, (uint32_t)c);
         u.nx = ax.x;
         u.ny = ax.y;
         u.nz = ax.z;
         u.pad0 = 0.0f;
         u.pad1 = 0.0f;
-        un[c] = u;
-        CellAcc zero = {0ull, 0ull, 0ull, 0u, 0u};
-        acc[c] = zero;
+        b.un[c] = u;
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_rotate(const Tile* __restrict__ tiles,
-                                                    const BoxDev* __restrict__ boxes,
-                                                    const BoxState* __restrict__ st,
-                                                    double* __restrict__ partials)
+__global__ __launch_bounds__(kBlock) void k_brick_rotate(const Tile* __restrict__ tiles,
+                                                          const BoxDev* __restrict__ boxes,
+                                                          const BoxState* __restrict__ st,
+                                                          double* __restrict__ partials)
 {
+    __shared__ uint32_t cnt[27];
+    __shared__ uint32_t base[27];
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const Tile tl = tiles[t];
     const BoxState s = st[tl.box];
     const BoxDev& b = boxes[tl.box];
     if (box_idle(s) || b.binning != 1) return;
-    float* __restrict__ vx = b.p[s.parity][3];
-    float* __restrict__ vy = b.p[s.parity][4];
-    float* __restrict__ vz = b.p[s.parity][5];
-    const uint32_t* __restrict__ cell = b.cell;
-    const CellUN* __restrict__ un = b.un;
+    const int brick = (int)tl.begin;
+    const int bx = brick % b.nb[0], by = (brick / b.nb[0]) % b.nb[1], bz = brick / (b.nb[0] * b.nb[1]);
+    const int src = s.parity, dst = s.parity ^ 1;
+    const float3 sh = grid_shift(b, s.k);
+    const float dt = b.dt, ca = b.ca, sa = b.sa, omc = b.omc;
+    const bool track = b.vacf_stride > 0;
     const bool vacf = vacf_due(b, s);
-    const float* __restrict__ w0x = b.v0[s.parity][0];
-    const float* __restrict__ w0y = b.v0[s.parity][1];
-    const float* __restrict__ w0z = b.v0[s.parity][2];
-    const float ca = b.ca, sa = b.sa, omc = b.omc;
+    const int64_t beg = b.bstart[src][brick], end = b.bstart[src][brick + 1];
     double d[kNumDiag] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int64_t i = tl.begin + threadIdx.x; i < tl.end; i += kBlock) {
-        const CellUN u = un[cell[i]];
-        const float3 v = rotate_about(u, vx[i], vy[i], vz[i], ca, sa, omc);
-        vx[i] = v.x;
-        vy[i] = v.y;
-        vz[i] = v.z;
-        d[0] += (double)v.x;
-        d[1] += (double)v.y;
-        d[2] += (double)v.z;
-        d[3] += (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z;
-        if (vacf) d[4] += (double)v.x * w0x[i] + (double)v.y * w0y[i] + (double)v.z * w0z[i];
-        range_check(v, d[3]);
+    constexpr int kChunk = kBlock * kItems;
+    for (int64_t c0 = beg; c0 < end; c0 += kChunk) {
+        if (threadIdx.x < 27) cnt[threadIdx.x] = 0u;
+        __syncthreads();
+        float px[kItems], py[kItems], pz[kItems], qx[kItems], qy[kItems], qz[kItems];
+        int32_t id[kItems];
+        uint32_t slot[kItems];   // rank in its bucket range, or the global slot
+        int rel[kItems];         // 0..26, 27 = far (slot is global), -1 = none
+#pragma unroll
+        for (int it = 0; it < kItems; ++it) {
+            const int64_t i = c0 + it * kBlock + threadIdx.x;
+            rel[it] = -1;
+            if (i < end) {
+                const float ux = b.p[src][3][i], uy = b.p[src][4][i], uz = b.p[src][5][i];
+                px[it] = fold(fmaf(ux, dt, b.p[src][0][i]), b.len[0]);
+                py[it] = fold(fmaf(uy, dt, b.p[src][1][i]), b.len[1]);
+                pz[it] = fold(fmaf(uz, dt, b.p[src][2][i]), b.len[2]);
+                id[it] = b.pid[src][i];
+                const uint32_t c = collision_cell(b, px[it], py[it], pz[it], sh);
+                const CellUN u = b.un[c];
+                const float3 v = rotate_about(u, ux, uy, uz, ca, sa, omc);
+                qx[it] = v.x;
+                qy[it] = v.y;
+                qz[it] = v.z;
+                d[0] += (double)v.x;
+                d[1] += (double)v.y;
+                d[2] += (double)v.z;
+                d[3] += (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z;
+                if (vacf)
+                    d[4] += (double)v.x * b.v0[src][0][i] + (double)v.y * b.v0[src][1][i] +
+                            (double)v.z * b.v0[src][2][i];
+                range_check(v, d[3]);
+                const int3 db = brick_of_pos(b, px[it], py[it], pz[it]);
+                const int rx = brick_rel(bx, db.x, b.nb[0]), ry = brick_rel(by, db.y, b.nb[1]),
+                          rz = brick_rel(bz, db.z, b.nb[2]);
+                if (rx <= 1 && ry <= 1 && rz <= 1) {
+                    rel[it] = (rx + 1) + 3 * ((ry + 1) + 3 * (rz + 1));
+                    slot[it] = atomicAdd(&cnt[rel[it]], 1u);
+                } else {
+                    rel[it] = 27;
+                    slot[it] = atomicAdd(&b.bcursor[db.x + b.nb[0] * (db.y + b.nb[1] * db.z)], 1u);
+                }
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < 27 && cnt[threadIdx.x] != 0u) {
+            const int r = threadIdx.x;
+            const int dx = (bx + (r % 3) - 1 + b.nb[0]) % b.nb[0];
+            const int dy = (by + (r / 3) % 3 - 1 + b.nb[1]) % b.nb[1];
+            const int dz = (bz + r / 9 - 1 + b.nb[2]) % b.nb[2];
+            base[r] = atomicAdd(&b.bcursor[dx + b.nb[0] * (dy + b.nb[1] * dz)], cnt[r]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < kItems; ++it) {
+            if (rel[it] < 0) continue;
+            const int64_t i = c0 + it * kBlock + threadIdx.x;
+            const int64_t j = (rel[it] < 27) ? (int64_t)base[rel[it]] + slot[it] : (int64_t)slot[it];
+            b.p[dst][0][j] = px[it];
+            b.p[dst][1][j] = py[it];
+            b.p[dst][2][j] = pz[it];
+            b.p[dst][3][j] = qx[it];
+            b.p[dst][4][j] = qy[it];
+            b.p[dst][5][j] = qz[it];
+            b.pid[dst][j] = id[it];
+            if (track) {
+                b.v0[dst][0][j] = b.v0[src][0][i];
+                b.v0[dst][1][j] = b.v0[src][1][i];
+                b.v0[dst][2][j] = b.v0[src][2][i];
+            }
+        }
+        __syncthreads();
     }
     block_diag(d, partials + (size_t)t * kNumDiag);
 }
 
 // --------------------------------------------------------------------------
-// counting sort (re-sort by logical cell for ATOMIC; by collision cell for SORT)
+// counting sort: by collision cell every step (SORT), or by brick once to
+// bucket a brick box's particles (after admission / set_state)
 
 __global__ __launch_bounds__(kBlock) void k_zero_counts(const Tile* __restrict__ tiles,
                                                          const BoxDev* __restrict__ boxes,
@@ -229,12 +430,16 @@ __global__ __launch_bounds__(kBlock) void k_count(const Tile* __restrict__ tiles
     const float dt = b.dt;
     for (int64_t i = tl.begin + threadIdx.x; i < tl.end; i += kBlock) {
         float px = x[i], py = y[i], pz = z[i];
+        uint32_t key;
         if (collide_key) {
             px = fold(fmaf(vx[i], dt, px), b.len[0]);
             py = fold(fmaf(vy[i], dt, py), b.len[1]);
             pz = fold(fmaf(vz[i], dt, pz), b.len[2]);
+            key = collision_cell(b, px, py, pz, sh);
+        } else {
+            const int3 d = brick_of_pos(b, px, py, pz);
+            key = (uint32_t)(d.x + b.nb[0] * (d.y + b.nb[1] * d.z));
         }
-        const uint32_t key = collision_cell(b, px, py, pz, sh);
         b.cell[i] = key;
         b.rank[i] = atomicAdd(&b.cstart[key], 1u);
     }
@@ -303,13 +508,24 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const Tile* __restrict__ 
         v += loc[j];
     }
     uint32_t total;
-    uint32_t run = tilesum[t] + block_exclusive_scan(v, &total);
+    const uint32_t start = tilesum[t] + block_exclusive_scan(v, &total);
+    // brick boxes: the keys are bricks; their starts are also the bucket
+    // starts of the buffer the scatter fills
+    uint32_t* __restrict__ next = (b.binning == 1) ? b.bstart[s.parity ^ 1] : nullptr;
+    uint32_t run = start;
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
-        if (c0 + j < tl.end) b.cstart[c0 + j] = run;
+        const int64_t c = c0 + j;
+        if (c < tl.end) {
+            b.cstart[c] = run;
+            if (next && c <= b.nbrick) next[c] = run;
+        }
         run += loc[j];
     }
-    if (tl.end == b.ncell && threadIdx.x == 0) b.cstart[b.ncell] = (uint32_t)b.n;
+    if (tl.end == b.ncell && threadIdx.x == 0) {
+        b.cstart[b.ncell] = (uint32_t)b.n;
+        if (next && b.nbrick == b.ncell) next[b.nbrick] = (uint32_t)b.n;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_scatter(const Tile* __restrict__ tiles,
@@ -356,8 +572,8 @@ __global__ void k_flip(const int32_t* __restrict__ active, int nactive,
     const int bx = active[i];
     BoxState& s = st[bx];
     const bool due = !box_idle(s) && sort_due(boxes[bx], s);
-    s.sorted_now = due ? 1 : 0;
     if (due) s.parity ^= 1;
+    s.rebucket = 0;
 }
 
 // SORT path: particles of cell c occupy [cstart[c], cstart[c+1]) in the
@@ -421,7 +637,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_rotate(const Tile* __restrict__
 __global__ __launch_bounds__(kBlock) void k_box_finish(const int32_t* __restrict__ active,
                                                         const BoxDev* __restrict__ boxes,
                                                         BoxState* __restrict__ st,
-                                                        const double* __restrict__ partials_p,
+                                                        const double* __restrict__ partials_b,
                                                         const double* __restrict__ partials_c)
 {
     const int bx = active[blockIdx.x];
@@ -429,9 +645,9 @@ __global__ __launch_bounds__(kBlock) void k_box_finish(const int32_t* __restrict
     if (box_idle(*sp)) return;
     const BoxDev& b = boxes[bx];
     const bool by_cell = (b.binning == 2);
-    const int t0 = by_cell ? b.ctile0 : b.ptile0;
-    const int t1 = by_cell ? b.ctile1 : b.ptile1;
-    const double* __restrict__ partials = by_cell ? partials_c : partials_p;
+    const int t0 = by_cell ? b.ctile0 : b.btile0;
+    const int t1 = by_cell ? b.ctile1 : b.btile1;
+    const double* __restrict__ partials = by_cell ? partials_c : partials_b;
     double d[kNumDiag] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int t = t0 + (int)threadIdx.x; t < t1; t += kBlock) {
 #pragma unroll
@@ -451,6 +667,7 @@ __global__ __launch_bounds__(kBlock) void k_box_finish(const int32_t* __restrict
             b.vacf[sp->vacf_len++] = tot[4] / (double)b.n;
         sp->k += 1;
         if (sp->remaining > 0) sp->remaining -= 1;
+        if (!by_cell) sp->parity ^= 1;   // the brick rotation wrote the other buffer
     }
 }
 
@@ -568,21 +785,35 @@ __global__ __launch_bounds__(kBlock) void k_fill_zero_u32(uint32_t* __restrict__
         if ((grid) > 0) hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, stream, __VA_ARGS__); \
     } while (0)
 
-void launch_stream_bin(const Tables& T, hipStream_t s)
+void launch_brick_accumulate(const Tables& T, hipStream_t s)
 {
-    MPCD_LAUNCH(k_stream_bin, T.nptiles, kBlock, s, T.ptiles, T.boxes, T.state);
+    static bool attr = false;
+    if (!attr) {   // allow windows above the default 64 KiB of dynamic LDS
+        (void)hipFuncSetAttribute((const void*)k_brick_accumulate,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  max_window_records() * (int)sizeof(CellAcc));
+        attr = true;
+    }
+    const size_t lds = (size_t)T.max_wsize * sizeof(CellAcc);
+    if (T.nbtiles > 0)
+        hipLaunchKernelGGL(k_brick_accumulate, dim3(T.nbtiles), dim3(kBlock), lds, s, T.btiles, T.boxes,
+                           T.state);
 }
-void launch_finalize(const Tables& T, hipStream_t s)
+void launch_brick_scan(const Tables& T, hipStream_t s)
 {
-    MPCD_LAUNCH(k_finalize, T.nctiles, kBlock, s, T.ctiles, T.boxes, T.state);
+    MPCD_LAUNCH(k_brick_scan, T.nactive, kBlock, s, T.active, T.boxes, T.state);
 }
-void launch_rotate(const Tables& T, hipStream_t s)
+void launch_brick_finalize(const Tables& T, hipStream_t s)
 {
-    MPCD_LAUNCH(k_rotate, T.nptiles, kBlock, s, T.ptiles, T.boxes, T.state, T.partials);
+    MPCD_LAUNCH(k_brick_finalize, T.nctiles, kBlock, s, T.ctiles, T.boxes, T.state);
+}
+void launch_brick_rotate(const Tables& T, hipStream_t s)
+{
+    MPCD_LAUNCH(k_brick_rotate, T.nbtiles, kBlock, s, T.btiles, T.boxes, T.state, T.partials_b);
 }
 void launch_box_finish(const Tables& T, hipStream_t s)
 {
-    MPCD_LAUNCH(k_box_finish, T.nactive, kBlock, s, T.active, T.boxes, T.state, T.partials,
+    MPCD_LAUNCH(k_box_finish, T.nactive, kBlock, s, T.active, T.boxes, T.state, T.partials_b,
                 T.partials_c);
 }
 void launch_zero_counts(const Tables& T, hipStream_t s)
@@ -612,6 +843,9 @@ void launch_cell_rotate(const Tables& T, hipStream_t s)
 {
     MPCD_LAUNCH(k_cell_rotate, T.nctiles, kBlock, s, T.ctiles, T.boxes, T.state, T.partials_c);
 }
+
+// Largest window (in records) one brick workgroup may hold in LDS.
+int max_window_records() { return (int)(96 * 1024 / sizeof(CellAcc)); }
 
 // The init/snapshot launchers take a sub-range of T.ptiles (one box); their
 // partials land at the same tile indices as the step's.

@@ -16,17 +16,22 @@ struct Tables {
     BoxState* state = nullptr;   // indexed by slot
     Tile* ptiles = nullptr;      // particle tiles of all live boxes
     Tile* ctiles = nullptr;      // cell tiles of all live boxes
+    Tile* btiles = nullptr;      // brick tiles (begin = brick index) of brick boxes
     int32_t* active = nullptr;   // live slots
-    double* partials = nullptr;  // kNumDiag per particle tile
-    double* partials_c = nullptr;  // kNumDiag per cell tile
+    double* partials = nullptr;    // kNumDiag per particle tile (initial state, snapshots)
+    double* partials_c = nullptr;  // kNumDiag per cell tile (SORT steps)
+    double* partials_b = nullptr;  // kNumDiag per brick tile (brick steps)
     uint32_t* tilesum = nullptr; // per cell tile
-    int nptiles = 0, nctiles = 0, nactive = 0;
+    int nptiles = 0, nctiles = 0, nbtiles = 0, nactive = 0;
+    int max_wsize = 0;             // largest brick window of the live boxes (records)
 };
 
-void launch_stream_bin(const Tables& T, hipStream_t s);
-void launch_finalize(const Tables& T, hipStream_t s);
-void launch_rotate(const Tables& T, hipStream_t s);
+void launch_brick_accumulate(const Tables& T, hipStream_t s);
+void launch_brick_scan(const Tables& T, hipStream_t s);
+void launch_brick_finalize(const Tables& T, hipStream_t s);
+void launch_brick_rotate(const Tables& T, hipStream_t s);
 void launch_box_finish(const Tables& T, hipStream_t s);
+int max_window_records();
 void launch_zero_counts(const Tables& T, hipStream_t s);
 void launch_count(const Tables& T, hipStream_t s);
 void launch_scan(const Tables& T, hipStream_t s);

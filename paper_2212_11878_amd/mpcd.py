@@ -55,7 +55,7 @@ mpcd_free_fn = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 class mpcd_options(ctypes.Structure):
     _fields_ = [
         ("binning", ctypes.c_int32),
-        ("resort_period", ctypes.c_int32),
+        ("brick", ctypes.c_int32 * 3),
         ("block", ctypes.c_int32),
         ("use_graph", ctypes.c_int32),
         ("hbm_budget", ctypes.c_int64),
@@ -80,7 +80,7 @@ class mpcd_observables(ctypes.Structure):
         ("vacf", ctypes.POINTER(ctypes.c_double)),
         ("n_particles", ctypes.c_int64),
         ("binning", ctypes.c_int32),
-        ("resort_period", ctypes.c_int32),
+        ("brick", ctypes.c_int32 * 3),
     ]
 
 
@@ -259,8 +259,8 @@ def make_desc(L, n_particles, dt=0.1, alpha_deg=130.0, seed=1, a=1.0, kT=1.0, ma
 class Context:
     """One library context on a torch-owned HIP stream."""
 
-    def __init__(self, device=0, binning=MPCD_BIN_AUTO, resort_period=0, use_graph=True,
-                 hbm_budget=0, max_slots=0, block=0):
+    def __init__(self, device=0, binning=MPCD_BIN_AUTO, brick=(0, 0, 0), use_graph=True,
+                 hbm_budget=0, max_slots=0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible to PyTorch; libmpcd needs a HIP device")
@@ -269,8 +269,11 @@ class Context:
         self.allocator = _TorchAllocator(self.device)
         opt = mpcd_options()
         opt.binning = binning
-        opt.resort_period = resort_period
-        opt.block = block
+        if isinstance(brick, int):
+            brick = (brick, brick, brick)
+        for i in range(3):
+            opt.brick[i] = int(brick[i])
+        opt.block = 0
         opt.use_graph = 1 if use_graph else 0
         opt.hbm_budget = int(hbm_budget)
         opt.stream = ctypes.c_void_p(self.stream.cuda_stream)
@@ -323,7 +326,7 @@ class Context:
         vacf = [obs.vacf[i] for i in range(obs.vacf_len)] if obs.vacf_len > 0 else []
         return dict(step=obs.step, P=np.array(obs.P[:]), E=obs.E_kin, T=obs.T, M=obs.mass_total,
                     status=obs.status, vacf=np.array(vacf), binning=obs.binning,
-                    resort_period=obs.resort_period, n=obs.n_particles)
+                    brick=tuple(obs.brick[:]), n=obs.n_particles)
 
     def release(self, slot):
         _check(mpcd_release(self.handle, slot), "mpcd_release")

@@ -24,10 +24,10 @@ def _say(*a):
     print("[case]", *a, flush=True)
 
 
-def _run(mp, boxes, steps, binning, use_graph=True, chunks=1, resort=0):
+def _run(mp, boxes, steps, binning, use_graph=True, chunks=1, brick=(0, 0, 0)):
     """Admit (L, n, seed, alpha) boxes with a shared-input state, run, return states."""
     out = []
-    with mp.Context(binning=binning, use_graph=use_graph, resort_period=resort) as ctx:
+    with mp.Context(binning=binning, use_graph=use_graph, brick=brick) as ctx:
         slots = []
         for (L, n, seed, alpha) in boxes:
             pos, vel = inputs.thermal_state(L, n, seed)
@@ -42,15 +42,33 @@ def _run(mp, boxes, steps, binning, use_graph=True, chunks=1, resort=0):
 
 
 def test_binning_modes_bit_identical(mp):
-    """Cell sums are exact integers, so atomic and sort binning (any re-sort
-    period) give the same bits for every particle."""
+    """Cell sums are exact integers, so brick binning (any brick shape) and
+    sort binning give the same bits for every particle."""
     _say("modes")
-    boxes = [((12, 12, 12), 17280, 4, 130.0)]
-    a = _run(mp, boxes, 25, mp.MPCD_BIN_ATOMIC, resort=7)[0]
+    boxes = [((12, 20, 9), 21600, 4, 130.0)]
+    a = _run(mp, boxes, 25, mp.MPCD_BIN_ATOMIC)[0]
     b = _run(mp, boxes, 25, mp.MPCD_BIN_SORT)[0]
-    c = _run(mp, boxes, 25, mp.MPCD_BIN_ATOMIC, resort=1)[0]
-    for x, y in ((a, b), (a, c)):
+    c = _run(mp, boxes, 25, mp.MPCD_BIN_ATOMIC, brick=(4, 4, 4))[0]
+    d = _run(mp, boxes, 25, mp.MPCD_BIN_ATOMIC, brick=(16, 6, 3))[0]
+    for x, y in ((a, b), (a, c), (a, d)):
         assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])
+
+
+def test_fast_particles_leave_their_window(mp):
+    """dt = 1.5 moves particles several cells per step: they leave their
+    brick's window (escape sums) and their neighbouring buckets; the result
+    must still equal sort binning bit for bit."""
+    _say("escapes")
+    L, n = (10, 12, 8), 9600
+    pos, vel = inputs.thermal_state(L, n, 19)
+    out = []
+    for binning in (mp.MPCD_BIN_ATOMIC, mp.MPCD_BIN_SORT):
+        with mp.Context(binning=binning, brick=(4, 4, 4)) as ctx:
+            s = ctx.admit(mp.make_desc(L, n, dt=1.5, seed=19, init="external"))
+            ctx.set_state(s, (pos, vel))
+            ctx.step(6)
+            out.append(ctx.get_state(s))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
 
 
 def test_graph_replay_matches_eager(mp):
@@ -108,6 +126,8 @@ def test_conservation_over_many_steps(mp):
         ctx.step(500)
         o1 = ctx.observe(s)
     assert o1["step"] == 500 and o1["status"] == 0
+    print("[conservation] E0 %.12e E1 %.12e rel %.3e P0 %s P1 %s" % (
+        o0["E"], o1["E"], (o1["E"] - o0["E"]) / o0["E"], o0["P"], o1["P"]), flush=True)
     assert abs(o1["E"] - o0["E"]) / o0["E"] < 1e-5, (o0["E"], o1["E"])
     assert np.all(np.abs(o1["P"] - o0["P"]) < 1e-3 * math.sqrt(n)), (o0["P"], o1["P"])
 
