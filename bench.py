@@ -30,6 +30,8 @@ WORKLOADS = {
     "srd_100cube_10ppc": ((100, 100, 100), 10, 0.1, 130.0, 2),
 }
 DEFAULT_WORKLOAD = "srd_256cube_10ppc"
+ENSEMBLE = "ensemble_512_boxes"      # 512 boxes, edges U{8..48}, densities U[5,20]
+SERVED = "served_poisson"            # Poisson arrivals of single-box requests
 
 # Algorithmic bytes each kernel's function has to move, per particle (P) and
 # per cell (C), independent of how the kernel is written:
@@ -115,7 +117,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS) + [ENSEMBLE, SERVED])
+    ap.add_argument("--rate", type=float, nargs="+", default=[200.0],
+                    help="served: arrival rates (req/s) to sweep")
+    ap.add_argument("--window", type=float, default=10.0, help="served: seconds of arrivals")
     ap.add_argument("--binning", default="auto", choices=["auto", "atomic", "sort"])
     ap.add_argument("--brick", type=int, nargs=3, default=[0, 0, 0])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -129,6 +134,11 @@ def main():
 
     import torch
     from paper_2212_11878_amd import mpcd
+
+    if args.workload == ENSEMBLE:
+        return bench_ensemble(args)
+    if args.workload == SERVED:
+        return bench_served(args)
 
     L, ppc, dt, alpha, seed = WORKLOADS[args.workload]
     n = ppc * L[0] * L[1] * L[2]
@@ -201,6 +211,92 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload)
+    print(json.dumps(out), flush=True)
+
+
+def bench_ensemble(args):
+    """512 independent boxes advanced together (one batched launch sequence
+    per step, graph replay) against the same boxes advanced one at a time."""
+    import torch
+    from paper_2212_11878_amd import inputs, mpcd
+    boxes = inputs.ensemble_boxes(512, seed=4)
+    total = sum(b["n"] for b in boxes)
+
+    def desc(b):
+        return mpcd.make_desc(b["L"], b["n"], dt=b["dt"], alpha_deg=b["alpha_deg"], seed=b["seed"])
+
+    print("[bench] ensemble: %d boxes, %d particles" % (len(boxes), total), file=sys.stderr, flush=True)
+    ctx = mpcd.Context(**context_options())
+    t_adm = time.perf_counter()
+    slots = [ctx.admit(desc(b)) for b in boxes]
+    t_adm = time.perf_counter() - t_adm
+    ctx.step(args.warmup)
+    ctx.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(args.steps)
+    ctx.synchronize()
+    t_batch = time.perf_counter() - t0
+    ctx.profile(True)
+    ctx.step(2)
+    stats = ctx.kernel_stats()
+    ctx.profile(False)
+    bad = [s for s in slots if ctx.observe(s)["status"] != 0]
+    ctx.close()
+    # baseline: the same boxes one at a time on the same GPU, same step count
+    print("[bench] ensemble: one box at a time", file=sys.stderr, flush=True)
+    solo = mpcd.Context(**context_options())
+    t_one = 0.0
+    for b in boxes:
+        s = solo.admit(desc(b))
+        solo.step(args.warmup)
+        solo.synchronize()
+        t1 = time.perf_counter()
+        solo.step(args.steps)
+        solo.synchronize()
+        t_one += time.perf_counter() - t1
+        solo.release(s)
+    solo.close()
+    value = total * args.steps / t_batch
+    one = total * args.steps / t_one
+    out = {"metric": "particle-steps/s", "value": value, "unit": "particle-steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1000 * t_batch / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": ENSEMBLE, "boxes": len(boxes), "particles": total,
+                      "edges": "U{8..48}", "density": "U[5,20]", "alpha_deg": [90, 120, 130], "dt": 0.1},
+           "one_box_at_a_time": {"value": one, "ms_per_step": 1000 * t_one / args.steps},
+           "batched_over_one_at_a_time": value / one, "admission_s": t_adm,
+           "nonfinite_boxes": len(bad),
+           "kernels": {k: {"launches": v[0], "avg_ms": round(v[1] / max(1, v[0]), 4)}
+                       for k, v in stats.items()}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_served(args):
+    """Continuous batching of Poisson-arriving single-box requests; p50/p99
+    latency and sustained throughput per arrival rate."""
+    from paper_2212_11878_amd import inputs, serve
+    sweep = []
+    for rate in args.rate:
+        reqs = inputs.served_requests(rate_hz=rate, window_s=args.window, seed=5)
+        eng = serve.LibraryEngine(hbm_budget=64 << 30)
+        print("[bench] served: %g req/s, %d requests" % (rate, len(reqs)), file=sys.stderr, flush=True)
+        summary, done = serve.Server(eng, chunk_steps=50).run(reqs, max_wall_s=args.window * 3)
+        eng.close()
+        summary["rate_hz"] = rate
+        summary["offered_particle_steps_per_s"] = sum(r["n"] * r["steps"] for r in reqs) / args.window
+        sweep.append(summary)
+        print("[bench] served %g req/s: %r" % (rate, summary), file=sys.stderr, flush=True)
+    head = sweep[-1]
+    out = {"metric": "p50/p99 request latency and particle-steps/s", "value": head["particle_steps_per_s"],
+           "unit": "particle-steps/s", "n_gpus": 1, "steps": None, "warmup": None, "ms_per_step": None,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": SERVED, "edges": "U{8..64}", "density": "U[5,20]", "dt": "U[0.05,0.2]",
+                      "alpha_deg": "U[90,150]", "steps": "U{200..2000}", "window_s": args.window},
+           "p50_latency_s": head["p50_latency_s"], "p99_latency_s": head["p99_latency_s"],
+           "sweep": sweep}
     print(json.dumps(out), flush=True)
 
 

@@ -178,8 +178,8 @@ __device__ __forceinline__ uint32_t collision_cell(const BoxDev& b, float x, flo
 
 // Brick geometry: brick i of a dimension with L cells split into nb bricks
 // covers cells [floor(i L / nb), floor((i+1) L / nb)).
-__device__ __forceinline__ int brick_lo(int i, int L, int nb) { return (int)(((long long)i * L) / nb); }
-__device__ __forceinline__ int brick_of(int c, int L, int nb)
+__host__ __device__ __forceinline__ int brick_lo(int i, int L, int nb) { return (int)(((long long)i * L) / nb); }
+__host__ __device__ __forceinline__ int brick_of(int c, int L, int nb)
 {
     return (int)((((long long)c + 1) * nb - 1) / L);
 }
@@ -196,11 +196,70 @@ __device__ __forceinline__ int3 brick_of_pos(const BoxDev& b, float x, float y, 
 
 // Offset (-1, 0, 1) of brick `to` from brick `from` along a dimension with nb
 // bricks (periodic); 2 when it is farther.
-__device__ __forceinline__ int brick_rel(int from, int to, int nb)
+__host__ __device__ __forceinline__ int brick_rel(int from, int to, int nb)
 {
     if (nb <= 2) return to - from;
     const int r = ((to - from + nb + 1) % nb) - 1;
     return r <= 1 ? r : 2;
+}
+
+// Windows (brick grown by m cells on each side) that contain cell c along
+// one dimension: up to three (brick, offset in window) pairs.
+__host__ __device__ __forceinline__ int windows_of(int c, int L, int nb, int m, int* bi, int* li)
+{
+    const int own = brick_of(c, L, nb);
+    int n = 0;
+    for (int k = -1; k <= 1; ++k) {
+        int i = own + k;
+        i += (i < 0) ? nb : 0;
+        i -= (i >= nb) ? nb : 0;
+        bool dup = false;
+        for (int j = 0; j < n; ++j) dup |= (bi[j] == i);
+        if (dup) continue;
+        const int lo = brick_lo(i, L, nb), ext = brick_lo(i + 1, L, nb) - lo + 2 * m;
+        int l = c - lo + m;
+        l += (l < 0) ? L : 0;
+        l -= (l >= L) ? L : 0;
+        if (l < ext) {
+            bi[n] = i;
+            li[n] = l;
+            ++n;
+        }
+    }
+    return n;
+}
+
+// Offset of canonical cell c inside the window of the brick starting at lo
+// (periodic), as the accumulation computes it.
+__host__ __device__ __forceinline__ int window_offset(int c, int lo, int m, int L)
+{
+    int l = c - lo + m;
+    l += (l < 0) ? L : 0;
+    l -= (l >= L) ? L : 0;
+    return l;
+}
+
+// Brick decomposition of one box: nb bricks per dimension of at most
+// `want` cells (8 when 0), windows grown by `margin` cells.
+struct BrickGeom {
+    int nb[3], bmax[3], wdim[3], margin, wsize, nbrick;
+};
+
+inline BrickGeom brick_geometry(const int32_t L[3], const int32_t want[3])
+{
+    BrickGeom g{};
+    g.margin = 1;
+    g.nbrick = 1;
+    g.wsize = 1;
+    for (int d = 0; d < 3; ++d) {
+        const int B = want[d] > 0 ? want[d] : 8;
+        g.nb[d] = (L[d] + B - 1) / B > 1 ? (L[d] + B - 1) / B : 1;
+        g.bmax[d] = (L[d] + g.nb[d] - 1) / g.nb[d];
+        g.wdim[d] = g.bmax[d] + 2 * g.margin;
+        g.nbrick *= g.nb[d];
+        g.wsize *= g.wdim[d];
+    }
+    return g;
 }
 
 // Velocity in 64-bit fixed point with quantum 2^-32 (exact for |v| >= 2^-9,

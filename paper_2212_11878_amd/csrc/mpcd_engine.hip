@@ -6,6 +6,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
+#include <string>
 #include <chrono>
 #include <map>
 #include <vector>
@@ -61,6 +63,9 @@ struct mpcd_ctx {
     int32_t binning = MPCD_BIN_AUTO;
     int32_t brick[3] = {0, 0, 0};
     bool pending_rebucket = false;
+    bool tuning = false;             // this context is an autotuner trial context
+    std::map<uint64_t, std::pair<int32_t, std::array<int32_t, 3>>> tuned;   // shape class -> choice
+    std::vector<std::pair<std::string, double>> tune_log;                  // last trial timings
     bool use_graph = false;
     int max_slots = 4096;
     std::vector<Slot> slots;
@@ -116,28 +121,6 @@ void drop_graph(mpcd_ctx* c)
     if (c->graph) (void)hipGraphDestroy(c->graph);
     c->graph_exec = nullptr;
     c->graph = nullptr;
-}
-
-// Brick decomposition of one box (brick binning).
-struct BrickGeom {
-    int nb[3], bmax[3], wdim[3], margin, wsize, nbrick;
-};
-
-BrickGeom brick_geometry(const int32_t L[3], const int32_t want[3])
-{
-    BrickGeom g{};
-    g.margin = 1;
-    g.nbrick = 1;
-    g.wsize = 1;
-    for (int d = 0; d < 3; ++d) {
-        const int B = want[d] > 0 ? want[d] : 8;
-        g.nb[d] = std::max(1, (L[d] + B - 1) / B);
-        g.bmax[d] = (L[d] + g.nb[d] - 1) / g.nb[d];
-        g.wdim[d] = g.bmax[d] + 2 * g.margin;
-        g.nbrick *= g.nb[d];
-        g.wsize *= g.wdim[d];
-    }
-    return g;
 }
 
 // Layout of one box's device allocation.
@@ -473,6 +456,114 @@ int init_maxwell(mpcd_ctx* c, int32_t s)
 }  // namespace
 
 // ==========================================================================
+// Autotuner: picks the binning (brick or sort) and the brick shape for a
+// class of boxes by timing short trial runs on a proxy box of the same
+// density and time step (at most 128^3 cells) in a private context on the
+// same stream.  Results do not depend on the choice (cell sums are exact),
+// only the speed does.
+
+static uint64_t shape_class(const mpcd_box_desc* d)
+{
+    const double C = (double)d->L[0] * d->L[1] * d->L[2];
+    const int lc = (int)std::floor(std::log2(std::max(1.0, C)));
+    const double dens = std::max(1e-3, (double)d->n_particles / C);
+    const int rho = (int)std::lround(std::min(255.0, std::max(0.0, 2.0 * std::log2(dens) + 20.0)));
+    const double vth = d->kT > 0 ? std::sqrt(d->kT / d->mass) : 1.0;
+    const int step = (int)std::min(15.0, std::floor(8.0 * d->dt * vth / d->a));   // free path / cell
+    return ((uint64_t)lc << 16) | ((uint64_t)rho << 4) | (uint64_t)step;
+}
+
+static int trial_ms(mpcd_ctx* parent, const mpcd_box_desc* proxy, int32_t binning, const int32_t brick[3],
+             double* ms)
+{
+    mpcd_options o{};
+    o.binning = binning;
+    for (int k = 0; k < 3; ++k) o.brick[k] = brick[k];
+    o.stream = parent->stream;
+    o.alloc = parent->alloc;
+    o.free = parent->free;
+    o.user = parent->user;
+    o.device = parent->device;
+    o.max_slots = 1;
+    mpcd_ctx* t = nullptr;
+    int rc = mpcd_create(&o, &t);
+    if (rc) return rc;
+    t->tuning = true;
+    int32_t slot = -1;
+    rc = mpcd_admit(t, proxy, &slot);
+    if (!rc) rc = mpcd_step(t, 3);   // bucket + warm up
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) rc = MPCD_EDEVICE;
+    if (!rc) {
+        const int reps = 5;
+        (void)hipEventRecord(e0, t->stream);
+        rc = mpcd_step(t, reps);
+        (void)hipEventRecord(e1, t->stream);
+        float f = 0.0f;
+        if (!rc && hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&f, e0, e1) == hipSuccess)
+            *ms = f / reps;
+        else if (!rc)
+            rc = MPCD_EDEVICE;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    mpcd_destroy(t);
+    return rc;
+}
+
+static int autotune(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* binning, int32_t brick[3])
+{
+    // defaults, also used inside trial contexts and for empty boxes
+    *binning = MPCD_BIN_ATOMIC;
+    brick[0] = brick[1] = brick[2] = 0;
+    if (c->tuning || d->n_particles == 0) return MPCD_OK;
+    const uint64_t key = shape_class(d);
+    auto it = c->tuned.find(key);
+    if (it != c->tuned.end()) {
+        *binning = it->second.first;
+        for (int k = 0; k < 3; ++k) brick[k] = it->second.second[k];
+        return MPCD_OK;
+    }
+    mpcd_box_desc p = *d;
+    double cells = 1.0;
+    for (int k = 0; k < 3; ++k) {
+        p.L[k] = std::min(d->L[k], 128);
+        cells *= p.L[k];
+    }
+    const double density = (double)d->n_particles / ((double)d->L[0] * d->L[1] * d->L[2]);
+    p.n_particles = std::max<int64_t>(1, std::llround(density * cells));
+    p.flags = MPCD_INIT_MAXWELL;
+    if (!(p.kT > 0.0)) p.kT = 1.0;
+    p.n_steps = 0;
+    p.vacf_stride = 0;
+    p.vacf_capacity = 0;
+    struct Cand { int32_t bin; int32_t b[3]; const char* name; };
+    const Cand cands[] = {
+        {MPCD_BIN_ATOMIC, {8, 8, 8}, "brick8x8x8"},
+        {MPCD_BIN_ATOMIC, {16, 8, 8}, "brick16x8x8"},
+        {MPCD_BIN_ATOMIC, {6, 6, 6}, "brick6x6x6"},
+        {MPCD_BIN_ATOMIC, {4, 4, 4}, "brick4x4x4"},
+        {MPCD_BIN_SORT, {0, 0, 0}, "sort"},
+    };
+    c->tune_log.clear();
+    double best = 1e300;
+    for (const Cand& cd : cands) {
+        double ms = 0.0;
+        const int rc = trial_ms(c, &p, cd.bin, cd.b, &ms);
+        if (rc == MPCD_EDEVICE) return rc;
+        if (rc) continue;   // e.g. over memory: skip the candidate
+        c->tune_log.push_back({cd.name, ms});
+        if (ms < best) {
+            best = ms;
+            *binning = cd.bin;
+            for (int k = 0; k < 3; ++k) brick[k] = cd.b[k];
+        }
+    }
+    c->tuned[key] = {*binning, {brick[0], brick[1], brick[2]}};
+    return MPCD_OK;
+}
+
+// ==========================================================================
 // C ABI
 
 extern "C" {
@@ -555,9 +646,14 @@ int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
     const bool vacf = (d->flags & MPCD_TRACK_VACF) != 0;
     const int64_t ncell = (int64_t)d->L[0] * d->L[1] * d->L[2];
     const int cap = vacf_capacity(d);
-    const int32_t binning = c->binning == MPCD_BIN_SORT ? MPCD_BIN_SORT : MPCD_BIN_ATOMIC;
+    int32_t binning = c->binning;
+    int32_t want[3] = {c->brick[0], c->brick[1], c->brick[2]};
+    if (binning == MPCD_BIN_AUTO) {
+        rc = autotune(c, d, &binning, want);
+        if (rc) return rc;
+    }
     const bool brick = binning == MPCD_BIN_ATOMIC;
-    const BrickGeom g = brick_geometry(d->L, c->brick);
+    const BrickGeom g = brick_geometry(d->L, want);
     if (brick && g.wsize > max_window_records()) return MPCD_EINVAL;
     const Layout L = box_layout(d->n_particles, ncell, vacf, cap, brick, g);
     if (c->budget > 0 && c->used + (int64_t)L.total > c->budget) return MPCD_ENOMEM;

@@ -145,10 +145,9 @@ __global__ __launch_bounds__(kBlock) void k_brick_accumulate(const Tile* __restr
         const int cx = axis_cell(px, sh.x, b.inv_a, b.L[0]);
         const int cy = axis_cell(py, sh.y, b.inv_a, b.L[1]);
         const int cz = axis_cell(pz, sh.z, b.inv_a, b.L[2]);
-        int lx = cx - lox + m, ly = cy - loy + m, lz = cz - loz + m;
-        lx += (lx < 0) ? b.L[0] : 0; lx -= (lx >= b.L[0]) ? b.L[0] : 0;
-        ly += (ly < 0) ? b.L[1] : 0; ly -= (ly >= b.L[1]) ? b.L[1] : 0;
-        lz += (lz < 0) ? b.L[2] : 0; lz -= (lz >= b.L[2]) ? b.L[2] : 0;
+        const int lx = window_offset(cx, lox, m, b.L[0]);
+        const int ly = window_offset(cy, loy, m, b.L[1]);
+        const int lz = window_offset(cz, loz, m, b.L[2]);
         const unsigned long long fx = to_fixed(ux), fy = to_fixed(uy), fz = to_fixed(uz);
         if (lx < ex && ly < ey && lz < ez) {
             CellAcc* w = &win[lx + wx * (ly + wy * lz)];
@@ -212,31 +211,6 @@ __global__ __launch_bounds__(kBlock) void k_brick_scan(const int32_t* __restrict
         run += c;
     }
     if (threadIdx.x == 0) next[nb] = total;
-}
-
-// windows of bricks along one dimension that contain cell c: (brick, offset)
-__device__ __forceinline__ int windows_of(int c, int L, int nb, int m, int* bi, int* li)
-{
-    const int own = brick_of(c, L, nb);
-    int n = 0;
-    for (int k = -1; k <= 1; ++k) {
-        int i = own + k;
-        i += (i < 0) ? nb : 0;
-        i -= (i >= nb) ? nb : 0;
-        bool dup = false;
-        for (int j = 0; j < n; ++j) dup |= (bi[j] == i);
-        if (dup) continue;
-        const int lo = brick_lo(i, L, nb), ext = brick_lo(i + 1, L, nb) - lo + 2 * m;
-        int l = c - lo + m;
-        l += (l < 0) ? L : 0;
-        l -= (l >= L) ? L : 0;
-        if (l < ext) {
-            bi[n] = i;
-            li[n] = l;
-            ++n;
-        }
-    }
-    return n;
 }
 
 __global__ __launch_bounds__(kBlock) void k_brick_finalize(const Tile* __restrict__ tiles,
@@ -318,6 +292,21 @@ __global__ __launch_bounds__(kBlock) void k_brick_rotate(const Tile* __restrict_
     const bool track = b.vacf_stride > 0;
     const bool vacf = vacf_due(b, s);
     const int64_t beg = b.bstart[src][brick], end = b.bstart[src][brick + 1];
+    const float* __restrict__ ix = b.p[src][0];
+    const float* __restrict__ iy = b.p[src][1];
+    const float* __restrict__ iz = b.p[src][2];
+    const float* __restrict__ ivx = b.p[src][3];
+    const float* __restrict__ ivy = b.p[src][4];
+    const float* __restrict__ ivz = b.p[src][5];
+    const int32_t* __restrict__ iid = b.pid[src];
+    float* __restrict__ ox = b.p[dst][0];
+    float* __restrict__ oy = b.p[dst][1];
+    float* __restrict__ oz = b.p[dst][2];
+    float* __restrict__ ovx = b.p[dst][3];
+    float* __restrict__ ovy = b.p[dst][4];
+    float* __restrict__ ovz = b.p[dst][5];
+    int32_t* __restrict__ oid = b.pid[dst];
+    const CellUN* __restrict__ un = b.un;
     double d[kNumDiag] = {0.0, 0.0, 0.0, 0.0, 0.0};
     constexpr int kChunk = kBlock * kItems;
     for (int64_t c0 = beg; c0 < end; c0 += kChunk) {
@@ -332,13 +321,13 @@ __global__ __launch_bounds__(kBlock) void k_brick_rotate(const Tile* __restrict_
             const int64_t i = c0 + it * kBlock + threadIdx.x;
             rel[it] = -1;
             if (i < end) {
-                const float ux = b.p[src][3][i], uy = b.p[src][4][i], uz = b.p[src][5][i];
-                px[it] = fold(fmaf(ux, dt, b.p[src][0][i]), b.len[0]);
-                py[it] = fold(fmaf(uy, dt, b.p[src][1][i]), b.len[1]);
-                pz[it] = fold(fmaf(uz, dt, b.p[src][2][i]), b.len[2]);
-                id[it] = b.pid[src][i];
+                const float ux = ivx[i], uy = ivy[i], uz = ivz[i];
+                px[it] = fold(fmaf(ux, dt, ix[i]), b.len[0]);
+                py[it] = fold(fmaf(uy, dt, iy[i]), b.len[1]);
+                pz[it] = fold(fmaf(uz, dt, iz[i]), b.len[2]);
+                id[it] = iid[i];
                 const uint32_t c = collision_cell(b, px[it], py[it], pz[it], sh);
-                const CellUN u = b.un[c];
+                const CellUN u = un[c];
                 const float3 v = rotate_about(u, ux, uy, uz, ca, sa, omc);
                 qx[it] = v.x;
                 qy[it] = v.y;
@@ -377,13 +366,13 @@ __global__ __launch_bounds__(kBlock) void k_brick_rotate(const Tile* __restrict_
             if (rel[it] < 0) continue;
             const int64_t i = c0 + it * kBlock + threadIdx.x;
             const int64_t j = (rel[it] < 27) ? (int64_t)base[rel[it]] + slot[it] : (int64_t)slot[it];
-            b.p[dst][0][j] = px[it];
-            b.p[dst][1][j] = py[it];
-            b.p[dst][2][j] = pz[it];
-            b.p[dst][3][j] = qx[it];
-            b.p[dst][4][j] = qy[it];
-            b.p[dst][5][j] = qz[it];
-            b.pid[dst][j] = id[it];
+            ox[j] = px[it];
+            oy[j] = py[it];
+            oz[j] = pz[it];
+            ovx[j] = qx[it];
+            ovy[j] = qy[it];
+            ovz[j] = qz[it];
+            oid[j] = id[it];
             if (track) {
                 b.v0[dst][0][j] = b.v0[src][0][i];
                 b.v0[dst][1][j] = b.v0[src][1][i];
