@@ -124,6 +124,8 @@ def main():
     ap.add_argument("--binning", default="auto", choices=["auto", "atomic", "sort"])
     ap.add_argument("--brick", type=int, nargs=3, default=[0, 0, 0])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run device-to-device copies of MIB MiB (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -134,6 +136,18 @@ def main():
 
     import torch
     from paper_2212_11878_amd import mpcd
+
+    if args.copy_calibration:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters per
+        # dispatch calibrate the kernels' counters to bytes
+        nbytes = args.copy_calibration << 20
+        a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": nbytes, "dispatches": 5}), flush=True)
+        return
 
     if args.workload == ENSEMBLE:
         return bench_ensemble(args)
