@@ -13,7 +13,7 @@ constexpr int kBlock = 256;          // threads per workgroup of the particle ke
 constexpr int kPartTile = 4096;      // particles per particle tile (16 per thread)
 constexpr int kCellTile = 2048;      // cells per cell tile
 constexpr int kItems = 8;            // particles per thread per chunk (brick rotation)
-constexpr int kNumDiag = 5;          // per-tile FP64 partials: sum v (3), sum v^2, sum v.v0
+constexpr int kNumDiag = 6;          // per-tile exact partials: sum v (3), sum v^2, sum v.v0, range violations
 
 // Per-cell accumulator: exact 64-bit fixed-point momentum sums (quantum
 // 2^-32 velocity units) and the particle count.  32 bytes, one sector.
@@ -73,7 +73,8 @@ struct BoxDev {
     int32_t btile0, btile1;   // brick tiles [btile0, btile1)
     float len[3];          // L_d * a
     float a, inv_a, dt;
-    float ca, sa, omc;     // cos(alpha), sin(alpha), 1 - cos(alpha) rounded from FP64
+    float ca, sa;          // FP32 cos(alpha), sin(alpha) with ca^2 + sa^2 closest to 1
+    float pad0;
     float mass;
     uint32_t key0, key1;   // Philox key = seed
 };
@@ -88,7 +89,7 @@ struct BoxState {
     int vacf_len;
     int status;            // 0 or MPCD_ESTATE
     int rebucket;          // brick mode: particles not yet in brick buckets
-    double diag[4];        // sum v (3), sum v^2 after the last step
+    double diag[4];        // sum v (3), sum v^2 after the last step (exact sums, rounded once)
 };
 
 // A contiguous range of one box's particles or cells.
@@ -142,7 +143,12 @@ __device__ __forceinline__ float3 cell_axis(const BoxDev& b, long long k, uint32
     float sp, cp;
     sincosf(phi, &sp, &cp);
     const float rho = sqrtf(fmaxf(0.0f, 1.0f - z * z));
-    return make_float3(rho * cp, rho * sp, z);
+    float3 n = make_float3(rho * cp, rho * sp, z);
+    // renormalise (one Newton step on rsqrt) so |n| = 1 to rounding, unbiased
+    const float nn = n.x * n.x + n.y * n.y + n.z * n.z;
+    float r = rsqrtf(nn);
+    r = r * (1.5f - 0.5f * nn * r * r);
+    return make_float3(n.x * r, n.y * r, n.z * r);
 }
 
 // Periodic fold of a streamed coordinate into [0, len).
@@ -274,14 +280,6 @@ __device__ __forceinline__ unsigned long long to_fixed(float v)
 // Largest speed component the fixed-point cell sums accept.
 constexpr float kVelocityLimit = 1073741824.0f;   // 2^30
 
-// Adds +inf to an energy partial when a velocity leaves the valid range or
-// is not finite, so the box's diagnostics flag it.
-__device__ __forceinline__ void range_check(float3 v, double& energy)
-{
-    const float m = fmaxf(fabsf(v.x), fmaxf(fabsf(v.y), fabsf(v.z)));
-    if (!(m < kVelocityLimit)) energy = __builtin_inf();
-}
-
 // Mean velocity of a cell from its exact fixed-point sum, rounded once to
 // FP32 (the 64-bit sum is split into exact 32-bit halves, combined and
 // divided in FP64).
@@ -292,18 +290,44 @@ __device__ __forceinline__ float fixed_mean(unsigned long long s, unsigned int n
     return (float)((hi + lo * 2.3283064365386963e-10) / (double)n);   // (hi 2^32 + lo) 2^-32 / n
 }
 
-// v' = u + w cos(a) + (n x w) sin(a) + n (n.w)(1 - cos(a)), w = v - u
+// v' = u + (n.w) n + cos(a) (w - (n.w) n) + sin(a) (n x w), w = v - u: the
+// component along the axis is kept, the perpendicular one turned by a.
 __device__ __forceinline__ float3 rotate_about(const CellUN& c, float vx, float vy, float vz,
-                                               float ca, float sa, float omc)
+                                               float ca, float sa)
 {
     const float wx = vx - c.ux, wy = vy - c.uy, wz = vz - c.uz;
+    const float d = c.nx * wx + c.ny * wy + c.nz * wz;
+    const float px = d * c.nx, py = d * c.ny, pz = d * c.nz;
     const float cx = c.ny * wz - c.nz * wy;
     const float cy = c.nz * wx - c.nx * wz;
     const float cz = c.nx * wy - c.ny * wx;
-    const float f = (c.nx * wx + c.ny * wy + c.nz * wz) * omc;
-    return make_float3(c.ux + fmaf(wx, ca, fmaf(cx, sa, c.nx * f)),
-                       c.uy + fmaf(wy, ca, fmaf(cy, sa, c.ny * f)),
-                       c.uz + fmaf(wz, ca, fmaf(cz, sa, c.nz * f)));
+    return make_float3(c.ux + (px + fmaf(ca, wx - px, sa * cx)),
+                       c.uy + (py + fmaf(ca, wy - py, sa * cy)),
+                       c.uz + (pz + fmaf(ca, wz - pz, sa * cz)));
+}
+
+// Exact diagnostics: per-particle terms in 64-bit fixed point (quantum 2^-32)
+// so block and box sums do not depend on summation order.
+__device__ __forceinline__ long long fixed_term(double t)
+{
+    t = fmin(fmax(t * 4294967296.0, -4.0e18), 4.0e18);
+    return (long long)rint(t);
+}
+
+__device__ __forceinline__ void diag_particle(long long (&d)[kNumDiag], float3 v)
+{
+    d[0] += (long long)to_fixed(v.x);
+    d[1] += (long long)to_fixed(v.y);
+    d[2] += (long long)to_fixed(v.z);
+    d[3] += fixed_term((double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z);
+    const float m = fmaxf(fabsf(v.x), fmaxf(fabsf(v.y), fabsf(v.z)));
+    if (!(m < kVelocityLimit)) d[5] += 1;
+}
+
+__device__ __forceinline__ void diag_vacf(long long (&d)[kNumDiag], float3 v, float w0x, float w0y,
+                                          float w0z)
+{
+    d[4] += fixed_term((double)v.x * w0x + (double)v.y * w0y + (double)v.z * w0z);
 }
 
 // Blocks are dealt round-robin to the 8 XCDs; renumber so that each XCD

@@ -158,6 +158,32 @@ Layout box_layout(int64_t n, int64_t ncell, bool vacf, int vacf_cap, bool brick,
     return L;
 }
 
+// FP32 (cos a, sin a) within a few ulps of the exact values, chosen so that
+// cos^2 + sin^2 is as close to 1 as FP32 allows: the rotation then keeps the
+// perpendicular kinetic energy without a systematic drift.
+void rotation_pair(double alpha, float* ca, float* sa)
+{
+    const float c0 = (float)cos(alpha), s0 = (float)sin(alpha);
+    float bc = c0, bs = s0;
+    double best = fabs((double)c0 * c0 + (double)s0 * s0 - 1.0);
+    float c = c0;
+    for (int i = 0; i < 4; ++i) c = nextafterf(c, -2.0f);
+    for (int i = -4; i <= 4; ++i, c = nextafterf(c, 2.0f)) {
+        float s = s0;
+        for (int j = 0; j < 4; ++j) s = nextafterf(s, -2.0f);
+        for (int j = -4; j <= 4; ++j, s = nextafterf(s, 2.0f)) {
+            const double e = fabs((double)c * c + (double)s * s - 1.0);
+            if (e < best) {
+                best = e;
+                bc = c;
+                bs = s;
+            }
+        }
+    }
+    *ca = bc;
+    *sa = bs;
+}
+
 int validate_desc(const mpcd_box_desc* d)
 {
     if (!d) return MPCD_EINVAL;
@@ -243,9 +269,9 @@ int rebuild_tables(mpcd_ctx* c)
     c->T.ctiles = (Tile*)(base + o); o += align256(ct.size() * sizeof(Tile) + 256);
     c->T.btiles = (Tile*)(base + o); o += align256(bt.size() * sizeof(Tile) + 256);
     c->T.active = (int32_t*)(base + o); o += align256(active.size() * 4 + 256);
-    c->T.partials = (double*)(base + o); o += align256(pt.size() * kNumDiag * 8 + 256);
-    c->T.partials_c = (double*)(base + o); o += align256(ct.size() * kNumDiag * 8 + 256);
-    c->T.partials_b = (double*)(base + o); o += align256(bt.size() * kNumDiag * 8 + 256);
+    c->T.partials = (long long*)(base + o); o += align256(pt.size() * kNumDiag * 8 + 256);
+    c->T.partials_c = (long long*)(base + o); o += align256(ct.size() * kNumDiag * 8 + 256);
+    c->T.partials_b = (long long*)(base + o); o += align256(bt.size() * kNumDiag * 8 + 256);
     c->T.tilesum = (uint32_t*)(base + o);
     c->T.nptiles = (int)pt.size();
     c->T.nctiles = (int)ct.size();
@@ -362,19 +388,21 @@ Slot* live_slot(mpcd_ctx* c, int32_t slot)
     return &c->slots[slot];
 }
 
-// FP64 sums of kNumDiag partials over one box's particle tiles (host side,
-// after a synchronising copy).
+// Exact sums of the fixed-point partials over one box's particle tiles
+// (host side, after a synchronising copy), rounded once to FP64.
 int read_box_partials(mpcd_ctx* c, const Slot& sl, double out[kNumDiag])
 {
     const int n = sl.dev.ptile1 - sl.dev.ptile0;
-    std::vector<double> h((size_t)n * kNumDiag);
+    std::vector<long long> h((size_t)n * kNumDiag);
     if (n > 0)
         HIPCHK(hipMemcpyAsync(h.data(), c->T.partials + (size_t)sl.dev.ptile0 * kNumDiag,
                               h.size() * 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
-    for (int j = 0; j < kNumDiag; ++j) out[j] = 0.0;
-    for (int t = 0; t < n; ++t)
-        for (int j = 0; j < kNumDiag; ++j) out[j] += h[(size_t)t * kNumDiag + j];
+    for (int j = 0; j < kNumDiag; ++j) {
+        __int128 acc = 0;
+        for (int t = 0; t < n; ++t) acc += h[(size_t)t * kNumDiag + j];
+        out[j] = (j == 5) ? (double)acc : (double)acc * 2.3283064365386963e-10;   // 2^-32
+    }
     return MPCD_OK;
 }
 
@@ -419,7 +447,7 @@ int take_snapshot(mpcd_ctx* c, int32_t s)
         HIPCHK(hipMemcpy(sl.dev.vacf, &c0, 8, hipMemcpyHostToDevice));
         st.vacf_len = 1;
     }
-    st.status = (d[3] < 1e300 && d[3] >= 0.0) ? 0 : MPCD_ESTATE;
+    st.status = (d[5] == 0.0 && d[3] < 1e300) ? 0 : MPCD_ESTATE;
     HIPCHK(hipMemcpy(&c->T.state[s], &st, sizeof(BoxState), hipMemcpyHostToDevice));
     return MPCD_OK;
 }
@@ -704,9 +732,7 @@ int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
     b.a = (float)d->a;
     b.inv_a = (float)(1.0 / d->a);
     b.dt = (float)d->dt;
-    b.ca = (float)cos(d->alpha);
-    b.sa = (float)sin(d->alpha);
-    b.omc = (float)(1.0 - cos(d->alpha));
+    rotation_pair(d->alpha, &b.ca, &b.sa);
     b.mass = (float)d->mass;
     b.key0 = (uint32_t)(d->seed & 0xffffffffu);
     b.key1 = (uint32_t)(d->seed >> 32);

@@ -46,26 +46,26 @@ __device__ __forceinline__ bool vacf_due(const BoxDev& b, const BoxState& s)
     return b.vacf_stride > 0 && ((s.k + 1 - s.vacf_origin) % b.vacf_stride) == 0;
 }
 
-__device__ __forceinline__ double wave_sum(double v)
+__device__ __forceinline__ long long wave_sum(long long v)
 {
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
     return v;
 }
 
-// Deterministic block sum of kNumDiag doubles; thread 0 writes out[0..].
-__device__ __forceinline__ void block_diag(double (&d)[kNumDiag], double* out)
+// Block sum of kNumDiag exact partials; threads 0..kNumDiag-1 write out[].
+__device__ __forceinline__ void block_diag(long long (&d)[kNumDiag], long long* out)
 {
-    __shared__ double red[kBlock / kWave][kNumDiag];
+    __shared__ long long red[kBlock / kWave][kNumDiag];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
 #pragma unroll
     for (int j = 0; j < kNumDiag; ++j) {
-        const double v = wave_sum(d[j]);
+        const long long v = wave_sum(d[j]);
         if (lane == 0) red[w][j] = v;
     }
     __syncthreads();
     if (threadIdx.x < kNumDiag) {
-        double v = 0.0;
+        long long v = 0;
         for (int i = 0; i < kBlock / kWave; ++i) v += red[i][threadIdx.x];
         out[threadIdx.x] = v;
     }
@@ -275,7 +275,7 @@ __global__ __launch_bounds__(kBlock) void k_brick_finalize(const Tile* __restric
 __global__ __launch_bounds__(kBlock) void k_brick_rotate(const Tile* __restrict__ tiles,
                                                           const BoxDev* __restrict__ boxes,
                                                           const BoxState* __restrict__ st,
-                                                          double* __restrict__ partials)
+                                                          long long* __restrict__ partials)
 {
     __shared__ uint32_t cnt[27];
     __shared__ uint32_t base[27];
@@ -288,7 +288,7 @@ __global__ __launch_bounds__(kBlock) void k_brick_rotate(const Tile* __restrict_
     const int bx = brick % b.nb[0], by = (brick / b.nb[0]) % b.nb[1], bz = brick / (b.nb[0] * b.nb[1]);
     const int src = s.parity, dst = s.parity ^ 1;
     const float3 sh = grid_shift(b, s.k);
-    const float dt = b.dt, ca = b.ca, sa = b.sa, omc = b.omc;
+    const float dt = b.dt, ca = b.ca, sa = b.sa;
     const bool track = b.vacf_stride > 0;
     const bool vacf = vacf_due(b, s);
     const int64_t beg = b.bstart[src][brick], end = b.bstart[src][brick + 1];
@@ -307,7 +307,7 @@ __global__ __launch_bounds__(kBlock) void k_brick_rotate(const Tile* __restrict_
     float* __restrict__ ovz = b.p[dst][5];
     int32_t* __restrict__ oid = b.pid[dst];
     const CellUN* __restrict__ un = b.un;
-    double d[kNumDiag] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    long long d[kNumDiag] = {0, 0, 0, 0, 0, 0};
     constexpr int kChunk = kBlock * kItems;
     for (int64_t c0 = beg; c0 < end; c0 += kChunk) {
         if (threadIdx.x < 27) cnt[threadIdx.x] = 0u;
@@ -328,29 +328,36 @@ __global__ __launch_bounds__(kBlock) void k_brick_rotate(const Tile* __restrict_
                 id[it] = iid[i];
                 const uint32_t c = collision_cell(b, px[it], py[it], pz[it], sh);
                 const CellUN u = un[c];
-                const float3 v = rotate_about(u, ux, uy, uz, ca, sa, omc);
+                const float3 v = rotate_about(u, ux, uy, uz, ca, sa);
                 qx[it] = v.x;
                 qy[it] = v.y;
                 qz[it] = v.z;
-                d[0] += (double)v.x;
-                d[1] += (double)v.y;
-                d[2] += (double)v.z;
-                d[3] += (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z;
-                if (vacf)
-                    d[4] += (double)v.x * b.v0[src][0][i] + (double)v.y * b.v0[src][1][i] +
-                            (double)v.z * b.v0[src][2][i];
-                range_check(v, d[3]);
+                diag_particle(d, v);
+                if (vacf) diag_vacf(d, v, b.v0[src][0][i], b.v0[src][1][i], b.v0[src][2][i]);
                 const int3 db = brick_of_pos(b, px[it], py[it], pz[it]);
                 const int rx = brick_rel(bx, db.x, b.nb[0]), ry = brick_rel(by, db.y, b.nb[1]),
                           rz = brick_rel(bz, db.z, b.nb[2]);
                 if (rx <= 1 && ry <= 1 && rz <= 1) {
                     rel[it] = (rx + 1) + 3 * ((ry + 1) + 3 * (rz + 1));
-                    slot[it] = atomicAdd(&cnt[rel[it]], 1u);
                 } else {
                     rel[it] = 27;
                     slot[it] = atomicAdd(&b.bcursor[db.x + b.nb[0] * (db.y + b.nb[1] * db.z)], 1u);
                 }
             }
+            // ranks in the bucket ranges; particles that stay in this brick
+            // (most of them) take consecutive ranks per wave, so the writes
+            // below coalesce
+            const bool stay = (rel[it] == 13);
+            const unsigned long long mask = __ballot(stay);
+            if (mask) {
+                const int lane = threadIdx.x & (kWave - 1);
+                const int leader = __ffsll((long long)mask) - 1;
+                uint32_t wbase = 0;
+                if (lane == leader) wbase = atomicAdd(&cnt[13], (uint32_t)__popcll(mask));
+                wbase = __shfl(wbase, leader, kWave);
+                if (stay) slot[it] = wbase + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+            }
+            if (rel[it] >= 0 && rel[it] < 27 && !stay) slot[it] = atomicAdd(&cnt[rel[it]], 1u);
         }
         __syncthreads();
         if (threadIdx.x < 27 && cnt[threadIdx.x] != 0u) {
@@ -570,7 +577,7 @@ __global__ void k_flip(const int32_t* __restrict__ active, int nactive,
 __global__ __launch_bounds__(kBlock) void k_cell_rotate(const Tile* __restrict__ tiles,
                                                          const BoxDev* __restrict__ boxes,
                                                          const BoxState* __restrict__ st,
-                                                         double* __restrict__ partials)
+                                                         long long* __restrict__ partials)
 {
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const Tile tl = tiles[t];
@@ -584,8 +591,8 @@ __global__ __launch_bounds__(kBlock) void k_cell_rotate(const Tile* __restrict__
     const float* __restrict__ w0x = b.v0[s.parity][0];
     const float* __restrict__ w0y = b.v0[s.parity][1];
     const float* __restrict__ w0z = b.v0[s.parity][2];
-    const float ca = b.ca, sa = b.sa, omc = b.omc;
-    double d[kNumDiag] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    const float ca = b.ca, sa = b.sa;
+    long long d[kNumDiag] = {0, 0, 0, 0, 0, 0};
     for (int64_t c = tl.begin + threadIdx.x; c < tl.end; c += kBlock) {
         const uint32_t beg = b.cstart[c], end = b.cstart[c + 1];
         if (beg == end) continue;
@@ -605,16 +612,12 @@ __global__ __launch_bounds__(kBlock) void k_cell_rotate(const Tile* __restrict__
         u.ny = ax.y;
         u.nz = ax.z;
         for (uint32_t j = beg; j < end; ++j) {
-            const float3 v = rotate_about(u, vx[j], vy[j], vz[j], ca, sa, omc);
+            const float3 v = rotate_about(u, vx[j], vy[j], vz[j], ca, sa);
             vx[j] = v.x;
             vy[j] = v.y;
             vz[j] = v.z;
-            d[0] += (double)v.x;
-            d[1] += (double)v.y;
-            d[2] += (double)v.z;
-            d[3] += (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z;
-            if (vacf) d[4] += (double)v.x * w0x[j] + (double)v.y * w0y[j] + (double)v.z * w0z[j];
-            range_check(v, d[3]);
+            diag_particle(d, v);
+            if (vacf) diag_vacf(d, v, w0x[j], w0y[j], w0z[j]);
         }
     }
     block_diag(d, partials + (size_t)t * kNumDiag);
@@ -626,8 +629,8 @@ __global__ __launch_bounds__(kBlock) void k_cell_rotate(const Tile* __restrict__
 __global__ __launch_bounds__(kBlock) void k_box_finish(const int32_t* __restrict__ active,
                                                         const BoxDev* __restrict__ boxes,
                                                         BoxState* __restrict__ st,
-                                                        const double* __restrict__ partials_b,
-                                                        const double* __restrict__ partials_c)
+                                                        const long long* __restrict__ partials_b,
+                                                        const long long* __restrict__ partials_c)
 {
     const int bx = active[blockIdx.x];
     BoxState* sp = &st[bx];
@@ -636,22 +639,32 @@ __global__ __launch_bounds__(kBlock) void k_box_finish(const int32_t* __restrict
     const bool by_cell = (b.binning == 2);
     const int t0 = by_cell ? b.ctile0 : b.btile0;
     const int t1 = by_cell ? b.ctile1 : b.btile1;
-    const double* __restrict__ partials = by_cell ? partials_c : partials_b;
-    double d[kNumDiag] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    const long long* __restrict__ partials = by_cell ? partials_c : partials_b;
+    // exact sum of the 64-bit tile partials as (high, low) 32-bit halves
+    long long hi[kNumDiag] = {0, 0, 0, 0, 0, 0}, lo[kNumDiag] = {0, 0, 0, 0, 0, 0};
     for (int t = t0 + (int)threadIdx.x; t < t1; t += kBlock) {
 #pragma unroll
-        for (int j = 0; j < kNumDiag; ++j) d[j] += partials[(size_t)t * kNumDiag + j];
+        for (int j = 0; j < kNumDiag; ++j) {
+            const long long v = partials[(size_t)t * kNumDiag + j];
+            hi[j] += v >> 32;
+            lo[j] += (long long)(unsigned long long)(unsigned)(v & 0xffffffffll);
+        }
     }
-    __shared__ double tot[kNumDiag];
-    block_diag(d, tot);
+    __shared__ long long thi[kNumDiag], tlo[kNumDiag];
+    block_diag(hi, thi);
+    __syncthreads();
+    block_diag(lo, tlo);
     __syncthreads();
     if (threadIdx.x == 0) {
+        double tot[kNumDiag];
+        for (int j = 0; j < kNumDiag; ++j)   // (hi 2^32 + lo) 2^-32, one rounding
+            tot[j] = (double)thi[j] + (double)tlo[j] * 2.3283064365386963e-10;
         const bool vac = vacf_due(b, *sp);
         sp->diag[0] = tot[0];
         sp->diag[1] = tot[1];
         sp->diag[2] = tot[2];
         sp->diag[3] = tot[3];
-        if (!(tot[3] < 1e300 && tot[3] >= 0.0)) sp->status = -5;   // NaN or Inf
+        if (thi[5] != 0 || tlo[5] != 0) sp->status = -5;   // velocity out of range / not finite
         if (vac && sp->vacf_len < b.vacf_cap && b.n > 0)
             b.vacf[sp->vacf_len++] = tot[4] / (double)b.n;
         sp->k += 1;
@@ -666,13 +679,13 @@ __global__ __launch_bounds__(kBlock) void k_box_finish(const int32_t* __restrict
 __global__ __launch_bounds__(kBlock) void k_init_maxwell(const Tile* __restrict__ tiles,
                                                           const BoxDev* __restrict__ boxes,
                                                           const BoxState* __restrict__ st,
-                                                          float vscale, double* __restrict__ partials)
+                                                          float vscale, long long* __restrict__ partials)
 {
     const int t = blockIdx.x;
     const Tile tl = tiles[t];
     const BoxDev& b = boxes[tl.box];
     const int par = st[tl.box].parity;
-    double d[kNumDiag] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    long long d[kNumDiag] = {0, 0, 0, 0, 0, 0};
     for (int64_t i = tl.begin + threadIdx.x; i < tl.end; i += kBlock) {
         const uint32_t lo = (uint32_t)i, hi = (uint32_t)((uint64_t)i >> 32);
         const uint4 r = philox4x32_10(make_uint4(lo, hi, 0u, 2u), b.key0, b.key1);
@@ -690,9 +703,7 @@ __global__ __launch_bounds__(kBlock) void k_init_maxwell(const Tile* __restrict_
         b.p[par][4][i] = vy;
         b.p[par][5][i] = vz;
         b.pid[par][i] = (int32_t)i;
-        d[0] += vx;
-        d[1] += vy;
-        d[2] += vz;
+        diag_particle(d, make_float3(vx, vy, vz));
     }
     block_diag(d, partials + (size_t)t * kNumDiag);
 }
@@ -702,13 +713,13 @@ __global__ __launch_bounds__(kBlock) void k_init_adjust(const Tile* __restrict__
                                                          const BoxDev* __restrict__ boxes,
                                                          const BoxState* __restrict__ st,
                                                          float mx, float my, float mz, float scale,
-                                                         double* __restrict__ partials)
+                                                         long long* __restrict__ partials)
 {
     const int t = blockIdx.x;
     const Tile tl = tiles[t];
     const BoxDev& b = boxes[tl.box];
     const int par = st[tl.box].parity;
-    double d[kNumDiag] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    long long d[kNumDiag] = {0, 0, 0, 0, 0, 0};
     for (int64_t i = tl.begin + threadIdx.x; i < tl.end; i += kBlock) {
         const float vx = (b.p[par][3][i] - mx) * scale;
         const float vy = (b.p[par][4][i] - my) * scale;
@@ -716,10 +727,7 @@ __global__ __launch_bounds__(kBlock) void k_init_adjust(const Tile* __restrict__
         b.p[par][3][i] = vx;
         b.p[par][4][i] = vy;
         b.p[par][5][i] = vz;
-        d[0] += vx;
-        d[1] += vy;
-        d[2] += vz;
-        d[3] += (double)vx * vx + (double)vy * vy + (double)vz * vz;
+        diag_particle(d, make_float3(vx, vy, vz));
     }
     block_diag(d, partials + (size_t)t * kNumDiag);
 }
@@ -728,14 +736,14 @@ __global__ __launch_bounds__(kBlock) void k_init_adjust(const Tile* __restrict__
 __global__ __launch_bounds__(kBlock) void k_snapshot(const Tile* __restrict__ tiles,
                                                       const BoxDev* __restrict__ boxes,
                                                       const BoxState* __restrict__ st,
-                                                      int set_v0, double* __restrict__ partials)
+                                                      int set_v0, long long* __restrict__ partials)
 {
     const int t = blockIdx.x;
     const Tile tl = tiles[t];
     const BoxDev& b = boxes[tl.box];
     const int par = st[tl.box].parity;
     const bool has_v0 = b.vacf_stride > 0;
-    double d[kNumDiag] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    long long d[kNumDiag] = {0, 0, 0, 0, 0, 0};
     for (int64_t i = tl.begin + threadIdx.x; i < tl.end; i += kBlock) {
         const float vx = b.p[par][3][i], vy = b.p[par][4][i], vz = b.p[par][5][i];
         if (has_v0 && set_v0) {
@@ -743,13 +751,8 @@ __global__ __launch_bounds__(kBlock) void k_snapshot(const Tile* __restrict__ ti
             b.v0[par][1][i] = vy;
             b.v0[par][2][i] = vz;
         }
-        d[0] += vx;
-        d[1] += vy;
-        d[2] += vz;
-        d[3] += (double)vx * vx + (double)vy * vy + (double)vz * vz;
-        if (has_v0)
-            d[4] += (double)vx * b.v0[par][0][i] + (double)vy * b.v0[par][1][i] +
-                    (double)vz * b.v0[par][2][i];
+        diag_particle(d, make_float3(vx, vy, vz));
+        if (has_v0) diag_vacf(d, make_float3(vx, vy, vz), b.v0[par][0][i], b.v0[par][1][i], b.v0[par][2][i]);
     }
     block_diag(d, partials + (size_t)t * kNumDiag);
 }
@@ -838,7 +841,7 @@ int max_window_records() { return (int)(96 * 1024 / sizeof(CellAcc)); }
 
 // The init/snapshot launchers take a sub-range of T.ptiles (one box); their
 // partials land at the same tile indices as the step's.
-static double* partials_at(const Tile* tiles, const Tables& T)
+static long long* partials_at(const Tile* tiles, const Tables& T)
 {
     return T.partials + (size_t)(tiles - T.ptiles) * kNumDiag;
 }

@@ -18,9 +18,9 @@ struct Tables {
     Tile* ctiles = nullptr;      // cell tiles of all live boxes
     Tile* btiles = nullptr;      // brick tiles (begin = brick index) of brick boxes
     int32_t* active = nullptr;   // live slots
-    double* partials = nullptr;    // kNumDiag per particle tile (initial state, snapshots)
-    double* partials_c = nullptr;  // kNumDiag per cell tile (SORT steps)
-    double* partials_b = nullptr;  // kNumDiag per brick tile (brick steps)
+    long long* partials = nullptr;    // kNumDiag per particle tile (initial state, snapshots)
+    long long* partials_c = nullptr;  // kNumDiag per cell tile (SORT steps)
+    long long* partials_b = nullptr;  // kNumDiag per brick tile (brick steps)
     uint32_t* tilesum = nullptr; // per cell tile
     int nptiles = 0, nctiles = 0, nbtiles = 0, nactive = 0;
     int max_wsize = 0;             // largest brick window of the live boxes (records)

@@ -116,8 +116,9 @@ def test_device_maxwell_initial_state(mp):
 
 
 def test_conservation_over_many_steps(mp):
-    """FP32 state, exact cell sums: momentum and energy drift stay at FP32
-    rounding level over 500 steps of a 10^6-particle box."""
+    """FP32 state, exact cell sums: over 500 steps of a 10^6-particle box the
+    energy drifts by less than 1e-6 relative and the momentum by less than
+    1e-8 N m sqrt(kT/m)."""
     _say("conservation")
     L, n = (50, 50, 40), 1000000
     with mp.Context() as ctx:
@@ -128,8 +129,8 @@ def test_conservation_over_many_steps(mp):
     assert o1["step"] == 500 and o1["status"] == 0
     print("[conservation] E0 %.12e E1 %.12e rel %.3e P0 %s P1 %s" % (
         o0["E"], o1["E"], (o1["E"] - o0["E"]) / o0["E"], o0["P"], o1["P"]), flush=True)
-    assert abs(o1["E"] - o0["E"]) / o0["E"] < 1e-5, (o0["E"], o1["E"])
-    assert np.all(np.abs(o1["P"] - o0["P"]) < 1e-3 * math.sqrt(n)), (o0["P"], o1["P"])
+    assert abs(o1["E"] - o0["E"]) / o0["E"] < 1e-6, (o0["E"], o1["E"])
+    assert np.all(np.abs(o1["P"] - o0["P"]) < 1e-8 * n), (o0["P"], o1["P"])
 
 
 def test_diagnostics_match_oracle(mp):
