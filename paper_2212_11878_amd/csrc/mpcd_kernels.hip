@@ -277,6 +277,7 @@ __global__ __launch_bounds__(kBlock) void k_brick_rotate(const Tile* __restrict_
                                                           const BoxState* __restrict__ st,
                                                           long long* __restrict__ partials)
 {
+    extern __shared__ CellUN wun[];   // u_c and axis of the brick's window cells
     __shared__ uint32_t cnt[27];
     __shared__ uint32_t base[27];
     const int t = xcd_tile(blockIdx.x, gridDim.x);
@@ -286,6 +287,25 @@ __global__ __launch_bounds__(kBlock) void k_brick_rotate(const Tile* __restrict_
     if (box_idle(s) || b.binning != 1) return;
     const int brick = (int)tl.begin;
     const int bx = brick % b.nb[0], by = (brick / b.nb[0]) % b.nb[1], bz = brick / (b.nb[0] * b.nb[1]);
+    const int m = b.margin;
+    const int lox = brick_lo(bx, b.L[0], b.nb[0]), loy = brick_lo(by, b.L[1], b.nb[1]),
+              loz = brick_lo(bz, b.L[2], b.nb[2]);
+    const int ex = brick_lo(bx + 1, b.L[0], b.nb[0]) - lox + 2 * m;
+    const int ey = brick_lo(by + 1, b.L[1], b.nb[1]) - loy + 2 * m;
+    const int ez = brick_lo(bz + 1, b.L[2], b.nb[2]) - loz + 2 * m;
+    const int wx = b.wdim[0], wy = b.wdim[1];
+    // stage the window's cell data in LDS (cells of empty slots are never read)
+    for (int i = threadIdx.x; i < b.wsize; i += kBlock) {
+        const int lx = i % wx, ly = (i / wx) % wy, lz = i / (wx * wy);
+        if (lx < ex && ly < ey && lz < ez) {
+            int cx = lox - m + lx, cy = loy - m + ly, cz = loz - m + lz;
+            cx = ((cx % b.L[0]) + b.L[0]) % b.L[0];
+            cy = ((cy % b.L[1]) + b.L[1]) % b.L[1];
+            cz = ((cz % b.L[2]) + b.L[2]) % b.L[2];
+            wun[i] = b.un[(uint32_t)cx + (uint32_t)b.L[0] * ((uint32_t)cy + (uint32_t)b.L[1] * (uint32_t)cz)];
+        }
+    }
+    __syncthreads();
     const int src = s.parity, dst = s.parity ^ 1;
     const float3 sh = grid_shift(b, s.k);
     const float dt = b.dt, ca = b.ca, sa = b.sa;
@@ -326,8 +346,15 @@ __global__ __launch_bounds__(kBlock) void k_brick_rotate(const Tile* __restrict_
                 py[it] = fold(fmaf(uy, dt, iy[i]), b.len[1]);
                 pz[it] = fold(fmaf(uz, dt, iz[i]), b.len[2]);
                 id[it] = iid[i];
-                const uint32_t c = collision_cell(b, px[it], py[it], pz[it], sh);
-                const CellUN u = un[c];
+                const int cx = axis_cell(px[it], sh.x, b.inv_a, b.L[0]);
+                const int cy = axis_cell(py[it], sh.y, b.inv_a, b.L[1]);
+                const int cz = axis_cell(pz[it], sh.z, b.inv_a, b.L[2]);
+                const int lx = window_offset(cx, lox, m, b.L[0]);
+                const int ly = window_offset(cy, loy, m, b.L[1]);
+                const int lz = window_offset(cz, loz, m, b.L[2]);
+                const CellUN u = (lx < ex && ly < ey && lz < ez)
+                    ? wun[lx + wx * (ly + wy * lz)]
+                    : un[(uint32_t)cx + (uint32_t)b.L[0] * ((uint32_t)cy + (uint32_t)b.L[1] * (uint32_t)cz)];
                 const float3 v = rotate_about(u, ux, uy, uz, ca, sa);
                 qx[it] = v.x;
                 qy[it] = v.y;
@@ -801,7 +828,16 @@ void launch_brick_finalize(const Tables& T, hipStream_t s)
 }
 void launch_brick_rotate(const Tables& T, hipStream_t s)
 {
-    MPCD_LAUNCH(k_brick_rotate, T.nbtiles, kBlock, s, T.btiles, T.boxes, T.state, T.partials_b);
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void*)k_brick_rotate, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  max_window_records() * (int)sizeof(CellUN));
+        attr = true;
+    }
+    const size_t lds = (size_t)T.max_wsize * sizeof(CellUN);
+    if (T.nbtiles > 0)
+        hipLaunchKernelGGL(k_brick_rotate, dim3(T.nbtiles), dim3(kBlock), lds, s, T.btiles, T.boxes, T.state,
+                           T.partials_b);
 }
 void launch_box_finish(const Tables& T, hipStream_t s)
 {
