@@ -65,6 +65,9 @@ typedef enum {
 #define MPCD_INIT_EXTERNAL 0x2u  /* caller supplies the state with
                                     mpcd_set_state before the first step    */
 #define MPCD_TRACK_VACF 0x4u     /* record the velocity autocorrelation     */
+#define MPCD_PARTICLE_MASS 0x8u  /* every particle carries its own mass
+                                    (initially desc.mass; mpcd_set_mass);
+                                    cell velocities are mass weighted       */
 
 /* mpcd_options.binning */
 #define MPCD_BIN_AUTO 0    /* autotuner chooses per box-shape class         */
@@ -83,7 +86,8 @@ typedef struct {
     double dt;             /* streaming time step, > 0                       */
     double alpha;          /* rotation angle in radians, finite              */
     double kT;             /* initial temperature (MPCD_INIT_MAXWELL), > 0   */
-    double mass;           /* particle mass, > 0 (all particles equal)       */
+    double mass;           /* particle mass, > 0 (all particles, or the
+                              initial one with MPCD_PARTICLE_MASS)          */
     uint64_t seed;         /* Philox key                                     */
     int64_t n_steps;       /* steps this box runs, then idles; 0 = unbounded */
     uint32_t flags;        /* MPCD_INIT_* | MPCD_TRACK_VACF                   */
@@ -170,6 +174,14 @@ int mpcd_get_state(mpcd_ctx* ctx, int32_t slot, float* xyzv, int64_t* step);
  * the VACF reference v(0).  EINVAL if a position is out of range or not
  * finite (state unchanged).  Synchronises. */
 int mpcd_set_state(mpcd_ctx* ctx, int32_t slot, const float* xyzv, int64_t step);
+
+/* Per-particle masses (box admitted with MPCD_PARTICLE_MASS): host mass[N],
+ * indexed like mpcd_set_state's particles, each finite and > 0.  The cell
+ * velocity becomes sum(m v) / sum(m) (Sec. 3.3, Listing 4) and the
+ * diagnostics are mass weighted.  Masses travel with their particles and
+ * survive mpcd_set_state.  EINVAL for a box without per-particle masses or a
+ * bad value (state unchanged).  Synchronises. */
+int mpcd_set_mass(mpcd_ctx* ctx, int32_t slot, const float* mass);
 
 /* Free a box's device state; the slot number may be reused.  Synchronises. */
 int mpcd_release(mpcd_ctx* ctx, int32_t slot);

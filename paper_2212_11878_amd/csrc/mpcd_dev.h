@@ -15,12 +15,12 @@ constexpr int kCellTile = 2048;      // cells per cell tile
 constexpr int kItems = 8;            // particles per thread per chunk (brick rotation)
 constexpr int kNumDiag = 6;          // per-tile exact partials: sum v (3), sum v^2, sum v.v0, range violations
 
-// Per-cell accumulator: exact 64-bit fixed-point momentum sums (quantum
-// 2^-32 velocity units) and the particle count.  32 bytes, one sector.
+// Per-cell accumulator: exact 64-bit fixed-point sums (quantum 2^-32) of the
+// momentum m v and of the mass m (equal masses count as m = 1, so w is
+// 2^32 times the particle count).  32 bytes, one sector.
 struct alignas(32) CellAcc {
     unsigned long long sx, sy, sz;
-    unsigned int n;
-    unsigned int pad;
+    unsigned long long w;
 };
 
 // Per-cell collision data: centre-of-mass velocity and rotation axis.
@@ -45,6 +45,7 @@ struct BoxDev {
     float* p[2][6];        // x, y, z, vx, vy, vz
     float* v0[2][3];       // VACF reference velocities (null if untracked)
     int32_t* pid[2];       // particle identity (admission order)
+    float* m[2];           // per-particle masses (null: all particles equal)
     uint32_t* cell;        // sort key of each particle
     uint32_t* rank;        // rank of each particle inside its key (sort)
     uint32_t* cstart;      // counts, then exclusive starts, per key (C + 1)
@@ -280,14 +281,26 @@ __device__ __forceinline__ unsigned long long to_fixed(float v)
 // Largest speed component the fixed-point cell sums accept.
 constexpr float kVelocityLimit = 1073741824.0f;   // 2^30
 
-// Mean velocity of a cell from its exact fixed-point sum, rounded once to
-// FP32 (the 64-bit sum is split into exact 32-bit halves, combined and
-// divided in FP64).
-__device__ __forceinline__ float fixed_mean(unsigned long long s, unsigned int n)
+// Exact value of a two's-complement 64-bit fixed-point sum as FP64 (hi and
+// lo 32-bit halves are exact; their combination rounds once).
+__device__ __forceinline__ double fixed_to_double(unsigned long long s)
 {
     const double hi = (double)(int)(unsigned)(s >> 32);
     const double lo = (double)(unsigned)(s & 0xffffffffu);
-    return (float)((hi + lo * 2.3283064365386963e-10) / (double)n);   // (hi 2^32 + lo) 2^-32 / n
+    return hi * 4294967296.0 + lo;
+}
+
+// Mass-weighted mean velocity of a cell, sum(m v) / sum(m), from the exact
+// fixed-point sums; one division, rounded to FP32.
+__device__ __forceinline__ float fixed_mean(unsigned long long s, unsigned long long w)
+{
+    return (float)(fixed_to_double(s) / fixed_to_double(w));
+}
+
+// mass of particle i (1 when the box has equal masses)
+__device__ __forceinline__ float mass_of(const float* __restrict__ m, int64_t i)
+{
+    return m ? m[i] : 1.0f;
 }
 
 // v' = u + (n.w) n + cos(a) (w - (n.w) n) + sin(a) (n x w), w = v - u: the
@@ -314,14 +327,15 @@ __device__ __forceinline__ long long fixed_term(double t)
     return (long long)rint(t);
 }
 
-__device__ __forceinline__ void diag_particle(long long (&d)[kNumDiag], float3 v)
+// momentum m v and twice the kinetic energy m v^2 of one particle
+__device__ __forceinline__ void diag_particle(long long (&d)[kNumDiag], float3 v, float m)
 {
-    d[0] += (long long)to_fixed(v.x);
-    d[1] += (long long)to_fixed(v.y);
-    d[2] += (long long)to_fixed(v.z);
-    d[3] += fixed_term((double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z);
-    const float m = fmaxf(fabsf(v.x), fmaxf(fabsf(v.y), fabsf(v.z)));
-    if (!(m < kVelocityLimit)) d[5] += 1;
+    d[0] += (long long)to_fixed(m * v.x);
+    d[1] += (long long)to_fixed(m * v.y);
+    d[2] += (long long)to_fixed(m * v.z);
+    d[3] += fixed_term((double)m * ((double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z));
+    const float vm = fmaxf(fabsf(v.x), fmaxf(fabsf(v.y), fabsf(v.z)));
+    if (!(vm < kVelocityLimit)) d[5] += 1;
 }
 
 __device__ __forceinline__ void diag_vacf(long long (&d)[kNumDiag], float3 v, float w0x, float w0y,

@@ -48,6 +48,7 @@ struct Slot {
     BoxDev dev{};
     int64_t ptiles = 0, ctiles = 0;
     int32_t part_tile = kPartTile;   // particles per tile
+    double mass_total = 0.0;         // sum of the per-particle masses (MPCD_PARTICLE_MASS)
 };
 
 }  // namespace
@@ -125,11 +126,12 @@ void drop_graph(mpcd_ctx* c)
 
 // Layout of one box's device allocation.
 struct Layout {
-    size_t off_p[2][6], off_v0[2][3], off_pid[2], off_cell, off_rank, off_cstart, off_un, off_part,
+    size_t off_p[2][6], off_v0[2][3], off_pid[2], off_m[2], off_cell, off_rank, off_cstart, off_un, off_part,
         off_esc, off_eflag, off_bstart[2], off_bcount, off_bcursor, off_vacf, total;
 };
 
-Layout box_layout(int64_t n, int64_t ncell, bool vacf, int vacf_cap, bool brick, const BrickGeom& g)
+Layout box_layout(int64_t n, int64_t ncell, bool vacf, int vacf_cap, bool brick, const BrickGeom& g,
+                  bool masses)
 {
     Layout L{};
     size_t o = 0;
@@ -142,6 +144,10 @@ Layout box_layout(int64_t n, int64_t ncell, bool vacf, int vacf_cap, bool brick,
             if (vacf) o += pf;
         }
     for (int b = 0; b < 2; ++b) { L.off_pid[b] = o; o += pf; }
+    for (int b = 0; b < 2; ++b) {
+        L.off_m[b] = o;
+        if (masses) o += pf;
+    }
     L.off_cell = o; o += pf;
     L.off_rank = o; o += pf;
     L.off_cstart = o; o += align256((size_t)(ncell + 1) * 4);
@@ -199,7 +205,8 @@ int validate_desc(const mpcd_box_desc* d)
     if (!isfinite(d->alpha)) return MPCD_EINVAL;
     if (!(d->mass > 0.0) || !isfinite(d->mass)) return MPCD_EINVAL;
     if (d->n_steps < 0) return MPCD_EINVAL;
-    if (d->flags & ~(MPCD_INIT_MAXWELL | MPCD_INIT_EXTERNAL | MPCD_TRACK_VACF)) return MPCD_EINVAL;
+    if (d->flags & ~(MPCD_INIT_MAXWELL | MPCD_INIT_EXTERNAL | MPCD_TRACK_VACF | MPCD_PARTICLE_MASS))
+        return MPCD_EINVAL;
     const uint32_t init = d->flags & (MPCD_INIT_MAXWELL | MPCD_INIT_EXTERNAL);
     if (init != MPCD_INIT_MAXWELL && init != MPCD_INIT_EXTERNAL) return MPCD_EINVAL;
     if ((d->flags & MPCD_INIT_MAXWELL) && (!(d->kT > 0.0) || !isfinite(d->kT))) return MPCD_EINVAL;
@@ -424,13 +431,13 @@ int reset_state(mpcd_ctx* c, int32_t s, int64_t step, int parity)
     return MPCD_OK;
 }
 
-// v0 <- v (if tracked), record VACF sample 0 and the diagnostics of the
-// current state.
-int take_snapshot(mpcd_ctx* c, int32_t s)
+// Diagnostics of the current state; with new_origin also v0 <- v (if
+// tracked) and VACF sample 0.
+int take_snapshot(mpcd_ctx* c, int32_t s, bool new_origin = true)
 {
     Slot& sl = c->slots[s];
     const Tile* tiles = c->T.ptiles + sl.dev.ptile0;
-    launch_snapshot(tiles, sl.dev.ptile1 - sl.dev.ptile0, c->T, 1, c->stream);
+    launch_snapshot(tiles, sl.dev.ptile1 - sl.dev.ptile0, c->T, new_origin ? 1 : 0, c->stream);
     HIPCHK(hipGetLastError());
     double d[kNumDiag];
     int rc = read_box_partials(c, sl, d);
@@ -441,8 +448,8 @@ int take_snapshot(mpcd_ctx* c, int32_t s)
     st.diag[1] = d[1];
     st.diag[2] = d[2];
     st.diag[3] = d[3];
-    st.vacf_len = 0;
-    if (sl.dev.vacf_stride > 0 && sl.dev.n > 0) {
+    if (new_origin) st.vacf_len = 0;
+    if (new_origin && sl.dev.vacf_stride > 0 && sl.dev.n > 0) {
         const double c0 = d[4] / (double)sl.dev.n;
         HIPCHK(hipMemcpy(sl.dev.vacf, &c0, 8, hipMemcpyHostToDevice));
         st.vacf_len = 1;
@@ -683,7 +690,8 @@ int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
     const bool brick = binning == MPCD_BIN_ATOMIC;
     const BrickGeom g = brick_geometry(d->L, want);
     if (brick && g.wsize > max_window_records()) return MPCD_EINVAL;
-    const Layout L = box_layout(d->n_particles, ncell, vacf, cap, brick, g);
+    const bool masses = (d->flags & MPCD_PARTICLE_MASS) != 0;
+    const Layout L = box_layout(d->n_particles, ncell, vacf, cap, brick, g, masses);
     if (c->budget > 0 && c->used + (int64_t)L.total > c->budget) return MPCD_ENOMEM;
     HIPCHK(hipSetDevice(c->device));
     void* mem = ctx_alloc(c, L.total);
@@ -700,6 +708,7 @@ int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
         for (int k = 0; k < 6; ++k) b.p[p][k] = (float*)(m + L.off_p[p][k]);
         for (int k = 0; k < 3; ++k) b.v0[p][k] = vacf ? (float*)(m + L.off_v0[p][k]) : nullptr;
         b.pid[p] = (int32_t*)(m + L.off_pid[p]);
+        b.m[p] = masses ? (float*)(m + L.off_m[p]) : nullptr;
     }
     b.cell = (uint32_t*)(m + L.off_cell);
     b.rank = (uint32_t*)(m + L.off_rank);
@@ -764,6 +773,10 @@ int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
     }
     rc = reset_state(c, s, 0, 0);
     if (rc) return undo(rc);
+    if (masses) {
+        launch_fill_f32(S.dev.m[0], S.dev.n, (float)d->mass, c->stream);
+        S.mass_total = (double)(float)d->mass * (double)S.dev.n;
+    }
     if (d->flags & MPCD_INIT_MAXWELL) {
         rc = init_maxwell(c, s);
     } else {
@@ -828,16 +841,19 @@ int mpcd_observe(mpcd_ctx* c, int32_t slot, mpcd_observables* out)
     c->vacf_host.assign((size_t)std::max(st.vacf_len, 0), 0.0);
     if (st.vacf_len > 0)
         HIPCHK(hipMemcpy(c->vacf_host.data(), sl->dev.vacf, (size_t)st.vacf_len * 8, hipMemcpyDeviceToHost));
-    const double m = sl->desc.mass;
+    // the kernels sum m v and m v^2 with m = 1 for equal masses
+    const bool masses = sl->dev.m[0] != nullptr;
+    const double m = masses ? 1.0 : sl->desc.mass;
     const int64_t n = sl->dev.n;
+    const double M = masses ? sl->mass_total : sl->desc.mass * (double)n;
     memset(out, 0, sizeof(*out));
     out->step = st.k;
     for (int d = 0; d < 3; ++d) out->P[d] = m * st.diag[d];
     out->E_kin = 0.5 * m * st.diag[3];
-    out->mass_total = m * (double)n;
-    if (n > 1) {
-        const double P2 = st.diag[0] * st.diag[0] + st.diag[1] * st.diag[1] + st.diag[2] * st.diag[2];
-        out->T = m * (st.diag[3] - P2 / (double)n) / (3.0 * (double)(n - 1));
+    out->mass_total = M;
+    if (n > 1 && M > 0) {
+        const double P2 = out->P[0] * out->P[0] + out->P[1] * out->P[1] + out->P[2] * out->P[2];
+        out->T = (m * st.diag[3] - P2 / M) / (3.0 * (double)(n - 1));
     }
     out->status = st.status ? MPCD_ESTATE : MPCD_OK;
     out->vacf_len = st.vacf_len;
@@ -892,6 +908,15 @@ int mpcd_set_state(mpcd_ctx* c, int32_t slot, const float* xyzv, int64_t step)
         if (!isfinite(xyzv[i])) return MPCD_EINVAL;
     HIPCHK(hipSetDevice(c->device));
     HIPCHK(hipStreamSynchronize(c->stream));
+    if (n > 0 && sl->dev.m[0]) {   // masses back into particle-id order, in buffer 0
+        BoxState st;
+        HIPCHK(hipMemcpy(&st, &c->T.state[slot], sizeof(BoxState), hipMemcpyDeviceToHost));
+        const int par = st.parity;
+        launch_permute_f32(sl->dev.m[par ^ 1], sl->dev.m[par], sl->dev.pid[par], n, 1, c->stream);
+        if (par == 0)
+            HIPCHK(hipMemcpyAsync(sl->dev.m[0], sl->dev.m[1], (size_t)n * 4, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+    }
     if (n > 0) {
         for (int d = 0; d < 6; ++d)
             HIPCHK(hipMemcpy(sl->dev.p[0][d], xyzv + (size_t)d * n, (size_t)n * 4, hipMemcpyHostToDevice));
@@ -901,6 +926,36 @@ int mpcd_set_state(mpcd_ctx* c, int32_t slot, const float* xyzv, int64_t step)
     int rc = reset_state(c, slot, step, 0);
     if (rc) return rc;
     rc = take_snapshot(c, slot);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return MPCD_OK;
+}
+
+int mpcd_set_mass(mpcd_ctx* c, int32_t slot, const float* mass)
+{
+    Slot* sl = live_slot(c, slot);
+    if (!c || !mass) return MPCD_EINVAL;
+    if (!sl) return MPCD_ENOTFOUND;
+    if (!sl->dev.m[0]) return MPCD_EINVAL;
+    const int64_t n = sl->dev.n;
+    double total = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!(mass[i] > 0.0f) || !isfinite(mass[i])) return MPCD_EINVAL;
+        total += mass[i];
+    }
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (n > 0) {
+        BoxState st;
+        HIPCHK(hipMemcpy(&st, &c->T.state[slot], sizeof(BoxState), hipMemcpyDeviceToHost));
+        const int par = st.parity;
+        // stage the id-ordered masses in the idle buffer, then gather by id
+        HIPCHK(hipMemcpy(sl->dev.m[par ^ 1], mass, (size_t)n * 4, hipMemcpyHostToDevice));
+        launch_permute_f32(sl->dev.m[par], sl->dev.m[par ^ 1], sl->dev.pid[par], n, 0, c->stream);
+        HIPCHK(hipGetLastError());
+    }
+    sl->mass_total = total;
+    int rc = take_snapshot(c, slot, false);
     if (rc) return rc;
     HIPCHK(hipStreamSynchronize(c->stream));
     return MPCD_OK;

@@ -120,7 +120,7 @@ __global__ __launch_bounds__(kBlock) void k_brick_accumulate(const Tile* __restr
     const int ez = brick_lo(bz + 1, b.L[2], b.nb[2]) - loz + 2 * m;
     const int wx = b.wdim[0], wy = b.wdim[1];
     for (int i = threadIdx.x; i < b.wsize; i += kBlock) {
-        CellAcc z = {0ull, 0ull, 0ull, 0u, 0u};
+        CellAcc z = {0ull, 0ull, 0ull, 0ull};
         win[i] = z;
     }
     if (threadIdx.x < 27) cnt[threadIdx.x] = 0u;
@@ -133,6 +133,7 @@ __global__ __launch_bounds__(kBlock) void k_brick_accumulate(const Tile* __restr
     const float* __restrict__ vx = b.p[par][3];
     const float* __restrict__ vy = b.p[par][4];
     const float* __restrict__ vz = b.p[par][5];
+    const float* __restrict__ mp = b.m[par];
     const float3 sh = grid_shift(b, s.k);
     const float dt = b.dt;
     const uint32_t stamp = (uint32_t)(s.k + 1);
@@ -148,19 +149,21 @@ __global__ __launch_bounds__(kBlock) void k_brick_accumulate(const Tile* __restr
         const int lx = window_offset(cx, lox, m, b.L[0]);
         const int ly = window_offset(cy, loy, m, b.L[1]);
         const int lz = window_offset(cz, loz, m, b.L[2]);
-        const unsigned long long fx = to_fixed(ux), fy = to_fixed(uy), fz = to_fixed(uz);
+        const float mi = mass_of(mp, i);
+        const unsigned long long fx = to_fixed(mi * ux), fy = to_fixed(mi * uy), fz = to_fixed(mi * uz);
+        const unsigned long long fw = to_fixed(mi);
         if (lx < ex && ly < ey && lz < ez) {
             CellAcc* w = &win[lx + wx * (ly + wy * lz)];
             atomicAdd(&w->sx, fx);
             atomicAdd(&w->sy, fy);
             atomicAdd(&w->sz, fz);
-            atomicAdd(&w->n, 1u);
+            atomicAdd(&w->w, fw);
         } else {   // left the window: exact global sums, flag the owner brick
             const uint32_t c = (uint32_t)cx + (uint32_t)b.L[0] * ((uint32_t)cy + (uint32_t)b.L[1] * (uint32_t)cz);
             atomicAdd(&b.esc[c].sx, fx);
             atomicAdd(&b.esc[c].sy, fy);
             atomicAdd(&b.esc[c].sz, fz);
-            atomicAdd(&b.esc[c].n, 1u);
+            atomicAdd(&b.esc[c].w, fw);
             const int ob = brick_of(cx, b.L[0], b.nb[0]) +
                            b.nb[0] * (brick_of(cy, b.L[1], b.nb[1]) + b.nb[1] * brick_of(cz, b.L[2], b.nb[2]));
             b.eflag[ob] = stamp;
@@ -231,8 +234,7 @@ __global__ __launch_bounds__(kBlock) void k_brick_finalize(const Tile* __restric
         const int nx = windows_of(cx, b.L[0], b.nb[0], m, bxs, lxs);
         const int ny = windows_of(cy, b.L[1], b.nb[1], m, bys, lys);
         const int nz = windows_of(cz, b.L[2], b.nb[2], m, bzs, lzs);
-        unsigned long long sx = 0, sy = 0, sz = 0;
-        unsigned int n = 0;
+        unsigned long long sx = 0, sy = 0, sz = 0, sw = 0;
         for (int iz = 0; iz < nz; ++iz)
             for (int iy = 0; iy < ny; ++iy)
                 for (int ix = 0; ix < nx; ++ix) {
@@ -242,26 +244,26 @@ __global__ __launch_bounds__(kBlock) void k_brick_finalize(const Tile* __restric
                     sx += r.sx;
                     sy += r.sy;
                     sz += r.sz;
-                    n += r.n;
+                    sw += r.w;
                 }
         const int ob = brick_of(cx, b.L[0], b.nb[0]) +
                        b.nb[0] * (brick_of(cy, b.L[1], b.nb[1]) + b.nb[1] * brick_of(cz, b.L[2], b.nb[2]));
         if (b.eflag[ob] == stamp) {
             const CellAcc e = b.esc[c];
-            if (e.n) {
+            if (e.w) {
                 sx += e.sx;
                 sy += e.sy;
                 sz += e.sz;
-                n += e.n;
-                CellAcc zero = {0ull, 0ull, 0ull, 0u, 0u};
+                sw += e.w;
+                CellAcc zero = {0ull, 0ull, 0ull, 0ull};
                 b.esc[c] = zero;
             }
         }
-        if (n == 0) continue;
+        if (sw == 0) continue;
         CellUN u;
-        u.ux = fixed_mean(sx, n);
-        u.uy = fixed_mean(sy, n);
-        u.uz = fixed_mean(sz, n);
+        u.ux = fixed_mean(sx, sw);
+        u.uy = fixed_mean(sy, sw);
+        u.uz = fixed_mean(sz, sw);
         const float3 ax = cell_axis(b, s.k, (uint32_t)c);
         u.nx = ax.x;
         u.ny = ax.y;
@@ -326,6 +328,8 @@ __global__ __launch_bounds__(kBlock) void k_brick_rotate(const Tile* __restrict_
     float* __restrict__ ovy = b.p[dst][4];
     float* __restrict__ ovz = b.p[dst][5];
     int32_t* __restrict__ oid = b.pid[dst];
+    const float* __restrict__ im = b.m[src];
+    float* __restrict__ om = b.m[dst];
     const CellUN* __restrict__ un = b.un;
     long long d[kNumDiag] = {0, 0, 0, 0, 0, 0};
     constexpr int kChunk = kBlock * kItems;
@@ -359,7 +363,7 @@ __global__ __launch_bounds__(kBlock) void k_brick_rotate(const Tile* __restrict_
                 qx[it] = v.x;
                 qy[it] = v.y;
                 qz[it] = v.z;
-                diag_particle(d, v);
+                diag_particle(d, v, mass_of(im, i));
                 if (vacf) diag_vacf(d, v, b.v0[src][0][i], b.v0[src][1][i], b.v0[src][2][i]);
                 const int3 db = brick_of_pos(b, px[it], py[it], pz[it]);
                 const int rx = brick_rel(bx, db.x, b.nb[0]), ry = brick_rel(by, db.y, b.nb[1]),
@@ -407,6 +411,7 @@ __global__ __launch_bounds__(kBlock) void k_brick_rotate(const Tile* __restrict_
             ovy[j] = qy[it];
             ovz[j] = qz[it];
             oid[j] = id[it];
+            if (om) om[j] = im[i];
             if (track) {
                 b.v0[dst][0][j] = b.v0[src][0][i];
                 b.v0[dst][1][j] = b.v0[src][1][i];
@@ -579,6 +584,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const Tile* __restrict__ til
         b.p[dst][4][j] = vy;
         b.p[dst][5][j] = vz;
         b.pid[dst][j] = b.pid[src][i];
+        if (b.m[src]) b.m[dst][j] = b.m[src][i];
         if (vacf) {
             b.v0[dst][0][j] = b.v0[src][0][i];
             b.v0[dst][1][j] = b.v0[src][1][i];
@@ -618,22 +624,24 @@ __global__ __launch_bounds__(kBlock) void k_cell_rotate(const Tile* __restrict__
     const float* __restrict__ w0x = b.v0[s.parity][0];
     const float* __restrict__ w0y = b.v0[s.parity][1];
     const float* __restrict__ w0z = b.v0[s.parity][2];
+    const float* __restrict__ mp = b.m[s.parity];
     const float ca = b.ca, sa = b.sa;
     long long d[kNumDiag] = {0, 0, 0, 0, 0, 0};
     for (int64_t c = tl.begin + threadIdx.x; c < tl.end; c += kBlock) {
         const uint32_t beg = b.cstart[c], end = b.cstart[c + 1];
         if (beg == end) continue;
-        unsigned long long sx = 0, sy = 0, sz = 0;
+        unsigned long long sx = 0, sy = 0, sz = 0, sw = 0;
         for (uint32_t j = beg; j < end; ++j) {
-            sx += to_fixed(vx[j]);
-            sy += to_fixed(vy[j]);
-            sz += to_fixed(vz[j]);
+            const float mj = mass_of(mp, j);
+            sx += to_fixed(mj * vx[j]);
+            sy += to_fixed(mj * vy[j]);
+            sz += to_fixed(mj * vz[j]);
+            sw += to_fixed(mj);
         }
-        const unsigned int n = end - beg;
         CellUN u;
-        u.ux = fixed_mean(sx, n);
-        u.uy = fixed_mean(sy, n);
-        u.uz = fixed_mean(sz, n);
+        u.ux = fixed_mean(sx, sw);
+        u.uy = fixed_mean(sy, sw);
+        u.uz = fixed_mean(sz, sw);
         const float3 ax = cell_axis(b, s.k, (uint32_t)c);
         u.nx = ax.x;
         u.ny = ax.y;
@@ -643,7 +651,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_rotate(const Tile* __restrict__
             vx[j] = v.x;
             vy[j] = v.y;
             vz[j] = v.z;
-            diag_particle(d, v);
+            diag_particle(d, v, mass_of(mp, j));
             if (vacf) diag_vacf(d, v, w0x[j], w0y[j], w0z[j]);
         }
     }
@@ -730,7 +738,7 @@ __global__ __launch_bounds__(kBlock) void k_init_maxwell(const Tile* __restrict_
         b.p[par][4][i] = vy;
         b.p[par][5][i] = vz;
         b.pid[par][i] = (int32_t)i;
-        diag_particle(d, make_float3(vx, vy, vz));
+        diag_particle(d, make_float3(vx, vy, vz), 1.0f);
     }
     block_diag(d, partials + (size_t)t * kNumDiag);
 }
@@ -754,7 +762,7 @@ __global__ __launch_bounds__(kBlock) void k_init_adjust(const Tile* __restrict__
         b.p[par][3][i] = vx;
         b.p[par][4][i] = vy;
         b.p[par][5][i] = vz;
-        diag_particle(d, make_float3(vx, vy, vz));
+        diag_particle(d, make_float3(vx, vy, vz), 1.0f);
     }
     block_diag(d, partials + (size_t)t * kNumDiag);
 }
@@ -778,7 +786,7 @@ __global__ __launch_bounds__(kBlock) void k_snapshot(const Tile* __restrict__ ti
             b.v0[par][1][i] = vy;
             b.v0[par][2][i] = vz;
         }
-        diag_particle(d, make_float3(vx, vy, vz));
+        diag_particle(d, make_float3(vx, vy, vz), mass_of(b.m[par], i));
         if (has_v0) diag_vacf(d, make_float3(vx, vy, vz), b.v0[par][0][i], b.v0[par][1][i], b.v0[par][2][i]);
     }
     block_diag(d, partials + (size_t)t * kNumDiag);
@@ -788,6 +796,28 @@ __global__ __launch_bounds__(kBlock) void k_fill_iota(int32_t* __restrict__ p, i
 {
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
         p[i] = (int32_t)i;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_f32(float* __restrict__ p, int64_t n, float v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        p[i] = v;
+}
+
+// dst[i] = src[pid[i]] (gather_by_id) or dst[pid[i]] = src[i] (scatter_by_id);
+// pid is a permutation of [0, n)
+__global__ __launch_bounds__(kBlock) void k_permute_f32(float* __restrict__ dst, const float* __restrict__ src,
+                                                         const int32_t* __restrict__ pid, int64_t n,
+                                                         int scatter)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        const int64_t j = pid[i];
+        if (j < 0 || j >= n) continue;
+        if (scatter)
+            dst[j] = src[i];
+        else
+            dst[i] = src[j];
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill_zero_u32(uint32_t* __restrict__ p, int64_t n)
@@ -899,6 +929,16 @@ void launch_fill_iota(int32_t* p, int64_t n, hipStream_t s)
 {
     const int64_t g = (n + kBlock - 1) / kBlock;
     MPCD_LAUNCH(k_fill_iota, (int)(g < 65536 ? g : 65536), kBlock, s, p, n);
+}
+void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s)
+{
+    const int64_t g = (n + kBlock - 1) / kBlock;
+    MPCD_LAUNCH(k_fill_f32, (int)(g < 65536 ? g : 65536), kBlock, s, p, n, v);
+}
+void launch_permute_f32(float* dst, const float* src, const int32_t* pid, int64_t n, int scatter, hipStream_t s)
+{
+    const int64_t g = (n + kBlock - 1) / kBlock;
+    MPCD_LAUNCH(k_permute_f32, (int)(g < 65536 ? g : 65536), kBlock, s, dst, src, pid, n, scatter);
 }
 void launch_fill_zero_u32(uint32_t* p, int64_t n, hipStream_t s)
 {

@@ -45,5 +45,8 @@ void launch_init_adjust(const Tile* tiles, int ntiles, const Tables& T, float mx
 void launch_snapshot(const Tile* tiles, int ntiles, const Tables& T, int set_v0, hipStream_t s);
 void launch_fill_iota(int32_t* p, int64_t n, hipStream_t s);
 void launch_fill_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
+void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
+void launch_permute_f32(float* dst, const float* src, const int32_t* pid, int64_t n, int scatter,
+                        hipStream_t s);
 
 }  // namespace mpcd

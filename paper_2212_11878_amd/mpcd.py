@@ -25,6 +25,7 @@ MPCD_ENOTFOUND = -6
 MPCD_INIT_MAXWELL = 0x1
 MPCD_INIT_EXTERNAL = 0x2
 MPCD_TRACK_VACF = 0x4
+MPCD_PARTICLE_MASS = 0x8
 
 MPCD_BIN_AUTO = 0
 MPCD_BIN_ATOMIC = 1
@@ -103,6 +104,7 @@ _SIGNATURES = {
                                       ctypes.POINTER(ctypes.c_int64)]),
     "mpcd_set_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_float),
                                       ctypes.c_int64]),
+    "mpcd_set_mass": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_float)]),
     "mpcd_release": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "mpcd_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "mpcd_kernel_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(mpcd_kernel_stat), ctypes.c_int32,
@@ -181,6 +183,11 @@ def mpcd_set_state(ctx, slot, xyzv, step):
                                int(step))
 
 
+def mpcd_set_mass(ctx, slot, mass):
+    buf = np.ascontiguousarray(mass, dtype=np.float32).reshape(-1)
+    return _lib.mpcd_set_mass(ctx, int(slot), buf.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+
+
 def mpcd_release(ctx, slot):
     return _lib.mpcd_release(ctx, int(slot))
 
@@ -234,7 +241,8 @@ class _TorchAllocator:
 
 
 def make_desc(L, n_particles, dt=0.1, alpha_deg=130.0, seed=1, a=1.0, kT=1.0, mass=1.0,
-              n_steps=0, init="maxwell", vacf_stride=0, vacf_capacity=0, alpha_rad=None):
+              n_steps=0, init="maxwell", vacf_stride=0, vacf_capacity=0, alpha_rad=None,
+              particle_mass=False):
     d = mpcd_box_desc()
     if isinstance(L, int):
         L = (L, L, L)
@@ -249,6 +257,8 @@ def make_desc(L, n_particles, dt=0.1, alpha_deg=130.0, seed=1, a=1.0, kT=1.0, ma
     d.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
     d.n_steps = int(n_steps)
     d.flags = MPCD_INIT_MAXWELL if init == "maxwell" else MPCD_INIT_EXTERNAL
+    if particle_mass:
+        d.flags |= MPCD_PARTICLE_MASS
     if vacf_stride:
         d.flags |= MPCD_TRACK_VACF
         d.vacf_stride = int(vacf_stride)
@@ -310,6 +320,9 @@ class Context:
         xyzv = np.concatenate([np.asarray(pos, np.float32).reshape(3, -1),
                                np.asarray(vel, np.float32).reshape(3, -1)])
         _check(mpcd_set_state(self.handle, slot, xyzv, step), "mpcd_set_state")
+
+    def set_mass(self, slot, mass):
+        _check(mpcd_set_mass(self.handle, slot, mass), "mpcd_set_mass")
 
     def get_state(self, slot):
         rc, buf, step = mpcd_get_state(self.handle, slot, self.n[slot])

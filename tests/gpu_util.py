@@ -33,9 +33,10 @@ def f32_state(pos, vel, L, a=1.0):
     return pos32, np.asarray(vel, dtype=np.float32).copy()
 
 
-def oracle_one_step(pos32, vel32, box, k):
+def oracle_one_step(pos32, vel32, box, k, mass32=None):
     """One oracle step (stream + collide at step k) from the FP32 state."""
-    st = orc.State(pos32.astype(np.float64), vel32.astype(np.float64))
+    st = orc.State(pos32.astype(np.float64), vel32.astype(np.float64),
+                   None if mass32 is None else mass32.astype(np.float64))
     orc.stream(box, st)
     s = orc.shift(box.seed, k, box.a)
     cells = orc.cells(box, s, st)
@@ -97,8 +98,8 @@ def check_against(ref, s, cells, box, gpu_pos, gpu_vel, kT=1.0, mass=1.0):
     return int(band.sum()), float(err[keep].max()) if keep.any() else 0.0
 
 
-def compare_step(pos32, vel32, gpu_pos, gpu_vel, box, k, kT=1.0, mass=1.0):
+def compare_step(pos32, vel32, gpu_pos, gpu_vel, box, k, kT=1.0, mass=1.0, mass32=None):
     """Assert the GPU's one-step result matches the oracle's; returns the
     number of face-band particles and the largest kept velocity error."""
-    st, s, cells = oracle_one_step(pos32, vel32, box, k)
+    st, s, cells = oracle_one_step(pos32, vel32, box, k, mass32)
     return check_against(st, s, cells, box, gpu_pos, gpu_vel, kT, mass)
