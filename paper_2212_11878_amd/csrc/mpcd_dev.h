@@ -74,8 +74,7 @@ struct BoxDev {
     int32_t btile0, btile1;   // brick tiles [btile0, btile1)
     float len[3];          // L_d * a
     float a, inv_a, dt;
-    float ca, sa;          // FP32 cos(alpha), sin(alpha) with ca^2 + sa^2 closest to 1
-    float pad0;
+    double ca, sa;         // cos(alpha), sin(alpha)
     float mass;
     uint32_t key0, key1;   // Philox key = seed
 };
@@ -305,18 +304,29 @@ __device__ __forceinline__ float mass_of(const float* __restrict__ m, int64_t i)
 
 // v' = u + (n.w) n + cos(a) (w - (n.w) n) + sin(a) (n x w), w = v - u: the
 // component along the axis is kept, the perpendicular one turned by a.
+// Evaluated in FP64 from the FP32 inputs with the axis renormalised in FP64,
+// then rounded once to FP32: FP32 evaluation leaves a systematic bias of a
+// few 1e-8 per step in the kinetic energy (unit-norm and cos^2 + sin^2
+// rounding), which this removes; the kernel is bound by memory traffic, so
+// the FP64 arithmetic costs no time.
 __device__ __forceinline__ float3 rotate_about(const CellUN& c, float vx, float vy, float vz,
-                                               float ca, float sa)
+                                               double ca, double sa)
 {
-    const float wx = vx - c.ux, wy = vy - c.uy, wz = vz - c.uz;
-    const float d = c.nx * wx + c.ny * wy + c.nz * wz;
-    const float px = d * c.nx, py = d * c.ny, pz = d * c.nz;
-    const float cx = c.ny * wz - c.nz * wy;
-    const float cy = c.nz * wx - c.nx * wz;
-    const float cz = c.nx * wy - c.ny * wx;
-    return make_float3(c.ux + (px + fmaf(ca, wx - px, sa * cx)),
-                       c.uy + (py + fmaf(ca, wy - py, sa * cy)),
-                       c.uz + (pz + fmaf(ca, wz - pz, sa * cz)));
+    double nx = c.nx, ny = c.ny, nz = c.nz;
+    const double inv = 1.0 / sqrt(nx * nx + ny * ny + nz * nz);
+    nx *= inv;
+    ny *= inv;
+    nz *= inv;
+    const double ux = c.ux, uy = c.uy, uz = c.uz;
+    const double wx = (double)vx - ux, wy = (double)vy - uy, wz = (double)vz - uz;
+    const double d = nx * wx + ny * wy + nz * wz;
+    const double px = d * nx, py = d * ny, pz = d * nz;
+    const double cx = ny * wz - nz * wy;
+    const double cy = nz * wx - nx * wz;
+    const double cz = nx * wy - ny * wx;
+    return make_float3((float)(ux + px + ca * (wx - px) + sa * cx),
+                       (float)(uy + py + ca * (wy - py) + sa * cy),
+                       (float)(uz + pz + ca * (wz - pz) + sa * cz));
 }
 
 // Exact diagnostics: per-particle terms in 64-bit fixed point (quantum 2^-32)
@@ -330,9 +340,9 @@ __device__ __forceinline__ long long fixed_term(double t)
 // momentum m v and twice the kinetic energy m v^2 of one particle
 __device__ __forceinline__ void diag_particle(long long (&d)[kNumDiag], float3 v, float m)
 {
-    d[0] += (long long)to_fixed(m * v.x);
-    d[1] += (long long)to_fixed(m * v.y);
-    d[2] += (long long)to_fixed(m * v.z);
+    d[0] += fixed_term((double)m * v.x);
+    d[1] += fixed_term((double)m * v.y);
+    d[2] += fixed_term((double)m * v.z);
     d[3] += fixed_term((double)m * ((double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z));
     const float vm = fmaxf(fabsf(v.x), fmaxf(fabsf(v.y), fabsf(v.z)));
     if (!(vm < kVelocityLimit)) d[5] += 1;

@@ -164,32 +164,6 @@ Layout box_layout(int64_t n, int64_t ncell, bool vacf, int vacf_cap, bool brick,
     return L;
 }
 
-// FP32 (cos a, sin a) within a few ulps of the exact values, chosen so that
-// cos^2 + sin^2 is as close to 1 as FP32 allows: the rotation then keeps the
-// perpendicular kinetic energy without a systematic drift.
-void rotation_pair(double alpha, float* ca, float* sa)
-{
-    const float c0 = (float)cos(alpha), s0 = (float)sin(alpha);
-    float bc = c0, bs = s0;
-    double best = fabs((double)c0 * c0 + (double)s0 * s0 - 1.0);
-    float c = c0;
-    for (int i = 0; i < 4; ++i) c = nextafterf(c, -2.0f);
-    for (int i = -4; i <= 4; ++i, c = nextafterf(c, 2.0f)) {
-        float s = s0;
-        for (int j = 0; j < 4; ++j) s = nextafterf(s, -2.0f);
-        for (int j = -4; j <= 4; ++j, s = nextafterf(s, 2.0f)) {
-            const double e = fabs((double)c * c + (double)s * s - 1.0);
-            if (e < best) {
-                best = e;
-                bc = c;
-                bs = s;
-            }
-        }
-    }
-    *ca = bc;
-    *sa = bs;
-}
-
 int validate_desc(const mpcd_box_desc* d)
 {
     if (!d) return MPCD_EINVAL;
@@ -741,7 +715,8 @@ int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
     b.a = (float)d->a;
     b.inv_a = (float)(1.0 / d->a);
     b.dt = (float)d->dt;
-    rotation_pair(d->alpha, &b.ca, &b.sa);
+    b.ca = cos(d->alpha);
+    b.sa = sin(d->alpha);
     b.mass = (float)d->mass;
     b.key0 = (uint32_t)(d->seed & 0xffffffffu);
     b.key1 = (uint32_t)(d->seed >> 32);

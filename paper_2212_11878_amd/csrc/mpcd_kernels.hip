@@ -310,7 +310,8 @@ __global__ __launch_bounds__(kBlock) void k_brick_rotate(const Tile* __restrict_
     __syncthreads();
     const int src = s.parity, dst = s.parity ^ 1;
     const float3 sh = grid_shift(b, s.k);
-    const float dt = b.dt, ca = b.ca, sa = b.sa;
+    const float dt = b.dt;
+    const double ca = b.ca, sa = b.sa;
     const bool track = b.vacf_stride > 0;
     const bool vacf = vacf_due(b, s);
     const int64_t beg = b.bstart[src][brick], end = b.bstart[src][brick + 1];
@@ -625,7 +626,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_rotate(const Tile* __restrict__
     const float* __restrict__ w0y = b.v0[s.parity][1];
     const float* __restrict__ w0z = b.v0[s.parity][2];
     const float* __restrict__ mp = b.m[s.parity];
-    const float ca = b.ca, sa = b.sa;
+    const double ca = b.ca, sa = b.sa;
     long long d[kNumDiag] = {0, 0, 0, 0, 0, 0};
     for (int64_t c = tl.begin + threadIdx.x; c < tl.end; c += kBlock) {
         const uint32_t beg = b.cstart[c], end = b.cstart[c + 1];
