@@ -56,6 +56,8 @@ struct BoxDev {
     uint32_t* bstart[2];   // brick mode: bucket starts of each buffer (nbrick + 1)
     uint32_t* bcount;      // brick mode: particles bound for each bucket next step
     uint32_t* bcursor;     // brick mode: write cursors of the next buckets
+    uint16_t* bof[3];      // brick mode: brick index of each cell, per dimension (L_d entries)
+    int32_t* blo[3];       // brick mode: first cell of each brick, per dimension (nb_d + 1 entries)
     double* vacf;          // VACF samples
     int64_t n;             // particles
     int64_t ncell;
@@ -190,23 +192,25 @@ __host__ __device__ __forceinline__ int brick_of(int c, int L, int nb)
     return (int)((((long long)c + 1) * nb - 1) / L);
 }
 
-// Brick that holds a position (unshifted grid), per dimension.
+// Brick that holds a position (unshifted grid), per dimension (table lookups).
 __device__ __forceinline__ int3 brick_of_pos(const BoxDev& b, float x, float y, float z)
 {
     const int cx = axis_cell(x, 0.0f, b.inv_a, b.L[0]);
     const int cy = axis_cell(y, 0.0f, b.inv_a, b.L[1]);
     const int cz = axis_cell(z, 0.0f, b.inv_a, b.L[2]);
-    return make_int3(brick_of(cx, b.L[0], b.nb[0]), brick_of(cy, b.L[1], b.nb[1]),
-                     brick_of(cz, b.L[2], b.nb[2]));
+    return make_int3(b.bof[0][cx], b.bof[1][cy], b.bof[2][cz]);
 }
 
 // Offset (-1, 0, 1) of brick `to` from brick `from` along a dimension with nb
 // bricks (periodic); 2 when it is farther.
 __host__ __device__ __forceinline__ int brick_rel(int from, int to, int nb)
 {
-    if (nb <= 2) return to - from;
-    const int r = ((to - from + nb + 1) % nb) - 1;
-    return r <= 1 ? r : 2;
+    int r = to - from;
+    if (nb >= 3) {
+        if (r == nb - 1) r = -1;
+        else if (r == 1 - nb) r = 1;
+    }
+    return (r >= -1 && r <= 1) ? r : 2;
 }
 
 // Windows (brick grown by m cells on each side) that contain cell c along
@@ -235,6 +239,32 @@ __host__ __device__ __forceinline__ int windows_of(int c, int L, int nb, int m, 
     return n;
 }
 
+// windows_of with the box's brick tables (no integer division).
+__device__ __forceinline__ int windows_of_tab(int c, int L, int nb, int m, const uint16_t* bof,
+                                              const int32_t* blo, int* bi, int* li)
+{
+    const int own = bof[c];
+    int n = 0;
+    for (int k = -1; k <= 1; ++k) {
+        int i = own + k;
+        i += (i < 0) ? nb : 0;
+        i -= (i >= nb) ? nb : 0;
+        bool dup = false;
+        for (int j = 0; j < n; ++j) dup |= (bi[j] == i);
+        if (dup) continue;
+        const int lo = blo[i], ext = blo[i + 1] - lo + 2 * m;
+        int l = c - lo + m;
+        l += (l < 0) ? L : 0;
+        l -= (l >= L) ? L : 0;
+        if (l < ext) {
+            bi[n] = i;
+            li[n] = l;
+            ++n;
+        }
+    }
+    return n;
+}
+
 // Offset of canonical cell c inside the window of the brick starting at lo
 // (periodic), as the accumulation computes it.
 __host__ __device__ __forceinline__ int window_offset(int c, int lo, int m, int L)
@@ -248,7 +278,7 @@ __host__ __device__ __forceinline__ int window_offset(int c, int lo, int m, int 
 // Brick decomposition of one box: nb bricks per dimension of at most
 // `want` cells (8 when 0), windows grown by `margin` cells.
 struct BrickGeom {
-    int nb[3], bmax[3], wdim[3], margin, wsize, nbrick;
+    int L[3], nb[3], bmax[3], wdim[3], margin, wsize, nbrick;
 };
 
 inline BrickGeom brick_geometry(const int32_t L[3], const int32_t want[3])
@@ -258,6 +288,7 @@ inline BrickGeom brick_geometry(const int32_t L[3], const int32_t want[3])
     g.nbrick = 1;
     g.wsize = 1;
     for (int d = 0; d < 3; ++d) {
+        g.L[d] = L[d];
         const int B = want[d] > 0 ? want[d] : 8;
         g.nb[d] = (L[d] + B - 1) / B > 1 ? (L[d] + B - 1) / B : 1;
         g.bmax[d] = (L[d] + g.nb[d] - 1) / g.nb[d];

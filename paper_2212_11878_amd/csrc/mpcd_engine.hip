@@ -127,7 +127,7 @@ void drop_graph(mpcd_ctx* c)
 // Layout of one box's device allocation.
 struct Layout {
     size_t off_p[2][6], off_v0[2][3], off_pid[2], off_m[2], off_cell, off_rank, off_cstart, off_un, off_part,
-        off_esc, off_eflag, off_bstart[2], off_bcount, off_bcursor, off_vacf, total;
+        off_esc, off_eflag, off_bstart[2], off_bcount, off_bcursor, off_bof[3], off_blo[3], off_vacf, total;
 };
 
 Layout box_layout(int64_t n, int64_t ncell, bool vacf, int vacf_cap, bool brick, const BrickGeom& g,
@@ -159,6 +159,12 @@ Layout box_layout(int64_t n, int64_t ncell, bool vacf, int vacf_cap, bool brick,
     for (int b = 0; b < 2; ++b) { L.off_bstart[b] = o; o += align256((nbk + 1) * 4); }
     L.off_bcount = o; o += align256(nbk * 4);
     L.off_bcursor = o; o += align256(nbk * 4);
+    for (int d = 0; d < 3; ++d) {
+        L.off_bof[d] = o;
+        o += brick ? align256((size_t)g.L[d] * 2) : 0;
+        L.off_blo[d] = o;
+        o += brick ? align256((size_t)(g.nb[d] + 1) * 4) : 0;
+    }
     L.off_vacf = o; o += align256((size_t)std::max(vacf_cap, 1) * 8);
     L.total = o;
     return L;
@@ -695,6 +701,10 @@ int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
     b.bcount = brick ? (uint32_t*)(m + L.off_bcount) : nullptr;
     b.bcursor = brick ? (uint32_t*)(m + L.off_bcursor) : nullptr;
     for (int k = 0; k < 3; ++k) {
+        b.bof[k] = brick ? (uint16_t*)(m + L.off_bof[k]) : nullptr;
+        b.blo[k] = brick ? (int32_t*)(m + L.off_blo[k]) : nullptr;
+    }
+    for (int k = 0; k < 3; ++k) {
         b.nb[k] = brick ? g.nb[k] : 1;
         b.bmax[k] = brick ? g.bmax[k] : d->L[k];
         b.wdim[k] = brick ? g.wdim[k] : 0;
@@ -745,6 +755,17 @@ int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
             hipMemsetAsync(S.dev.bstart[0], 0, (nbk + 1) * 4, c->stream) != hipSuccess ||
             hipMemsetAsync(S.dev.bstart[1], 0, (nbk + 1) * 4, c->stream) != hipSuccess)
             return undo(MPCD_EDEVICE);
+        // brick tables: brick of every cell and first cell of every brick
+        if (hipStreamSynchronize(c->stream) != hipSuccess) return undo(MPCD_EDEVICE);
+        for (int k = 0; k < 3; ++k) {
+            std::vector<uint16_t> bof((size_t)d->L[k]);
+            std::vector<int32_t> blo((size_t)g.nb[k] + 1);
+            for (int cc = 0; cc < d->L[k]; ++cc) bof[cc] = (uint16_t)brick_of(cc, d->L[k], g.nb[k]);
+            for (int i = 0; i <= g.nb[k]; ++i) blo[i] = brick_lo(i, d->L[k], g.nb[k]);
+            if (hipMemcpy(S.dev.bof[k], bof.data(), bof.size() * 2, hipMemcpyHostToDevice) != hipSuccess ||
+                hipMemcpy(S.dev.blo[k], blo.data(), blo.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+                return undo(MPCD_EDEVICE);
+        }
     }
     rc = reset_state(c, s, 0, 0);
     if (rc) return undo(rc);

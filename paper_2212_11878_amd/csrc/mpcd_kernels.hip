@@ -113,11 +113,10 @@ __global__ __launch_bounds__(kBlock) void k_brick_accumulate(const Tile* __restr
     const int brick = (int)tl.begin;
     const int bx = brick % b.nb[0], by = (brick / b.nb[0]) % b.nb[1], bz = brick / (b.nb[0] * b.nb[1]);
     const int m = b.margin;
-    const int lox = brick_lo(bx, b.L[0], b.nb[0]), loy = brick_lo(by, b.L[1], b.nb[1]),
-              loz = brick_lo(bz, b.L[2], b.nb[2]);
-    const int ex = brick_lo(bx + 1, b.L[0], b.nb[0]) - lox + 2 * m;   // window extents
-    const int ey = brick_lo(by + 1, b.L[1], b.nb[1]) - loy + 2 * m;
-    const int ez = brick_lo(bz + 1, b.L[2], b.nb[2]) - loz + 2 * m;
+    const int lox = b.blo[0][bx], loy = b.blo[1][by], loz = b.blo[2][bz];
+    const int ex = b.blo[0][bx + 1] - lox + 2 * m;   // window extents
+    const int ey = b.blo[1][by + 1] - loy + 2 * m;
+    const int ez = b.blo[2][bz + 1] - loz + 2 * m;
     const int wx = b.wdim[0], wy = b.wdim[1];
     for (int i = threadIdx.x; i < b.wsize; i += kBlock) {
         CellAcc z = {0ull, 0ull, 0ull, 0ull};
@@ -164,8 +163,7 @@ __global__ __launch_bounds__(kBlock) void k_brick_accumulate(const Tile* __restr
             atomicAdd(&b.esc[c].sy, fy);
             atomicAdd(&b.esc[c].sz, fz);
             atomicAdd(&b.esc[c].w, fw);
-            const int ob = brick_of(cx, b.L[0], b.nb[0]) +
-                           b.nb[0] * (brick_of(cy, b.L[1], b.nb[1]) + b.nb[1] * brick_of(cz, b.L[2], b.nb[2]));
+            const int ob = b.bof[0][cx] + b.nb[0] * (b.bof[1][cy] + b.nb[1] * b.bof[2][cz]);
             b.eflag[ob] = stamp;
         }
         // bucket of the streamed position for the next step
@@ -226,14 +224,17 @@ __global__ __launch_bounds__(kBlock) void k_brick_finalize(const Tile* __restric
     if (box_idle(s) || b.binning != 1) return;
     const int m = b.margin;
     const uint32_t stamp = (uint32_t)(s.k + 1);
+    const uint32_t L0 = (uint32_t)b.L[0], L01 = (uint32_t)b.L[0] * (uint32_t)b.L[1];
     for (int64_t c = tl.begin + threadIdx.x; c < tl.end; c += kBlock) {
-        const int cx = (int)(c % b.L[0]);
-        const int cy = (int)((c / b.L[0]) % b.L[1]);
-        const int cz = (int)(c / ((int64_t)b.L[0] * b.L[1]));
+        const uint32_t cu = (uint32_t)c;
+        const int cz = (int)(cu / L01);
+        const uint32_t rem = cu - (uint32_t)cz * L01;
+        const int cy = (int)(rem / L0);
+        const int cx = (int)(rem - (uint32_t)cy * L0);
         int bxs[3], lxs[3], bys[3], lys[3], bzs[3], lzs[3];
-        const int nx = windows_of(cx, b.L[0], b.nb[0], m, bxs, lxs);
-        const int ny = windows_of(cy, b.L[1], b.nb[1], m, bys, lys);
-        const int nz = windows_of(cz, b.L[2], b.nb[2], m, bzs, lzs);
+        const int nx = windows_of_tab(cx, b.L[0], b.nb[0], m, b.bof[0], b.blo[0], bxs, lxs);
+        const int ny = windows_of_tab(cy, b.L[1], b.nb[1], m, b.bof[1], b.blo[1], bys, lys);
+        const int nz = windows_of_tab(cz, b.L[2], b.nb[2], m, b.bof[2], b.blo[2], bzs, lzs);
         unsigned long long sx = 0, sy = 0, sz = 0, sw = 0;
         for (int iz = 0; iz < nz; ++iz)
             for (int iy = 0; iy < ny; ++iy)
@@ -246,8 +247,7 @@ __global__ __launch_bounds__(kBlock) void k_brick_finalize(const Tile* __restric
                     sz += r.sz;
                     sw += r.w;
                 }
-        const int ob = brick_of(cx, b.L[0], b.nb[0]) +
-                       b.nb[0] * (brick_of(cy, b.L[1], b.nb[1]) + b.nb[1] * brick_of(cz, b.L[2], b.nb[2]));
+        const int ob = b.bof[0][cx] + b.nb[0] * (b.bof[1][cy] + b.nb[1] * b.bof[2][cz]);
         if (b.eflag[ob] == stamp) {
             const CellAcc e = b.esc[c];
             if (e.w) {
@@ -290,11 +290,10 @@ __global__ __launch_bounds__(kBlock) void k_brick_rotate(const Tile* __restrict_
     const int brick = (int)tl.begin;
     const int bx = brick % b.nb[0], by = (brick / b.nb[0]) % b.nb[1], bz = brick / (b.nb[0] * b.nb[1]);
     const int m = b.margin;
-    const int lox = brick_lo(bx, b.L[0], b.nb[0]), loy = brick_lo(by, b.L[1], b.nb[1]),
-              loz = brick_lo(bz, b.L[2], b.nb[2]);
-    const int ex = brick_lo(bx + 1, b.L[0], b.nb[0]) - lox + 2 * m;
-    const int ey = brick_lo(by + 1, b.L[1], b.nb[1]) - loy + 2 * m;
-    const int ez = brick_lo(bz + 1, b.L[2], b.nb[2]) - loz + 2 * m;
+    const int lox = b.blo[0][bx], loy = b.blo[1][by], loz = b.blo[2][bz];
+    const int ex = b.blo[0][bx + 1] - lox + 2 * m;
+    const int ey = b.blo[1][by + 1] - loy + 2 * m;
+    const int ez = b.blo[2][bz + 1] - loz + 2 * m;
     const int wx = b.wdim[0], wy = b.wdim[1];
     // stage the window's cell data in LDS (cells of empty slots are never read)
     for (int i = threadIdx.x; i < b.wsize; i += kBlock) {
