@@ -232,6 +232,176 @@ int oracle_collide_given(const oracle_box* b, const double s[3], const double* a
     return collide_with_axes(b, s, axes, 0, 0, 0, N, x, y, z, vx, vy, vz, m, NULL);
 }
 
+/* ---------------------------------------------------------------------- */
+/* Angular-momentum-conserving collision (SRD+a). */
+
+void oracle_cell_local(const oracle_box* b, const double s[3], double x, double y, double z,
+                       double r[3])
+{
+    double p[3] = { x, y, z };
+    for (int d = 0; d < 3; ++d) {
+        double q = p[d] - s[d];
+        r[d] = q - b->a * floor(q / b->a);
+        if (r[d] >= b->a) r[d] -= b->a;
+        if (r[d] < 0.0) r[d] = 0.0;
+    }
+}
+
+/* Cyclic Jacobi rotations diagonalise the symmetric matrix: A = V diag(e) V^T. */
+void oracle_sym3_pinv(const double A[9], double tol, double out[9])
+{
+    double a[3][3], v[3][3] = { { 1, 0, 0 }, { 0, 1, 0 }, { 0, 0, 1 } };
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) a[i][j] = A[3 * i + j];
+    for (int sweep = 0; sweep < 50; ++sweep) {
+        double off = fabs(a[0][1]) + fabs(a[0][2]) + fabs(a[1][2]);
+        if (off < 1e-300) break;
+        for (int p = 0; p < 2; ++p)
+            for (int q = p + 1; q < 3; ++q) {
+                if (fabs(a[p][q]) < 1e-300) continue;
+                double theta = (a[q][q] - a[p][p]) / (2.0 * a[p][q]);
+                double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+                for (int k = 0; k < 3; ++k) {   /* A <- A J */
+                    double akp = a[k][p], akq = a[k][q];
+                    a[k][p] = c * akp - sn * akq;
+                    a[k][q] = sn * akp + c * akq;
+                }
+                for (int k = 0; k < 3; ++k) {   /* A <- J^T A */
+                    double apk = a[p][k], aqk = a[q][k];
+                    a[p][k] = c * apk - sn * aqk;
+                    a[q][k] = sn * apk + c * aqk;
+                }
+                for (int k = 0; k < 3; ++k) {   /* V <- V J */
+                    double vkp = v[k][p], vkq = v[k][q];
+                    v[k][p] = c * vkp - sn * vkq;
+                    v[k][q] = sn * vkp + c * vkq;
+                }
+            }
+    }
+    double e[3] = { a[0][0], a[1][1], a[2][2] };
+    double emax = fmax(fabs(e[0]), fmax(fabs(e[1]), fabs(e[2])));
+    double inv[3];
+    for (int i = 0; i < 3; ++i) inv[i] = (emax > 0 && fabs(e[i]) > tol * emax) ? 1.0 / e[i] : 0.0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double acc = 0;
+            for (int k = 0; k < 3; ++k) acc += v[i][k] * inv[k] * v[j][k];
+            out[3 * i + j] = acc;
+        }
+}
+
+static void cross3(const double a[3], const double b[3], double out[3])
+{
+    out[0] = a[1] * b[2] - a[2] * b[1];
+    out[1] = a[2] * b[0] - a[0] * b[2];
+    out[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static int collide_am_with_axes(const oracle_box* b, const double s[3], const double* axes,
+                                uint64_t seed, uint64_t k, int draw_axes, int64_t N,
+                                const double* x, const double* y, const double* z,
+                                double* vx, double* vy, double* vz, const double* m)
+{
+    int64_t C = n_cells(b);
+    double* M = (double*)calloc((size_t)C, sizeof(double));
+    double* P = (double*)calloc(3 * (size_t)C, sizeof(double));     /* sum m v */
+    double* R1 = (double*)calloc(3 * (size_t)C, sizeof(double));    /* sum m r */
+    double* R2 = (double*)calloc(9 * (size_t)C, sizeof(double));    /* sum m r r^T */
+    double* dL = (double*)calloc(3 * (size_t)C, sizeof(double));
+    double* ax = draw_axes ? (double*)malloc(sizeof(double) * 3 * (size_t)C) : NULL;
+    if (!M || !P || !R1 || !R2 || !dL || (draw_axes && !ax)) {
+        free(M); free(P); free(R1); free(R2); free(dL); free(ax);
+        return -1;
+    }
+    /* pass 1: mass, momentum, first and second moments of position */
+    for (int64_t i = 0; i < N; ++i) {
+        int64_t c = oracle_cell_of(b, s, x[i], y[i], z[i]);
+        double mi = m ? m[i] : 1.0, r[3];
+        oracle_cell_local(b, s, x[i], y[i], z[i], r);
+        M[c] += mi;
+        P[3 * c + 0] += mi * vx[i];
+        P[3 * c + 1] += mi * vy[i];
+        P[3 * c + 2] += mi * vz[i];
+        for (int d = 0; d < 3; ++d) {
+            R1[3 * c + d] += mi * r[d];
+            for (int e = 0; e < 3; ++e) R2[9 * c + 3 * d + e] += mi * r[d] * r[e];
+        }
+    }
+    if (draw_axes) {
+        for (int64_t c = 0; c < C; ++c)
+            if (M[c] > 0) oracle_axis(seed, k, (uint32_t)c, &ax[3 * c]);
+        axes = ax;
+    }
+    double ca = cos(b->alpha), sa = sin(b->alpha);
+    /* pass 2: angular momentum change of the plain rotation, per cell */
+    for (int64_t i = 0; i < N; ++i) {
+        int64_t c = oracle_cell_of(b, s, x[i], y[i], z[i]);
+        double mi = m ? m[i] : 1.0, r[3], rc[3], w[3], rw[3], dw[3], l[3];
+        oracle_cell_local(b, s, x[i], y[i], z[i], r);
+        double v[3] = { vx[i], vy[i], vz[i] };
+        for (int d = 0; d < 3; ++d) {
+            rc[d] = r[d] - R1[3 * c + d] / M[c];
+            w[d] = v[d] - P[3 * c + d] / M[c];
+        }
+        oracle_rotate(&axes[3 * c], ca, sa, w, rw);
+        for (int d = 0; d < 3; ++d) dw[d] = rw[d] - w[d];
+        cross3(rc, dw, l);
+        for (int d = 0; d < 3; ++d) dL[3 * c + d] += mi * l[d];
+    }
+    /* per cell: omega = -I^+ dL, I about the centre of mass */
+    for (int64_t c = 0; c < C; ++c) {
+        if (M[c] <= 0) continue;
+        double rcm[3] = { R1[3 * c] / M[c], R1[3 * c + 1] / M[c], R1[3 * c + 2] / M[c] };
+        double Q[9], I[9], Ip[9];
+        for (int d = 0; d < 3; ++d)
+            for (int e = 0; e < 3; ++e) Q[3 * d + e] = R2[9 * c + 3 * d + e] - M[c] * rcm[d] * rcm[e];
+        double tr = Q[0] + Q[4] + Q[8];
+        for (int d = 0; d < 3; ++d)
+            for (int e = 0; e < 3; ++e) I[3 * d + e] = (d == e ? tr : 0.0) - Q[3 * d + e];
+        oracle_sym3_pinv(I, 1e-10, Ip);
+        double om[3];
+        for (int d = 0; d < 3; ++d)
+            om[d] = -(Ip[3 * d] * dL[3 * c] + Ip[3 * d + 1] * dL[3 * c + 1] + Ip[3 * d + 2] * dL[3 * c + 2]);
+        for (int d = 0; d < 3; ++d) dL[3 * c + d] = om[d];   /* reuse for omega */
+    }
+    /* pass 3: rotated relative velocity plus the rigid-body correction */
+    for (int64_t i = 0; i < N; ++i) {
+        int64_t c = oracle_cell_of(b, s, x[i], y[i], z[i]);
+        double r[3], rc[3], w[3], rw[3], corr[3];
+        oracle_cell_local(b, s, x[i], y[i], z[i], r);
+        double v[3] = { vx[i], vy[i], vz[i] }, u[3];
+        for (int d = 0; d < 3; ++d) {
+            u[d] = P[3 * c + d] / M[c];
+            rc[d] = r[d] - R1[3 * c + d] / M[c];
+            w[d] = v[d] - u[d];
+        }
+        oracle_rotate(&axes[3 * c], ca, sa, w, rw);
+        cross3(&dL[3 * c], rc, corr);
+        vx[i] = u[0] + rw[0] + corr[0];
+        vy[i] = u[1] + rw[1] + corr[1];
+        vz[i] = u[2] + rw[2] + corr[2];
+    }
+    free(M); free(P); free(R1); free(R2); free(dL); free(ax);
+    return 0;
+}
+
+int oracle_collide_am(const oracle_box* b, uint64_t k, int64_t N,
+                      const double* x, const double* y, const double* z,
+                      double* vx, double* vy, double* vz, const double* m)
+{
+    double s[3];
+    oracle_shift(b->seed, k, b->a, s);
+    return collide_am_with_axes(b, s, NULL, b->seed, k, 1, N, x, y, z, vx, vy, vz, m);
+}
+
+int oracle_collide_am_given(const oracle_box* b, const double s[3], const double* axes, int64_t N,
+                            const double* x, const double* y, const double* z,
+                            double* vx, double* vy, double* vz, const double* m)
+{
+    return collide_am_with_axes(b, s, axes, 0, 0, 0, N, x, y, z, vx, vy, vz, m);
+}
+
 int oracle_step(const oracle_box* b, uint64_t k, int64_t N,
                 double* x, double* y, double* z, double* vx, double* vy, double* vz,
                 const double* m, int64_t* cell_out)

@@ -99,6 +99,33 @@ int oracle_collide_given(const oracle_box* b, const double s[3], const double* a
                          const double* x, const double* y, const double* z,
                          double* vx, double* vy, double* vz, const double* m);
 
+/* Angular-momentum-conserving collision of step k (the "+a" variants the
+ * paper mentions in Sec. 2; rule of Noguchi and Gompper, as reviewed in
+ * Gompper et al. 2009): after the stochastic rotation every particle of a
+ * cell gets the rigid-body velocity w x r'_i, r'_i its position relative to
+ * the cell's centre of mass, with w = -I^+ dL, I the cell's moment of inertia
+ * tensor about that centre (pseudo-inverse for collinear cells) and dL the
+ * change of the cell's angular momentum caused by the rotation.  Linear and
+ * angular momentum of every cell are conserved; kinetic energy is not.
+ * Returns 0, or -1 if memory could not be allocated. */
+int oracle_collide_am(const oracle_box* b, uint64_t k, int64_t N,
+                      const double* x, const double* y, const double* z,
+                      double* vx, double* vy, double* vz, const double* m);
+
+/* oracle_collide_am with a caller-supplied shift and per-cell axes. */
+int oracle_collide_am_given(const oracle_box* b, const double s[3], const double* axes, int64_t N,
+                            const double* x, const double* y, const double* z,
+                            double* vx, double* vy, double* vz, const double* m);
+
+/* Position of a particle relative to the lower corner of its shifted cell,
+ * each component in [0, a). */
+void oracle_cell_local(const oracle_box* b, const double s[3], double x, double y, double z,
+                       double r[3]);
+
+/* Moore-Penrose pseudo-inverse of a symmetric 3x3 matrix (row major), by
+ * Jacobi eigen-decomposition; eigenvalues below tol * (largest) count as 0. */
+void oracle_sym3_pinv(const double A[9], double tol, double out[9]);
+
 /* One full step k: streaming, then collision. */
 int oracle_step(const oracle_box* b, uint64_t k, int64_t N,
                 double* x, double* y, double* z, double* vx, double* vy, double* vz,

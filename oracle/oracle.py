@@ -68,6 +68,14 @@ def lib():
         L.oracle_collide.restype = ctypes.c_int
         L.oracle_collide_given.argtypes = [bp, _dp, _dp, ctypes.c_int64] + [_dp] * 7
         L.oracle_collide_given.restype = ctypes.c_int
+        L.oracle_collide_am.argtypes = [bp, ctypes.c_uint64, ctypes.c_int64] + [_dp] * 7
+        L.oracle_collide_am.restype = ctypes.c_int
+        L.oracle_collide_am_given.argtypes = [bp, _dp, _dp, ctypes.c_int64] + [_dp] * 7
+        L.oracle_collide_am_given.restype = ctypes.c_int
+        L.oracle_cell_local.argtypes = [bp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
+        L.oracle_cell_local.restype = None
+        L.oracle_sym3_pinv.argtypes = [_dp, ctypes.c_double, _dp]
+        L.oracle_sym3_pinv.restype = None
         L.oracle_step.argtypes = [bp, ctypes.c_uint64, ctypes.c_int64] + [_dp] * 7 + [_i64p]
         L.oracle_step.restype = ctypes.c_int
         L.oracle_run.argtypes = [bp, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64] + [_dp] * 7
@@ -192,6 +200,34 @@ def collide_given(box, s, axes, st: State):
     rc = lib().oracle_collide_given(ctypes.byref(box), _ptr(s), _ptr(axes), st.n, *st._args())
     if rc:
         raise MemoryError("oracle_collide_given")
+
+
+def collide_am(box, k, st: State):
+    rc = lib().oracle_collide_am(ctypes.byref(box), int(k), st.n, *st._args())
+    if rc:
+        raise MemoryError("oracle_collide_am")
+
+
+def collide_am_given(box, s, axes, st: State):
+    s = _f64(s)
+    axes = _f64(np.asarray(axes, dtype=np.float64).reshape(-1))
+    rc = lib().oracle_collide_am_given(ctypes.byref(box), _ptr(s), _ptr(axes), st.n, *st._args())
+    if rc:
+        raise MemoryError("oracle_collide_am_given")
+
+
+def cell_local(box, s, x, y, z):
+    s = _f64(s)
+    r = np.zeros(3)
+    lib().oracle_cell_local(ctypes.byref(box), _ptr(s), float(x), float(y), float(z), _ptr(r))
+    return r
+
+
+def sym3_pinv(A, tol=1e-10):
+    A = _f64(np.asarray(A, dtype=np.float64).reshape(9))
+    out = np.zeros(9)
+    lib().oracle_sym3_pinv(_ptr(A), float(tol), _ptr(out))
+    return out.reshape(3, 3)
 
 
 def step(box, k, st: State, want_cells=False):
