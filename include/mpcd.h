@@ -65,6 +65,13 @@ typedef enum {
 #define MPCD_INIT_EXTERNAL 0x2u  /* caller supplies the state with
                                     mpcd_set_state before the first step    */
 #define MPCD_TRACK_VACF 0x4u     /* record the velocity autocorrelation     */
+#define MPCD_CONSERVE_L 0x10u    /* angular-momentum-conserving collision
+                                    (the "+a" variant of Sec. 2): after the
+                                    rotation each cell gets the rigid-body
+                                    velocity w x r' that restores its angular
+                                    momentum about its centre of mass,
+                                    w = -I^+ dL; kinetic energy is then not
+                                    conserved.  Uses MPCD_BIN_SORT.         */
 #define MPCD_PARTICLE_MASS 0x8u  /* every particle carries its own mass
                                     (initially desc.mass; mpcd_set_mass);
                                     cell velocities are mass weighted       */

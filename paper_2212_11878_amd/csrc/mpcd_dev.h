@@ -71,6 +71,7 @@ struct BoxDev {
     int32_t vacf_stride;   // 0 = untracked
     int32_t vacf_cap;
     int32_t binning;       // MPCD_BIN_ATOMIC (bricks) or MPCD_BIN_SORT
+    int32_t conserve_l;    // 1: angular-momentum-conserving rule (SORT binning only)
     int32_t ptile0, ptile1;   // particle tiles [ptile0, ptile1)
     int32_t ctile0, ctile1;   // cell tiles [ctile0, ctile1)
     int32_t btile0, btile1;   // brick tiles [btile0, btile1)
@@ -358,6 +359,63 @@ __device__ __forceinline__ float3 rotate_about(const CellUN& c, float vx, float 
     return make_float3((float)(ux + px + ca * (wx - px) + sa * cx),
                        (float)(uy + py + ca * (wy - py) + sa * cy),
                        (float)(uz + pz + ca * (wz - pz) + sa * cz));
+}
+
+// Rotated relative velocity R w in FP64 (same rule as rotate_about).
+__device__ __forceinline__ void rotate_w(double nx, double ny, double nz, double ca, double sa,
+                                         const double w[3], double out[3])
+{
+    const double d = nx * w[0] + ny * w[1] + nz * w[2];
+    const double px = d * nx, py = d * ny, pz = d * nz;
+    out[0] = px + ca * (w[0] - px) + sa * (ny * w[2] - nz * w[1]);
+    out[1] = py + ca * (w[1] - py) + sa * (nz * w[0] - nx * w[2]);
+    out[2] = pz + ca * (w[2] - pz) + sa * (nx * w[1] - ny * w[0]);
+}
+
+// Moore-Penrose pseudo-inverse of a symmetric 3x3 matrix a[3][3] by cyclic
+// Jacobi rotations (eigenvalues below tol times the largest count as zero).
+__device__ __forceinline__ void sym3_pinv(double a[3][3], double tol, double out[3][3])
+{
+    double v[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    for (int sweep = 0; sweep < 12; ++sweep) {
+        if (fabs(a[0][1]) + fabs(a[0][2]) + fabs(a[1][2]) < 1e-300) break;
+#pragma unroll
+        for (int pq = 0; pq < 3; ++pq) {
+            const int p = pq == 2 ? 1 : 0, q = pq == 0 ? 1 : 2;
+            if (fabs(a[p][q]) < 1e-300) continue;
+            const double th = (a[q][q] - a[p][p]) / (2.0 * a[p][q]);
+            const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+            const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const double akp = a[k][p], akq = a[k][q];
+                a[k][p] = c * akp - sn * akq;
+                a[k][q] = sn * akp + c * akq;
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const double apk = a[p][k], aqk = a[q][k];
+                a[p][k] = c * apk - sn * aqk;
+                a[q][k] = sn * apk + c * aqk;
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const double vkp = v[k][p], vkq = v[k][q];
+                v[k][p] = c * vkp - sn * vkq;
+                v[k][q] = sn * vkp + c * vkq;
+            }
+        }
+    }
+    const double e0 = a[0][0], e1 = a[1][1], e2 = a[2][2];
+    const double emax = fmax(fabs(e0), fmax(fabs(e1), fabs(e2)));
+    const double i0 = (emax > 0 && fabs(e0) > tol * emax) ? 1.0 / e0 : 0.0;
+    const double i1 = (emax > 0 && fabs(e1) > tol * emax) ? 1.0 / e1 : 0.0;
+    const double i2 = (emax > 0 && fabs(e2) > tol * emax) ? 1.0 / e2 : 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            out[i][j] = v[i][0] * i0 * v[j][0] + v[i][1] * i1 * v[j][1] + v[i][2] * i2 * v[j][2];
 }
 
 // Exact diagnostics: per-particle terms in 64-bit fixed point (quantum 2^-32)

@@ -185,7 +185,8 @@ int validate_desc(const mpcd_box_desc* d)
     if (!isfinite(d->alpha)) return MPCD_EINVAL;
     if (!(d->mass > 0.0) || !isfinite(d->mass)) return MPCD_EINVAL;
     if (d->n_steps < 0) return MPCD_EINVAL;
-    if (d->flags & ~(MPCD_INIT_MAXWELL | MPCD_INIT_EXTERNAL | MPCD_TRACK_VACF | MPCD_PARTICLE_MASS))
+    if (d->flags & ~(MPCD_INIT_MAXWELL | MPCD_INIT_EXTERNAL | MPCD_TRACK_VACF | MPCD_PARTICLE_MASS |
+                     MPCD_CONSERVE_L))
         return MPCD_EINVAL;
     const uint32_t init = d->flags & (MPCD_INIT_MAXWELL | MPCD_INIT_EXTERNAL);
     if (init != MPCD_INIT_MAXWELL && init != MPCD_INIT_EXTERNAL) return MPCD_EINVAL;
@@ -663,7 +664,9 @@ int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
     const int cap = vacf_capacity(d);
     int32_t binning = c->binning;
     int32_t want[3] = {c->brick[0], c->brick[1], c->brick[2]};
-    if (binning == MPCD_BIN_AUTO) {
+    if (d->flags & MPCD_CONSERVE_L) {
+        binning = MPCD_BIN_SORT;   // the per-cell moments need whole cells in one thread
+    } else if (binning == MPCD_BIN_AUTO) {
         rc = autotune(c, d, &binning, want);
         if (rc) return rc;
     }
@@ -722,6 +725,7 @@ int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
     b.vacf_stride = vacf ? d->vacf_stride : 0;
     b.vacf_cap = cap;
     b.binning = binning;
+    b.conserve_l = (d->flags & MPCD_CONSERVE_L) ? 1 : 0;
     b.a = (float)d->a;
     b.inv_a = (float)(1.0 / d->a);
     b.dt = (float)d->dt;

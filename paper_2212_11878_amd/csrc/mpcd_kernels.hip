@@ -605,6 +605,124 @@ __global__ void k_flip(const int32_t* __restrict__ active, int nactive,
     s.rebucket = 0;
 }
 
+// Angular-momentum-conserving collision of one cell whose particles occupy
+// [beg, end) of the current buffer (streamed, SORT binning): the plain
+// rotation followed by the rigid-body velocity omega x r' that restores the
+// cell's angular momentum about its centre of mass, omega = -I^+ dL.  All
+// cell sums are exact fixed point (independent of particle order); the
+// per-cell algebra is FP64.
+__device__ __forceinline__ void collide_cell_am(const BoxDev& b, int par, long long k, uint32_t c,
+                                                uint32_t beg, uint32_t end, float3 sh, double ca,
+                                                double sa, long long (&d)[kNumDiag], bool vacf)
+{
+    const float* __restrict__ px = b.p[par][0];
+    const float* __restrict__ py = b.p[par][1];
+    const float* __restrict__ pz = b.p[par][2];
+    float* __restrict__ vx = b.p[par][3];
+    float* __restrict__ vy = b.p[par][4];
+    float* __restrict__ vz = b.p[par][5];
+    const float* __restrict__ mp = b.m[par];
+    const double a = b.a;
+    // position inside the shifted cell, each component in [0, a)
+    auto local = [&](uint32_t j, double r[3]) {
+        const double q[3] = {(double)px[j] - sh.x, (double)py[j] - sh.y, (double)pz[j] - sh.z};
+#pragma unroll
+        for (int e = 0; e < 3; ++e) r[e] = q[e] - a * floor(q[e] / a);
+    };
+    // pass 1: mass, momentum, first and second position moments
+    long long sw = 0, sv[3] = {0, 0, 0}, s1[3] = {0, 0, 0}, s2[6] = {0, 0, 0, 0, 0, 0};
+    for (uint32_t j = beg; j < end; ++j) {
+        const double mj = mass_of(mp, j);
+        double r[3];
+        local(j, r);
+        sw += fixed_term(mj);
+        sv[0] += fixed_term(mj * vx[j]);
+        sv[1] += fixed_term(mj * vy[j]);
+        sv[2] += fixed_term(mj * vz[j]);
+#pragma unroll
+        for (int e = 0; e < 3; ++e) s1[e] += fixed_term(mj * r[e]);
+        s2[0] += fixed_term(mj * r[0] * r[0]);
+        s2[1] += fixed_term(mj * r[0] * r[1]);
+        s2[2] += fixed_term(mj * r[0] * r[2]);
+        s2[3] += fixed_term(mj * r[1] * r[1]);
+        s2[4] += fixed_term(mj * r[1] * r[2]);
+        s2[5] += fixed_term(mj * r[2] * r[2]);
+    }
+    const double M = fixed_to_double((unsigned long long)sw);
+    double u[3], rc[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        u[e] = fixed_to_double((unsigned long long)sv[e]) / M;
+        rc[e] = fixed_to_double((unsigned long long)s1[e]) / M;
+    }
+    // sums are in units of 2^-32: Mt is the true mass; u and rc are ratios
+    const double k2 = 2.3283064365386963e-10;
+    const double Mt = M * k2;
+    double Q[3][3];   // second moment of position about the centre of mass
+    Q[0][0] = fixed_to_double((unsigned long long)s2[0]) * k2 - Mt * rc[0] * rc[0];
+    Q[0][1] = fixed_to_double((unsigned long long)s2[1]) * k2 - Mt * rc[0] * rc[1];
+    Q[0][2] = fixed_to_double((unsigned long long)s2[2]) * k2 - Mt * rc[0] * rc[2];
+    Q[1][1] = fixed_to_double((unsigned long long)s2[3]) * k2 - Mt * rc[1] * rc[1];
+    Q[1][2] = fixed_to_double((unsigned long long)s2[4]) * k2 - Mt * rc[1] * rc[2];
+    Q[2][2] = fixed_to_double((unsigned long long)s2[5]) * k2 - Mt * rc[2] * rc[2];
+    Q[1][0] = Q[0][1];
+    Q[2][0] = Q[0][2];
+    Q[2][1] = Q[1][2];
+    const float3 ax = cell_axis(b, k, c);
+    double nx = ax.x, ny = ax.y, nz = ax.z;
+    const double inv = 1.0 / sqrt(nx * nx + ny * ny + nz * nz);
+    nx *= inv;
+    ny *= inv;
+    nz *= inv;
+    // pass 2: change of the cell's angular momentum under the plain rotation
+    long long sl[3] = {0, 0, 0};
+    for (uint32_t j = beg; j < end; ++j) {
+        const double mj = mass_of(mp, j);
+        double r[3], w[3], rw[3];
+        local(j, r);
+        w[0] = (double)vx[j] - u[0];
+        w[1] = (double)vy[j] - u[1];
+        w[2] = (double)vz[j] - u[2];
+        rotate_w(nx, ny, nz, ca, sa, w, rw);
+        const double rp[3] = {r[0] - rc[0], r[1] - rc[1], r[2] - rc[2]};
+        const double dw[3] = {rw[0] - w[0], rw[1] - w[1], rw[2] - w[2]};
+        sl[0] += fixed_term(mj * (rp[1] * dw[2] - rp[2] * dw[1]));
+        sl[1] += fixed_term(mj * (rp[2] * dw[0] - rp[0] * dw[2]));
+        sl[2] += fixed_term(mj * (rp[0] * dw[1] - rp[1] * dw[0]));
+    }
+    const double dL[3] = {fixed_to_double((unsigned long long)sl[0]) * k2,
+                          fixed_to_double((unsigned long long)sl[1]) * k2,
+                          fixed_to_double((unsigned long long)sl[2]) * k2};
+    double I[3][3], Ip[3][3];
+    const double tr = Q[0][0] + Q[1][1] + Q[2][2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) I[i][j] = (i == j ? tr : 0.0) - Q[i][j];
+    sym3_pinv(I, 1e-10, Ip);
+    double om[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) om[i] = -(Ip[i][0] * dL[0] + Ip[i][1] * dL[1] + Ip[i][2] * dL[2]);
+    // pass 3: rotated relative velocity plus the rigid-body correction
+    for (uint32_t j = beg; j < end; ++j) {
+        double r[3], w[3], rw[3];
+        local(j, r);
+        w[0] = (double)vx[j] - u[0];
+        w[1] = (double)vy[j] - u[1];
+        w[2] = (double)vz[j] - u[2];
+        rotate_w(nx, ny, nz, ca, sa, w, rw);
+        const double rp[3] = {r[0] - rc[0], r[1] - rc[1], r[2] - rc[2]};
+        const float3 v = make_float3((float)(u[0] + rw[0] + (om[1] * rp[2] - om[2] * rp[1])),
+                                     (float)(u[1] + rw[1] + (om[2] * rp[0] - om[0] * rp[2])),
+                                     (float)(u[2] + rw[2] + (om[0] * rp[1] - om[1] * rp[0])));
+        if (vacf) diag_vacf(d, v, b.v0[par][0][j], b.v0[par][1][j], b.v0[par][2][j]);
+        vx[j] = v.x;
+        vy[j] = v.y;
+        vz[j] = v.z;
+        diag_particle(d, v, mass_of(mp, j));
+    }
+}
+
 // SORT path: particles of cell c occupy [cstart[c], cstart[c+1]) in the
 // current buffer, already streamed.  One thread per cell.
 __global__ __launch_bounds__(kBlock) void k_cell_rotate(const Tile* __restrict__ tiles,
@@ -627,6 +745,15 @@ __global__ __launch_bounds__(kBlock) void k_cell_rotate(const Tile* __restrict__
     const float* __restrict__ mp = b.m[s.parity];
     const double ca = b.ca, sa = b.sa;
     long long d[kNumDiag] = {0, 0, 0, 0, 0, 0};
+    if (b.conserve_l) {
+        const float3 sh = grid_shift(b, s.k);
+        for (int64_t c = tl.begin + threadIdx.x; c < tl.end; c += kBlock) {
+            const uint32_t beg = b.cstart[c], end = b.cstart[c + 1];
+            if (beg != end) collide_cell_am(b, s.parity, s.k, (uint32_t)c, beg, end, sh, ca, sa, d, vacf);
+        }
+        block_diag(d, partials + (size_t)t * kNumDiag);
+        return;
+    }
     for (int64_t c = tl.begin + threadIdx.x; c < tl.end; c += kBlock) {
         const uint32_t beg = b.cstart[c], end = b.cstart[c + 1];
         if (beg == end) continue;

@@ -26,6 +26,7 @@ MPCD_INIT_MAXWELL = 0x1
 MPCD_INIT_EXTERNAL = 0x2
 MPCD_TRACK_VACF = 0x4
 MPCD_PARTICLE_MASS = 0x8
+MPCD_CONSERVE_L = 0x10
 
 MPCD_BIN_AUTO = 0
 MPCD_BIN_ATOMIC = 1
@@ -242,7 +243,7 @@ class _TorchAllocator:
 
 def make_desc(L, n_particles, dt=0.1, alpha_deg=130.0, seed=1, a=1.0, kT=1.0, mass=1.0,
               n_steps=0, init="maxwell", vacf_stride=0, vacf_capacity=0, alpha_rad=None,
-              particle_mass=False):
+              particle_mass=False, conserve_l=False):
     d = mpcd_box_desc()
     if isinstance(L, int):
         L = (L, L, L)
@@ -259,6 +260,8 @@ def make_desc(L, n_particles, dt=0.1, alpha_deg=130.0, seed=1, a=1.0, kT=1.0, ma
     d.flags = MPCD_INIT_MAXWELL if init == "maxwell" else MPCD_INIT_EXTERNAL
     if particle_mass:
         d.flags |= MPCD_PARTICLE_MASS
+    if conserve_l:
+        d.flags |= MPCD_CONSERVE_L
     if vacf_stride:
         d.flags |= MPCD_TRACK_VACF
         d.vacf_stride = int(vacf_stride)
