@@ -8,6 +8,27 @@
 
 namespace mpcd {
 
+// Pointers into device memory are read from the box table, so the compiler
+// cannot infer their address space and would emit flat (generic) memory
+// instructions; casting them to the global address space gives global_*
+// loads, stores and atomics (flat ones also occupy the LDS counter).
+#define MPCD_G __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ MPCD_G T* gp(T* p)
+{
+    return (MPCD_G T*)p;
+}
+template <class T>
+__device__ __forceinline__ const MPCD_G T* gp(const T* p)
+{
+    return (const MPCD_G T*)p;
+}
+template <class T>
+__device__ __forceinline__ T gatomic_add(MPCD_G T* p, T v)
+{
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 constexpr int kWave = 64;
 constexpr int kBlock = 256;          // threads per workgroup of the particle kernels
 constexpr int kPartTile = 4096;      // particles per particle tile (16 per thread)
@@ -23,9 +44,11 @@ struct alignas(32) CellAcc {
     unsigned long long w;
 };
 
-// Per-cell collision data: centre-of-mass velocity and rotation axis.
+// Per-cell collision data: centre-of-mass velocity, rotation axis n (FP32,
+// |n| = 1 only to rounding) and kappa = 1/|n|^2 - 1 (from FP64), which lets
+// the rotation use the exactly normalised axis without a square root.
 struct alignas(32) CellUN {
-    float ux, uy, uz, nx, ny, nz, pad0, pad1;
+    float ux, uy, uz, nx, ny, nz, kappa, pad1;
 };
 
 // Read-only description of one box, resident in device memory.  Particle
@@ -94,6 +117,49 @@ struct BoxState {
     int rebucket;          // brick mode: particles not yet in brick buckets
     double diag[4];        // sum v (3), sum v^2 after the last step (exact sums, rounded once)
 };
+
+// Record copies to and from global memory as native vectors (struct
+// assignment is not defined across address spaces).
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void store_acc(MPCD_G CellAcc* p, const CellAcc& a)
+{
+    MPCD_G u64x2* q = (MPCD_G u64x2*)p;
+    u64x2 lo, hi;
+    lo.x = a.sx; lo.y = a.sy; hi.x = a.sz; hi.y = a.w;
+    q[0] = lo;
+    q[1] = hi;
+}
+
+__device__ __forceinline__ CellAcc load_acc(const MPCD_G CellAcc* p)
+{
+    const MPCD_G u64x2* q = (const MPCD_G u64x2*)p;
+    const u64x2 lo = q[0], hi = q[1];
+    CellAcc a;
+    a.sx = lo.x; a.sy = lo.y; a.sz = hi.x; a.w = hi.y;
+    return a;
+}
+
+__device__ __forceinline__ void store_un(MPCD_G CellUN* p, const CellUN& u)
+{
+    MPCD_G f32x4* q = (MPCD_G f32x4*)p;
+    f32x4 a, b;
+    a.x = u.ux; a.y = u.uy; a.z = u.uz; a.w = u.nx;
+    b.x = u.ny; b.y = u.nz; b.z = u.kappa; b.w = u.pad1;
+    q[0] = a;
+    q[1] = b;
+}
+
+__device__ __forceinline__ CellUN load_un(const MPCD_G CellUN* p)
+{
+    const MPCD_G f32x4* q = (const MPCD_G f32x4*)p;
+    const f32x4 a = q[0], b = q[1];
+    CellUN u;
+    u.ux = a.x; u.uy = a.y; u.uz = a.z; u.nx = a.w;
+    u.ny = b.x; u.nz = b.y; u.kappa = b.z; u.pad1 = b.w;
+    return u;
+}
 
 // A contiguous range of one box's particles or cells.
 struct Tile {
@@ -334,31 +400,37 @@ __device__ __forceinline__ float mass_of(const float* __restrict__ m, int64_t i)
     return m ? m[i] : 1.0f;
 }
 
-// v' = u + (n.w) n + cos(a) (w - (n.w) n) + sin(a) (n x w), w = v - u: the
-// component along the axis is kept, the perpendicular one turned by a.
-// Evaluated in FP64 from the FP32 inputs with the axis renormalised in FP64,
-// then rounded once to FP32: FP32 evaluation leaves a systematic bias of a
-// few 1e-8 per step in the kinetic energy (unit-norm and cos^2 + sin^2
-// rounding), which this removes; the kernel is bound by memory traffic, so
-// the FP64 arithmetic costs no time.
+// 1/|n|^2 - 1 of an FP32 axis, from FP64 (a few 1e-8).
+__device__ __forceinline__ float axis_kappa(float3 n)
+{
+    const double nn = (double)n.x * n.x + (double)n.y * n.y + (double)n.z * n.z;
+    return (float)(1.0 / nn - 1.0);
+}
+
+// v' = u + (n.w) n + cos(a) (w - (n.w) n) + sin(a) (n x w), w = v - u, with
+// n the unit axis: the component along the axis is kept, the perpendicular
+// one turned by a.  Evaluated in FP64 from the FP32 inputs (the stored axis is
+// normalised through kappa: n n^T/|n|^2 = (1 + kappa) n n^T and
+// n/|n| = (1 + kappa/2) n to O(kappa^2) ~ 1e-15), then rounded once to FP32.
+// FP32 evaluation would leave a systematic kinetic-energy bias of a few 1e-8
+// per step (unit-norm and cos^2 + sin^2 rounding); the kernels are bound by
+// memory traffic, so the FP64 arithmetic costs no time.
 __device__ __forceinline__ float3 rotate_about(const CellUN& c, float vx, float vy, float vz,
                                                double ca, double sa)
 {
-    double nx = c.nx, ny = c.ny, nz = c.nz;
-    const double inv = 1.0 / sqrt(nx * nx + ny * ny + nz * nz);
-    nx *= inv;
-    ny *= inv;
-    nz *= inv;
+    const double nx = c.nx, ny = c.ny, nz = c.nz;
+    const double kp = 1.0 + (double)c.kappa, kc = 1.0 + 0.5 * (double)c.kappa;
     const double ux = c.ux, uy = c.uy, uz = c.uz;
     const double wx = (double)vx - ux, wy = (double)vy - uy, wz = (double)vz - uz;
-    const double d = nx * wx + ny * wy + nz * wz;
+    const double d = (nx * wx + ny * wy + nz * wz) * kp;
     const double px = d * nx, py = d * ny, pz = d * nz;
+    const double s = sa * kc;
     const double cx = ny * wz - nz * wy;
     const double cy = nz * wx - nx * wz;
     const double cz = nx * wy - ny * wx;
-    return make_float3((float)(ux + px + ca * (wx - px) + sa * cx),
-                       (float)(uy + py + ca * (wy - py) + sa * cy),
-                       (float)(uz + pz + ca * (wz - pz) + sa * cz));
+    return make_float3((float)(ux + px + ca * (wx - px) + s * cx),
+                       (float)(uy + py + ca * (wy - py) + s * cy),
+                       (float)(uz + pz + ca * (wz - pz) + s * cz));
 }
 
 // Rotated relative velocity R w in FP64 (same rule as rotate_about).

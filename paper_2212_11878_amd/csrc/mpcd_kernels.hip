@@ -126,13 +126,15 @@ __global__ __launch_bounds__(kBlock) void k_brick_accumulate(const Tile* __restr
     __syncthreads();
 
     const int par = s.parity;
-    const float* __restrict__ x = b.p[par][0];
-    const float* __restrict__ y = b.p[par][1];
-    const float* __restrict__ z = b.p[par][2];
-    const float* __restrict__ vx = b.p[par][3];
-    const float* __restrict__ vy = b.p[par][4];
-    const float* __restrict__ vz = b.p[par][5];
+    const MPCD_G float* __restrict__ x = gp(b.p[par][0]);
+    const MPCD_G float* __restrict__ y = gp(b.p[par][1]);
+    const MPCD_G float* __restrict__ z = gp(b.p[par][2]);
+    const MPCD_G float* __restrict__ vx = gp(b.p[par][3]);
+    const MPCD_G float* __restrict__ vy = gp(b.p[par][4]);
+    const MPCD_G float* __restrict__ vz = gp(b.p[par][5]);
     const float* __restrict__ mp = b.m[par];
+    MPCD_G CellAcc* __restrict__ esc = gp(b.esc);
+    MPCD_G uint32_t* __restrict__ bcount = gp(b.bcount);
     const float3 sh = grid_shift(b, s.k);
     const float dt = b.dt;
     const uint32_t stamp = (uint32_t)(s.k + 1);
@@ -148,7 +150,7 @@ __global__ __launch_bounds__(kBlock) void k_brick_accumulate(const Tile* __restr
         const int lx = window_offset(cx, lox, m, b.L[0]);
         const int ly = window_offset(cy, loy, m, b.L[1]);
         const int lz = window_offset(cz, loz, m, b.L[2]);
-        const float mi = mass_of(mp, i);
+        const float mi = mp ? gp(mp)[i] : 1.0f;
         const unsigned long long fx = to_fixed(mi * ux), fy = to_fixed(mi * uy), fz = to_fixed(mi * uz);
         const unsigned long long fw = to_fixed(mi);
         if (lx < ex && ly < ey && lz < ez) {
@@ -159,12 +161,12 @@ __global__ __launch_bounds__(kBlock) void k_brick_accumulate(const Tile* __restr
             atomicAdd(&w->w, fw);
         } else {   // left the window: exact global sums, flag the owner brick
             const uint32_t c = (uint32_t)cx + (uint32_t)b.L[0] * ((uint32_t)cy + (uint32_t)b.L[1] * (uint32_t)cz);
-            atomicAdd(&b.esc[c].sx, fx);
-            atomicAdd(&b.esc[c].sy, fy);
-            atomicAdd(&b.esc[c].sz, fz);
-            atomicAdd(&b.esc[c].w, fw);
+            gatomic_add(&esc[c].sx, fx);
+            gatomic_add(&esc[c].sy, fy);
+            gatomic_add(&esc[c].sz, fz);
+            gatomic_add(&esc[c].w, fw);
             const int ob = b.bof[0][cx] + b.nb[0] * (b.bof[1][cy] + b.nb[1] * b.bof[2][cz]);
-            b.eflag[ob] = stamp;
+            gp(b.eflag)[ob] = stamp;
         }
         // bucket of the streamed position for the next step
         const int3 d = brick_of_pos(b, px, py, pz);
@@ -173,17 +175,17 @@ __global__ __launch_bounds__(kBlock) void k_brick_accumulate(const Tile* __restr
         if (rx <= 1 && ry <= 1 && rz <= 1)
             atomicAdd(&cnt[(rx + 1) + 3 * ((ry + 1) + 3 * (rz + 1))], 1u);
         else
-            atomicAdd(&b.bcount[d.x + b.nb[0] * (d.y + b.nb[1] * d.z)], 1u);
+            gatomic_add(&bcount[d.x + b.nb[0] * (d.y + b.nb[1] * d.z)], 1u);
     }
     __syncthreads();
-    CellAcc* __restrict__ out = b.part + (size_t)brick * b.wsize;
-    for (int i = threadIdx.x; i < b.wsize; i += kBlock) out[i] = win[i];
+    MPCD_G CellAcc* __restrict__ out = gp(b.part) + (size_t)brick * b.wsize;
+    for (int i = threadIdx.x; i < b.wsize; i += kBlock) store_acc(out + i, win[i]);
     if (threadIdx.x < 27 && cnt[threadIdx.x] != 0u) {
         const int r = threadIdx.x;
         const int dx = (bx + (r % 3) - 1 + b.nb[0]) % b.nb[0];
         const int dy = (by + (r / 3) % 3 - 1 + b.nb[1]) % b.nb[1];
         const int dz = (bz + r / 9 - 1 + b.nb[2]) % b.nb[2];
-        atomicAdd(&b.bcount[dx + b.nb[0] * (dy + b.nb[1] * dz)], cnt[r]);
+        gatomic_add(&bcount[dx + b.nb[0] * (dy + b.nb[1] * dz)], cnt[r]);
     }
 }
 
@@ -241,22 +243,22 @@ __global__ __launch_bounds__(kBlock) void k_brick_finalize(const Tile* __restric
                 for (int ix = 0; ix < nx; ++ix) {
                     const int br = bxs[ix] + b.nb[0] * (bys[iy] + b.nb[1] * bzs[iz]);
                     const int sl = lxs[ix] + b.wdim[0] * (lys[iy] + b.wdim[1] * lzs[iz]);
-                    const CellAcc r = b.part[(size_t)br * b.wsize + sl];
+                    const CellAcc r = load_acc(gp(b.part) + (size_t)br * b.wsize + sl);
                     sx += r.sx;
                     sy += r.sy;
                     sz += r.sz;
                     sw += r.w;
                 }
         const int ob = b.bof[0][cx] + b.nb[0] * (b.bof[1][cy] + b.nb[1] * b.bof[2][cz]);
-        if (b.eflag[ob] == stamp) {
-            const CellAcc e = b.esc[c];
+        if (gp(b.eflag)[ob] == stamp) {
+            const CellAcc e = load_acc(gp(b.esc) + c);
             if (e.w) {
                 sx += e.sx;
                 sy += e.sy;
                 sz += e.sz;
                 sw += e.w;
                 CellAcc zero = {0ull, 0ull, 0ull, 0ull};
-                b.esc[c] = zero;
+                store_acc(gp(b.esc) + c, zero);
             }
         }
         if (sw == 0) continue;
@@ -268,9 +270,9 @@ __global__ __launch_bounds__(kBlock) void k_brick_finalize(const Tile* __restric
         u.nx = ax.x;
         u.ny = ax.y;
         u.nz = ax.z;
-        u.pad0 = 0.0f;
+        u.kappa = axis_kappa(ax);
         u.pad1 = 0.0f;
-        b.un[c] = u;
+        store_un(gp(b.un) + c, u);
     }
 }
 
@@ -303,7 +305,7 @@ __global__ __launch_bounds__(kBlock) void k_brick_rotate(const Tile* __restrict_
             cx = ((cx % b.L[0]) + b.L[0]) % b.L[0];
             cy = ((cy % b.L[1]) + b.L[1]) % b.L[1];
             cz = ((cz % b.L[2]) + b.L[2]) % b.L[2];
-            wun[i] = b.un[(uint32_t)cx + (uint32_t)b.L[0] * ((uint32_t)cy + (uint32_t)b.L[1] * (uint32_t)cz)];
+            wun[i] = load_un(gp(b.un) + ((uint32_t)cx + (uint32_t)b.L[0] * ((uint32_t)cy + (uint32_t)b.L[1] * (uint32_t)cz)));
         }
     }
     __syncthreads();
@@ -314,23 +316,24 @@ __global__ __launch_bounds__(kBlock) void k_brick_rotate(const Tile* __restrict_
     const bool track = b.vacf_stride > 0;
     const bool vacf = vacf_due(b, s);
     const int64_t beg = b.bstart[src][brick], end = b.bstart[src][brick + 1];
-    const float* __restrict__ ix = b.p[src][0];
-    const float* __restrict__ iy = b.p[src][1];
-    const float* __restrict__ iz = b.p[src][2];
-    const float* __restrict__ ivx = b.p[src][3];
-    const float* __restrict__ ivy = b.p[src][4];
-    const float* __restrict__ ivz = b.p[src][5];
-    const int32_t* __restrict__ iid = b.pid[src];
-    float* __restrict__ ox = b.p[dst][0];
-    float* __restrict__ oy = b.p[dst][1];
-    float* __restrict__ oz = b.p[dst][2];
-    float* __restrict__ ovx = b.p[dst][3];
-    float* __restrict__ ovy = b.p[dst][4];
-    float* __restrict__ ovz = b.p[dst][5];
-    int32_t* __restrict__ oid = b.pid[dst];
-    const float* __restrict__ im = b.m[src];
-    float* __restrict__ om = b.m[dst];
-    const CellUN* __restrict__ un = b.un;
+    const MPCD_G float* __restrict__ ix = gp(b.p[src][0]);
+    const MPCD_G float* __restrict__ iy = gp(b.p[src][1]);
+    const MPCD_G float* __restrict__ iz = gp(b.p[src][2]);
+    const MPCD_G float* __restrict__ ivx = gp(b.p[src][3]);
+    const MPCD_G float* __restrict__ ivy = gp(b.p[src][4]);
+    const MPCD_G float* __restrict__ ivz = gp(b.p[src][5]);
+    const MPCD_G int32_t* __restrict__ iid = gp(b.pid[src]);
+    MPCD_G float* __restrict__ ox = gp(b.p[dst][0]);
+    MPCD_G float* __restrict__ oy = gp(b.p[dst][1]);
+    MPCD_G float* __restrict__ oz = gp(b.p[dst][2]);
+    MPCD_G float* __restrict__ ovx = gp(b.p[dst][3]);
+    MPCD_G float* __restrict__ ovy = gp(b.p[dst][4]);
+    MPCD_G float* __restrict__ ovz = gp(b.p[dst][5]);
+    MPCD_G int32_t* __restrict__ oid = gp(b.pid[dst]);
+    const MPCD_G float* __restrict__ im = b.m[src] ? gp(b.m[src]) : nullptr;
+    MPCD_G float* __restrict__ om = b.m[dst] ? gp(b.m[dst]) : nullptr;
+    const MPCD_G CellUN* __restrict__ un = gp(b.un);
+    MPCD_G uint32_t* __restrict__ bcursor = gp(b.bcursor);
     long long d[kNumDiag] = {0, 0, 0, 0, 0, 0};
     constexpr int kChunk = kBlock * kItems;
     for (int64_t c0 = beg; c0 < end; c0 += kChunk) {
@@ -356,15 +359,17 @@ __global__ __launch_bounds__(kBlock) void k_brick_rotate(const Tile* __restrict_
                 const int lx = window_offset(cx, lox, m, b.L[0]);
                 const int ly = window_offset(cy, loy, m, b.L[1]);
                 const int lz = window_offset(cz, loz, m, b.L[2]);
-                const CellUN u = (lx < ex && ly < ey && lz < ez)
-                    ? wun[lx + wx * (ly + wy * lz)]
-                    : un[(uint32_t)cx + (uint32_t)b.L[0] * ((uint32_t)cy + (uint32_t)b.L[1] * (uint32_t)cz)];
+                CellUN u;
+                if (lx < ex && ly < ey && lz < ez)
+                    u = wun[lx + wx * (ly + wy * lz)];
+                else
+                    u = load_un(un + ((uint32_t)cx + (uint32_t)b.L[0] * ((uint32_t)cy + (uint32_t)b.L[1] * (uint32_t)cz)));
                 const float3 v = rotate_about(u, ux, uy, uz, ca, sa);
                 qx[it] = v.x;
                 qy[it] = v.y;
                 qz[it] = v.z;
-                diag_particle(d, v, mass_of(im, i));
-                if (vacf) diag_vacf(d, v, b.v0[src][0][i], b.v0[src][1][i], b.v0[src][2][i]);
+                diag_particle(d, v, im ? im[i] : 1.0f);
+                if (vacf) diag_vacf(d, v, gp(b.v0[src][0])[i], gp(b.v0[src][1])[i], gp(b.v0[src][2])[i]);
                 const int3 db = brick_of_pos(b, px[it], py[it], pz[it]);
                 const int rx = brick_rel(bx, db.x, b.nb[0]), ry = brick_rel(by, db.y, b.nb[1]),
                           rz = brick_rel(bz, db.z, b.nb[2]);
@@ -372,7 +377,7 @@ __global__ __launch_bounds__(kBlock) void k_brick_rotate(const Tile* __restrict_
                     rel[it] = (rx + 1) + 3 * ((ry + 1) + 3 * (rz + 1));
                 } else {
                     rel[it] = 27;
-                    slot[it] = atomicAdd(&b.bcursor[db.x + b.nb[0] * (db.y + b.nb[1] * db.z)], 1u);
+                    slot[it] = gatomic_add(&bcursor[db.x + b.nb[0] * (db.y + b.nb[1] * db.z)], 1u);
                 }
             }
             // ranks in the bucket ranges; particles that stay in this brick
@@ -396,7 +401,7 @@ __global__ __launch_bounds__(kBlock) void k_brick_rotate(const Tile* __restrict_
             const int dx = (bx + (r % 3) - 1 + b.nb[0]) % b.nb[0];
             const int dy = (by + (r / 3) % 3 - 1 + b.nb[1]) % b.nb[1];
             const int dz = (bz + r / 9 - 1 + b.nb[2]) % b.nb[2];
-            base[r] = atomicAdd(&b.bcursor[dx + b.nb[0] * (dy + b.nb[1] * dz)], cnt[r]);
+            base[r] = gatomic_add(&bcursor[dx + b.nb[0] * (dy + b.nb[1] * dz)], cnt[r]);
         }
         __syncthreads();
 #pragma unroll
@@ -413,9 +418,9 @@ __global__ __launch_bounds__(kBlock) void k_brick_rotate(const Tile* __restrict_
             oid[j] = id[it];
             if (om) om[j] = im[i];
             if (track) {
-                b.v0[dst][0][j] = b.v0[src][0][i];
-                b.v0[dst][1][j] = b.v0[src][1][i];
-                b.v0[dst][2][j] = b.v0[src][2][i];
+                gp(b.v0[dst][0])[j] = gp(b.v0[src][0])[i];
+                gp(b.v0[dst][1])[j] = gp(b.v0[src][1])[i];
+                gp(b.v0[dst][2])[j] = gp(b.v0[src][2])[i];
             }
         }
         __syncthreads();
@@ -773,6 +778,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_rotate(const Tile* __restrict__
         u.nx = ax.x;
         u.ny = ax.y;
         u.nz = ax.z;
+        u.kappa = axis_kappa(ax);
         for (uint32_t j = beg; j < end; ++j) {
             const float3 v = rotate_about(u, vx[j], vy[j], vz[j], ca, sa);
             vx[j] = v.x;
