@@ -77,8 +77,11 @@ struct BoxDev {
     CellAcc* esc;          // brick mode: per cell, sums of escaped particles
     uint32_t* eflag;       // brick mode: per brick, k+1 when esc holds data for it
     uint32_t* bstart[2];   // brick mode: bucket starts of each buffer (nbrick + 1)
-    uint32_t* bcount;      // brick mode: particles bound for each bucket next step
-    uint32_t* bcursor;     // brick mode: write cursors of the next buckets
+    uint32_t* bcount;      // brick mode: particles bound for each bucket from farther than a neighbour
+    uint32_t* bcursor;     // brick mode: write cursors of those far particles (end of each bucket)
+    uint32_t* outcnt;      // brick mode: [brick][27] particles going to each neighbouring bucket
+    uint32_t* outbase;     // brick mode: [brick][27] where they start in that bucket
+    uint32_t* bsize;       // brick mode: particles of each bucket next step
     uint16_t* bof[3];      // brick mode: brick index of each cell, per dimension (L_d entries)
     int32_t* blo[3];       // brick mode: first cell of each brick, per dimension (nb_d + 1 entries)
     double* vacf;          // VACF samples
@@ -266,6 +269,19 @@ __device__ __forceinline__ int3 brick_of_pos(const BoxDev& b, float x, float y, 
     const int cy = axis_cell(y, 0.0f, b.inv_a, b.L[1]);
     const int cz = axis_cell(z, 0.0f, b.inv_a, b.L[2]);
     return make_int3(b.bof[0][cx], b.bof[1][cy], b.bof[2][cz]);
+}
+
+// Neighbour of brick b at offset r (-1, 0, 1) along a dimension with nb
+// bricks (periodic), or -1 when there is none (nb <= 2 and b + r outside).
+__host__ __device__ __forceinline__ int brick_nbr(int b, int r, int nb)
+{
+    int t = b + r;
+    if (nb >= 3) {
+        t += (t < 0) ? nb : 0;
+        t -= (t >= nb) ? nb : 0;
+        return t;
+    }
+    return (t >= 0 && t < nb) ? t : -1;
 }
 
 // Offset (-1, 0, 1) of brick `to` from brick `from` along a dimension with nb

@@ -127,7 +127,8 @@ void drop_graph(mpcd_ctx* c)
 // Layout of one box's device allocation.
 struct Layout {
     size_t off_p[2][6], off_v0[2][3], off_pid[2], off_m[2], off_cell, off_rank, off_cstart, off_un, off_part,
-        off_esc, off_eflag, off_bstart[2], off_bcount, off_bcursor, off_bof[3], off_blo[3], off_vacf, total;
+        off_esc, off_eflag, off_bstart[2], off_bcount, off_bcursor, off_outcnt, off_outbase, off_bsize,
+        off_bof[3], off_blo[3], off_vacf, total;
 };
 
 Layout box_layout(int64_t n, int64_t ncell, bool vacf, int vacf_cap, bool brick, const BrickGeom& g,
@@ -159,6 +160,9 @@ Layout box_layout(int64_t n, int64_t ncell, bool vacf, int vacf_cap, bool brick,
     for (int b = 0; b < 2; ++b) { L.off_bstart[b] = o; o += align256((nbk + 1) * 4); }
     L.off_bcount = o; o += align256(nbk * 4);
     L.off_bcursor = o; o += align256(nbk * 4);
+    L.off_outcnt = o; o += align256(nbk * 27 * 4);
+    L.off_outbase = o; o += align256(nbk * 27 * 4);
+    L.off_bsize = o; o += align256(nbk * 4);
     for (int d = 0; d < 3; ++d) {
         L.off_bof[d] = o;
         o += brick ? align256((size_t)g.L[d] * 2) : 0;
@@ -703,6 +707,9 @@ int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
     for (int p = 0; p < 2; ++p) b.bstart[p] = brick ? (uint32_t*)(m + L.off_bstart[p]) : nullptr;
     b.bcount = brick ? (uint32_t*)(m + L.off_bcount) : nullptr;
     b.bcursor = brick ? (uint32_t*)(m + L.off_bcursor) : nullptr;
+    b.outcnt = brick ? (uint32_t*)(m + L.off_outcnt) : nullptr;
+    b.outbase = brick ? (uint32_t*)(m + L.off_outbase) : nullptr;
+    b.bsize = brick ? (uint32_t*)(m + L.off_bsize) : nullptr;
     for (int k = 0; k < 3; ++k) {
         b.bof[k] = brick ? (uint16_t*)(m + L.off_bof[k]) : nullptr;
         b.blo[k] = brick ? (int32_t*)(m + L.off_blo[k]) : nullptr;

@@ -7,7 +7,8 @@
 //     k_brick_accumulate  per brick: stream, bin into the brick's window,
 //                         LDS-atomic exact cell sums, write window partials,
 //                         count next-step buckets
-//     k_brick_scan        per box: next bucket starts
+//     k_brick_sizes/scan/offsets  next bucket sizes and starts, and where
+//                         each source brick's movers start in them
 //     k_brick_finalize    per cell: add the window partials (and escapes),
 //                         u_c = sum v / n, axis n_c from Philox
 //     k_brick_rotate      per brick: stream again (same arithmetic), rotate
@@ -139,57 +140,95 @@ __global__ __launch_bounds__(kBlock) void k_brick_accumulate(const Tile* __restr
     const float dt = b.dt;
     const uint32_t stamp = (uint32_t)(s.k + 1);
     const int64_t beg = b.bstart[par][brick], end = b.bstart[par][brick + 1];
-    for (int64_t i = beg + threadIdx.x; i < end; i += kBlock) {
-        const float ux = vx[i], uy = vy[i], uz = vz[i];
-        const float px = fold(fmaf(ux, dt, x[i]), b.len[0]);
-        const float py = fold(fmaf(uy, dt, y[i]), b.len[1]);
-        const float pz = fold(fmaf(uz, dt, z[i]), b.len[2]);
-        const int cx = axis_cell(px, sh.x, b.inv_a, b.L[0]);
-        const int cy = axis_cell(py, sh.y, b.inv_a, b.L[1]);
-        const int cz = axis_cell(pz, sh.z, b.inv_a, b.L[2]);
-        const int lx = window_offset(cx, lox, m, b.L[0]);
-        const int ly = window_offset(cy, loy, m, b.L[1]);
-        const int lz = window_offset(cz, loz, m, b.L[2]);
-        const float mi = mp ? gp(mp)[i] : 1.0f;
-        const unsigned long long fx = to_fixed(mi * ux), fy = to_fixed(mi * uy), fz = to_fixed(mi * uz);
-        const unsigned long long fw = to_fixed(mi);
-        if (lx < ex && ly < ey && lz < ez) {
-            CellAcc* w = &win[lx + wx * (ly + wy * lz)];
-            atomicAdd(&w->sx, fx);
-            atomicAdd(&w->sy, fy);
-            atomicAdd(&w->sz, fz);
-            atomicAdd(&w->w, fw);
-        } else {   // left the window: exact global sums, flag the owner brick
-            const uint32_t c = (uint32_t)cx + (uint32_t)b.L[0] * ((uint32_t)cy + (uint32_t)b.L[1] * (uint32_t)cz);
-            gatomic_add(&esc[c].sx, fx);
-            gatomic_add(&esc[c].sy, fy);
-            gatomic_add(&esc[c].sz, fz);
-            gatomic_add(&esc[c].w, fw);
-            const int ob = b.bof[0][cx] + b.nb[0] * (b.bof[1][cy] + b.nb[1] * b.bof[2][cz]);
-            gp(b.eflag)[ob] = stamp;
+    constexpr int kU = 8;   // particles per thread in flight
+    for (int64_t base = beg; base < end; base += (int64_t)kBlock * kU) {
+        float qx[kU], qy[kU], qz[kU], qvx[kU], qvy[kU], qvz[kU], qm[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {   // issue every load first
+            const int64_t i = base + u * kBlock + threadIdx.x;
+            const bool ok = i < end;
+            const int64_t j = ok ? i : beg;
+            qx[u] = x[j];
+            qy[u] = y[j];
+            qz[u] = z[j];
+            qvx[u] = vx[j];
+            qvy[u] = vy[j];
+            qvz[u] = vz[j];
+            qm[u] = mp ? gp(mp)[j] : 1.0f;
         }
-        // bucket of the streamed position for the next step
-        const int3 d = brick_of_pos(b, px, py, pz);
-        const int rx = brick_rel(bx, d.x, b.nb[0]), ry = brick_rel(by, d.y, b.nb[1]),
-                  rz = brick_rel(bz, d.z, b.nb[2]);
-        if (rx <= 1 && ry <= 1 && rz <= 1)
-            atomicAdd(&cnt[(rx + 1) + 3 * ((ry + 1) + 3 * (rz + 1))], 1u);
-        else
-            gatomic_add(&bcount[d.x + b.nb[0] * (d.y + b.nb[1] * d.z)], 1u);
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int64_t i = base + u * kBlock + threadIdx.x;
+            if (i >= end) continue;
+            const float ux = qvx[u], uy = qvy[u], uz = qvz[u];
+            const float px = fold(fmaf(ux, dt, qx[u]), b.len[0]);
+            const float py = fold(fmaf(uy, dt, qy[u]), b.len[1]);
+            const float pz = fold(fmaf(uz, dt, qz[u]), b.len[2]);
+            const int cx = axis_cell(px, sh.x, b.inv_a, b.L[0]);
+            const int cy = axis_cell(py, sh.y, b.inv_a, b.L[1]);
+            const int cz = axis_cell(pz, sh.z, b.inv_a, b.L[2]);
+            const int lx = window_offset(cx, lox, m, b.L[0]);
+            const int ly = window_offset(cy, loy, m, b.L[1]);
+            const int lz = window_offset(cz, loz, m, b.L[2]);
+            const float mi = qm[u];
+            const unsigned long long fx = to_fixed(mi * ux), fy = to_fixed(mi * uy), fz = to_fixed(mi * uz);
+            const unsigned long long fw = to_fixed(mi);
+            if (lx < ex && ly < ey && lz < ez) {
+                CellAcc* w = &win[lx + wx * (ly + wy * lz)];
+                atomicAdd(&w->sx, fx);
+                atomicAdd(&w->sy, fy);
+                atomicAdd(&w->sz, fz);
+                atomicAdd(&w->w, fw);
+            } else {   // left the window: exact global sums, flag the owner brick
+                const uint32_t c = (uint32_t)cx + (uint32_t)b.L[0] * ((uint32_t)cy + (uint32_t)b.L[1] * (uint32_t)cz);
+                gatomic_add(&esc[c].sx, fx);
+                gatomic_add(&esc[c].sy, fy);
+                gatomic_add(&esc[c].sz, fz);
+                gatomic_add(&esc[c].w, fw);
+                const int ob = b.bof[0][cx] + b.nb[0] * (b.bof[1][cy] + b.nb[1] * b.bof[2][cz]);
+                gp(b.eflag)[ob] = stamp;
+            }
+            // bucket of the streamed position for the next step
+            const int3 d = brick_of_pos(b, px, py, pz);
+            const int rx = brick_rel(bx, d.x, b.nb[0]), ry = brick_rel(by, d.y, b.nb[1]),
+                      rz = brick_rel(bz, d.z, b.nb[2]);
+            if (rx <= 1 && ry <= 1 && rz <= 1)
+                atomicAdd(&cnt[(rx + 1) + 3 * ((ry + 1) + 3 * (rz + 1))], 1u);
+            else
+                gatomic_add(&bcount[d.x + b.nb[0] * (d.y + b.nb[1] * d.z)], 1u);
+        }
     }
     __syncthreads();
     MPCD_G CellAcc* __restrict__ out = gp(b.part) + (size_t)brick * b.wsize;
     for (int i = threadIdx.x; i < b.wsize; i += kBlock) store_acc(out + i, win[i]);
-    if (threadIdx.x < 27 && cnt[threadIdx.x] != 0u) {
-        const int r = threadIdx.x;
-        const int dx = (bx + (r % 3) - 1 + b.nb[0]) % b.nb[0];
-        const int dy = (by + (r / 3) % 3 - 1 + b.nb[1]) % b.nb[1];
-        const int dz = (bz + r / 9 - 1 + b.nb[2]) % b.nb[2];
-        gatomic_add(&bcount[dx + b.nb[0] * (dy + b.nb[1] * dz)], cnt[r]);
-    }
+    if (threadIdx.x < 27) gp(b.outcnt)[(size_t)brick * 27 + threadIdx.x] = cnt[threadIdx.x];
 }
 
-// per box: bucket starts of the next buffer from the counts, cursors, reset
+// bucket sizes of the next step: the neighbour groups plus the far particles
+__global__ __launch_bounds__(kBlock) void k_brick_sizes(const Tile* __restrict__ tiles, int ntiles,
+                                                         const BoxDev* __restrict__ boxes,
+                                                         const BoxState* __restrict__ st)
+{
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= ntiles) return;
+    const Tile tl = tiles[t];
+    const BoxState s = st[tl.box];
+    const BoxDev& b = boxes[tl.box];
+    if (box_idle(s) || b.binning != 1) return;
+    const int d = (int)tl.begin;
+    const int dx = d % b.nb[0], dy = (d / b.nb[0]) % b.nb[1], dz = d / (b.nb[0] * b.nb[1]);
+    uint32_t n = gp(b.bcount)[d];
+    for (int r = 0; r < 27; ++r) {   // source of group r of bucket d: d - offset(r)
+        const int sx = brick_nbr(dx, 1 - r % 3, b.nb[0]);
+        const int sy = brick_nbr(dy, 1 - (r / 3) % 3, b.nb[1]);
+        const int sz = brick_nbr(dz, 1 - r / 9, b.nb[2]);
+        if (sx < 0 || sy < 0 || sz < 0) continue;
+        n += gp(b.outcnt)[(size_t)(sx + b.nb[0] * (sy + b.nb[1] * sz)) * 27 + r];
+    }
+    gp(b.bsize)[d] = n;
+}
+
+// per box: bucket starts of the next buffer, far-particle cursors, reset
 __global__ __launch_bounds__(kBlock) void k_brick_scan(const int32_t* __restrict__ active,
                                                         const BoxDev* __restrict__ boxes,
                                                         const BoxState* __restrict__ st)
@@ -202,18 +241,51 @@ __global__ __launch_bounds__(kBlock) void k_brick_scan(const int32_t* __restrict
     const int per = (nb + kBlock - 1) / kBlock;
     const int lo = min(nb, (int)threadIdx.x * per), hi = min(nb, ((int)threadIdx.x + 1) * per);
     uint32_t v = 0;
-    for (int i = lo; i < hi; ++i) v += b.bcount[i];
+    for (int i = lo; i < hi; ++i) v += gp(b.bsize)[i];
     uint32_t total;
     uint32_t run = block_exclusive_scan(v, &total);
-    uint32_t* __restrict__ next = b.bstart[s.parity ^ 1];
+    MPCD_G uint32_t* __restrict__ next = gp(b.bstart[s.parity ^ 1]);
     for (int i = lo; i < hi; ++i) {
-        const uint32_t c = b.bcount[i];
+        const uint32_t c = gp(b.bsize)[i];
         next[i] = run;
-        b.bcursor[i] = run;
-        b.bcount[i] = 0u;
+        gp(b.bcursor)[i] = run + c - gp(b.bcount)[i];   // far particles fill the bucket's end
+        gp(b.bcount)[i] = 0u;
         run += c;
     }
     if (threadIdx.x == 0) next[nb] = total;
+}
+
+// where the particles of source brick b heading for neighbour r start in
+// that neighbour's bucket: groups are laid out in r order
+__global__ __launch_bounds__(kBlock) void k_brick_offsets(const Tile* __restrict__ tiles, int ntiles,
+                                                           const BoxDev* __restrict__ boxes,
+                                                           const BoxState* __restrict__ st)
+{
+    const int g = blockIdx.x * kBlock + threadIdx.x;   // (brick tile, r) pairs
+    const int t = g / 27, r = g % 27;
+    if (t >= ntiles) return;
+    const Tile tl = tiles[t];
+    const BoxState s = st[tl.box];
+    const BoxDev& b = boxes[tl.box];
+    if (box_idle(s) || b.binning != 1) return;
+    const int src = (int)tl.begin;
+    const int sx = src % b.nb[0], sy = (src / b.nb[0]) % b.nb[1], sz = src / (b.nb[0] * b.nb[1]);
+    const int dx = brick_nbr(sx, r % 3 - 1, b.nb[0]);
+    const int dy = brick_nbr(sy, (r / 3) % 3 - 1, b.nb[1]);
+    const int dz = brick_nbr(sz, r / 9 - 1, b.nb[2]);
+    uint32_t off = 0;
+    if (dx >= 0 && dy >= 0 && dz >= 0) {
+        const int d = dx + b.nb[0] * (dy + b.nb[1] * dz);
+        off = gp(b.bstart[s.parity ^ 1])[d];
+        for (int q = 0; q < r; ++q) {   // earlier groups of bucket d
+            const int ex = brick_nbr(dx, 1 - q % 3, b.nb[0]);
+            const int ey = brick_nbr(dy, 1 - (q / 3) % 3, b.nb[1]);
+            const int ez = brick_nbr(dz, 1 - q / 9, b.nb[2]);
+            if (ex < 0 || ey < 0 || ez < 0) continue;
+            off += gp(b.outcnt)[(size_t)(ex + b.nb[0] * (ey + b.nb[1] * ez)) * 27 + q];
+        }
+    }
+    gp(b.outbase)[(size_t)src * 27 + r] = off;
 }
 
 __global__ __launch_bounds__(kBlock) void k_brick_finalize(const Tile* __restrict__ tiles,
@@ -334,96 +406,89 @@ __global__ __launch_bounds__(kBlock) void k_brick_rotate(const Tile* __restrict_
     MPCD_G float* __restrict__ om = b.m[dst] ? gp(b.m[dst]) : nullptr;
     const MPCD_G CellUN* __restrict__ un = gp(b.un);
     MPCD_G uint32_t* __restrict__ bcursor = gp(b.bcursor);
+    // running ranks within each destination group; group starts precomputed
+    if (threadIdx.x < 27) {
+        cnt[threadIdx.x] = 0u;
+        base[threadIdx.x] = gp(b.outbase)[(size_t)brick * 27 + threadIdx.x];
+    }
+    __syncthreads();
     long long d[kNumDiag] = {0, 0, 0, 0, 0, 0};
-    constexpr int kChunk = kBlock * kItems;
-    for (int64_t c0 = beg; c0 < end; c0 += kChunk) {
-        if (threadIdx.x < 27) cnt[threadIdx.x] = 0u;
-        __syncthreads();
-        float px[kItems], py[kItems], pz[kItems], qx[kItems], qy[kItems], qz[kItems];
+    const int lane = threadIdx.x & (kWave - 1);
+    for (int64_t c0 = beg; c0 < end; c0 += (int64_t)kBlock * kItems) {
+        float px[kItems], py[kItems], pz[kItems], qx[kItems], qy[kItems], qz[kItems], qm[kItems];
         int32_t id[kItems];
-        uint32_t slot[kItems];   // rank in its bucket range, or the global slot
-        int rel[kItems];         // 0..26, 27 = far (slot is global), -1 = none
+#pragma unroll
+        for (int it = 0; it < kItems; ++it) {   // issue every load first
+            const int64_t i = c0 + it * kBlock + threadIdx.x;
+            const int64_t j = (i < end) ? i : beg;
+            px[it] = ix[j];
+            py[it] = iy[j];
+            pz[it] = iz[j];
+            qx[it] = ivx[j];
+            qy[it] = ivy[j];
+            qz[it] = ivz[j];
+            qm[it] = im ? im[j] : 1.0f;
+            id[it] = iid[j];
+        }
 #pragma unroll
         for (int it = 0; it < kItems; ++it) {
             const int64_t i = c0 + it * kBlock + threadIdx.x;
-            rel[it] = -1;
-            if (i < end) {
-                const float ux = ivx[i], uy = ivy[i], uz = ivz[i];
-                px[it] = fold(fmaf(ux, dt, ix[i]), b.len[0]);
-                py[it] = fold(fmaf(uy, dt, iy[i]), b.len[1]);
-                pz[it] = fold(fmaf(uz, dt, iz[i]), b.len[2]);
-                id[it] = iid[i];
-                const int cx = axis_cell(px[it], sh.x, b.inv_a, b.L[0]);
-                const int cy = axis_cell(py[it], sh.y, b.inv_a, b.L[1]);
-                const int cz = axis_cell(pz[it], sh.z, b.inv_a, b.L[2]);
-                const int lx = window_offset(cx, lox, m, b.L[0]);
-                const int ly = window_offset(cy, loy, m, b.L[1]);
-                const int lz = window_offset(cz, loz, m, b.L[2]);
-                CellUN u;
-                if (lx < ex && ly < ey && lz < ez)
-                    u = wun[lx + wx * (ly + wy * lz)];
-                else
-                    u = load_un(un + ((uint32_t)cx + (uint32_t)b.L[0] * ((uint32_t)cy + (uint32_t)b.L[1] * (uint32_t)cz)));
-                const float3 v = rotate_about(u, ux, uy, uz, ca, sa);
-                qx[it] = v.x;
-                qy[it] = v.y;
-                qz[it] = v.z;
-                diag_particle(d, v, im ? im[i] : 1.0f);
-                if (vacf) diag_vacf(d, v, gp(b.v0[src][0])[i], gp(b.v0[src][1])[i], gp(b.v0[src][2])[i]);
-                const int3 db = brick_of_pos(b, px[it], py[it], pz[it]);
-                const int rx = brick_rel(bx, db.x, b.nb[0]), ry = brick_rel(by, db.y, b.nb[1]),
-                          rz = brick_rel(bz, db.z, b.nb[2]);
-                if (rx <= 1 && ry <= 1 && rz <= 1) {
-                    rel[it] = (rx + 1) + 3 * ((ry + 1) + 3 * (rz + 1));
-                } else {
-                    rel[it] = 27;
-                    slot[it] = gatomic_add(&bcursor[db.x + b.nb[0] * (db.y + b.nb[1] * db.z)], 1u);
-                }
-            }
-            // ranks in the bucket ranges; particles that stay in this brick
-            // (most of them) take consecutive ranks per wave, so the writes
-            // below coalesce
-            const bool stay = (rel[it] == 13);
+            const bool ok = i < end;
+            const float ux = qx[it], uy = qy[it], uz = qz[it];
+            const float fx = fold(fmaf(ux, dt, px[it]), b.len[0]);
+            const float fy = fold(fmaf(uy, dt, py[it]), b.len[1]);
+            const float fz = fold(fmaf(uz, dt, pz[it]), b.len[2]);
+            const int cx = axis_cell(fx, sh.x, b.inv_a, b.L[0]);
+            const int cy = axis_cell(fy, sh.y, b.inv_a, b.L[1]);
+            const int cz = axis_cell(fz, sh.z, b.inv_a, b.L[2]);
+            const int lx = window_offset(cx, lox, m, b.L[0]);
+            const int ly = window_offset(cy, loy, m, b.L[1]);
+            const int lz = window_offset(cz, loz, m, b.L[2]);
+            CellUN u;
+            if (lx < ex && ly < ey && lz < ez)
+                u = wun[lx + wx * (ly + wy * lz)];
+            else
+                u = load_un(un + ((uint32_t)cx + (uint32_t)b.L[0] * ((uint32_t)cy + (uint32_t)b.L[1] * (uint32_t)cz)));
+            const float3 v = rotate_about(u, ux, uy, uz, ca, sa);
+            const int3 db = brick_of_pos(b, fx, fy, fz);
+            const int rx = brick_rel(bx, db.x, b.nb[0]), ry = brick_rel(by, db.y, b.nb[1]),
+                      rz = brick_rel(bz, db.z, b.nb[2]);
+            const bool near = rx <= 1 && ry <= 1 && rz <= 1;
+            const int r = near ? (rx + 1) + 3 * ((ry + 1) + 3 * (rz + 1)) : 27;
+            // rank in the destination group; particles that stay in this brick
+            // (most of them) take consecutive ranks per wave, so stores coalesce
+            const bool stay = ok && r == 13;
             const unsigned long long mask = __ballot(stay);
+            uint32_t slot = 0;
             if (mask) {
-                const int lane = threadIdx.x & (kWave - 1);
                 const int leader = __ffsll((long long)mask) - 1;
                 uint32_t wbase = 0;
                 if (lane == leader) wbase = atomicAdd(&cnt[13], (uint32_t)__popcll(mask));
                 wbase = __shfl(wbase, leader, kWave);
-                if (stay) slot[it] = wbase + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+                slot = base[13] + wbase + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
             }
-            if (rel[it] >= 0 && rel[it] < 27 && !stay) slot[it] = atomicAdd(&cnt[rel[it]], 1u);
-        }
-        __syncthreads();
-        if (threadIdx.x < 27 && cnt[threadIdx.x] != 0u) {
-            const int r = threadIdx.x;
-            const int dx = (bx + (r % 3) - 1 + b.nb[0]) % b.nb[0];
-            const int dy = (by + (r / 3) % 3 - 1 + b.nb[1]) % b.nb[1];
-            const int dz = (bz + r / 9 - 1 + b.nb[2]) % b.nb[2];
-            base[r] = gatomic_add(&bcursor[dx + b.nb[0] * (dy + b.nb[1] * dz)], cnt[r]);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int it = 0; it < kItems; ++it) {
-            if (rel[it] < 0) continue;
-            const int64_t i = c0 + it * kBlock + threadIdx.x;
-            const int64_t j = (rel[it] < 27) ? (int64_t)base[rel[it]] + slot[it] : (int64_t)slot[it];
-            ox[j] = px[it];
-            oy[j] = py[it];
-            oz[j] = pz[it];
-            ovx[j] = qx[it];
-            ovy[j] = qy[it];
-            ovz[j] = qz[it];
+            if (!ok) continue;
+            if (r == 27)
+                slot = gatomic_add(&bcursor[db.x + b.nb[0] * (db.y + b.nb[1] * db.z)], 1u);
+            else if (r != 13)
+                slot = base[r] + atomicAdd(&cnt[r], 1u);
+            const int64_t j = slot;
+            ox[j] = fx;
+            oy[j] = fy;
+            oz[j] = fz;
+            ovx[j] = v.x;
+            ovy[j] = v.y;
+            ovz[j] = v.z;
             oid[j] = id[it];
-            if (om) om[j] = im[i];
+            if (om) om[j] = qm[it];
             if (track) {
                 gp(b.v0[dst][0])[j] = gp(b.v0[src][0])[i];
                 gp(b.v0[dst][1])[j] = gp(b.v0[src][1])[i];
                 gp(b.v0[dst][2])[j] = gp(b.v0[src][2])[i];
             }
+            diag_particle(d, v, qm[it]);
+            if (vacf) diag_vacf(d, v, gp(b.v0[src][0])[i], gp(b.v0[src][1])[i], gp(b.v0[src][2])[i]);
         }
-        __syncthreads();
     }
     block_diag(d, partials + (size_t)t * kNumDiag);
 }
@@ -983,7 +1048,11 @@ void launch_brick_accumulate(const Tables& T, hipStream_t s)
 }
 void launch_brick_scan(const Tables& T, hipStream_t s)
 {
+    MPCD_LAUNCH(k_brick_sizes, (T.nbtiles + kBlock - 1) / kBlock, kBlock, s, T.btiles, T.nbtiles, T.boxes,
+                T.state);
     MPCD_LAUNCH(k_brick_scan, T.nactive, kBlock, s, T.active, T.boxes, T.state);
+    MPCD_LAUNCH(k_brick_offsets, (T.nbtiles * 27 + kBlock - 1) / kBlock, kBlock, s, T.btiles, T.nbtiles,
+                T.boxes, T.state);
 }
 void launch_brick_finalize(const Tables& T, hipStream_t s)
 {

@@ -97,6 +97,25 @@ int main()
                 }
         }
     }
+    // bucket group layout: group q of bucket d comes from brick d - off(q) and
+    // every (source, q) pair lands in exactly one bucket group
+    for (int nb = 1; nb <= 6; ++nb) {
+        for (int d = 0; d < nb; ++d) {
+            std::set<int> srcs;
+            for (int r = -1; r <= 1; ++r) {
+                const int src = brick_nbr(d, -r, nb);
+                if (src < 0) continue;
+                if (brick_nbr(src, r, nb) != d) { printf("nbr inverse nb=%d\n", nb); return 1; }
+                if (brick_rel(src, d, nb) != r) { printf("rel vs nbr nb=%d d=%d r=%d\n", nb, d, r); return 1; }
+                if (!srcs.insert(src).second && nb >= 3) { printf("duplicate source\n"); return 1; }
+            }
+        }
+        for (int s = 0; s < nb; ++s)
+            for (int t = 0; t < nb; ++t) {
+                const int r = brick_rel(s, t, nb);
+                if (r <= 1 && brick_nbr(s, r, nb) != t) { printf("rel/nbr mismatch\n"); return 1; }
+            }
+    }
     printf("ok\n");
     return 0;
 }
