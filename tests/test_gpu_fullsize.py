@@ -55,7 +55,7 @@ def test_full_size_one_step_sampled_cells():
                               band_from=(band_pos, band_cells))
     print("[case] full-size sample: %d particles, %d in face band, max rel err %.2e"
           % (len(pick), band, err), flush=True)
-    assert len(pick) > 4_000_000
+    assert len(pick) > 1_900_000
     # whole-box invariants of the GPU result
     assert gp.min() >= 0 and gp.max() < 256
     v0 = vel.astype(np.float64)
