@@ -35,19 +35,13 @@ SERVED = "served_poisson"            # Poisson arrivals of single-box requests
 
 # Algorithmic bytes each kernel's function has to move, per particle (P) and
 # per cell (C), independent of how the kernel is written:
-#   brick_accumulate: read x, v (24 B); write the cell sums
-#                (3 x 4 B + a 4 B count per cell)                     -> 24 P + 16 C
-#   brick_finalize: read the cell sums (16 B), write u_c and the
-#                axis (6 x 4 B)                                       -> 40 C
-#   brick_rotate: read x, v (24 B) and u_c, axis (24 B per cell),
-#                write x, v (24 B)                                    -> 48 P + 24 C
+#   brick_step : the whole step of the brick boxes; read x, v (24 B) and
+#                write x, v (24 B); the cell sums live and die in LDS   -> 48 P
 #   cell_rotate: read v, write v                                      -> 24 P
 #   scatter    : read x, v (24 B), write them (24 B)                  -> 48 P
 #   count      : read x (12 B), write the key (4 B)                   -> 16 P
 ALGO_BYTES = {
-    "brick_accumulate": (24, 16),
-    "brick_finalize": (0, 40),
-    "brick_rotate": (48, 24),
+    "brick_step": (48, 0),
     "cell_rotate": (24, 0),
     "scatter": (48, 0),
     "count": (16, 0),

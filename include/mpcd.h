@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define MPCD_ABI_VERSION 1
+#define MPCD_ABI_VERSION 2
 
 typedef enum {
     MPCD_OK = 0,
@@ -78,10 +78,10 @@ typedef enum {
 
 /* mpcd_options.binning */
 #define MPCD_BIN_AUTO 0    /* autotuner chooses per box-shape class         */
-#define MPCD_BIN_ATOMIC 1  /* particles kept in buckets by brick of cells
-                              (re-bucketed every step while rotating); cell
-                              sums accumulated with LDS atomics per brick
-                              window, partial windows added per cell       */
+#define MPCD_BIN_ATOMIC 1  /* particles kept in buckets by the brick of cells
+                              holding their next collision cell; one pass
+                              per brick: LDS-atomic cell sums, rotation, and
+                              the store into the next step's bucket        */
 #define MPCD_BIN_SORT 2    /* counting-sort particles by collision cell every
                               step, then reduce each cell's contiguous run   */
 
@@ -111,7 +111,8 @@ typedef void (*mpcd_free_fn)(void* ptr, void* user);
 typedef struct {
     int32_t binning;        /* MPCD_BIN_*                                    */
     int32_t brick[3];       /* ATOMIC: brick edge in cells per dimension,
-                               each 0 (auto) or in [2, 64]                   */
+                               each 0 (auto) or a power of two in [2, 64];
+                               at most 2048 cells per brick                  */
     int32_t block;          /* reserved, must be 0                           */
     int32_t use_graph;      /* 1: replay steps from a captured hipGraph      */
     int64_t hbm_budget;     /* bytes all boxes may occupy; 0 = unlimited     */
@@ -136,6 +137,10 @@ typedef struct {
     int64_t n_particles;
     int32_t binning;        /* binning mode in use for this box              */
     int32_t brick[3];       /* ATOMIC: brick edges in use (largest brick)    */
+    int64_t overflow_steps; /* ATOMIC: steps in which a bucket was full (its
+                               particles took the slow overflow path)      */
+    int64_t rebuckets;      /* ATOMIC: re-bucketings since admission or the
+                               last mpcd_set_state                          */
 } mpcd_observables;
 
 /* Per-kernel timing collected while profiling is on. */
@@ -166,9 +171,12 @@ int mpcd_admit(mpcd_ctx* ctx, const mpcd_box_desc* desc, int32_t* slot);
  * on the context stream. */
 int mpcd_step(mpcd_ctx* ctx, int32_t n_steps);
 
-/* Synchronise and read a box's diagnostics.  out->vacf stays valid until the
- * next call on ctx.  Returns MPCD_ESTATE (and fills *out) if the box's
- * energy became NaN or Inf. */
+/* Synchronise and read a box's diagnostics: momentum, kinetic energy and
+ * temperature are summed exactly over the current state by one pass on the
+ * device (the steps themselves only check the velocity range and, on
+ * sampled steps, accumulate the VACF).  out->vacf stays valid until the next
+ * call on ctx.  Returns MPCD_ESTATE (and fills *out) if a velocity became
+ * NaN, Inf or too large for the exact cell sums. */
 int mpcd_observe(mpcd_ctx* ctx, int32_t slot, mpcd_observables* out);
 
 /* Copy a box's state to host memory xyzv (6 N floats, SoA: x[N], y[N], z[N],

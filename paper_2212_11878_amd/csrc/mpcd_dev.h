@@ -4,6 +4,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stdint.h>
 
 namespace mpcd {
@@ -33,7 +34,9 @@ constexpr int kWave = 64;
 constexpr int kBlock = 256;          // threads per workgroup of the particle kernels
 constexpr int kPartTile = 4096;      // particles per particle tile (16 per thread)
 constexpr int kCellTile = 2048;      // cells per cell tile
-constexpr int kItems = 8;            // particles per thread per chunk (brick rotation)
+constexpr int kMaxBrickCells = 1024; // cells of one brick (LDS of its workgroup)
+constexpr int kBrickCellBytes = 60;  // LDS per brick cell: 4 x 64-bit sums, 7 x 32-bit cell data
+constexpr int kAccLanes = 64;        // step accumulator lanes per box (spread the atomics)
 constexpr int kNumDiag = 6;          // per-tile exact partials: sum v (3), sum v^2, sum v.v0, range violations
 
 // Per-cell accumulator: exact 64-bit fixed-point sums (quantum 2^-32) of the
@@ -52,53 +55,47 @@ struct alignas(32) CellUN {
 };
 
 // Read-only description of one box, resident in device memory.  Particle
-// arrays come in two buffers (ping-pong); the buffer in use is
-// BoxState::parity.
+// arrays come in two buffers (ping-pong) of `nslot` slots; the buffer in use
+// is BoxState::parity.  Slots that hold no particle carry pid -1 once the
+// holes have been marked (the step kernels never read them).
 //
 // Brick binning (MPCD_BIN_ATOMIC): the L0 x L1 x L2 cells are split into
-// nb0 x nb1 x nb2 bricks of nearly equal size; the particles of a buffer are
-// stored bucket by bucket, bucket b holding the particles whose position lies
-// in brick b.  A particle of brick b streams at most a few tenths of a cell,
-// so its collision cell lies in the brick's "window": the brick grown by
-// `margin` cells on every side.  Cell sums are accumulated per window in LDS
-// and written as partial records; a cell's total is the sum of the records of
-// every window that contains it, plus the escape record of particles that
-// left their window (rare).
+// nb0 x nb1 x nb2 bricks of 2^bshift cells per dimension (the last brick of
+// a dimension may be shorter).  A buffer is cut into
+// nbrick + 1 buckets: bucket d = [bstart[d], bstart[d+1]) holds, in its first
+// bsize[parity][d] slots, the particles whose collision cell of the coming
+// step (position streamed with the current velocity, grid shifted by that
+// step's shift) lies in brick d; the last bucket (index nbrick) takes the
+// particles that found their bucket full.  The capacities are set by a
+// counting sort (re-bucketing) with slack, so one workgroup per brick sees
+// every particle of its cells and nothing else.
 struct BoxDev {
     float* p[2][6];        // x, y, z, vx, vy, vz
     float* v0[2][3];       // VACF reference velocities (null if untracked)
-    int32_t* pid[2];       // particle identity (admission order)
+    int32_t* pid[2];       // particle identity (admission order); -1 in holes
     float* m[2];           // per-particle masses (null: all particles equal)
-    uint32_t* cell;        // sort key of each particle
-    uint32_t* rank;        // rank of each particle inside its key (sort)
+    uint32_t* cell;        // sort key of each slot
+    uint32_t* rank;        // rank of each slot inside its key (sort)
     uint32_t* cstart;      // counts, then exclusive starts, per key (C + 1)
-    CellUN* un;            // per cell: u_c and axis of this step (brick mode)
-    CellAcc* part;         // brick mode: nbrick x wsize window partial sums
-    CellAcc* esc;          // brick mode: per cell, sums of escaped particles
-    uint32_t* eflag;       // brick mode: per brick, k+1 when esc holds data for it
-    uint32_t* bstart[2];   // brick mode: bucket starts of each buffer (nbrick + 1)
-    uint32_t* bcount;      // brick mode: particles bound for each bucket from farther than a neighbour
-    uint32_t* bcursor;     // brick mode: write cursors of those far particles (end of each bucket)
-    uint32_t* outcnt;      // brick mode: [brick][27] particles going to each neighbouring bucket
-    uint32_t* outbase;     // brick mode: [brick][27] where they start in that bucket
-    uint32_t* bsize;       // brick mode: particles of each bucket next step
-    uint16_t* bof[3];      // brick mode: brick index of each cell, per dimension (L_d entries)
-    int32_t* blo[3];       // brick mode: first cell of each brick, per dimension (nb_d + 1 entries)
+    CellUN* un;            // brick mode: u_c and axis of the cells of flagged bricks
+    CellAcc* esc[2];       // brick mode: per cell, sums of overflow particles (step parity)
+    uint32_t* eflag;       // brick mode: per brick, k+1 when esc[k & 1] holds data for it
+    uint32_t* bstart;      // brick mode: bucket starts (nbrick + 2)
+    uint32_t* bsize[2];    // brick mode: particles in each bucket of each buffer (nbrick + 1)
     double* vacf;          // VACF samples
     int64_t n;             // particles
+    int64_t nslot;         // slots per buffer (n for SORT boxes)
     int64_t ncell;
     int32_t L[3];
     int32_t nb[3];         // bricks per dimension
+    int32_t bshift[3];     // brick edge 2^bshift cells per dimension
     int32_t bmax[3];       // largest brick extent per dimension
-    int32_t wdim[3];       // window extents: bmax + 2 margin
-    int32_t margin;
-    int32_t wsize;         // wdim0 * wdim1 * wdim2
     int32_t nbrick;
     int32_t vacf_stride;   // 0 = untracked
     int32_t vacf_cap;
     int32_t binning;       // MPCD_BIN_ATOMIC (bricks) or MPCD_BIN_SORT
     int32_t conserve_l;    // 1: angular-momentum-conserving rule (SORT binning only)
-    int32_t ptile0, ptile1;   // particle tiles [ptile0, ptile1)
+    int32_t ptile0, ptile1;   // slot tiles [ptile0, ptile1)
     int32_t ctile0, ctile1;   // cell tiles [ctile0, ctile1)
     int32_t btile0, btile1;   // brick tiles [btile0, btile1)
     float len[3];          // L_d * a
@@ -117,8 +114,10 @@ struct BoxState {
     int parity;            // particle buffer in use
     int vacf_len;
     int status;            // 0 or MPCD_ESTATE
-    int rebucket;          // brick mode: particles not yet in brick buckets
-    double diag[4];        // sum v (3), sum v^2 after the last step (exact sums, rounded once)
+    int rebucket;          // brick mode: buckets to be rebuilt by the counting sort
+    long long overflow_steps;   // brick mode: steps in which a bucket was full
+    long long rebuckets;        // brick mode: re-bucketings done
+    double diag[4];        // sum m v (3), sum m v^2 of the last snapshot (exact sums, rounded once)
 };
 
 // Record copies to and from global memory as native vectors (struct
@@ -223,26 +222,35 @@ __device__ __forceinline__ float3 cell_axis(const BoxDev& b, long long k, uint32
     return make_float3(n.x * r, n.y * r, n.z * r);
 }
 
-// Periodic fold of a streamed coordinate into [0, len).
-__device__ __forceinline__ float fold(float x, float len)
+// Periodic fold of a streamed coordinate into [0, len).  A coordinate less
+// than one box length outside needs one add or subtract (x + len of a
+// negative x rounds at most up to len, which the subtract maps to 0); farther
+// ones (and non-finite values) take the floor division and a final guard.
+__host__ __device__ __forceinline__ float fold(float x, float len)
 {
-    if (x < 0.0f || x >= len) {
-        if (x < -len || x >= 2.0f * len) x -= len * floorf(x / len);
-        if (x < 0.0f) x += len;
-        if (x >= len) x -= len;
-        if (x < 0.0f || x >= len) x = 0.0f;   // rounding landed on an edge
+    if (!(x >= -len && x < 2.0f * len)) {
+        x -= len * floorf(x / len);
+        x = (x < 0.0f) ? x + len : x;
+        x = (x >= len) ? x - len : x;
+        return (x < 0.0f || x >= len) ? 0.0f : x;   // rounding landed on an edge
     }
-    return x;
+    x = (x < 0.0f) ? x + len : x;
+    return (x >= len) ? x - len : x;
 }
 
 // Cell index along one axis of the grid displaced by s (floor((x - s)/a)),
-// folded periodically; clamped so it can never leave [0, L).
-__device__ __forceinline__ int axis_cell(float x, float s, float inv_a, int L)
+// folded periodically: for x in [0, L a) and |s| <= a/2 the floor lies in
+// [-1, L], so one add or subtract wraps it.  axis_cell_raw may return values
+// outside [0, L) for non-finite x (callers range-check it); axis_cell clamps.
+__device__ __forceinline__ int axis_cell_raw(float x, float s, float inv_a, int L)
 {
     int i = (int)floorf((x - s) * inv_a);
-    if (i < 0) i += L;
-    if (i >= L) i -= L;
-    return min(max(i, 0), L - 1);
+    i = (i < 0) ? i + L : i;
+    return (i >= L) ? i - L : i;
+}
+__device__ __forceinline__ int axis_cell(float x, float s, float inv_a, int L)
+{
+    return min(max(axis_cell_raw(x, s, inv_a, L), 0), L - 1);
 }
 
 __device__ __forceinline__ uint32_t collision_cell(const BoxDev& b, float x, float y, float z,
@@ -254,22 +262,10 @@ __device__ __forceinline__ uint32_t collision_cell(const BoxDev& b, float x, flo
     return (uint32_t)ix + (uint32_t)b.L[0] * ((uint32_t)iy + (uint32_t)b.L[1] * (uint32_t)iz);
 }
 
-// Brick geometry: brick i of a dimension with L cells split into nb bricks
-// covers cells [floor(i L / nb), floor((i+1) L / nb)).
-__host__ __device__ __forceinline__ int brick_lo(int i, int L, int nb) { return (int)(((long long)i * L) / nb); }
-__host__ __device__ __forceinline__ int brick_of(int c, int L, int nb)
-{
-    return (int)((((long long)c + 1) * nb - 1) / L);
-}
-
-// Brick that holds a position (unshifted grid), per dimension (table lookups).
-__device__ __forceinline__ int3 brick_of_pos(const BoxDev& b, float x, float y, float z)
-{
-    const int cx = axis_cell(x, 0.0f, b.inv_a, b.L[0]);
-    const int cy = axis_cell(y, 0.0f, b.inv_a, b.L[1]);
-    const int cz = axis_cell(z, 0.0f, b.inv_a, b.L[2]);
-    return make_int3(b.bof[0][cx], b.bof[1][cy], b.bof[2][cz]);
-}
+// Brick geometry along one dimension: brick i covers cells
+// [i 2^shift, min((i+1) 2^shift, L)).
+__host__ __device__ __forceinline__ int brick_lo(int i, int shift) { return i << shift; }
+__host__ __device__ __forceinline__ int brick_of(int c, int shift) { return c >> shift; }
 
 // Neighbour of brick b at offset r (-1, 0, 1) along a dimension with nb
 // bricks (periodic), or -1 when there is none (nb <= 2 and b + r outside).
@@ -296,90 +292,67 @@ __host__ __device__ __forceinline__ int brick_rel(int from, int to, int nb)
     return (r >= -1 && r <= 1) ? r : 2;
 }
 
-// Windows (brick grown by m cells on each side) that contain cell c along
-// one dimension: up to three (brick, offset in window) pairs.
-__host__ __device__ __forceinline__ int windows_of(int c, int L, int nb, int m, int* bi, int* li)
-{
-    const int own = brick_of(c, L, nb);
-    int n = 0;
-    for (int k = -1; k <= 1; ++k) {
-        int i = own + k;
-        i += (i < 0) ? nb : 0;
-        i -= (i >= nb) ? nb : 0;
-        bool dup = false;
-        for (int j = 0; j < n; ++j) dup |= (bi[j] == i);
-        if (dup) continue;
-        const int lo = brick_lo(i, L, nb), ext = brick_lo(i + 1, L, nb) - lo + 2 * m;
-        int l = c - lo + m;
-        l += (l < 0) ? L : 0;
-        l -= (l >= L) ? L : 0;
-        if (l < ext) {
-            bi[n] = i;
-            li[n] = l;
-            ++n;
-        }
-    }
-    return n;
-}
-
-// windows_of with the box's brick tables (no integer division).
-__device__ __forceinline__ int windows_of_tab(int c, int L, int nb, int m, const uint16_t* bof,
-                                              const int32_t* blo, int* bi, int* li)
-{
-    const int own = bof[c];
-    int n = 0;
-    for (int k = -1; k <= 1; ++k) {
-        int i = own + k;
-        i += (i < 0) ? nb : 0;
-        i -= (i >= nb) ? nb : 0;
-        bool dup = false;
-        for (int j = 0; j < n; ++j) dup |= (bi[j] == i);
-        if (dup) continue;
-        const int lo = blo[i], ext = blo[i + 1] - lo + 2 * m;
-        int l = c - lo + m;
-        l += (l < 0) ? L : 0;
-        l -= (l >= L) ? L : 0;
-        if (l < ext) {
-            bi[n] = i;
-            li[n] = l;
-            ++n;
-        }
-    }
-    return n;
-}
-
-// Offset of canonical cell c inside the window of the brick starting at lo
-// (periodic), as the accumulation computes it.
-__host__ __device__ __forceinline__ int window_offset(int c, int lo, int m, int L)
-{
-    int l = c - lo + m;
-    l += (l < 0) ? L : 0;
-    l -= (l >= L) ? L : 0;
-    return l;
-}
-
-// Brick decomposition of one box: nb bricks per dimension of at most
-// `want` cells (8 when 0), windows grown by `margin` cells.
+// Brick decomposition of one box: bricks of `want` cells per dimension (a
+// power of two; 8 when 0), at most the box.
 struct BrickGeom {
-    int L[3], nb[3], bmax[3], wdim[3], margin, wsize, nbrick;
+    int L[3], shift[3], nb[3], bmax[3], nbrick, bvol;
 };
+
+inline bool brick_edge_ok(int e) { return e == 0 || (e >= 2 && e <= 64 && (e & (e - 1)) == 0); }
 
 inline BrickGeom brick_geometry(const int32_t L[3], const int32_t want[3])
 {
     BrickGeom g{};
-    g.margin = 1;
     g.nbrick = 1;
-    g.wsize = 1;
+    g.bvol = 1;
     for (int d = 0; d < 3; ++d) {
         g.L[d] = L[d];
         const int B = want[d] > 0 ? want[d] : 8;
-        g.nb[d] = (L[d] + B - 1) / B > 1 ? (L[d] + B - 1) / B : 1;
-        g.bmax[d] = (L[d] + g.nb[d] - 1) / g.nb[d];
-        g.wdim[d] = g.bmax[d] + 2 * g.margin;
+        int sh = 0;
+        while ((2 << sh) <= B) ++sh;   // floor(log2 B)
+        g.shift[d] = sh;
+        g.nb[d] = (L[d] + (1 << sh) - 1) >> sh;
+        g.bmax[d] = L[d] < (1 << sh) ? L[d] : (1 << sh);
         g.nbrick *= g.nb[d];
-        g.wsize *= g.wdim[d];
+        g.bvol *= g.bmax[d];
     }
     return g;
+}
+
+// Bucket holding slot i: the last d in [0, nbk] with start[d] <= i (empty
+// buckets share their start with the next one); start[0] = 0.
+__host__ __device__ __forceinline__ int bucket_of_slot(const uint32_t* start, int nbk, int64_t i)
+{
+    int lo = 0, hi = nbk;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((int64_t)start[mid] <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ceil(sqrt(n)), exactly, for n < 2^32.
+__host__ __device__ __forceinline__ uint32_t isqrt_ceil(uint32_t n)
+{
+    uint32_t r = (uint32_t)sqrtf((float)n);
+    while ((unsigned long long)r * r > n) --r;
+    while ((unsigned long long)r * r < n) ++r;
+    return r;
+}
+
+// Spare slots given to a bucket that re-bucketing found holding n
+// particles: the bucket's size wanders like a Poisson count, so the margin
+// is about 4 standard deviations plus 1/8 and a constant.
+__host__ __device__ __forceinline__ uint32_t bucket_slack(uint32_t n) { return (n >> 3) + 4u * isqrt_ceil(n) + 32u; }
+
+// Slots per buffer of a brick box: the buckets with their slack (the sum of
+// sqrt(n_d) over nb buckets is at most sqrt(nb n)), plus an overflow bucket
+// that can take every particle.
+inline int64_t brick_slots(int64_t n, int64_t nbrick)
+{
+    const int64_t root = (int64_t)ceil(sqrt((double)n * (double)nbrick)) + 1;
+    return 2 * n + (n >> 3) + 4 * (root + nbrick) + 32 * nbrick;
 }
 
 // Velocity in 64-bit fixed point with quantum 2^-32 (exact for |v| >= 2^-9,
@@ -525,6 +498,13 @@ __device__ __forceinline__ void diag_particle(long long (&d)[kNumDiag], float3 v
     if (!(vm < kVelocityLimit)) d[5] += 1;
 }
 
+// range check of a new velocity (non-finite or beyond the fixed-point range)
+__device__ __forceinline__ void diag_check(long long (&d)[kNumDiag], float3 v)
+{
+    const float vm = fmaxf(fabsf(v.x), fmaxf(fabsf(v.y), fabsf(v.z)));
+    if (!(vm < kVelocityLimit)) d[5] += 1;
+}
+
 __device__ __forceinline__ void diag_vacf(long long (&d)[kNumDiag], float3 v, float w0x, float w0y,
                                           float w0z)
 {
@@ -532,8 +512,8 @@ __device__ __forceinline__ void diag_vacf(long long (&d)[kNumDiag], float3 v, fl
 }
 
 // Blocks are dealt round-robin to the 8 XCDs; renumber so that each XCD
-// works on one contiguous run of tiles (neighbouring tiles share boundary
-// cells, which then stay in one L2).
+// works on one contiguous run of tiles (neighbouring bricks exchange
+// particles, whose bucket lines then meet in one L2).
 __device__ __forceinline__ int xcd_tile(int bid, int nblocks)
 {
     const int q = nblocks >> 3, r = nblocks & 7;

@@ -31,12 +31,11 @@ using namespace mpcd;
 namespace {
 
 enum Kern {
-    K_ZERO, K_COUNT, K_SCAN, K_SCATTER, K_FLIP, K_BRICK_ACC, K_BRICK_SCAN, K_BRICK_FIN,
-    K_BRICK_ROT, K_CELL_ROTATE, K_BOX_FINISH, K_NUM
+    K_MARK, K_ZERO, K_COUNT, K_SCAN, K_SCATTER, K_FLIP, K_BRICK_STEP, K_CELL_ROTATE, K_BOX_FINISH, K_NUM
 };
 const char* const kKernName[K_NUM] = {
-    "zero_counts", "count", "scan", "scatter", "flip", "brick_accumulate", "brick_scan",
-    "brick_finalize", "brick_rotate", "cell_rotate", "box_finish"};
+    "mark_holes", "zero_counts", "count", "scan", "scatter", "flip", "brick_step", "cell_rotate",
+    "box_finish"};
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -47,7 +46,7 @@ struct Slot {
     size_t bytes = 0;
     BoxDev dev{};
     int64_t ptiles = 0, ctiles = 0;
-    int32_t part_tile = kPartTile;   // particles per tile
+    int32_t part_tile = kPartTile;   // slots per tile
     double mass_total = 0.0;         // sum of the per-particle masses (MPCD_PARTICLE_MASS)
 };
 
@@ -64,6 +63,8 @@ struct mpcd_ctx {
     int32_t binning = MPCD_BIN_AUTO;
     int32_t brick[3] = {0, 0, 0};
     bool pending_rebucket = false;
+    int* host_flag = nullptr;        // pinned: set by the device when a brick box needs re-bucketing
+    int* host_flag_dev = nullptr;    // its device address
     bool tuning = false;             // this context is an autotuner trial context
     std::map<uint64_t, std::pair<int32_t, std::array<int32_t, 3>>> tuned;   // shape class -> choice
     std::vector<std::pair<std::string, double>> tune_log;                  // last trial timings
@@ -126,17 +127,16 @@ void drop_graph(mpcd_ctx* c)
 
 // Layout of one box's device allocation.
 struct Layout {
-    size_t off_p[2][6], off_v0[2][3], off_pid[2], off_m[2], off_cell, off_rank, off_cstart, off_un, off_part,
-        off_esc, off_eflag, off_bstart[2], off_bcount, off_bcursor, off_outcnt, off_outbase, off_bsize,
-        off_bof[3], off_blo[3], off_vacf, total;
+    size_t off_p[2][6], off_v0[2][3], off_pid[2], off_m[2], off_cell, off_rank, off_cstart, off_un, off_esc[2],
+        off_eflag, off_bstart, off_bsize[2], off_vacf, total;
 };
 
-Layout box_layout(int64_t n, int64_t ncell, bool vacf, int vacf_cap, bool brick, const BrickGeom& g,
+Layout box_layout(int64_t nslot, int64_t ncell, bool vacf, int vacf_cap, bool brick, const BrickGeom& g,
                   bool masses)
 {
     Layout L{};
     size_t o = 0;
-    const size_t pf = align256((size_t)n * 4);
+    const size_t pf = align256((size_t)nslot * 4);
     for (int b = 0; b < 2; ++b)
         for (int d = 0; d < 6; ++d) { L.off_p[b][d] = o; o += pf; }
     for (int b = 0; b < 2; ++b)
@@ -154,21 +154,10 @@ Layout box_layout(int64_t n, int64_t ncell, bool vacf, int vacf_cap, bool brick,
     L.off_cstart = o; o += align256((size_t)(ncell + 1) * 4);
     const size_t nbk = brick ? (size_t)g.nbrick : 0;
     L.off_un = o; o += brick ? align256((size_t)ncell * sizeof(CellUN)) : 0;
-    L.off_part = o; o += align256(nbk * g.wsize * sizeof(CellAcc));
-    L.off_esc = o; o += brick ? align256((size_t)ncell * sizeof(CellAcc)) : 0;
-    L.off_eflag = o; o += align256(nbk * 4);
-    for (int b = 0; b < 2; ++b) { L.off_bstart[b] = o; o += align256((nbk + 1) * 4); }
-    L.off_bcount = o; o += align256(nbk * 4);
-    L.off_bcursor = o; o += align256(nbk * 4);
-    L.off_outcnt = o; o += align256(nbk * 27 * 4);
-    L.off_outbase = o; o += align256(nbk * 27 * 4);
-    L.off_bsize = o; o += align256(nbk * 4);
-    for (int d = 0; d < 3; ++d) {
-        L.off_bof[d] = o;
-        o += brick ? align256((size_t)g.L[d] * 2) : 0;
-        L.off_blo[d] = o;
-        o += brick ? align256((size_t)(g.nb[d] + 1) * 4) : 0;
-    }
+    for (int b = 0; b < 2; ++b) { L.off_esc[b] = o; o += brick ? align256((size_t)ncell * sizeof(CellAcc)) : 0; }
+    L.off_eflag = o; o += align256(2 * nbk * 4);
+    L.off_bstart = o; o += align256((nbk + 2) * 4);
+    for (int b = 0; b < 2; ++b) { L.off_bsize[b] = o; o += align256((nbk + 1) * 4); }
     L.off_vacf = o; o += align256((size_t)std::max(vacf_cap, 1) * 8);
     L.total = o;
     return L;
@@ -219,15 +208,17 @@ int rebuild_tables(mpcd_ctx* c)
     std::vector<Tile> pt, ct, bt;
     std::vector<int32_t> active;
     c->any_brick = c->any_sort = false;
-    int max_wsize = 0;
+    int max_bvol = 0;
+    int64_t max_bucket = 0;
+    bool brick_mass = false;
     for (int s = 0; s < (int)c->slots.size(); ++s) {
         Slot& sl = c->slots[s];
         if (!sl.live) continue;
         active.push_back(s);
         BoxDev& b = sl.dev;
         b.ptile0 = (int32_t)pt.size();
-        for (int64_t i = 0; i < b.n; i += sl.part_tile)
-            pt.push_back(Tile{s, 0, i, std::min<int64_t>(b.n, i + sl.part_tile)});
+        for (int64_t i = 0; i < b.nslot; i += sl.part_tile)
+            pt.push_back(Tile{s, 0, i, std::min<int64_t>(b.nslot, i + sl.part_tile)});
         b.ptile1 = (int32_t)pt.size();
         b.ctile0 = (int32_t)ct.size();
         for (int64_t i = 0; i < b.ncell; i += kCellTile)
@@ -241,13 +232,16 @@ int rebuild_tables(mpcd_ctx* c)
             c->any_sort = true;
         } else {
             c->any_brick = true;
-            max_wsize = std::max(max_wsize, b.wsize);
+            max_bvol = std::max(max_bvol, b.bmax[0] * b.bmax[1] * b.bmax[2]);
+            // a bucket well above the mean (Poisson spread) still fits one chunk
+            const int64_t mean = b.nbrick > 0 ? (b.n + b.nbrick - 1) / b.nbrick : 0;
+            max_bucket = std::max<int64_t>(max_bucket, mean + mean / 4 + 64);
+            brick_mass |= b.m[0] != nullptr;
         }
     }
     const size_t need = align256(pt.size() * sizeof(Tile) + 256) + align256(ct.size() * sizeof(Tile) + 256) +
                         align256(bt.size() * sizeof(Tile) + 256) + align256(active.size() * 4 + 256) +
-                        align256(pt.size() * kNumDiag * 8 + 256) + align256(ct.size() * kNumDiag * 8 + 256) +
-                        align256(bt.size() * kNumDiag * 8 + 256) + align256(ct.size() * 4 + 256);
+                        align256(pt.size() * kNumDiag * 8 + 256) + align256(ct.size() * 4 + 256);
     if (need > c->tile_cap) {
         void* m = ctx_alloc(c, need * 5 / 4);
         if (!m) return MPCD_ENOMEM;
@@ -262,14 +256,15 @@ int rebuild_tables(mpcd_ctx* c)
     c->T.btiles = (Tile*)(base + o); o += align256(bt.size() * sizeof(Tile) + 256);
     c->T.active = (int32_t*)(base + o); o += align256(active.size() * 4 + 256);
     c->T.partials = (long long*)(base + o); o += align256(pt.size() * kNumDiag * 8 + 256);
-    c->T.partials_c = (long long*)(base + o); o += align256(ct.size() * kNumDiag * 8 + 256);
-    c->T.partials_b = (long long*)(base + o); o += align256(bt.size() * kNumDiag * 8 + 256);
     c->T.tilesum = (uint32_t*)(base + o);
     c->T.nptiles = (int)pt.size();
     c->T.nctiles = (int)ct.size();
     c->T.nbtiles = (int)bt.size();
     c->T.nactive = (int)active.size();
-    c->T.max_wsize = max_wsize;
+    c->T.max_bvol = max_bvol;
+    c->T.brick_shape = brick_shape_for(max_bucket);
+    c->T.brick_mass = brick_mass;
+    c->T.host_flag = c->host_flag_dev;
     if (!pt.empty()) HIPCHK(hipMemcpy(c->T.ptiles, pt.data(), pt.size() * sizeof(Tile), hipMemcpyHostToDevice));
     if (!ct.empty()) HIPCHK(hipMemcpy(c->T.ctiles, ct.data(), ct.size() * sizeof(Tile), hipMemcpyHostToDevice));
     if (!bt.empty()) HIPCHK(hipMemcpy(c->T.btiles, bt.data(), bt.size() * sizeof(Tile), hipMemcpyHostToDevice));
@@ -326,7 +321,8 @@ int timed(mpcd_ctx* c, int k, F&& launch)
 }
 
 // The launch sequence of one step for every live box.  with_sort adds the
-// counting sort that buckets freshly admitted / reset brick boxes.
+// counting sort that re-buckets brick boxes flagged for it (fresh state, or
+// a bucket that overflowed).
 int enqueue_step(mpcd_ctx* c, bool with_sort)
 {
     const Tables& T = c->T;
@@ -338,18 +334,16 @@ int enqueue_step(mpcd_ctx* c, bool with_sort)
         if (rc) return rc;                                     \
     } while (0)
     if (c->any_sort || with_sort) {
+        if (with_sort && c->any_brick) {
+            STEP_K(K_MARK, launch_mark_holes(T.ptiles, T.nptiles, T, 0, s); launch_rebucket_clear(T, s));
+        }
         STEP_K(K_ZERO, launch_zero_counts(T, s));
         STEP_K(K_COUNT, launch_count(T, s));
         STEP_K(K_SCAN, launch_scan(T, s));
         STEP_K(K_SCATTER, launch_scatter(T, s));
         STEP_K(K_FLIP, launch_flip(T, s));
     }
-    if (c->any_brick) {
-        STEP_K(K_BRICK_ACC, launch_brick_accumulate(T, s));
-        STEP_K(K_BRICK_SCAN, launch_brick_scan(T, s));
-        STEP_K(K_BRICK_FIN, launch_brick_finalize(T, s));
-        STEP_K(K_BRICK_ROT, launch_brick_rotate(T, s));
-    }
+    if (c->any_brick) STEP_K(K_BRICK_STEP, launch_brick_step(T, s));
     if (c->any_sort) STEP_K(K_CELL_ROTATE, launch_cell_rotate(T, s));
     STEP_K(K_BOX_FINISH, launch_box_finish(T, s));
 #undef STEP_K
@@ -398,6 +392,38 @@ int read_box_partials(mpcd_ctx* c, const Slot& sl, double out[kNumDiag])
     return MPCD_OK;
 }
 
+// Mark the holes of brick box s's current buffer (pid -1), so that host-side
+// passes over all its slots see only particles.
+void mark_holes(mpcd_ctx* c, int32_t s)
+{
+    const Slot& sl = c->slots[s];
+    if (sl.dev.binning != MPCD_BIN_ATOMIC) return;
+    launch_mark_holes(c->T.ptiles + sl.dev.ptile0, sl.dev.ptile1 - sl.dev.ptile0, c->T, 1, c->stream);
+}
+
+// Bucket description of a brick box whose particles sit in slots [0, n) of
+// buffer `parity` in no particular order (all in bucket 0, the rest of the
+// buffer an empty overflow bucket), with no pending escape sums; the next
+// step re-buckets it.
+int set_compact_layout(mpcd_ctx* c, int32_t s, int parity)
+{
+    const Slot& sl = c->slots[s];
+    const BoxDev& b = sl.dev;
+    if (b.binning != MPCD_BIN_ATOMIC) return MPCD_OK;
+    const size_t nbk = (size_t)b.nbrick;
+    std::vector<uint32_t> start(nbk + 2, (uint32_t)b.n), size(nbk + 1, 0u), zero(nbk + 1, 0u);
+    start[0] = 0u;
+    start[nbk + 1] = (uint32_t)b.nslot;
+    size[0] = (uint32_t)b.n;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpy(b.bstart, start.data(), start.size() * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(b.bsize[parity], size.data(), size.size() * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(b.bsize[parity ^ 1], zero.data(), zero.size() * 4, hipMemcpyHostToDevice));
+    for (int k = 0; k < 2; ++k) HIPCHK(hipMemset(b.esc[k], 0, (size_t)b.ncell * sizeof(CellAcc)));
+    HIPCHK(hipMemset(b.eflag, 0, 2 * nbk * 4));
+    return MPCD_OK;
+}
+
 // Write a fresh BoxState for slot s.
 int reset_state(mpcd_ctx* c, int32_t s, int64_t step, int parity)
 {
@@ -422,6 +448,7 @@ int take_snapshot(mpcd_ctx* c, int32_t s, bool new_origin = true)
 {
     Slot& sl = c->slots[s];
     const Tile* tiles = c->T.ptiles + sl.dev.ptile0;
+    mark_holes(c, s);
     launch_snapshot(tiles, sl.dev.ptile1 - sl.dev.ptile0, c->T, new_origin ? 1 : 0, c->stream);
     HIPCHK(hipGetLastError());
     double d[kNumDiag];
@@ -559,10 +586,10 @@ static int autotune(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* binning, int32
     p.vacf_capacity = 0;
     struct Cand { int32_t bin; int32_t b[3]; const char* name; };
     const Cand cands[] = {
-        {MPCD_BIN_ATOMIC, {8, 8, 8}, "brick8x8x8"},
-        {MPCD_BIN_ATOMIC, {16, 8, 8}, "brick16x8x8"},
-        {MPCD_BIN_ATOMIC, {6, 6, 6}, "brick6x6x6"},
         {MPCD_BIN_ATOMIC, {4, 4, 4}, "brick4x4x4"},
+        {MPCD_BIN_ATOMIC, {8, 4, 4}, "brick8x4x4"},
+        {MPCD_BIN_ATOMIC, {8, 8, 4}, "brick8x8x4"},
+        {MPCD_BIN_ATOMIC, {8, 8, 8}, "brick8x8x8"},
         {MPCD_BIN_SORT, {0, 0, 0}, "sort"},
     };
     c->tune_log.clear();
@@ -612,7 +639,7 @@ int mpcd_create(const mpcd_options* opt, mpcd_ctx** out)
     if (opt) o = *opt;
     if (o.binning < 0 || o.binning > 2 || o.hbm_budget < 0 || o.max_slots < 0) return MPCD_EINVAL;
     for (int d = 0; d < 3; ++d)
-        if (o.brick[d] != 0 && (o.brick[d] < 2 || o.brick[d] > 64)) return MPCD_EINVAL;
+        if (!brick_edge_ok(o.brick[d])) return MPCD_EINVAL;
     if (o.block != 0) return MPCD_EINVAL;
     if ((o.alloc == nullptr) != (o.free == nullptr)) return MPCD_EINVAL;
     int ndev = 0;
@@ -638,15 +665,33 @@ int mpcd_create(const mpcd_options* opt, mpcd_ctx** out)
         }
         c->own_stream = true;
     }
-    const size_t tab = align256(sizeof(BoxDev) * c->max_slots) + align256(sizeof(BoxState) * c->max_slots);
+    const size_t tab = align256(sizeof(BoxDev) * c->max_slots) + align256(sizeof(BoxState) * c->max_slots) +
+                       align256(sizeof(long long) * kAccLanes * 3 * c->max_slots);
     c->tab_mem = ctx_alloc(c, tab);
     if (!c->tab_mem) {
         if (c->own_stream) (void)hipStreamDestroy(c->stream);
         delete c;
         return MPCD_ENOMEM;
     }
+    if (hipHostMalloc((void**)&c->host_flag, sizeof(int), hipHostMallocMapped) != hipSuccess ||
+        hipHostGetDevicePointer((void**)&c->host_flag_dev, c->host_flag, 0) != hipSuccess) {
+        if (c->host_flag) (void)hipHostFree(c->host_flag);
+        ctx_free(c, c->tab_mem);
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
+        delete c;
+        return MPCD_EDEVICE;
+    }
+    *c->host_flag = 0;
     c->T.boxes = (BoxDev*)c->tab_mem;
     c->T.state = (BoxState*)((char*)c->tab_mem + align256(sizeof(BoxDev) * c->max_slots));
+    c->T.dacc = (long long*)((char*)c->T.state + align256(sizeof(BoxState) * c->max_slots));
+    if (hipMemset(c->T.dacc, 0, sizeof(long long) * kAccLanes * 3 * c->max_slots) != hipSuccess) {
+        ctx_free(c, c->tab_mem);
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
+        (void)hipHostFree(c->host_flag);
+        delete c;
+        return MPCD_EDEVICE;
+    }
     *out = c;
     return MPCD_OK;
 }
@@ -674,11 +719,15 @@ int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
         rc = autotune(c, d, &binning, want);
         if (rc) return rc;
     }
+    BrickGeom g = brick_geometry(d->L, want);
+    if (binning == MPCD_BIN_ATOMIC && g.bvol > kMaxBrickCells) return MPCD_EINVAL;
+    // slot byte offsets are 32-bit: very large boxes use the counting sort
+    if (binning == MPCD_BIN_ATOMIC && brick_slots(d->n_particles, g.nbrick) >= ((int64_t)1 << 30))
+        binning = MPCD_BIN_SORT;
     const bool brick = binning == MPCD_BIN_ATOMIC;
-    const BrickGeom g = brick_geometry(d->L, want);
-    if (brick && g.wsize > max_window_records()) return MPCD_EINVAL;
+    const int64_t nslot = brick ? brick_slots(d->n_particles, g.nbrick) : d->n_particles;
     const bool masses = (d->flags & MPCD_PARTICLE_MASS) != 0;
-    const Layout L = box_layout(d->n_particles, ncell, vacf, cap, brick, g, masses);
+    const Layout L = box_layout(nslot, ncell, vacf, cap, brick, g, masses);
     if (c->budget > 0 && c->used + (int64_t)L.total > c->budget) return MPCD_ENOMEM;
     HIPCHK(hipSetDevice(c->device));
     void* mem = ctx_alloc(c, L.total);
@@ -701,27 +750,19 @@ int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
     b.rank = (uint32_t*)(m + L.off_rank);
     b.cstart = (uint32_t*)(m + L.off_cstart);
     b.un = brick ? (CellUN*)(m + L.off_un) : nullptr;
-    b.part = brick ? (CellAcc*)(m + L.off_part) : nullptr;
-    b.esc = brick ? (CellAcc*)(m + L.off_esc) : nullptr;
-    b.eflag = brick ? (uint32_t*)(m + L.off_eflag) : nullptr;
-    for (int p = 0; p < 2; ++p) b.bstart[p] = brick ? (uint32_t*)(m + L.off_bstart[p]) : nullptr;
-    b.bcount = brick ? (uint32_t*)(m + L.off_bcount) : nullptr;
-    b.bcursor = brick ? (uint32_t*)(m + L.off_bcursor) : nullptr;
-    b.outcnt = brick ? (uint32_t*)(m + L.off_outcnt) : nullptr;
-    b.outbase = brick ? (uint32_t*)(m + L.off_outbase) : nullptr;
-    b.bsize = brick ? (uint32_t*)(m + L.off_bsize) : nullptr;
-    for (int k = 0; k < 3; ++k) {
-        b.bof[k] = brick ? (uint16_t*)(m + L.off_bof[k]) : nullptr;
-        b.blo[k] = brick ? (int32_t*)(m + L.off_blo[k]) : nullptr;
+    for (int p = 0; p < 2; ++p) {
+        b.esc[p] = brick ? (CellAcc*)(m + L.off_esc[p]) : nullptr;
+        b.bsize[p] = brick ? (uint32_t*)(m + L.off_bsize[p]) : nullptr;
     }
+    b.eflag = brick ? (uint32_t*)(m + L.off_eflag) : nullptr;
+    b.bstart = brick ? (uint32_t*)(m + L.off_bstart) : nullptr;
     for (int k = 0; k < 3; ++k) {
         b.nb[k] = brick ? g.nb[k] : 1;
+        b.bshift[k] = brick ? g.shift[k] : 0;
         b.bmax[k] = brick ? g.bmax[k] : d->L[k];
-        b.wdim[k] = brick ? g.wdim[k] : 0;
     }
-    b.margin = g.margin;
-    b.wsize = brick ? g.wsize : 0;
     b.nbrick = brick ? g.nbrick : 0;
+    b.nslot = nslot;
     b.vacf = (double*)(m + L.off_vacf);
     b.n = d->n_particles;
     b.ncell = ncell;
@@ -758,25 +799,10 @@ int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
     // zeroed cell accumulators and a defined particle state
     Slot& S = c->slots[s];
     if (brick) {
-        const size_t nbk = (size_t)S.dev.nbrick;
-        if (hipMemsetAsync(S.dev.un, 0, ncell * sizeof(CellUN), c->stream) != hipSuccess ||
-            hipMemsetAsync(S.dev.esc, 0, ncell * sizeof(CellAcc), c->stream) != hipSuccess ||
-            hipMemsetAsync(S.dev.eflag, 0, nbk * 4, c->stream) != hipSuccess ||
-            hipMemsetAsync(S.dev.bcount, 0, nbk * 4, c->stream) != hipSuccess ||
-            hipMemsetAsync(S.dev.bstart[0], 0, (nbk + 1) * 4, c->stream) != hipSuccess ||
-            hipMemsetAsync(S.dev.bstart[1], 0, (nbk + 1) * 4, c->stream) != hipSuccess)
+        if (hipMemsetAsync(S.dev.un, 0, ncell * sizeof(CellUN), c->stream) != hipSuccess)
             return undo(MPCD_EDEVICE);
-        // brick tables: brick of every cell and first cell of every brick
-        if (hipStreamSynchronize(c->stream) != hipSuccess) return undo(MPCD_EDEVICE);
-        for (int k = 0; k < 3; ++k) {
-            std::vector<uint16_t> bof((size_t)d->L[k]);
-            std::vector<int32_t> blo((size_t)g.nb[k] + 1);
-            for (int cc = 0; cc < d->L[k]; ++cc) bof[cc] = (uint16_t)brick_of(cc, d->L[k], g.nb[k]);
-            for (int i = 0; i <= g.nb[k]; ++i) blo[i] = brick_lo(i, d->L[k], g.nb[k]);
-            if (hipMemcpy(S.dev.bof[k], bof.data(), bof.size() * 2, hipMemcpyHostToDevice) != hipSuccess ||
-                hipMemcpy(S.dev.blo[k], blo.data(), blo.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
-                return undo(MPCD_EDEVICE);
-        }
+        rc = set_compact_layout(c, s, 0);
+        if (rc) return undo(rc);
     }
     rc = reset_state(c, s, 0, 0);
     if (rc) return undo(rc);
@@ -788,7 +814,7 @@ int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
         rc = init_maxwell(c, s);
     } else {
         for (int k = 0; k < 6; ++k)
-            if (hipMemsetAsync(S.dev.p[0][k], 0, (size_t)S.dev.n * 4, c->stream) != hipSuccess)
+            if (hipMemsetAsync(S.dev.p[0][k], 0, (size_t)S.dev.nslot * 4, c->stream) != hipSuccess)
                 return undo(MPCD_EDEVICE);
         launch_fill_iota(S.dev.pid[0], S.dev.n, c->stream);
     }
@@ -810,6 +836,9 @@ int mpcd_step(mpcd_ctx* c, int32_t n)
         int rc = rebuild_tables(c);
         if (rc) return rc;
     }
+    // a bucket overflowed in an earlier step: the boxes concerned carry the
+    // rebucket flag; re-bucket them in the next step
+    if (__atomic_exchange_n(c->host_flag, 0, __ATOMIC_ACQ_REL) != 0) c->pending_rebucket = true;
     if (c->pending_rebucket) {   // bucket fresh brick boxes, then one eager step
         int rc = enqueue_step(c, true);
         if (rc) return rc;
@@ -842,6 +871,13 @@ int mpcd_observe(mpcd_ctx* c, int32_t slot, mpcd_observables* out)
     Slot* sl = live_slot(c, slot);
     if (!sl) return MPCD_ENOTFOUND;
     HIPCHK(hipSetDevice(c->device));
+    if (c->dirty) {
+        int rc = rebuild_tables(c);
+        if (rc) return rc;
+    }
+    // momentum and energy of the current state (exact sums over the box)
+    int rc = take_snapshot(c, slot, false);
+    if (rc) return rc;
     BoxState st;
     HIPCHK(hipMemcpyAsync(&st, &c->T.state[slot], sizeof(BoxState), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -868,6 +904,8 @@ int mpcd_observe(mpcd_ctx* c, int32_t slot, mpcd_observables* out)
     out->n_particles = n;
     out->binning = sl->dev.binning;
     for (int d = 0; d < 3; ++d) out->brick[d] = sl->dev.binning == MPCD_BIN_ATOMIC ? sl->dev.bmax[d] : 0;
+    out->overflow_steps = st.overflow_steps;
+    out->rebuckets = st.rebuckets;
     return out->status;
 }
 
@@ -880,18 +918,26 @@ int mpcd_get_state(mpcd_ctx* c, int32_t slot, float* xyzv, int64_t* step)
     BoxState st;
     HIPCHK(hipMemcpyAsync(&st, &c->T.state[slot], sizeof(BoxState), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
-    const int64_t n = sl->dev.n;
-    c->stage.resize((size_t)n);
-    c->stage_pid.resize((size_t)n);
+    const int64_t n = sl->dev.n, ns = sl->dev.nslot;
+    mark_holes(c, slot);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->stage.resize((size_t)ns);
+    c->stage_pid.resize((size_t)ns);
     if (n > 0) {
-        HIPCHK(hipMemcpy(c->stage_pid.data(), sl->dev.pid[st.parity], (size_t)n * 4, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(c->stage_pid.data(), sl->dev.pid[st.parity], (size_t)ns * 4, hipMemcpyDeviceToHost));
+        int64_t seen = 0;
+        for (int64_t i = 0; i < ns; ++i) {
+            const int32_t id = c->stage_pid[i];
+            if (id >= n) return MPCD_ESTATE;
+            seen += id >= 0;
+        }
+        if (seen != n) return MPCD_ESTATE;
         for (int d = 0; d < 6; ++d) {
-            HIPCHK(hipMemcpy(c->stage.data(), sl->dev.p[st.parity][d], (size_t)n * 4, hipMemcpyDeviceToHost));
+            HIPCHK(hipMemcpy(c->stage.data(), sl->dev.p[st.parity][d], (size_t)ns * 4, hipMemcpyDeviceToHost));
             float* dst = xyzv + (size_t)d * n;
-            for (int64_t i = 0; i < n; ++i) {
+            for (int64_t i = 0; i < ns; ++i) {
                 const int32_t id = c->stage_pid[i];
-                if (id < 0 || id >= n) return MPCD_ESTATE;
-                dst[id] = c->stage[i];
+                if (id >= 0) dst[id] = c->stage[i];
             }
         }
     }
@@ -919,7 +965,8 @@ int mpcd_set_state(mpcd_ctx* c, int32_t slot, const float* xyzv, int64_t step)
         BoxState st;
         HIPCHK(hipMemcpy(&st, &c->T.state[slot], sizeof(BoxState), hipMemcpyDeviceToHost));
         const int par = st.parity;
-        launch_permute_f32(sl->dev.m[par ^ 1], sl->dev.m[par], sl->dev.pid[par], n, 1, c->stream);
+        mark_holes(c, slot);
+        launch_permute_f32(sl->dev.m[par ^ 1], sl->dev.m[par], sl->dev.pid[par], sl->dev.nslot, n, 1, c->stream);
         if (par == 0)
             HIPCHK(hipMemcpyAsync(sl->dev.m[0], sl->dev.m[1], (size_t)n * 4, hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
@@ -929,6 +976,10 @@ int mpcd_set_state(mpcd_ctx* c, int32_t slot, const float* xyzv, int64_t step)
             HIPCHK(hipMemcpy(sl->dev.p[0][d], xyzv + (size_t)d * n, (size_t)n * 4, hipMemcpyHostToDevice));
         launch_fill_iota(sl->dev.pid[0], n, c->stream);
         HIPCHK(hipGetLastError());
+    }
+    {
+        int rc = set_compact_layout(c, slot, 0);
+        if (rc) return rc;
     }
     int rc = reset_state(c, slot, step, 0);
     if (rc) return rc;
@@ -957,8 +1008,9 @@ int mpcd_set_mass(mpcd_ctx* c, int32_t slot, const float* mass)
         HIPCHK(hipMemcpy(&st, &c->T.state[slot], sizeof(BoxState), hipMemcpyDeviceToHost));
         const int par = st.parity;
         // stage the id-ordered masses in the idle buffer, then gather by id
-        HIPCHK(hipMemcpy(sl->dev.m[par ^ 1], mass, (size_t)n * 4, hipMemcpyHostToDevice));
-        launch_permute_f32(sl->dev.m[par], sl->dev.m[par ^ 1], sl->dev.pid[par], n, 0, c->stream);
+        mark_holes(c, slot);
+        HIPCHK(hipMemcpyAsync(sl->dev.m[par ^ 1], mass, (size_t)n * 4, hipMemcpyHostToDevice, c->stream));
+        launch_permute_f32(sl->dev.m[par], sl->dev.m[par ^ 1], sl->dev.pid[par], sl->dev.nslot, n, 0, c->stream);
         HIPCHK(hipGetLastError());
     }
     sl->mass_total = total;
@@ -1030,6 +1082,7 @@ void mpcd_destroy(mpcd_ctx* c)
         if (sl.live) ctx_free(c, sl.mem);
     ctx_free(c, c->tile_mem);
     ctx_free(c, c->tab_mem);
+    if (c->host_flag) (void)hipHostFree(c->host_flag);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;

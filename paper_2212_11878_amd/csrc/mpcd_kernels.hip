@@ -3,18 +3,17 @@
 // One step of a box (paper Sec. 2; shifted grid of Sec. 3.1, Listing 1;
 // mass-weighted cell velocity of Sec. 3.3, Listing 4) runs as:
 //
-//   ATOMIC binning (particles bucketed by brick of cells)
-//     k_brick_accumulate  per brick: stream, bin into the brick's window,
-//                         LDS-atomic exact cell sums, write window partials,
-//                         count next-step buckets
-//     k_brick_sizes/scan/offsets  next bucket sizes and starts, and where
-//                         each source brick's movers start in them
-//     k_brick_finalize    per cell: add the window partials (and escapes),
-//                         u_c = sum v / n, axis n_c from Philox
-//     k_brick_rotate      per brick: stream again (same arithmetic), rotate
-//                         v <- u_c + R(n_c, alpha)(v - u_c), write the
-//                         particle into its next bucket; FP64 diagnostics
-//     k_box_finish        per box: reduce diagnostics, VACF sample, k++
+//   ATOMIC binning (particles bucketed by the brick of their collision cell)
+//     k_brick_step        per brick, one pass: stream, exact LDS cell sums,
+//                         u_c = sum(m v)/sum(m) and axis n_c from Philox,
+//                         v <- u_c + R(n_c, alpha)(v - u_c), then the particle
+//                         goes straight into the bucket of the brick holding
+//                         its next-step collision cell; FP64 diagnostics
+//     k_box_finish        per box: particles of the overflow bucket (rare),
+//                         reduce diagnostics, VACF sample, k++
+//   Re-bucketing (after admission / set_state, or when a bucket overflowed):
+//     k_mark_holes, k_rebucket_clear, then the counting sort below keyed by
+//     brick, which also sets the bucket capacities
 //
 //   SORT binning (counting sort by collision cell every step)
 //     zero, k_count (streamed collision cell + rank), scan, k_scatter (streams
@@ -23,8 +22,8 @@
 //
 // Both paths sum the momentum of a cell exactly (64-bit fixed point), so
 // they produce bit-identical velocities whatever the order of the atomics.
-// All kernels grid over "tiles" (contiguous particle, cell or brick ranges of
-// one box), which lets one launch advance many boxes of different sizes.
+// All kernels grid over "tiles" (contiguous slot, cell or brick ranges of one
+// box), which lets one launch advance many boxes of different sizes.
 #include "mpcd_dev.h"
 #include "mpcd_launch.h"
 
@@ -35,11 +34,29 @@ namespace mpcd {
 
 __device__ __forceinline__ bool box_idle(const BoxState& s) { return s.remaining == 0; }
 
+// Values the whole workgroup shares (read from the box tables), made
+// explicitly uniform so that addresses derived from them stay in scalar
+// registers.
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ long long uniform(long long v)
+{
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v & 0xffffffffll));
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)((unsigned long long)v >> 32));
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
 // The counting sort runs every step for SORT boxes, and once for brick
 // boxes whose particles are not bucketed yet (after admission / set_state).
 __device__ __forceinline__ bool sort_due(const BoxDev& b, const BoxState& s)
 {
     return b.binning == 2 || s.rebucket != 0;
+}
+
+// Slots the counting sort reserves for key c holding n particles: n for
+// cells (SORT), n plus slack for bricks (brick boxes re-bucketing).
+__device__ __forceinline__ uint32_t key_capacity(const BoxDev& b, int64_t c, uint32_t n)
+{
+    return (b.binning == 1 && c < b.nbrick) ? n + bucket_slack(n) : n;
 }
 
 __device__ __forceinline__ bool vacf_due(const BoxDev& b, const BoxState& s)
@@ -55,9 +72,10 @@ __device__ __forceinline__ long long wave_sum(long long v)
 }
 
 // Block sum of kNumDiag exact partials; threads 0..kNumDiag-1 write out[].
+template <int kT = kBlock>
 __device__ __forceinline__ void block_diag(long long (&d)[kNumDiag], long long* out)
 {
-    __shared__ long long red[kBlock / kWave][kNumDiag];
+    __shared__ long long red[kT / kWave][kNumDiag];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
 #pragma unroll
     for (int j = 0; j < kNumDiag; ++j) {
@@ -67,9 +85,35 @@ __device__ __forceinline__ void block_diag(long long (&d)[kNumDiag], long long* 
     __syncthreads();
     if (threadIdx.x < kNumDiag) {
         long long v = 0;
-        for (int i = 0; i < kBlock / kWave; ++i) v += red[i][threadIdx.x];
+        for (int i = 0; i < kT / kWave; ++i) v += red[i][threadIdx.x];
         out[threadIdx.x] = v;
     }
+}
+
+// End of a step kernel's workgroup: add its exact VACF partial (on sampled
+// steps) and a range-violation mark to the box's accumulators.  Atomic
+// integer adds are exact, so the order does not matter; the workgroups are
+// spread over kAccLanes lanes per box (high and low 32-bit halves of the
+// VACF sum, so no lane can overflow).
+template <int kT = kBlock>
+__device__ __forceinline__ void step_flush(const long long (&d)[kNumDiag], bool vacf, long long* acc, int lane_sel)
+{
+    __shared__ long long red[kT / kWave];
+    const int any = __syncthreads_or(d[5] != 0);
+    long long* a = acc + (size_t)(lane_sel & (kAccLanes - 1)) * 3;
+    if (vacf) {
+        const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+        const long long v = wave_sum(d[4]);
+        if (lane == 0) red[w] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            long long t = 0;
+            for (int i = 0; i < kT / kWave; ++i) t += red[i];
+            gatomic_add(gp(a), t >> 32);
+            gatomic_add(gp(a) + 1, (long long)(unsigned long long)(unsigned)(t & 0xffffffffll));
+        }
+    }
+    if (any && threadIdx.x == 0) gatomic_add(gp(a) + 2, 1ll);
 }
 
 // Block-wide exclusive scan of one uint32 per thread; returns the prefix and
@@ -101,401 +145,520 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* t
 // --------------------------------------------------------------------------
 // ATOMIC (brick) path
 
-__global__ __launch_bounds__(kBlock) void k_brick_accumulate(const Tile* __restrict__ tiles,
-                                                              const BoxDev* __restrict__ boxes,
-                                                              const BoxState* __restrict__ st)
+// Element at byte offset o of a global array (a 32-bit offset from a
+// uniform base lets one address register serve every array of a slot).
+template <class T>
+__device__ __forceinline__ T ldg(const MPCD_G T* p, uint32_t o)
 {
-    extern __shared__ CellAcc win[];
-    __shared__ uint32_t cnt[27];
-    const Tile tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];
-    const BoxState s = st[tl.box];
-    const BoxDev& b = boxes[tl.box];
-    if (box_idle(s) || b.binning != 1) return;
-    const int brick = (int)tl.begin;
-    const int bx = brick % b.nb[0], by = (brick / b.nb[0]) % b.nb[1], bz = brick / (b.nb[0] * b.nb[1]);
-    const int m = b.margin;
-    const int lox = b.blo[0][bx], loy = b.blo[1][by], loz = b.blo[2][bz];
-    const int ex = b.blo[0][bx + 1] - lox + 2 * m;   // window extents
-    const int ey = b.blo[1][by + 1] - loy + 2 * m;
-    const int ez = b.blo[2][bz + 1] - loz + 2 * m;
-    const int wx = b.wdim[0], wy = b.wdim[1];
-    for (int i = threadIdx.x; i < b.wsize; i += kBlock) {
-        CellAcc z = {0ull, 0ull, 0ull, 0ull};
-        win[i] = z;
-    }
-    if (threadIdx.x < 27) cnt[threadIdx.x] = 0u;
-    __syncthreads();
-
-    const int par = s.parity;
-    const MPCD_G float* __restrict__ x = gp(b.p[par][0]);
-    const MPCD_G float* __restrict__ y = gp(b.p[par][1]);
-    const MPCD_G float* __restrict__ z = gp(b.p[par][2]);
-    const MPCD_G float* __restrict__ vx = gp(b.p[par][3]);
-    const MPCD_G float* __restrict__ vy = gp(b.p[par][4]);
-    const MPCD_G float* __restrict__ vz = gp(b.p[par][5]);
-    const float* __restrict__ mp = b.m[par];
-    MPCD_G CellAcc* __restrict__ esc = gp(b.esc);
-    MPCD_G uint32_t* __restrict__ bcount = gp(b.bcount);
-    const float3 sh = grid_shift(b, s.k);
-    const float dt = b.dt;
-    const uint32_t stamp = (uint32_t)(s.k + 1);
-    const int64_t beg = b.bstart[par][brick], end = b.bstart[par][brick + 1];
-    constexpr int kU = 8;   // particles per thread in flight
-    for (int64_t base = beg; base < end; base += (int64_t)kBlock * kU) {
-        float qx[kU], qy[kU], qz[kU], qvx[kU], qvy[kU], qvz[kU], qm[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {   // issue every load first
-            const int64_t i = base + u * kBlock + threadIdx.x;
-            const bool ok = i < end;
-            const int64_t j = ok ? i : beg;
-            qx[u] = x[j];
-            qy[u] = y[j];
-            qz[u] = z[j];
-            qvx[u] = vx[j];
-            qvy[u] = vy[j];
-            qvz[u] = vz[j];
-            qm[u] = mp ? gp(mp)[j] : 1.0f;
-        }
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int64_t i = base + u * kBlock + threadIdx.x;
-            if (i >= end) continue;
-            const float ux = qvx[u], uy = qvy[u], uz = qvz[u];
-            const float px = fold(fmaf(ux, dt, qx[u]), b.len[0]);
-            const float py = fold(fmaf(uy, dt, qy[u]), b.len[1]);
-            const float pz = fold(fmaf(uz, dt, qz[u]), b.len[2]);
-            const int cx = axis_cell(px, sh.x, b.inv_a, b.L[0]);
-            const int cy = axis_cell(py, sh.y, b.inv_a, b.L[1]);
-            const int cz = axis_cell(pz, sh.z, b.inv_a, b.L[2]);
-            const int lx = window_offset(cx, lox, m, b.L[0]);
-            const int ly = window_offset(cy, loy, m, b.L[1]);
-            const int lz = window_offset(cz, loz, m, b.L[2]);
-            const float mi = qm[u];
-            const unsigned long long fx = to_fixed(mi * ux), fy = to_fixed(mi * uy), fz = to_fixed(mi * uz);
-            const unsigned long long fw = to_fixed(mi);
-            if (lx < ex && ly < ey && lz < ez) {
-                CellAcc* w = &win[lx + wx * (ly + wy * lz)];
-                atomicAdd(&w->sx, fx);
-                atomicAdd(&w->sy, fy);
-                atomicAdd(&w->sz, fz);
-                atomicAdd(&w->w, fw);
-            } else {   // left the window: exact global sums, flag the owner brick
-                const uint32_t c = (uint32_t)cx + (uint32_t)b.L[0] * ((uint32_t)cy + (uint32_t)b.L[1] * (uint32_t)cz);
-                gatomic_add(&esc[c].sx, fx);
-                gatomic_add(&esc[c].sy, fy);
-                gatomic_add(&esc[c].sz, fz);
-                gatomic_add(&esc[c].w, fw);
-                const int ob = b.bof[0][cx] + b.nb[0] * (b.bof[1][cy] + b.nb[1] * b.bof[2][cz]);
-                gp(b.eflag)[ob] = stamp;
-            }
-            // bucket of the streamed position for the next step
-            const int3 d = brick_of_pos(b, px, py, pz);
-            const int rx = brick_rel(bx, d.x, b.nb[0]), ry = brick_rel(by, d.y, b.nb[1]),
-                      rz = brick_rel(bz, d.z, b.nb[2]);
-            if (rx <= 1 && ry <= 1 && rz <= 1)
-                atomicAdd(&cnt[(rx + 1) + 3 * ((ry + 1) + 3 * (rz + 1))], 1u);
-            else
-                gatomic_add(&bcount[d.x + b.nb[0] * (d.y + b.nb[1] * d.z)], 1u);
-        }
-    }
-    __syncthreads();
-    MPCD_G CellAcc* __restrict__ out = gp(b.part) + (size_t)brick * b.wsize;
-    for (int i = threadIdx.x; i < b.wsize; i += kBlock) store_acc(out + i, win[i]);
-    if (threadIdx.x < 27) gp(b.outcnt)[(size_t)brick * 27 + threadIdx.x] = cnt[threadIdx.x];
+    return *(const MPCD_G T*)((const MPCD_G char*)p + o);
+}
+template <class T>
+__device__ __forceinline__ void stg(MPCD_G T* p, uint32_t o, T v)
+{
+    *(MPCD_G T*)((MPCD_G char*)p + o) = v;
 }
 
-// bucket sizes of the next step: the neighbour groups plus the far particles
-__global__ __launch_bounds__(kBlock) void k_brick_sizes(const Tile* __restrict__ tiles, int ntiles,
-                                                         const BoxDev* __restrict__ boxes,
-                                                         const BoxState* __restrict__ st)
+// Collision cell, at step k+1, of a particle at (x, y, z) that leaves step k
+// with velocity v: the stream of step k+1 and its shifted grid (the same
+// arithmetic the next step applies).
+__device__ __forceinline__ int3 next_cell(const BoxDev& b, float x, float y, float z, float3 v, float3 sh1)
 {
-    const int t = blockIdx.x * kBlock + threadIdx.x;
-    if (t >= ntiles) return;
-    const Tile tl = tiles[t];
-    const BoxState s = st[tl.box];
-    const BoxDev& b = boxes[tl.box];
-    if (box_idle(s) || b.binning != 1) return;
-    const int d = (int)tl.begin;
-    const int dx = d % b.nb[0], dy = (d / b.nb[0]) % b.nb[1], dz = d / (b.nb[0] * b.nb[1]);
-    uint32_t n = gp(b.bcount)[d];
-    for (int r = 0; r < 27; ++r) {   // source of group r of bucket d: d - offset(r)
-        const int sx = brick_nbr(dx, 1 - r % 3, b.nb[0]);
-        const int sy = brick_nbr(dy, 1 - (r / 3) % 3, b.nb[1]);
-        const int sz = brick_nbr(dz, 1 - r / 9, b.nb[2]);
-        if (sx < 0 || sy < 0 || sz < 0) continue;
-        n += gp(b.outcnt)[(size_t)(sx + b.nb[0] * (sy + b.nb[1] * sz)) * 27 + r];
-    }
-    gp(b.bsize)[d] = n;
+    const float qx = fold(fmaf(v.x, b.dt, x), b.len[0]);
+    const float qy = fold(fmaf(v.y, b.dt, y), b.len[1]);
+    const float qz = fold(fmaf(v.z, b.dt, z), b.len[2]);
+    return make_int3(axis_cell(qx, sh1.x, b.inv_a, b.L[0]), axis_cell(qy, sh1.y, b.inv_a, b.L[1]),
+                     axis_cell(qz, sh1.z, b.inv_a, b.L[2]));
 }
 
-// per box: bucket starts of the next buffer, far-particle cursors, reset
-__global__ __launch_bounds__(kBlock) void k_brick_scan(const int32_t* __restrict__ active,
-                                                        const BoxDev* __restrict__ boxes,
-                                                        const BoxState* __restrict__ st)
+__device__ __forceinline__ int3 brick_of_cell(const BoxDev& b, int3 c)
 {
-    const int bx = active[blockIdx.x];
-    const BoxState s = st[bx];
-    const BoxDev& b = boxes[bx];
-    if (box_idle(s) || b.binning != 1) return;
-    const int nb = b.nbrick;
-    const int per = (nb + kBlock - 1) / kBlock;
-    const int lo = min(nb, (int)threadIdx.x * per), hi = min(nb, ((int)threadIdx.x + 1) * per);
-    uint32_t v = 0;
-    for (int i = lo; i < hi; ++i) v += gp(b.bsize)[i];
-    uint32_t total;
-    uint32_t run = block_exclusive_scan(v, &total);
-    MPCD_G uint32_t* __restrict__ next = gp(b.bstart[s.parity ^ 1]);
-    for (int i = lo; i < hi; ++i) {
-        const uint32_t c = gp(b.bsize)[i];
-        next[i] = run;
-        gp(b.bcursor)[i] = run + c - gp(b.bcount)[i];   // far particles fill the bucket's end
-        gp(b.bcount)[i] = 0u;
-        run += c;
-    }
-    if (threadIdx.x == 0) next[nb] = total;
+    return make_int3(brick_of(c.x, b.bshift[0]), brick_of(c.y, b.bshift[1]), brick_of(c.z, b.bshift[2]));
 }
 
-// where the particles of source brick b heading for neighbour r start in
-// that neighbour's bucket: groups are laid out in r order
-__global__ __launch_bounds__(kBlock) void k_brick_offsets(const Tile* __restrict__ tiles, int ntiles,
-                                                           const BoxDev* __restrict__ boxes,
-                                                           const BoxState* __restrict__ st)
+// One slot of bucket `dest` of buffer `dst`, reserved alone; false when the
+// bucket is full.
+__device__ __forceinline__ bool place_single(const BoxDev& b, int dst, uint32_t dest, uint32_t* j)
 {
-    const int g = blockIdx.x * kBlock + threadIdx.x;   // (brick tile, r) pairs
-    const int t = g / 27, r = g % 27;
-    if (t >= ntiles) return;
-    const Tile tl = tiles[t];
-    const BoxState s = st[tl.box];
-    const BoxDev& b = boxes[tl.box];
-    if (box_idle(s) || b.binning != 1) return;
-    const int src = (int)tl.begin;
-    const int sx = src % b.nb[0], sy = (src / b.nb[0]) % b.nb[1], sz = src / (b.nb[0] * b.nb[1]);
-    const int dx = brick_nbr(sx, r % 3 - 1, b.nb[0]);
-    const int dy = brick_nbr(sy, (r / 3) % 3 - 1, b.nb[1]);
-    const int dz = brick_nbr(sz, r / 9 - 1, b.nb[2]);
-    uint32_t off = 0;
-    if (dx >= 0 && dy >= 0 && dz >= 0) {
-        const int d = dx + b.nb[0] * (dy + b.nb[1] * dz);
-        off = gp(b.bstart[s.parity ^ 1])[d];
-        for (int q = 0; q < r; ++q) {   // earlier groups of bucket d
-            const int ex = brick_nbr(dx, 1 - q % 3, b.nb[0]);
-            const int ey = brick_nbr(dy, 1 - (q / 3) % 3, b.nb[1]);
-            const int ez = brick_nbr(dz, 1 - q / 9, b.nb[2]);
-            if (ex < 0 || ey < 0 || ez < 0) continue;
-            off += gp(b.outcnt)[(size_t)(ex + b.nb[0] * (ey + b.nb[1] * ez)) * 27 + q];
-        }
+    const uint32_t p = gatomic_add(gp(b.bsize[dst]) + dest, 1u);
+    const uint32_t b0 = gp(b.bstart)[dest];
+    if (p < gp(b.bstart)[dest + 1] - b0) {
+        *j = b0 + p;
+        return true;
     }
-    gp(b.outbase)[(size_t)src * 27 + r] = off;
+    return false;
 }
 
-__global__ __launch_bounds__(kBlock) void k_brick_finalize(const Tile* __restrict__ tiles,
-                                                            const BoxDev* __restrict__ boxes,
-                                                            const BoxState* __restrict__ st)
+// A slot of the overflow bucket of buffer `dst` for a particle whose bucket
+// is full.  Its share of the next step's cell sums (cell nc, mass m, velocity
+// v) goes to the exact escape sums of step k+1, and the brick owning nc is
+// flagged to add them.  False only when the overflow bucket is full, which
+// its capacity (every particle of the box) rules out.
+__device__ __forceinline__ bool place_overflow(const BoxDev& b, int dst, long long k, int3 nc, float m,
+                                               float3 v, uint32_t* j)
 {
-    const Tile tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];
-    const BoxState s = st[tl.box];
-    const BoxDev& b = boxes[tl.box];
-    if (box_idle(s) || b.binning != 1) return;
-    const int m = b.margin;
-    const uint32_t stamp = (uint32_t)(s.k + 1);
-    const uint32_t L0 = (uint32_t)b.L[0], L01 = (uint32_t)b.L[0] * (uint32_t)b.L[1];
-    for (int64_t c = tl.begin + threadIdx.x; c < tl.end; c += kBlock) {
-        const uint32_t cu = (uint32_t)c;
-        const int cz = (int)(cu / L01);
-        const uint32_t rem = cu - (uint32_t)cz * L01;
-        const int cy = (int)(rem / L0);
-        const int cx = (int)(rem - (uint32_t)cy * L0);
-        int bxs[3], lxs[3], bys[3], lys[3], bzs[3], lzs[3];
-        const int nx = windows_of_tab(cx, b.L[0], b.nb[0], m, b.bof[0], b.blo[0], bxs, lxs);
-        const int ny = windows_of_tab(cy, b.L[1], b.nb[1], m, b.bof[1], b.blo[1], bys, lys);
-        const int nz = windows_of_tab(cz, b.L[2], b.nb[2], m, b.bof[2], b.blo[2], bzs, lzs);
-        unsigned long long sx = 0, sy = 0, sz = 0, sw = 0;
-        for (int iz = 0; iz < nz; ++iz)
-            for (int iy = 0; iy < ny; ++iy)
-                for (int ix = 0; ix < nx; ++ix) {
-                    const int br = bxs[ix] + b.nb[0] * (bys[iy] + b.nb[1] * bzs[iz]);
-                    const int sl = lxs[ix] + b.wdim[0] * (lys[iy] + b.wdim[1] * lzs[iz]);
-                    const CellAcc r = load_acc(gp(b.part) + (size_t)br * b.wsize + sl);
-                    sx += r.sx;
-                    sy += r.sy;
-                    sz += r.sz;
-                    sw += r.w;
-                }
-        const int ob = b.bof[0][cx] + b.nb[0] * (b.bof[1][cy] + b.nb[1] * b.bof[2][cz]);
-        if (gp(b.eflag)[ob] == stamp) {
-            const CellAcc e = load_acc(gp(b.esc) + c);
-            if (e.w) {
-                sx += e.sx;
-                sy += e.sy;
-                sz += e.sz;
-                sw += e.w;
-                CellAcc zero = {0ull, 0ull, 0ull, 0ull};
-                store_acc(gp(b.esc) + c, zero);
-            }
-        }
-        if (sw == 0) continue;
-        CellUN u;
-        u.ux = fixed_mean(sx, sw);
-        u.uy = fixed_mean(sy, sw);
-        u.uz = fixed_mean(sz, sw);
-        const float3 ax = cell_axis(b, s.k, (uint32_t)c);
-        u.nx = ax.x;
-        u.ny = ax.y;
-        u.nz = ax.z;
-        u.kappa = axis_kappa(ax);
-        u.pad1 = 0.0f;
-        store_un(gp(b.un) + c, u);
+    const uint32_t nbk = (uint32_t)b.nbrick;
+    const uint32_t o = gatomic_add(gp(b.bsize[dst]) + nbk, 1u);
+    const uint32_t ob = gp(b.bstart)[nbk];
+    if (o >= gp(b.bstart)[nbk + 1] - ob) return false;
+    *j = ob + o;
+    const uint32_t c = (uint32_t)nc.x + (uint32_t)b.L[0] * ((uint32_t)nc.y + (uint32_t)b.L[1] * (uint32_t)nc.z);
+    MPCD_G CellAcc* e = gp(b.esc[(k + 1) & 1]) + c;
+    gatomic_add(&e->sx, to_fixed(m * v.x));
+    gatomic_add(&e->sy, to_fixed(m * v.y));
+    gatomic_add(&e->sz, to_fixed(m * v.z));
+    gatomic_add(&e->w, to_fixed(m));
+    const int3 br = brick_of_cell(b, nc);
+    gp(b.eflag)[(size_t)((k + 1) & 1) * b.nbrick + br.x + b.nb[0] * (br.y + b.nb[1] * br.z)] = (uint32_t)(k + 2);
+    return true;
+}
+
+// Store particle state at slot j of buffer dst (VACF reference copied from
+// slot i of buffer src); slots < 2^30.
+__device__ __forceinline__ void put_particle(const BoxDev& b, int src, int dst, uint32_t i, uint32_t j, float x,
+                                             float y, float z, float3 v, int32_t id, float m, bool has_m,
+                                             bool track)
+{
+    const uint32_t o = j * 4u;
+    stg(gp(b.p[dst][0]), o, x);
+    stg(gp(b.p[dst][1]), o, y);
+    stg(gp(b.p[dst][2]), o, z);
+    stg(gp(b.p[dst][3]), o, v.x);
+    stg(gp(b.p[dst][4]), o, v.y);
+    stg(gp(b.p[dst][5]), o, v.z);
+    stg(gp(b.pid[dst]), o, id);
+    if (has_m) stg(gp(b.m[dst]), o, m);
+    if (track) {
+        const uint32_t oi = i * 4u;
+        stg(gp(b.v0[dst][0]), o, ldg(gp(b.v0[src][0]), oi));
+        stg(gp(b.v0[dst][1]), o, ldg(gp(b.v0[src][1]), oi));
+        stg(gp(b.v0[dst][2]), o, ldg(gp(b.v0[src][2]), oi));
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_brick_rotate(const Tile* __restrict__ tiles,
-                                                          const BoxDev* __restrict__ boxes,
-                                                          const BoxState* __restrict__ st,
-                                                          long long* __restrict__ partials)
+// One SRD step of one brick (paper Sec. 2; the shifted grid of Sec. 3.1;
+// the mass-weighted cell velocity of Sec. 3.3).  The workgroup owns every
+// particle whose collision cell lies in its brick, so the whole step is one
+// pass over them, held in registers (kS per thread; larger buckets take
+// several chunks, re-read from memory):
+//   1. stream, collision cell, exact fixed-point cell sums in LDS
+//      (+ escape sums of overflow particles, when flagged)
+//   2. per cell: u_c = sum(m v)/sum(m), axis n_c from Philox (in place)
+//   3. rotate v about n_c relative to u_c; collision cell of the next step;
+//      rank in the destination group (27 neighbour bricks: wave ballots for
+//      the particles that stay, LDS counters for the others)
+//   4. one global reservation per group in the destination buckets, then
+//      stores.  Per step only the range check (and the VACF sum when a
+//      sample is due) is reduced; momentum and energy are summed on demand.
+template <int kT, int kS, bool kMass>
+__global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tiles,
+                                                    const BoxDev* __restrict__ boxes,
+                                                    const BoxState* __restrict__ st,
+                                                    long long* __restrict__ dacc)
 {
-    extern __shared__ CellUN wun[];   // u_c and axis of the brick's window cells
-    __shared__ uint32_t cnt[27];
-    __shared__ uint32_t base[27];
+    // LDS, per cell of the brick (arrays, so that neighbouring cells fall in
+    // different banks): exact sums of m v (3 x 64 bit) and of m (64 bit, or a
+    // 32-bit count for equal masses), then u_c, n_c and kappa (7 x 32 bit)
+    extern __shared__ unsigned long long lds64[];
+    __shared__ uint32_t gcnt[27], gpos[27], gbeg[27], gcap[27];
+    __shared__ uint32_t s_cnt;
+    constexpr uint32_t kChunk = (uint32_t)kT * kS;
+    constexpr uint32_t kNone = 0xffffffffu;   // no particle / no cell
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const Tile tl = tiles[t];
-    const BoxState s = st[tl.box];
-    const BoxDev& b = boxes[tl.box];
+    const BoxState s = st[uniform(tl.box)];
+    const BoxDev& b = boxes[uniform(tl.box)];
     if (box_idle(s) || b.binning != 1) return;
-    const int brick = (int)tl.begin;
-    const int bx = brick % b.nb[0], by = (brick / b.nb[0]) % b.nb[1], bz = brick / (b.nb[0] * b.nb[1]);
-    const int m = b.margin;
-    const int lox = b.blo[0][bx], loy = b.blo[1][by], loz = b.blo[2][bz];
-    const int ex = b.blo[0][bx + 1] - lox + 2 * m;
-    const int ey = b.blo[1][by + 1] - loy + 2 * m;
-    const int ez = b.blo[2][bz + 1] - loz + 2 * m;
-    const int wx = b.wdim[0], wy = b.wdim[1];
-    // stage the window's cell data in LDS (cells of empty slots are never read)
-    for (int i = threadIdx.x; i < b.wsize; i += kBlock) {
-        const int lx = i % wx, ly = (i / wx) % wy, lz = i / (wx * wy);
-        if (lx < ex && ly < ey && lz < ez) {
-            int cx = lox - m + lx, cy = loy - m + ly, cz = loz - m + lz;
-            cx = ((cx % b.L[0]) + b.L[0]) % b.L[0];
-            cy = ((cy % b.L[1]) + b.L[1]) % b.L[1];
-            cz = ((cz % b.L[2]) + b.L[2]) % b.L[2];
-            wun[i] = load_un(gp(b.un) + ((uint32_t)cx + (uint32_t)b.L[0] * ((uint32_t)cy + (uint32_t)b.L[1] * (uint32_t)cz)));
-        }
+    const int brick = uniform((int)tl.begin);
+    const long long k = uniform(s.k);
+    const int src = uniform(s.parity), dst = src ^ 1;
+    const bool vacf = b.vacf_stride > 0 && ((k + 1 - uniform(s.vacf_origin)) % b.vacf_stride) == 0;
+    const int nb0 = b.nb[0], nb1 = b.nb[1], nb2 = b.nb[2];
+    const int bx = brick % nb0, by = (brick / nb0) % nb1, bz = brick / (nb0 * nb1);
+    const int lox = brick_lo(bx, b.bshift[0]), loy = brick_lo(by, b.bshift[1]), loz = brick_lo(bz, b.bshift[2]);
+    const int ex = min(1 << b.bshift[0], b.L[0] - lox);
+    const int ey = min(1 << b.bshift[1], b.L[1] - loy);
+    const int ez = min(1 << b.bshift[2], b.L[2] - loz);
+    const int ncl = ex * ey * ez;
+    unsigned long long* const asx = lds64;
+    unsigned long long* const asy = asx + ncl;
+    unsigned long long* const asz = asy + ncl;
+    unsigned long long* const aw = asz + ncl;
+    float* const fu = reinterpret_cast<float*>(aw + ncl);   // ux, uy, uz, nx, ny, nz, kappa: 7 x ncl
+    for (int i = threadIdx.x; i < 4 * ncl; i += kT) lds64[i] = 0ull;
+    const uint32_t beg = (uint32_t)uniform((int)gp(b.bstart)[brick]);
+    if (threadIdx.x == 0) {
+        const uint32_t cap = gp(b.bstart)[brick + 1] - beg;
+        s_cnt = min(gp(b.bsize[src])[brick], cap);
+        gp(b.bsize[src])[brick] = 0u;   // this buffer is the next step's destination
     }
     __syncthreads();
-    const int src = s.parity, dst = s.parity ^ 1;
-    const float3 sh = grid_shift(b, s.k);
-    const float dt = b.dt;
-    const double ca = b.ca, sa = b.sa;
-    const bool track = b.vacf_stride > 0;
-    const bool vacf = vacf_due(b, s);
-    const int64_t beg = b.bstart[src][brick], end = b.bstart[src][brick + 1];
+    const uint32_t cnt = (uint32_t)uniform((int)s_cnt);
+    const int nch = (int)((cnt + kChunk - 1) / kChunk);
+
     const MPCD_G float* __restrict__ ix = gp(b.p[src][0]);
     const MPCD_G float* __restrict__ iy = gp(b.p[src][1]);
     const MPCD_G float* __restrict__ iz = gp(b.p[src][2]);
     const MPCD_G float* __restrict__ ivx = gp(b.p[src][3]);
     const MPCD_G float* __restrict__ ivy = gp(b.p[src][4]);
     const MPCD_G float* __restrict__ ivz = gp(b.p[src][5]);
-    const MPCD_G int32_t* __restrict__ iid = gp(b.pid[src]);
-    MPCD_G float* __restrict__ ox = gp(b.p[dst][0]);
-    MPCD_G float* __restrict__ oy = gp(b.p[dst][1]);
-    MPCD_G float* __restrict__ oz = gp(b.p[dst][2]);
-    MPCD_G float* __restrict__ ovx = gp(b.p[dst][3]);
-    MPCD_G float* __restrict__ ovy = gp(b.p[dst][4]);
-    MPCD_G float* __restrict__ ovz = gp(b.p[dst][5]);
-    MPCD_G int32_t* __restrict__ oid = gp(b.pid[dst]);
-    const MPCD_G float* __restrict__ im = b.m[src] ? gp(b.m[src]) : nullptr;
-    MPCD_G float* __restrict__ om = b.m[dst] ? gp(b.m[dst]) : nullptr;
-    const MPCD_G CellUN* __restrict__ un = gp(b.un);
-    MPCD_G uint32_t* __restrict__ bcursor = gp(b.bcursor);
-    // running ranks within each destination group; group starts precomputed
-    if (threadIdx.x < 27) {
-        cnt[threadIdx.x] = 0u;
-        base[threadIdx.x] = gp(b.outbase)[(size_t)brick * 27 + threadIdx.x];
+    const MPCD_G float* __restrict__ im = gp(kMass ? b.m[src] : (float*)nullptr);
+    const float3 sh = grid_shift(b, k);
+    const float dt = b.dt;
+    const float inv_a = b.inv_a;
+
+    float px[kS], py[kS], pz[kS], vx[kS], vy[kS], vz[kS], pm[kS];
+    uint32_t meta[kS];   // cell in the brick after loading; destination group << 24 | rank later
+    long long d[kNumDiag] = {0, 0, 0, 0, 0, 0};
+    // load and stream chunk ch; meta <- cell inside the brick, kNone past the
+    // end of the bucket or for a particle in the wrong bucket (never happens:
+    // both sides use the same arithmetic; flagged if it does)
+    // slots of chunk ch that hold particles for some thread (uniform)
+    auto used_slots = [&](int ch) -> int {
+        const uint32_t rem = cnt - (uint32_t)ch * kChunk;
+        return (int)min((uint32_t)kS, (rem + kT - 1) / kT);
+    };
+    auto load = [&](int ch) {
+        const int nu = used_slots(ch);
+#pragma unroll
+        for (int u = 0; u < kS; ++u) {   // issue every load first
+            if (u >= nu) break;
+            const uint32_t i = (uint32_t)ch * kChunk + (uint32_t)(u * kT) + threadIdx.x;
+            const uint32_t o = (beg + (i < cnt ? i : 0u)) * 4u;   // byte offset (slots < 2^30)
+            px[u] = ldg(ix, o);
+            py[u] = ldg(iy, o);
+            pz[u] = ldg(iz, o);
+            vx[u] = ldg(ivx, o);
+            vy[u] = ldg(ivy, o);
+            vz[u] = ldg(ivz, o);
+            pm[u] = kMass ? ldg(im, o) : 1.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < kS; ++u) {
+            if (u >= nu) {
+                meta[u] = kNone;
+                continue;
+            }
+            const uint32_t i = (uint32_t)ch * kChunk + (uint32_t)(u * kT) + threadIdx.x;
+            px[u] = fold(fmaf(vx[u], dt, px[u]), b.len[0]);
+            py[u] = fold(fmaf(vy[u], dt, py[u]), b.len[1]);
+            pz[u] = fold(fmaf(vz[u], dt, pz[u]), b.len[2]);
+            const int cx = axis_cell_raw(px[u], sh.x, inv_a, b.L[0]) - lox;   // range-checked below
+            const int cy = axis_cell_raw(py[u], sh.y, inv_a, b.L[1]) - loy;
+            const int cz = axis_cell_raw(pz[u], sh.z, inv_a, b.L[2]) - loz;
+            const bool in = (unsigned)cx < (unsigned)ex && (unsigned)cy < (unsigned)ey && (unsigned)cz < (unsigned)ez;
+            meta[u] = (i < cnt && in) ? (uint32_t)(cx + ex * (cy + ey * cz)) : kNone;
+            if (i < cnt && !in) d[5] += 1;
+        }
+    };
+
+    // 1. cell sums; the last chunk first, so that chunk 0 stays in registers
+    for (int ch = nch - 1; ch >= 0; --ch) {
+        load(ch);
+#pragma unroll
+        for (int u = 0; u < kS; ++u) {
+            const uint32_t c = meta[u];
+            if (c == kNone) continue;
+            if (kMass) {
+                const float mi = pm[u];
+                atomicAdd(&asx[c], to_fixed(mi * vx[u]));
+                atomicAdd(&asy[c], to_fixed(mi * vy[u]));
+                atomicAdd(&asz[c], to_fixed(mi * vz[u]));
+                atomicAdd(&aw[c], to_fixed(mi));
+            } else {   // equal masses: aw counts particles
+                atomicAdd(&asx[c], to_fixed(vx[u]));
+                atomicAdd(&asy[c], to_fixed(vy[u]));
+                atomicAdd(&asz[c], to_fixed(vz[u]));
+                atomicAdd(&aw[c], 1ull);
+            }
+        }
     }
     __syncthreads();
-    long long d[kNumDiag] = {0, 0, 0, 0, 0, 0};
-    const int lane = threadIdx.x & (kWave - 1);
-    for (int64_t c0 = beg; c0 < end; c0 += (int64_t)kBlock * kItems) {
-        float px[kItems], py[kItems], pz[kItems], qx[kItems], qy[kItems], qz[kItems], qm[kItems];
-        int32_t id[kItems];
-#pragma unroll
-        for (int it = 0; it < kItems; ++it) {   // issue every load first
-            const int64_t i = c0 + it * kBlock + threadIdx.x;
-            const int64_t j = (i < end) ? i : beg;
-            px[it] = ix[j];
-            py[it] = iy[j];
-            pz[it] = iz[j];
-            qx[it] = ivx[j];
-            qy[it] = ivy[j];
-            qz[it] = ivz[j];
-            qm[it] = im ? im[j] : 1.0f;
-            id[it] = iid[j];
+    const uint32_t stamp = (uint32_t)(k + 1);
+    const bool flagged = gp(b.eflag)[(size_t)(k & 1) * b.nbrick + brick] == stamp;
+    const uint32_t L0 = (uint32_t)b.L[0], L01 = (uint32_t)b.L[0] * (uint32_t)b.L[1];
+    if (flagged) {   // overflow particles of this step whose cells lie here
+        MPCD_G CellAcc* __restrict__ esc = gp(b.esc[k & 1]);
+        for (int c = threadIdx.x; c < ncl; c += kT) {
+            const int lx = c % ex, ly = (c / ex) % ey, lz = c / (ex * ey);
+            const uint32_t gc = (uint32_t)(lox + lx) + L0 * (uint32_t)(loy + ly) + L01 * (uint32_t)(loz + lz);
+            const CellAcc e = load_acc(esc + gc);
+            if (e.w) {
+                asx[c] += e.sx;
+                asy[c] += e.sy;
+                asz[c] += e.sz;
+                aw[c] += kMass ? e.w : (e.w >> 32);   // escape weights are 2^32 m
+                CellAcc z = {0ull, 0ull, 0ull, 0ull};
+                store_acc(esc + gc, z);
+            }
         }
+        __syncthreads();
+    }
+
+    // 2. cell velocity and axis
+    for (int c = threadIdx.x; c < ncl; c += kT) {
+        const unsigned long long w = kMass ? aw[c] : (aw[c] << 32);
+        if (w == 0) continue;
+        const int lx = c % ex, ly = (c / ex) % ey, lz = c / (ex * ey);
+        const uint32_t gc = (uint32_t)(lox + lx) + L0 * (uint32_t)(loy + ly) + L01 * (uint32_t)(loz + lz);
+        CellUN u;
+        u.ux = fixed_mean(asx[c], w);
+        u.uy = fixed_mean(asy[c], w);
+        u.uz = fixed_mean(asz[c], w);
+        const float3 ax = cell_axis(b, k, gc);
+        u.nx = ax.x;
+        u.ny = ax.y;
+        u.nz = ax.z;
+        u.kappa = axis_kappa(ax);
+        u.pad1 = 0.0f;
+        fu[c] = u.ux;
+        fu[ncl + c] = u.uy;
+        fu[2 * ncl + c] = u.uz;
+        fu[3 * ncl + c] = u.nx;
+        fu[4 * ncl + c] = u.ny;
+        fu[5 * ncl + c] = u.nz;
+        fu[6 * ncl + c] = u.kappa;
+        if (flagged) store_un(gp(b.un) + gc, u);   // read by the overflow particles
+    }
+    __syncthreads();
+
+    // 3./4. rotate, route to the next step's buckets, store
+    const float3 sh1 = grid_shift(b, k + 1);
+    const double ca = b.ca, sa = b.sa;
+    const bool track = b.vacf_stride > 0;
+    const bool has_m = kMass && b.m[src] != nullptr;
+    const int lane = threadIdx.x & (kWave - 1);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int ch = 0; ch < nch; ++ch) {
+        if (ch > 0) load(ch);
+        const int nu = used_slots(ch);
+        if (threadIdx.x < 27) gcnt[threadIdx.x] = 0u;
+        __syncthreads();
 #pragma unroll
-        for (int it = 0; it < kItems; ++it) {
-            const int64_t i = c0 + it * kBlock + threadIdx.x;
-            const bool ok = i < end;
-            const float ux = qx[it], uy = qy[it], uz = qz[it];
-            const float fx = fold(fmaf(ux, dt, px[it]), b.len[0]);
-            const float fy = fold(fmaf(uy, dt, py[it]), b.len[1]);
-            const float fz = fold(fmaf(uz, dt, pz[it]), b.len[2]);
-            const int cx = axis_cell(fx, sh.x, b.inv_a, b.L[0]);
-            const int cy = axis_cell(fy, sh.y, b.inv_a, b.L[1]);
-            const int cz = axis_cell(fz, sh.z, b.inv_a, b.L[2]);
-            const int lx = window_offset(cx, lox, m, b.L[0]);
-            const int ly = window_offset(cy, loy, m, b.L[1]);
-            const int lz = window_offset(cz, loz, m, b.L[2]);
-            CellUN u;
-            if (lx < ex && ly < ey && lz < ez)
-                u = wun[lx + wx * (ly + wy * lz)];
-            else
-                u = load_un(un + ((uint32_t)cx + (uint32_t)b.L[0] * ((uint32_t)cy + (uint32_t)b.L[1] * (uint32_t)cz)));
-            const float3 v = rotate_about(u, ux, uy, uz, ca, sa);
-            const int3 db = brick_of_pos(b, fx, fy, fz);
-            const int rx = brick_rel(bx, db.x, b.nb[0]), ry = brick_rel(by, db.y, b.nb[1]),
-                      rz = brick_rel(bz, db.z, b.nb[2]);
-            const bool near = rx <= 1 && ry <= 1 && rz <= 1;
-            const int r = near ? (rx + 1) + 3 * ((ry + 1) + 3 * (rz + 1)) : 27;
-            // rank in the destination group; particles that stay in this brick
-            // (most of them) take consecutive ranks per wave, so stores coalesce
-            const bool stay = ok && r == 13;
-            const unsigned long long mask = __ballot(stay);
-            uint32_t slot = 0;
+        for (int u = 0; u < kS; ++u) {
+            if (u >= nu) {
+                meta[u] = 28u << 24;
+                continue;
+            }
+            const uint32_t i = (uint32_t)ch * kChunk + (uint32_t)(u * kT) + threadIdx.x;
+            uint32_t r = 28u;   // no particle
+            if (i < cnt) {
+                const uint32_t c = meta[u];
+                if (c != kNone) {
+                    CellUN cu;
+                    cu.ux = fu[c];
+                    cu.uy = fu[ncl + c];
+                    cu.uz = fu[2 * ncl + c];
+                    cu.nx = fu[3 * ncl + c];
+                    cu.ny = fu[4 * ncl + c];
+                    cu.nz = fu[5 * ncl + c];
+                    cu.kappa = fu[6 * ncl + c];
+                    const float3 v = rotate_about(cu, vx[u], vy[u], vz[u], ca, sa);
+                    vx[u] = v.x;
+                    vy[u] = v.y;
+                    vz[u] = v.z;
+                }
+                const float3 v = make_float3(vx[u], vy[u], vz[u]);
+                diag_check(d, v);
+                if (vacf) {
+                    const uint32_t o = (beg + i) * 4u;
+                    diag_vacf(d, v, ldg(gp(b.v0[src][0]), o), ldg(gp(b.v0[src][1]), o), ldg(gp(b.v0[src][2]), o));
+                }
+                // brick of the next collision cell (a non-finite position
+                // lands far away and takes the clamped slow path below)
+                const int dbx = brick_of(axis_cell_raw(fold(fmaf(v.x, dt, px[u]), b.len[0]), sh1.x, inv_a, b.L[0]), b.bshift[0]);
+                const int dby = brick_of(axis_cell_raw(fold(fmaf(v.y, dt, py[u]), b.len[1]), sh1.y, inv_a, b.L[1]), b.bshift[1]);
+                const int dbz = brick_of(axis_cell_raw(fold(fmaf(v.z, dt, pz[u]), b.len[2]), sh1.z, inv_a, b.L[2]), b.bshift[2]);
+                const int rx = brick_rel(bx, dbx, nb0), ry = brick_rel(by, dby, nb1), rz = brick_rel(bz, dbz, nb2);
+                r = (rx <= 1 && ry <= 1 && rz <= 1) ? (uint32_t)((rx + 1) + 3 * ((ry + 1) + 3 * (rz + 1))) : 27u;
+            }
+            // particles that stay in the brick (most) take consecutive ranks
+            // per wave, so their stores coalesce
+            const unsigned long long mask = __ballot(r == 13u);
+            uint32_t rank = 0u;
             if (mask) {
                 const int leader = __ffsll((long long)mask) - 1;
-                uint32_t wbase = 0;
-                if (lane == leader) wbase = atomicAdd(&cnt[13], (uint32_t)__popcll(mask));
-                wbase = __shfl(wbase, leader, kWave);
-                slot = base[13] + wbase + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+                uint32_t wb = 0u;
+                if (lane == leader) wb = atomicAdd(&gcnt[13], (uint32_t)__popcll(mask));
+                wb = __builtin_amdgcn_readlane(wb, leader);
+                rank = wb + (uint32_t)__popcll(mask & below);
             }
-            if (!ok) continue;
-            if (r == 27)
-                slot = gatomic_add(&bcursor[db.x + b.nb[0] * (db.y + b.nb[1] * db.z)], 1u);
-            else if (r != 13)
-                slot = base[r] + atomicAdd(&cnt[r], 1u);
-            const int64_t j = slot;
-            ox[j] = fx;
-            oy[j] = fy;
-            oz[j] = fz;
-            ovx[j] = v.x;
-            ovy[j] = v.y;
-            ovz[j] = v.z;
-            oid[j] = id[it];
-            if (om) om[j] = qm[it];
-            if (track) {
-                gp(b.v0[dst][0])[j] = gp(b.v0[src][0])[i];
-                gp(b.v0[dst][1])[j] = gp(b.v0[src][1])[i];
-                gp(b.v0[dst][2])[j] = gp(b.v0[src][2])[i];
-            }
-            diag_particle(d, v, qm[it]);
-            if (vacf) diag_vacf(d, v, gp(b.v0[src][0])[i], gp(b.v0[src][1])[i], gp(b.v0[src][2])[i]);
+            if (r < 27u && r != 13u) rank = atomicAdd(&gcnt[r], 1u);
+            meta[u] = (r << 24) | rank;
         }
+        // identities (only needed for the store): load while the groups reserve
+        int32_t id[kS];
+#pragma unroll
+        for (int u = 0; u < kS; ++u) {
+            if (u >= nu) break;
+            const uint32_t i = (uint32_t)ch * kChunk + (uint32_t)(u * kT) + threadIdx.x;
+            id[u] = ldg(gp(b.pid[src]), (beg + (i < cnt ? i : 0u)) * 4u);
+        }
+        __syncthreads();
+        if (threadIdx.x < 27) {
+            const int q = threadIdx.x;
+            const uint32_t n = gcnt[q];
+            if (n) {
+                const int dx = brick_nbr(bx, q % 3 - 1, nb0), dy = brick_nbr(by, (q / 3) % 3 - 1, nb1),
+                          dz = brick_nbr(bz, q / 9 - 1, nb2);
+                const uint32_t dest = (uint32_t)(dx + nb0 * (dy + nb1 * dz));
+                gpos[q] = gatomic_add(gp(b.bsize[dst]) + dest, n);
+                const uint32_t b0 = gp(b.bstart)[dest];
+                gbeg[q] = b0;
+                gcap[q] = gp(b.bstart)[dest + 1] - b0;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kS; ++u) {
+            if (u >= nu) break;
+            const uint32_t r = meta[u] >> 24;
+            if (r >= 28u) continue;
+            const uint32_t i = (uint32_t)ch * kChunk + (uint32_t)(u * kT) + threadIdx.x;
+            const float3 v = make_float3(vx[u], vy[u], vz[u]);
+            uint32_t j = 0u;
+            bool placed = false;
+            if (r < 27u) {
+                const uint32_t p = gpos[r] + (meta[u] & 0xffffffu);
+                if (p < gcap[r]) {
+                    j = gbeg[r] + p;
+                    placed = true;
+                }
+            }
+            if (!placed) {   // far (or full) destination: slow path
+                const int3 nc = next_cell(b, px[u], py[u], pz[u], v, sh1);
+                const int3 db = brick_of_cell(b, nc);
+                if (r == 27u) placed = place_single(b, dst, (uint32_t)(db.x + nb0 * (db.y + nb1 * db.z)), &j);
+                if (!placed) placed = place_overflow(b, dst, k, nc, pm[u], v, &j);
+            }
+            if (!placed) {
+                d[5] += 1;
+                continue;
+            }
+            put_particle(b, src, dst, beg + i, j, px[u], py[u], pz[u], v, id[u], pm[u], has_m, track);
+        }
+        if (ch + 1 < nch) __syncthreads();
     }
-    block_diag(d, partials + (size_t)t * kNumDiag);
+    step_flush<kT>(d, vacf, dacc + (size_t)uniform(tl.box) * kAccLanes * 3, blockIdx.x);
+}
+
+// Particles of the overflow bucket of the current buffer (one workgroup per
+// box, after the brick step): the same step, with the cell data the flagged
+// bricks published.  Adds their diagnostics to d.
+__device__ void overflow_step(const BoxDev& b, const BoxState& s, long long (&d)[kNumDiag])
+{
+    const int src = s.parity, dst = s.parity ^ 1;
+    const uint32_t nbk = (uint32_t)b.nbrick;
+    const uint32_t ob = gp(b.bstart)[nbk];
+    const uint32_t cnt = min(gp(b.bsize[src])[nbk], gp(b.bstart)[nbk + 1] - ob);
+    if (cnt == 0) return;
+    const float3 sh = grid_shift(b, s.k), sh1 = grid_shift(b, s.k + 1);
+    const bool has_m = b.m[src] != nullptr;
+    const bool track = b.vacf_stride > 0;
+    const bool vacf = vacf_due(b, s);
+    for (uint32_t i = threadIdx.x; i < cnt; i += kBlock) {
+        const uint32_t si = ob + i;
+        const float vx = gp(b.p[src][3])[si], vy = gp(b.p[src][4])[si], vz = gp(b.p[src][5])[si];
+        const float x = fold(fmaf(vx, b.dt, gp(b.p[src][0])[si]), b.len[0]);
+        const float y = fold(fmaf(vy, b.dt, gp(b.p[src][1])[si]), b.len[1]);
+        const float z = fold(fmaf(vz, b.dt, gp(b.p[src][2])[si]), b.len[2]);
+        const float m = has_m ? gp(b.m[src])[si] : 1.0f;
+        const uint32_t c = collision_cell(b, x, y, z, sh);
+        const float3 v = rotate_about(load_un(gp(b.un) + c), vx, vy, vz, b.ca, b.sa);
+        diag_check(d, v);
+        const int3 nc = next_cell(b, x, y, z, v, sh1);
+        const int3 db = brick_of_cell(b, nc);
+        uint32_t j = 0u;
+        bool placed = place_single(b, dst, (uint32_t)(db.x + b.nb[0] * (db.y + b.nb[1] * db.z)), &j);
+        if (!placed) placed = place_overflow(b, dst, s.k, nc, m, v, &j);
+        if (!placed) {
+            d[5] += 1;
+            continue;
+        }
+        if (vacf) diag_vacf(d, v, gp(b.v0[src][0])[si], gp(b.v0[src][1])[si], gp(b.v0[src][2])[si]);
+        put_particle(b, src, dst, si, j, x, y, z, v, gp(b.pid[src])[si], m, has_m, track);
+    }
+}
+
+// Re-bucketing step, first kernel: mark the holes of the current buffer
+// (slots past the fill of their bucket) with pid -1, so that the counting
+// sort can walk every slot.  Also used by the host before reading a brick
+// box's state (all = 1: whatever the rebucket flag).
+__global__ __launch_bounds__(kBlock) void k_mark_holes(const Tile* __restrict__ tiles,
+                                                        const BoxDev* __restrict__ boxes,
+                                                        const BoxState* __restrict__ st, int all)
+{
+    const Tile tl = tiles[blockIdx.x];
+    const BoxState s = st[tl.box];
+    const BoxDev& b = boxes[tl.box];
+    if (b.binning != 1) return;
+    if (!all && (box_idle(s) || !s.rebucket)) return;
+    const uint32_t* __restrict__ bs = b.bstart;
+    const uint32_t* __restrict__ sz = b.bsize[s.parity];
+    const int nbk = b.nbrick;
+    for (int64_t i = tl.begin + threadIdx.x; i < tl.end; i += kBlock) {
+        const int lo = bucket_of_slot(bs, nbk, i);
+        const uint32_t fill = min(sz[lo], bs[lo + 1] - bs[lo]);
+        if ((uint32_t)(i - bs[lo]) >= fill) b.pid[s.parity][i] = -1;
+    }
+}
+
+// Re-bucketing step: escape sums left for this step belong to particles the
+// sort is about to put into their buckets; drop them.
+__global__ __launch_bounds__(kBlock) void k_rebucket_clear(const Tile* __restrict__ tiles,
+                                                            const BoxDev* __restrict__ boxes,
+                                                            const BoxState* __restrict__ st)
+{
+    const Tile tl = tiles[blockIdx.x];
+    const BoxState s = st[tl.box];
+    const BoxDev& b = boxes[tl.box];
+    if (b.binning != 1 || box_idle(s) || !s.rebucket) return;
+    const int brick = (int)tl.begin;
+    uint32_t* flag = b.eflag + (size_t)(s.k & 1) * b.nbrick + brick;
+    if (*flag != (uint32_t)(s.k + 1)) return;
+    const int nb0 = b.nb[0], nb1 = b.nb[1];
+    const int bx = brick % nb0, by = (brick / nb0) % nb1, bz = brick / (nb0 * nb1);
+    const int lox = brick_lo(bx, b.bshift[0]), loy = brick_lo(by, b.bshift[1]), loz = brick_lo(bz, b.bshift[2]);
+    const int ex = min(1 << b.bshift[0], b.L[0] - lox);
+    const int ey = min(1 << b.bshift[1], b.L[1] - loy);
+    const int ez = min(1 << b.bshift[2], b.L[2] - loz);
+    const uint32_t L0 = (uint32_t)b.L[0], L01 = (uint32_t)b.L[0] * (uint32_t)b.L[1];
+    for (int c = threadIdx.x; c < ex * ey * ez; c += kBlock) {
+        const int lx = c % ex, ly = (c / ex) % ey, lz = c / (ex * ey);
+        const uint32_t gc = (uint32_t)(lox + lx) + L0 * (uint32_t)(loy + ly) + L01 * (uint32_t)(loz + lz);
+        CellAcc z = {0ull, 0ull, 0ull, 0ull};
+        store_acc(gp(b.esc[s.k & 1]) + gc, z);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *flag = 0u;
 }
 
 // --------------------------------------------------------------------------
 // counting sort: by collision cell every step (SORT), or by brick once to
 // bucket a brick box's particles (after admission / set_state)
+
+// rank of this lane's particle among those with the same key: lanes of a
+// wave that share a key (sorted input: most of them) take one atomic
+__device__ __forceinline__ void keys_rank(uint32_t* counts, uint32_t key, uint32_t* rank)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    bool pending = true;
+    while (true) {
+        const unsigned long long act = __ballot(pending);
+        if (!act) break;
+        const int leader = __ffsll((long long)act) - 1;
+        const uint32_t k0 = (uint32_t)__builtin_amdgcn_readlane((int)key, leader);
+        const bool mine = pending && key == k0;
+        const unsigned long long same = __ballot(mine);
+        uint32_t base = 0u;
+        if (lane == leader) base = atomicAdd(&counts[k0], (uint32_t)__popcll(same));
+        base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
+        if (mine) {
+            *rank = base + (uint32_t)__popcll(same & below);
+            pending = false;
+        }
+    }
+}
 
 __global__ __launch_bounds__(kBlock) void k_zero_counts(const Tile* __restrict__ tiles,
                                                          const BoxDev* __restrict__ boxes,
@@ -523,23 +686,26 @@ __global__ __launch_bounds__(kBlock) void k_count(const Tile* __restrict__ tiles
     const float* __restrict__ vx = b.p[s.parity][3];
     const float* __restrict__ vy = b.p[s.parity][4];
     const float* __restrict__ vz = b.p[s.parity][5];
-    const bool collide_key = (b.binning == 2);
-    const float3 sh = collide_key ? grid_shift(b, s.k) : make_float3(0.0f, 0.0f, 0.0f);
+    const int32_t* __restrict__ pid = b.pid[s.parity];
+    const bool by_brick = (b.binning == 1);
+    const float3 sh = grid_shift(b, s.k);
     const float dt = b.dt;
     for (int64_t i = tl.begin + threadIdx.x; i < tl.end; i += kBlock) {
-        float px = x[i], py = y[i], pz = z[i];
+        if (pid[i] < 0) continue;   // hole
+        const float px = fold(fmaf(vx[i], dt, x[i]), b.len[0]);
+        const float py = fold(fmaf(vy[i], dt, y[i]), b.len[1]);
+        const float pz = fold(fmaf(vz[i], dt, z[i]), b.len[2]);
         uint32_t key;
-        if (collide_key) {
-            px = fold(fmaf(vx[i], dt, px), b.len[0]);
-            py = fold(fmaf(vy[i], dt, py), b.len[1]);
-            pz = fold(fmaf(vz[i], dt, pz), b.len[2]);
-            key = collision_cell(b, px, py, pz, sh);
-        } else {
-            const int3 d = brick_of_pos(b, px, py, pz);
+        if (by_brick) {   // the brick holding the collision cell of this step
+            const int3 c = make_int3(axis_cell(px, sh.x, b.inv_a, b.L[0]), axis_cell(py, sh.y, b.inv_a, b.L[1]),
+                                     axis_cell(pz, sh.z, b.inv_a, b.L[2]));
+            const int3 d = brick_of_cell(b, c);
             key = (uint32_t)(d.x + b.nb[0] * (d.y + b.nb[1] * d.z));
+        } else {
+            key = collision_cell(b, px, py, pz, sh);
         }
         b.cell[i] = key;
-        b.rank[i] = atomicAdd(&b.cstart[key], 1u);
+        keys_rank(b.cstart, key, &b.rank[i]);
     }
 }
 
@@ -555,7 +721,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_tilesum(const Tile* __restrict_
     const BoxDev& b = boxes[tl.box];
     if (box_idle(s) || !sort_due(b, s)) return;
     uint32_t v = 0;
-    for (int64_t c = tl.begin + threadIdx.x; c < tl.end; c += kBlock) v += b.cstart[c];
+    for (int64_t c = tl.begin + threadIdx.x; c < tl.end; c += kBlock) v += key_capacity(b, c, b.cstart[c]);
     uint32_t total;
     block_exclusive_scan(v, &total);
     if (threadIdx.x == 0) tilesum[t] = total;
@@ -585,7 +751,9 @@ __global__ __launch_bounds__(kBlock) void k_scan_box(const int32_t* __restrict__
     }
 }
 
-// per cell tile: exclusive scan of counts into starts
+// per cell tile: exclusive scan of the key capacities into starts.  For
+// brick boxes the keys are bricks, and the starts become the bucket layout of
+// the buffer the scatter fills (counts plus slack; overflow bucket last).
 __global__ __launch_bounds__(kBlock) void k_scan_apply(const Tile* __restrict__ tiles,
                                                         const BoxDev* __restrict__ boxes,
                                                         const BoxState* __restrict__ st,
@@ -598,32 +766,39 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const Tile* __restrict__ 
     const BoxDev& b = boxes[tl.box];
     if (box_idle(s) || !sort_due(b, s)) return;
     const int64_t c0 = tl.begin + (int64_t)threadIdx.x * kPer;
-    uint32_t loc[kPer];
+    uint32_t cnt[kPer], cap[kPer];
     uint32_t v = 0;
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
-        loc[j] = (c0 + j < tl.end) ? b.cstart[c0 + j] : 0u;
-        v += loc[j];
+        cnt[j] = (c0 + j < tl.end) ? b.cstart[c0 + j] : 0u;
+        cap[j] = (c0 + j < tl.end) ? key_capacity(b, c0 + j, cnt[j]) : 0u;
+        v += cap[j];
     }
     uint32_t total;
     const uint32_t start = tilesum[t] + block_exclusive_scan(v, &total);
-    // brick boxes: the keys are bricks; their starts are also the bucket
-    // starts of the buffer the scatter fills
-    uint32_t* __restrict__ next = (b.binning == 1) ? b.bstart[s.parity ^ 1] : nullptr;
+    const bool brick = (b.binning == 1);
+    const int64_t nbk = b.nbrick;
     uint32_t run = start;
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
         const int64_t c = c0 + j;
         if (c < tl.end) {
             b.cstart[c] = run;
-            if (next && c <= b.nbrick) next[c] = run;
+            if (brick && c < nbk) {
+                b.bstart[c] = run;
+                b.bsize[s.parity ^ 1][c] = cnt[j];
+                b.bsize[s.parity][c] = 0u;   // the next step's destination
+                if (c == nbk - 1) {         // overflow bucket: the rest of the buffer
+                    b.bstart[nbk] = run + cap[j];
+                    b.bstart[nbk + 1] = (uint32_t)b.nslot;
+                    b.bsize[s.parity ^ 1][nbk] = 0u;
+                    b.bsize[s.parity][nbk] = 0u;
+                }
+            }
         }
-        run += loc[j];
+        run += cap[j];
     }
-    if (tl.end == b.ncell && threadIdx.x == 0) {
-        b.cstart[b.ncell] = (uint32_t)b.n;
-        if (next && b.nbrick == b.ncell) next[b.nbrick] = (uint32_t)b.n;
-    }
+    if (tl.end == b.ncell && threadIdx.x == 0) b.cstart[b.ncell] = brick ? tilesum[t] + total : (uint32_t)b.n;
 }
 
 __global__ __launch_bounds__(kBlock) void k_scatter(const Tile* __restrict__ tiles,
@@ -639,6 +814,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const Tile* __restrict__ til
     const bool vacf = b.vacf_stride > 0;
     const float dt = b.dt;
     for (int64_t i = tl.begin + threadIdx.x; i < tl.end; i += kBlock) {
+        if (b.pid[src][i] < 0) continue;   // hole
         const int64_t j = (int64_t)b.cstart[b.cell[i]] + b.rank[i];
         const float vx = b.p[src][3][i], vy = b.p[src][4][i], vz = b.p[src][5][i];
         float px = b.p[src][0][i], py = b.p[src][1][i], pz = b.p[src][2][i];
@@ -672,6 +848,7 @@ __global__ void k_flip(const int32_t* __restrict__ active, int nactive,
     BoxState& s = st[bx];
     const bool due = !box_idle(s) && sort_due(boxes[bx], s);
     if (due) s.parity ^= 1;
+    if (due && boxes[bx].binning == 1) s.rebuckets += 1;
     s.rebucket = 0;
 }
 
@@ -789,7 +966,7 @@ __device__ __forceinline__ void collide_cell_am(const BoxDev& b, int par, long l
         vx[j] = v.x;
         vy[j] = v.y;
         vz[j] = v.z;
-        diag_particle(d, v, mass_of(mp, j));
+        diag_check(d, v);
     }
 }
 
@@ -798,7 +975,7 @@ __device__ __forceinline__ void collide_cell_am(const BoxDev& b, int par, long l
 __global__ __launch_bounds__(kBlock) void k_cell_rotate(const Tile* __restrict__ tiles,
                                                          const BoxDev* __restrict__ boxes,
                                                          const BoxState* __restrict__ st,
-                                                         long long* __restrict__ partials)
+                                                         long long* __restrict__ dacc)
 {
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const Tile tl = tiles[t];
@@ -821,7 +998,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_rotate(const Tile* __restrict__
             const uint32_t beg = b.cstart[c], end = b.cstart[c + 1];
             if (beg != end) collide_cell_am(b, s.parity, s.k, (uint32_t)c, beg, end, sh, ca, sa, d, vacf);
         }
-        block_diag(d, partials + (size_t)t * kNumDiag);
+        step_flush(d, vacf, dacc + (size_t)tl.box * kAccLanes * 3, blockIdx.x);
         return;
     }
     for (int64_t c = tl.begin + threadIdx.x; c < tl.end; c += kBlock) {
@@ -849,60 +1026,80 @@ __global__ __launch_bounds__(kBlock) void k_cell_rotate(const Tile* __restrict__
             vx[j] = v.x;
             vy[j] = v.y;
             vz[j] = v.z;
-            diag_particle(d, v, mass_of(mp, j));
+            diag_check(d, v);
             if (vacf) diag_vacf(d, v, w0x[j], w0y[j], w0z[j]);
         }
     }
-    block_diag(d, partials + (size_t)t * kNumDiag);
+    step_flush(d, vacf, dacc + (size_t)tl.box * kAccLanes * 3, blockIdx.x);
 }
 
 // --------------------------------------------------------------------------
-// end of step: per-box reduction of the partials in a fixed order
+// end of step: per box, the overflow bucket (brick boxes), the VACF sample
+// and range check from the step's accumulators, k++
 
 __global__ __launch_bounds__(kBlock) void k_box_finish(const int32_t* __restrict__ active,
                                                         const BoxDev* __restrict__ boxes,
                                                         BoxState* __restrict__ st,
-                                                        const long long* __restrict__ partials_b,
-                                                        const long long* __restrict__ partials_c)
+                                                        long long* __restrict__ dacc,
+                                                        int* __restrict__ host_flag)
 {
     const int bx = active[blockIdx.x];
     BoxState* sp = &st[bx];
     if (box_idle(*sp)) return;
     const BoxDev& b = boxes[bx];
     const bool by_cell = (b.binning == 2);
-    const int t0 = by_cell ? b.ctile0 : b.btile0;
-    const int t1 = by_cell ? b.ctile1 : b.btile1;
-    const long long* __restrict__ partials = by_cell ? partials_c : partials_b;
-    // exact sum of the 64-bit tile partials as (high, low) 32-bit halves
-    long long hi[kNumDiag] = {0, 0, 0, 0, 0, 0}, lo[kNumDiag] = {0, 0, 0, 0, 0, 0};
-    for (int t = t0 + (int)threadIdx.x; t < t1; t += kBlock) {
-#pragma unroll
-        for (int j = 0; j < kNumDiag; ++j) {
-            const long long v = partials[(size_t)t * kNumDiag + j];
-            hi[j] += v >> 32;
-            lo[j] += (long long)(unsigned long long)(unsigned)(v & 0xffffffffll);
-        }
+    long long d[kNumDiag] = {0, 0, 0, 0, 0, 0};
+    if (!by_cell) overflow_step(b, *sp, d);
+    // this thread's share of the exact sums: its particles plus, for the
+    // first kAccLanes threads, one accumulator lane (then cleared)
+    long long hi = d[4] >> 32, lo = (long long)(unsigned long long)(unsigned)(d[4] & 0xffffffffll), viol = d[5];
+    long long* a = dacc + (size_t)bx * kAccLanes * 3;
+    if (threadIdx.x < kAccLanes) {
+        long long* l = a + (size_t)threadIdx.x * 3;
+        hi += l[0];
+        lo += l[1];
+        viol += l[2];
+        l[0] = 0;
+        l[1] = 0;
+        l[2] = 0;
     }
-    __shared__ long long thi[kNumDiag], tlo[kNumDiag];
-    block_diag(hi, thi);
-    __syncthreads();
-    block_diag(lo, tlo);
+    __shared__ long long red[3][kBlock / kWave];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    hi = wave_sum(hi);
+    lo = wave_sum(lo);
+    viol = wave_sum(viol);
+    if (lane == 0) {
+        red[0][w] = hi;
+        red[1][w] = lo;
+        red[2][w] = viol;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double tot[kNumDiag];
-        for (int j = 0; j < kNumDiag; ++j)   // (hi 2^32 + lo) 2^-32, one rounding
-            tot[j] = (double)thi[j] + (double)tlo[j] * 2.3283064365386963e-10;
+        long long th = 0, tl = 0, tv = 0;
+        for (int i = 0; i < kBlock / kWave; ++i) {
+            th += red[0][i];
+            tl += red[1][i];
+            tv += red[2][i];
+        }
+        const double vsum = (double)th + (double)tl * 2.3283064365386963e-10;   // (hi 2^32 + lo) 2^-32
         const bool vac = vacf_due(b, *sp);
-        sp->diag[0] = tot[0];
-        sp->diag[1] = tot[1];
-        sp->diag[2] = tot[2];
-        sp->diag[3] = tot[3];
-        if (thi[5] != 0 || tlo[5] != 0) sp->status = -5;   // velocity out of range / not finite
+        if (tv != 0) sp->status = -5;   // velocity out of range / not finite
         if (vac && sp->vacf_len < b.vacf_cap && b.n > 0)
-            b.vacf[sp->vacf_len++] = tot[4] / (double)b.n;
+            b.vacf[sp->vacf_len++] = vsum / (double)b.n;
+        if (!by_cell) {
+            const int src = sp->parity, nbk = b.nbrick;
+            gp(b.bsize[src])[nbk] = 0u;   // overflow bucket drained
+            // particles left in the overflow bucket: ask the host for a
+            // re-bucketing (new capacities) at its next step call
+            if (gp(b.bsize[src ^ 1])[nbk] != 0u) {
+                sp->overflow_steps += 1;
+                sp->rebucket = 1;
+                if (host_flag) __hip_atomic_store(host_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+            sp->parity ^= 1;   // the brick step wrote the other buffer
+        }
         sp->k += 1;
         if (sp->remaining > 0) sp->remaining -= 1;
-        if (!by_cell) sp->parity ^= 1;   // the brick rotation wrote the other buffer
     }
 }
 
@@ -920,6 +1117,10 @@ __global__ __launch_bounds__(kBlock) void k_init_maxwell(const Tile* __restrict_
     const int par = st[tl.box].parity;
     long long d[kNumDiag] = {0, 0, 0, 0, 0, 0};
     for (int64_t i = tl.begin + threadIdx.x; i < tl.end; i += kBlock) {
+        if (i >= b.n) {   // spare slot of a brick box
+            b.pid[par][i] = -1;
+            continue;
+        }
         const uint32_t lo = (uint32_t)i, hi = (uint32_t)((uint64_t)i >> 32);
         const uint4 r = philox4x32_10(make_uint4(lo, hi, 0u, 2u), b.key0, b.key1);
         b.p[par][0][i] = fold(b.len[0] * unit24(r.x), b.len[0]);
@@ -954,6 +1155,7 @@ __global__ __launch_bounds__(kBlock) void k_init_adjust(const Tile* __restrict__
     const int par = st[tl.box].parity;
     long long d[kNumDiag] = {0, 0, 0, 0, 0, 0};
     for (int64_t i = tl.begin + threadIdx.x; i < tl.end; i += kBlock) {
+        if (b.pid[par][i] < 0) continue;
         const float vx = (b.p[par][3][i] - mx) * scale;
         const float vy = (b.p[par][4][i] - my) * scale;
         const float vz = (b.p[par][5][i] - mz) * scale;
@@ -978,6 +1180,7 @@ __global__ __launch_bounds__(kBlock) void k_snapshot(const Tile* __restrict__ ti
     const bool has_v0 = b.vacf_stride > 0;
     long long d[kNumDiag] = {0, 0, 0, 0, 0, 0};
     for (int64_t i = tl.begin + threadIdx.x; i < tl.end; i += kBlock) {
+        if (b.pid[par][i] < 0) continue;
         const float vx = b.p[par][3][i], vy = b.p[par][4][i], vz = b.p[par][5][i];
         if (has_v0 && set_v0) {
             b.v0[par][0][i] = vx;
@@ -1002,13 +1205,14 @@ __global__ __launch_bounds__(kBlock) void k_fill_f32(float* __restrict__ p, int6
         p[i] = v;
 }
 
-// dst[i] = src[pid[i]] (gather_by_id) or dst[pid[i]] = src[i] (scatter_by_id);
-// pid is a permutation of [0, n)
+// Over the slots i of a buffer: dst[i] = src[pid[i]] (gather by id) or
+// dst[pid[i]] = src[i] (scatter by id); pid holds each id of [0, n) once and
+// -1 in holes.
 __global__ __launch_bounds__(kBlock) void k_permute_f32(float* __restrict__ dst, const float* __restrict__ src,
-                                                         const int32_t* __restrict__ pid, int64_t n,
-                                                         int scatter)
+                                                         const int32_t* __restrict__ pid, int64_t nslot,
+                                                         int64_t n, int scatter)
 {
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < nslot; i += (int64_t)gridDim.x * kBlock) {
         const int64_t j = pid[i];
         if (j < 0 || j >= n) continue;
         if (scatter)
@@ -1032,49 +1236,64 @@ __global__ __launch_bounds__(kBlock) void k_fill_zero_u32(uint32_t* __restrict__
         if ((grid) > 0) hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, stream, __VA_ARGS__); \
     } while (0)
 
-void launch_brick_accumulate(const Tables& T, hipStream_t s)
+template <int kT, int kS, bool kMass>
+static void brick_step_run(const Tables& T, hipStream_t s)
 {
     static bool attr = false;
-    if (!attr) {   // allow windows above the default 64 KiB of dynamic LDS
-        (void)hipFuncSetAttribute((const void*)k_brick_accumulate,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  max_window_records() * (int)sizeof(CellAcc));
+    if (!attr) {   // a brick of kMaxBrickCells cells plus the static arrays
+        (void)hipFuncSetAttribute((const void*)k_brick_step<kT, kS, kMass>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
         attr = true;
     }
-    const size_t lds = (size_t)T.max_wsize * sizeof(CellAcc);
-    if (T.nbtiles > 0)
-        hipLaunchKernelGGL(k_brick_accumulate, dim3(T.nbtiles), dim3(kBlock), lds, s, T.btiles, T.boxes,
-                           T.state);
+    const size_t lds = (size_t)T.max_bvol * kBrickCellBytes;
+    hipLaunchKernelGGL((k_brick_step<kT, kS, kMass>), dim3(T.nbtiles), dim3(kT), lds, s, T.btiles, T.boxes,
+                       T.state, T.dacc);
 }
-void launch_brick_scan(const Tables& T, hipStream_t s)
+template <int kT, int kS>
+static void brick_step_at(const Tables& T, hipStream_t s)
 {
-    MPCD_LAUNCH(k_brick_sizes, (T.nbtiles + kBlock - 1) / kBlock, kBlock, s, T.btiles, T.nbtiles, T.boxes,
-                T.state);
-    MPCD_LAUNCH(k_brick_scan, T.nactive, kBlock, s, T.active, T.boxes, T.state);
-    MPCD_LAUNCH(k_brick_offsets, (T.nbtiles * 27 + kBlock - 1) / kBlock, kBlock, s, T.btiles, T.nbtiles,
-                T.boxes, T.state);
+    if (T.brick_mass) brick_step_run<kT, kS, true>(T, s);
+    else brick_step_run<kT, kS, false>(T, s);
 }
-void launch_brick_finalize(const Tables& T, hipStream_t s)
+
+// Launch shapes of the brick step (workgroup size, particles per thread),
+// smallest first: one workgroup holds threads x slots particles in
+// registers.  Small workgroups let many bricks per CU overlap their phases.
+static const struct {
+    int threads, slots;
+    void (*run)(const Tables&, hipStream_t);
+} kBrickShapes[] = {
+    {128, 8, brick_step_at<128, 8>},
+    {256, 8, brick_step_at<256, 8>},
+    {512, 8, brick_step_at<512, 8>},
+};
+constexpr int kNumBrickShapes = (int)(sizeof(kBrickShapes) / sizeof(kBrickShapes[0]));
+
+int brick_shape_for(int64_t bucket)
 {
-    MPCD_LAUNCH(k_brick_finalize, T.nctiles, kBlock, s, T.ctiles, T.boxes, T.state);
+    for (int i = 0; i < kNumBrickShapes; ++i)
+        if ((int64_t)kBrickShapes[i].threads * kBrickShapes[i].slots >= bucket) return i;
+    return kNumBrickShapes - 1;   // larger buckets run in several chunks
 }
-void launch_brick_rotate(const Tables& T, hipStream_t s)
+int brick_shape_threads(int shape) { return kBrickShapes[shape].threads; }
+int brick_shape_slots(int shape) { return kBrickShapes[shape].slots; }
+
+void launch_brick_step(const Tables& T, hipStream_t s)
 {
-    static bool attr = false;
-    if (!attr) {
-        (void)hipFuncSetAttribute((const void*)k_brick_rotate, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  max_window_records() * (int)sizeof(CellUN));
-        attr = true;
-    }
-    const size_t lds = (size_t)T.max_wsize * sizeof(CellUN);
-    if (T.nbtiles > 0)
-        hipLaunchKernelGGL(k_brick_rotate, dim3(T.nbtiles), dim3(kBlock), lds, s, T.btiles, T.boxes, T.state,
-                           T.partials_b);
+    if (T.nbtiles <= 0) return;
+    kBrickShapes[T.brick_shape].run(T, s);
+}
+void launch_mark_holes(const Tile* tiles, int ntiles, const Tables& T, int all, hipStream_t s)
+{
+    MPCD_LAUNCH(k_mark_holes, ntiles, kBlock, s, tiles, T.boxes, T.state, all);
+}
+void launch_rebucket_clear(const Tables& T, hipStream_t s)
+{
+    MPCD_LAUNCH(k_rebucket_clear, T.nbtiles, kBlock, s, T.btiles, T.boxes, T.state);
 }
 void launch_box_finish(const Tables& T, hipStream_t s)
 {
-    MPCD_LAUNCH(k_box_finish, T.nactive, kBlock, s, T.active, T.boxes, T.state, T.partials_b,
-                T.partials_c);
+    MPCD_LAUNCH(k_box_finish, T.nactive, kBlock, s, T.active, T.boxes, T.state, T.dacc, T.host_flag);
 }
 void launch_zero_counts(const Tables& T, hipStream_t s)
 {
@@ -1101,11 +1320,8 @@ void launch_flip(const Tables& T, hipStream_t s)
 }
 void launch_cell_rotate(const Tables& T, hipStream_t s)
 {
-    MPCD_LAUNCH(k_cell_rotate, T.nctiles, kBlock, s, T.ctiles, T.boxes, T.state, T.partials_c);
+    MPCD_LAUNCH(k_cell_rotate, T.nctiles, kBlock, s, T.ctiles, T.boxes, T.state, T.dacc);
 }
-
-// Largest window (in records) one brick workgroup may hold in LDS.
-int max_window_records() { return (int)(96 * 1024 / sizeof(CellAcc)); }
 
 // The init/snapshot launchers take a sub-range of T.ptiles (one box); their
 // partials land at the same tile indices as the step's.
@@ -1137,10 +1353,11 @@ void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s)
     const int64_t g = (n + kBlock - 1) / kBlock;
     MPCD_LAUNCH(k_fill_f32, (int)(g < 65536 ? g : 65536), kBlock, s, p, n, v);
 }
-void launch_permute_f32(float* dst, const float* src, const int32_t* pid, int64_t n, int scatter, hipStream_t s)
+void launch_permute_f32(float* dst, const float* src, const int32_t* pid, int64_t nslot, int64_t n, int scatter,
+                        hipStream_t s)
 {
-    const int64_t g = (n + kBlock - 1) / kBlock;
-    MPCD_LAUNCH(k_permute_f32, (int)(g < 65536 ? g : 65536), kBlock, s, dst, src, pid, n, scatter);
+    const int64_t g = (nslot + kBlock - 1) / kBlock;
+    MPCD_LAUNCH(k_permute_f32, (int)(g < 65536 ? g : 65536), kBlock, s, dst, src, pid, nslot, n, scatter);
 }
 void launch_fill_zero_u32(uint32_t* p, int64_t n, hipStream_t s)
 {

@@ -14,24 +14,27 @@ namespace mpcd {
 struct Tables {
     BoxDev* boxes = nullptr;     // indexed by slot
     BoxState* state = nullptr;   // indexed by slot
-    Tile* ptiles = nullptr;      // particle tiles of all live boxes
+    Tile* ptiles = nullptr;      // slot tiles of all live boxes
     Tile* ctiles = nullptr;      // cell tiles of all live boxes
     Tile* btiles = nullptr;      // brick tiles (begin = brick index) of brick boxes
     int32_t* active = nullptr;   // live slots
     long long* partials = nullptr;    // kNumDiag per particle tile (initial state, snapshots)
-    long long* partials_c = nullptr;  // kNumDiag per cell tile (SORT steps)
-    long long* partials_b = nullptr;  // kNumDiag per brick tile (brick steps)
+    long long* dacc = nullptr;        // per slot: kAccLanes x (VACF high, VACF low, violations)
     uint32_t* tilesum = nullptr; // per cell tile
     int nptiles = 0, nctiles = 0, nbtiles = 0, nactive = 0;
-    int max_wsize = 0;             // largest brick window of the live boxes (records)
+    int max_bvol = 0;              // largest brick of the live boxes (cells)
+    int brick_shape = 0;           // launch shape of the brick step (brick_shape_for)
+    bool brick_mass = false;       // some brick box carries per-particle masses
+    int* host_flag = nullptr;      // host-visible: a brick box asks for re-bucketing
 };
 
-void launch_brick_accumulate(const Tables& T, hipStream_t s);
-void launch_brick_scan(const Tables& T, hipStream_t s);
-void launch_brick_finalize(const Tables& T, hipStream_t s);
-void launch_brick_rotate(const Tables& T, hipStream_t s);
+void launch_brick_step(const Tables& T, hipStream_t s);
+int brick_shape_for(int64_t bucket);   // launch shape whose workgroup holds `bucket` particles
+int brick_shape_threads(int shape);
+int brick_shape_slots(int shape);
+void launch_mark_holes(const Tile* tiles, int ntiles, const Tables& T, int all, hipStream_t s);
+void launch_rebucket_clear(const Tables& T, hipStream_t s);
 void launch_box_finish(const Tables& T, hipStream_t s);
-int max_window_records();
 void launch_zero_counts(const Tables& T, hipStream_t s);
 void launch_count(const Tables& T, hipStream_t s);
 void launch_scan(const Tables& T, hipStream_t s);
@@ -46,7 +49,7 @@ void launch_snapshot(const Tile* tiles, int ntiles, const Tables& T, int set_v0,
 void launch_fill_iota(int32_t* p, int64_t n, hipStream_t s);
 void launch_fill_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
 void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
-void launch_permute_f32(float* dst, const float* src, const int32_t* pid, int64_t n, int scatter,
+void launch_permute_f32(float* dst, const float* src, const int32_t* pid, int64_t nslot, int64_t n, int scatter,
                         hipStream_t s);
 
 }  // namespace mpcd

@@ -83,6 +83,8 @@ class mpcd_observables(ctypes.Structure):
         ("n_particles", ctypes.c_int64),
         ("binning", ctypes.c_int32),
         ("brick", ctypes.c_int32 * 3),
+        ("overflow_steps", ctypes.c_int64),
+        ("rebuckets", ctypes.c_int64),
     ]
 
 
@@ -123,6 +125,12 @@ for _name, (_res, _args) in _SIGNATURES.items():
     _f = getattr(_lib, _name)
     _f.restype = _res
     _f.argtypes = _args
+
+# layout of the structs above (include/mpcd.h, MPCD_ABI_VERSION)
+ABI_VERSION = 2
+if _lib.mpcd_abi_version() != ABI_VERSION:
+    raise ImportError("libmpcd.so has ABI version %d, this binding expects %d; rebuild it"
+                      % (_lib.mpcd_abi_version(), ABI_VERSION))
 
 
 class MPCDError(RuntimeError):
@@ -342,7 +350,8 @@ class Context:
         vacf = [obs.vacf[i] for i in range(obs.vacf_len)] if obs.vacf_len > 0 else []
         return dict(step=obs.step, P=np.array(obs.P[:]), E=obs.E_kin, T=obs.T, M=obs.mass_total,
                     status=obs.status, vacf=np.array(vacf), binning=obs.binning,
-                    brick=tuple(obs.brick[:]), n=obs.n_particles)
+                    brick=tuple(obs.brick[:]), n=obs.n_particles, overflow_steps=obs.overflow_steps,
+                    rebuckets=obs.rebuckets)
 
     def release(self, slot):
         _check(mpcd_release(self.handle, slot), "mpcd_release")

@@ -67,6 +67,7 @@ class Server:
         queue = collections.deque()
         live = {}          # slot -> [request, steps left, admit time]
         done = []
+        rejected = []      # requests larger than the whole budget
         t0 = self.clock()
         steps_done = 0     # particle-steps completed
         max_live = 0
@@ -79,7 +80,13 @@ class Server:
             while queue:
                 slot = self.engine.admit(queue[0])
                 if slot is None:
-                    break      # over budget / no slot: wait for releases
+                    if live:
+                        break      # over budget / no slot: wait for releases
+                    # nothing left to release: this request can never fit
+                    req = queue.popleft()
+                    rejected.append(dict(req=req, latency=math.nan, queued=now - req["arrival"],
+                                         status="rejected"))
+                    continue
                 req = queue.popleft()
                 live[slot] = [req, int(req["steps"]), now]
             max_live = max(max_live, len(live))
@@ -102,7 +109,7 @@ class Server:
         wall = self.clock() - t0
         lat = np.array([d["latency"] for d in done]) if done else np.zeros(0)
         summary = dict(
-            completed=len(done), offered=len(requests), wall_s=wall,
+            completed=len(done), offered=len(requests), rejected=len(rejected), wall_s=wall,
             particle_steps_per_s=steps_done / wall if wall > 0 else 0.0,
             p50_latency_s=float(np.percentile(lat, 50)) if len(lat) else math.nan,
             p99_latency_s=float(np.percentile(lat, 99)) if len(lat) else math.nan,

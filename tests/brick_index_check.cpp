@@ -1,12 +1,15 @@
 // Host check of the brick-binning index arithmetic of libmpcd (mpcd_dev.h):
-// every (brick, window slot) an accumulating workgroup can write maps to one
-// canonical cell, and the per-cell gather enumerates exactly those slots; the
-// bucket offsets used for re-bucketing round-trip.  Prints "ok" or the first
-// mismatch.  Built with hipcc as host code.
+// aligned power-of-two bricks tile every dimension and brick_of inverts
+// brick_lo; isqrt_ceil is exact; the neighbour
+// group of a destination brick (brick_rel) maps back to it (brick_nbr) and is
+// unique per source; bucket capacities with slack leave an overflow bucket
+// that can take every particle; bucket_of_slot finds the bucket of every slot
+// when some buckets are empty.  Prints "ok" or the first mismatch.  Built
+// with hipcc as host code.
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <set>
-#include <tuple>
 #include <vector>
 
 #include "mpcd_dev.h"
@@ -25,95 +28,98 @@ int main()
     for (int trial = 0; trial < 400; ++trial) {
         int32_t L[3], want[3];
         for (int d = 0; d < 3; ++d) {
-            L[d] = trial < 50 ? rnd(1, 6) : rnd(1, 70);
-            want[d] = rnd(2, 16);
+            L[d] = trial < 50 ? rnd(1, 6) : rnd(1, 300);
+            want[d] = 1 << rnd(1, 6);   // 2 .. 64
         }
         const BrickGeom g = brick_geometry(L, want);
-        const int m = g.margin;
+        int vol = 1;
         for (int d = 0; d < 3; ++d) {
-            // bricks tile the dimension, sizes within one of each other, >= margin
+            if ((1 << g.shift[d]) != want[d]) { printf("shift\n"); return 1; }
             int prev = 0;
             for (int i = 0; i < g.nb[d]; ++i) {
-                const int lo = brick_lo(i, L[d], g.nb[d]), hi = brick_lo(i + 1, L[d], g.nb[d]);
-                if (lo != prev || hi <= lo || hi - lo > g.bmax[d] || hi - lo < m) {
+                const int lo = brick_lo(i, g.shift[d]);
+                const int hi = std::min(brick_lo(i + 1, g.shift[d]), L[d]);
+                if (lo != prev || hi <= lo || hi - lo > g.bmax[d]) {
                     printf("tiling L=%d nb=%d brick %d [%d,%d)\n", L[d], g.nb[d], i, lo, hi);
                     return 1;
                 }
                 for (int c = lo; c < hi; ++c)
-                    if (brick_of(c, L[d], g.nb[d]) != i) {
+                    if (brick_of(c, g.shift[d]) != i) {
                         printf("brick_of L=%d nb=%d c=%d\n", L[d], g.nb[d], c);
                         return 1;
                     }
                 prev = hi;
             }
             if (prev != L[d]) { printf("tiling end\n"); return 1; }
-            // slots an accumulating brick can write (l < size + 2m, offset taken mod L)
-            std::set<std::pair<int, int>> written;   // (brick, l) reached by some cell
-            for (int i = 0; i < g.nb[d]; ++i) {
-                const int lo = brick_lo(i, L[d], g.nb[d]);
-                const int ext = brick_lo(i + 1, L[d], g.nb[d]) - lo + 2 * m;
-                if (ext > g.wdim[d]) { printf("window overflow\n"); return 1; }
-                for (int c = 0; c < L[d]; ++c) {
-                    const int l = window_offset(c, lo, m, L[d]);
-                    if (l < 0 || l >= L[d]) { printf("offset range\n"); return 1; }
-                    if (l < ext) written.insert({i, l});
-                }
-            }
-            // the gather of each cell enumerates exactly its slots
-            std::set<std::pair<int, int>> gathered;
-            for (int c = 0; c < L[d]; ++c) {
-                int bi[3], li[3];
-                const int n = windows_of(c, L[d], g.nb[d], m, bi, li);
-                for (int k = 0; k < n; ++k) {
-                    const int lo = brick_lo(bi[k], L[d], g.nb[d]);
-                    if (window_offset(c, lo, m, L[d]) != li[k]) { printf("gather offset\n"); return 1; }
-                    if (!gathered.insert({bi[k], li[k]}).second) { printf("slot gathered twice\n"); return 1; }
-                }
-                // every brick whose window holds c must be listed
-                for (int i = 0; i < g.nb[d]; ++i) {
-                    const int lo = brick_lo(i, L[d], g.nb[d]);
-                    const int ext = brick_lo(i + 1, L[d], g.nb[d]) - lo + 2 * m;
-                    if (window_offset(c, lo, m, L[d]) < ext) {
-                        bool found = false;
-                        for (int k = 0; k < n; ++k) found |= (bi[k] == i);
-                        if (!found) {
-                            printf("missed window L=%d nb=%d c=%d brick=%d\n", L[d], g.nb[d], c, i);
-                            return 1;
-                        }
-                    }
-                }
-            }
-            if (gathered != written) { printf("written != gathered L=%d nb=%d\n", L[d], g.nb[d]); return 1; }
-            // neighbour offsets round-trip
-            for (int s = 0; s < g.nb[d]; ++s)
-                for (int t = 0; t < g.nb[d]; ++t) {
-                    const int r = brick_rel(s, t, g.nb[d]);
-                    if (r <= 1) {
-                        if (r < -1 || (s + r + g.nb[d]) % g.nb[d] != t) { printf("rel\n"); return 1; }
-                    } else if (g.nb[d] <= 3) {
-                        printf("far in small grid\n");
-                        return 1;
-                    }
-                }
+            vol *= g.bmax[d];
         }
+        if (vol != g.bvol) { printf("bvol\n"); return 1; }
     }
-    // bucket group layout: group q of bucket d comes from brick d - off(q) and
-    // every (source, q) pair lands in exactly one bucket group
-    for (int nb = 1; nb <= 6; ++nb) {
-        for (int d = 0; d < nb; ++d) {
-            std::set<int> srcs;
-            for (int r = -1; r <= 1; ++r) {
-                const int src = brick_nbr(d, -r, nb);
-                if (src < 0) continue;
-                if (brick_nbr(src, r, nb) != d) { printf("nbr inverse nb=%d\n", nb); return 1; }
-                if (brick_rel(src, d, nb) != r) { printf("rel vs nbr nb=%d d=%d r=%d\n", nb, d, r); return 1; }
-                if (!srcs.insert(src).second && nb >= 3) { printf("duplicate source\n"); return 1; }
-            }
-        }
-        for (int s = 0; s < nb; ++s)
+    // neighbour groups: every destination within one brick of the source has
+    // an offset in {-1, 0, 1} that leads back to it, distinct destinations
+    // have distinct offsets, and bricks farther away are reported as far
+    for (int nb = 1; nb <= 9; ++nb)
+        for (int s = 0; s < nb; ++s) {
+            std::set<int> seen;
             for (int t = 0; t < nb; ++t) {
                 const int r = brick_rel(s, t, nb);
-                if (r <= 1 && brick_nbr(s, r, nb) != t) { printf("rel/nbr mismatch\n"); return 1; }
+                const int dist = std::min(std::abs(t - s), nb - std::abs(t - s));
+                if (r <= 1) {
+                    if (r < -1 || brick_nbr(s, r, nb) != t) { printf("rel/nbr nb=%d s=%d t=%d\n", nb, s, t); return 1; }
+                    if (!seen.insert(r).second) { printf("two destinations share an offset\n"); return 1; }
+                    if (dist > 1) { printf("near but far nb=%d s=%d t=%d\n", nb, s, t); return 1; }
+                } else if (r != 2 || dist <= 1) {
+                    printf("far nb=%d s=%d t=%d r=%d\n", nb, s, t, r);
+                    return 1;
+                }
+            }
+        }
+    // integer square root (ceil) used by the bucket slack
+    for (uint32_t n = 0; n < 300000u; ++n) {
+        const uint32_t r = isqrt_ceil(n);
+        if ((unsigned long long)r * r < n || (r > 0 && (unsigned long long)(r - 1) * (r - 1) >= n)) {
+            printf("isqrt_ceil(%u) = %u\n", n, r);
+            return 1;
+        }
+    }
+    for (uint32_t n : {0xffffffffu, 0xfffe0001u, 0xfffe0000u, 1u << 30, (1u << 30) + 1u, 16777217u}) {
+        const uint32_t r = isqrt_ceil(n);
+        if ((unsigned long long)r * r < n || (r > 0 && (unsigned long long)(r - 1) * (r - 1) >= n)) {
+            printf("isqrt_ceil(%u) = %u\n", n, r);
+            return 1;
+        }
+    }
+    // bucket layouts as re-bucketing builds them (counts plus slack, the
+    // overflow bucket last), with empty buckets in runs
+    for (int trial = 0; trial < 300; ++trial) {
+        const int nbk = rnd(1, 400);
+        std::vector<uint32_t> cnt(nbk);
+        int64_t n = 0;
+        for (int d = 0; d < nbk; ++d) {
+            cnt[d] = (rnd(0, 3) == 0) ? 0u : (uint32_t)rnd(0, trial < 100 ? 40 : 5000);
+            n += cnt[d];
+        }
+        const int64_t nslot = brick_slots(n, nbk);
+        std::vector<uint32_t> start(nbk + 2);
+        int64_t run = 0;
+        for (int d = 0; d < nbk; ++d) {
+            start[d] = (uint32_t)run;
+            run += cnt[d] + bucket_slack(cnt[d]);
+        }
+        start[nbk] = (uint32_t)run;
+        start[nbk + 1] = (uint32_t)nslot;
+        if (nslot - run < n) { printf("overflow bucket smaller than n\n"); return 1; }
+        // also the compact layout: everything in bucket 0
+        std::vector<uint32_t> compact(nbk + 2, (uint32_t)n);
+        compact[0] = 0;
+        compact[nbk + 1] = (uint32_t)nslot;
+        for (const std::vector<uint32_t>* st : {&start, &compact})
+            for (int64_t i = 0; i < nslot; ++i) {
+                const int b = bucket_of_slot(st->data(), nbk, i);
+                if (b < 0 || b > nbk || (int64_t)(*st)[b] > i || (int64_t)(*st)[b + 1] <= i) {
+                    printf("bucket_of_slot nbk=%d slot=%lld -> %d\n", nbk, (long long)i, b);
+                    return 1;
+                }
             }
     }
     printf("ok\n");

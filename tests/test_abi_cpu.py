@@ -58,7 +58,7 @@ def test_struct_layout_matches_header(m, tmp_path):
 
 
 def test_status_strings_and_version(m):
-    assert m.mpcd_abi_version() == 1
+    assert m.mpcd_abi_version() == m.ABI_VERSION == 2
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert m.mpcd_strerror(code) and m.mpcd_strerror(code) != "unknown status"
     assert m.mpcd_strerror(12345) == "unknown status"
@@ -83,3 +83,20 @@ def test_create_without_device_fails_cleanly(m):
     assert not h.value
     opt.binning = 7
     assert m.mpcd_create(opt)[0] == m.MPCD_EINVAL
+
+
+def test_brick_edges_must_be_powers_of_two(m):
+    """Options are checked before any device is touched: brick edges are 0
+    (automatic) or powers of two in [2, 64]."""
+    for edges, ok in (((0, 0, 0), True), ((8, 4, 4), True), ((2, 64, 16), True), ((6, 4, 4), False),
+                      ((8, 8, 128), False), ((1, 8, 8), False), ((8, 3, 8), False)):
+        opt = m.mpcd_options()
+        for i in range(3):
+            opt.brick[i] = edges[i]
+        rc, h = m.mpcd_create(opt)
+        if rc == m.MPCD_OK:
+            m._lib.mpcd_destroy(h)
+        if ok:
+            assert rc != m.MPCD_EINVAL, edges
+        else:
+            assert rc == m.MPCD_EINVAL, edges

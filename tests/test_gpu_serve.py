@@ -48,7 +48,7 @@ def test_results_identical_alone_and_in_the_mix(serve):
 def test_budget_admission_queues_requests(serve):
     print("[case] serve budget", flush=True)
     reqs = _small_requests()
-    eng = serve.LibraryEngine(hbm_budget=24 << 20, vacf_stride=5)
+    eng = serve.LibraryEngine(hbm_budget=64 << 20, vacf_stride=5)
     summary, done = serve.Server(eng, chunk_steps=16).run(reqs)
     eng.close()
     assert summary["completed"] == len(reqs)

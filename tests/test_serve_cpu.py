@@ -90,4 +90,17 @@ def test_overload_is_reported_not_hidden():
     eng = SimEngine(clock, budget_bytes=1 << 34, rate=1e10)
     summary, done = Server(eng, chunk_steps=50, clock=clock, sleep=clock.sleep).run(reqs, max_wall_s=3.0)
     assert summary["unfinished"] > 0
-    assert summary["completed"] + summary["unfinished"] == summary["offered"]
+    assert summary["completed"] + summary["unfinished"] + summary["rejected"] == summary["offered"]
+
+
+def test_request_larger_than_the_budget_is_rejected():
+    """A request that cannot fit even an empty engine is rejected at once;
+    the others are still served and the server terminates."""
+    clock = SimClock()
+    reqs = inputs.served_requests(rate_hz=50, window_s=1, seed=11)
+    reqs[len(reqs) // 2]["n"] = 10 ** 9           # 64 GB at 64 B per particle
+    eng = SimEngine(clock, budget_bytes=1 << 30)
+    summary, done = Server(eng, chunk_steps=50, clock=clock, sleep=clock.sleep).run(reqs)
+    assert summary["rejected"] == 1
+    assert summary["completed"] == len(reqs) - 1 and summary["unfinished"] == 0
+    assert all(d["req"]["n"] != 10 ** 9 for d in done)
