@@ -35,7 +35,9 @@ constexpr int kBlock = 256;          // threads per workgroup of the particle ke
 constexpr int kPartTile = 4096;      // particles per particle tile (16 per thread)
 constexpr int kCellTile = 2048;      // cells per cell tile
 constexpr int kMaxBrickCells = 1024; // cells of one brick (LDS of its workgroup)
-constexpr int kBrickCellBytes = 60;  // LDS per brick cell: 4 x 64-bit sums, 7 x 32-bit cell data
+constexpr int kAccWords = 5;         // 64-bit words per brick cell's sums record (4 used)
+constexpr int kUnWords = 12;         // 32-bit words per brick cell's data record (7 used)
+constexpr int kBrickCellBytes = 8 * kAccWords + 4 * kUnWords;   // LDS per brick cell
 constexpr int kAccLanes = 64;        // step accumulator lanes per box (spread the atomics)
 constexpr int kNumDiag = 6;          // per-tile exact partials: sum v (3), sum v^2, sum v.v0, range violations
 

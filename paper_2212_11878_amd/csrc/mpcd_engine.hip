@@ -503,8 +503,9 @@ int init_maxwell(mpcd_ctx* c, int32_t s)
 }  // namespace
 
 // ==========================================================================
-// Autotuner: picks the binning (brick or sort) and the brick shape for a
-// class of boxes by timing short trial runs on a proxy box of the same
+// Autotuner: picks the binning (brick or sort) and the brick shape.  Boxes
+// below 2^21 cells take the shape the density rule gives; for larger ones a
+// class of boxes is timed once on short trial runs of a proxy box of the same
 // density and time step (at most 128^3 cells) in a private context on the
 // same stream.  Results do not depend on the choice (cell sums are exact),
 // only the speed does.
@@ -558,12 +559,34 @@ static int trial_ms(mpcd_ctx* parent, const mpcd_box_desc* proxy, int32_t binnin
     return rc;
 }
 
+// Brick shapes by volume; the step's cost depends mostly on the particles
+// per brick, so the shape follows the density: the largest brick whose
+// expected bucket (with its Poisson margin) fits a 256-thread workgroup's
+// registers in one chunk.
+static const int32_t kRuleShapes[][3] = {{2, 2, 2}, {4, 2, 2}, {4, 4, 2}, {4, 4, 4}, {8, 4, 4},
+                                         {8, 8, 4}, {8, 8, 8}, {16, 8, 8}};
+constexpr int kNumRuleShapes = (int)(sizeof(kRuleShapes) / sizeof(kRuleShapes[0]));
+
+static int rule_shape(double density)
+{
+    const double fit = (double)brick_shape_threads(1) * brick_shape_slots(1);   // 256 x 8
+    int best = 0;
+    for (int i = 0; i < kNumRuleShapes; ++i) {
+        const double v = (double)kRuleShapes[i][0] * kRuleShapes[i][1] * kRuleShapes[i][2];
+        if (v * density * 1.25 + 64.0 <= fit) best = i;
+    }
+    return best;
+}
+
 static int autotune(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* binning, int32_t brick[3])
 {
-    // defaults, also used inside trial contexts and for empty boxes
+    const double C = (double)d->L[0] * d->L[1] * d->L[2];
+    const double density = (double)d->n_particles / C;
+    const int r = rule_shape(density);
+    // defaults, also used inside trial contexts, for empty and for small boxes
     *binning = MPCD_BIN_ATOMIC;
-    brick[0] = brick[1] = brick[2] = 0;
-    if (c->tuning || d->n_particles == 0) return MPCD_OK;
+    for (int k = 0; k < 3; ++k) brick[k] = kRuleShapes[r][k];
+    if (c->tuning || d->n_particles == 0 || C < (double)(1 << 21)) return MPCD_OK;
     const uint64_t key = shape_class(d);
     auto it = c->tuned.find(key);
     if (it != c->tuned.end()) {
@@ -571,27 +594,28 @@ static int autotune(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* binning, int32
         for (int k = 0; k < 3; ++k) brick[k] = it->second.second[k];
         return MPCD_OK;
     }
+    // large boxes: time the rule's shape, its neighbours and sort binning on
+    // a proxy box of the same density and time step (at most 128^3 cells)
     mpcd_box_desc p = *d;
     double cells = 1.0;
     for (int k = 0; k < 3; ++k) {
         p.L[k] = std::min(d->L[k], 128);
         cells *= p.L[k];
     }
-    const double density = (double)d->n_particles / ((double)d->L[0] * d->L[1] * d->L[2]);
     p.n_particles = std::max<int64_t>(1, std::llround(density * cells));
     p.flags = MPCD_INIT_MAXWELL;
     if (!(p.kT > 0.0)) p.kT = 1.0;
     p.n_steps = 0;
     p.vacf_stride = 0;
     p.vacf_capacity = 0;
-    struct Cand { int32_t bin; int32_t b[3]; const char* name; };
-    const Cand cands[] = {
-        {MPCD_BIN_ATOMIC, {4, 4, 4}, "brick4x4x4"},
-        {MPCD_BIN_ATOMIC, {8, 4, 4}, "brick8x4x4"},
-        {MPCD_BIN_ATOMIC, {8, 8, 4}, "brick8x8x4"},
-        {MPCD_BIN_ATOMIC, {8, 8, 8}, "brick8x8x8"},
-        {MPCD_BIN_SORT, {0, 0, 0}, "sort"},
-    };
+    struct Cand { int32_t bin; int32_t b[3]; std::string name; };
+    std::vector<Cand> cands;
+    for (int i = std::max(0, r - 1); i <= std::min(kNumRuleShapes - 1, r + 1); ++i) {
+        const int32_t* sh = kRuleShapes[i];
+        cands.push_back({MPCD_BIN_ATOMIC, {sh[0], sh[1], sh[2]},
+                         "brick" + std::to_string(sh[0]) + "x" + std::to_string(sh[1]) + "x" + std::to_string(sh[2])});
+    }
+    cands.push_back({MPCD_BIN_SORT, {0, 0, 0}, "sort"});
     c->tune_log.clear();
     double best = 1e300;
     for (const Cand& cd : cands) {

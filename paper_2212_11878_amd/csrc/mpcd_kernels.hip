@@ -255,10 +255,11 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
                                                     const BoxState* __restrict__ st,
                                                     long long* __restrict__ dacc)
 {
-    // LDS, per cell of the brick (arrays, so that neighbouring cells fall in
-    // different banks): exact sums of m v (3 x 64 bit) and of m (64 bit, or a
-    // 32-bit count for equal masses), then u_c, n_c and kappa (7 x 32 bit)
-    extern __shared__ unsigned long long lds64[];
+    // LDS, per cell of the brick: exact sums of m v (3 x 64 bit) and of m (64
+    // bit, or a 32-bit count for equal masses) in 40-byte records, then u_c,
+    // n_c and kappa in 48-byte records (two 16-byte reads); both strides
+    // spread neighbouring cells over the LDS banks
+    extern __shared__ __align__(16) unsigned long long lds64[];
     __shared__ uint32_t gcnt[27], gpos[27], gbeg[27], gcap[27];
     __shared__ uint32_t s_cnt;
     constexpr uint32_t kChunk = (uint32_t)kT * kS;
@@ -279,12 +280,9 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
     const int ey = min(1 << b.bshift[1], b.L[1] - loy);
     const int ez = min(1 << b.bshift[2], b.L[2] - loz);
     const int ncl = ex * ey * ez;
-    unsigned long long* const asx = lds64;
-    unsigned long long* const asy = asx + ncl;
-    unsigned long long* const asz = asy + ncl;
-    unsigned long long* const aw = asz + ncl;
-    float* const fu = reinterpret_cast<float*>(aw + ncl);   // ux, uy, uz, nx, ny, nz, kappa: 7 x ncl
-    for (int i = threadIdx.x; i < 4 * ncl; i += kT) lds64[i] = 0ull;
+    unsigned long long* const acc = lds64;   // [ncl][kAccWords]: sx, sy, sz, w
+    float* const fu = reinterpret_cast<float*>(lds64 + ((kAccWords * ncl + 1) & ~1));   // [ncl][kUnWords]
+    for (int i = threadIdx.x; i < kAccWords * ncl; i += kT) lds64[i] = 0ull;
     const uint32_t beg = (uint32_t)uniform((int)gp(b.bstart)[brick]);
     if (threadIdx.x == 0) {
         const uint32_t cap = gp(b.bstart)[brick + 1] - beg;
@@ -358,17 +356,18 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
         for (int u = 0; u < kS; ++u) {
             const uint32_t c = meta[u];
             if (c == kNone) continue;
+            unsigned long long* const r = acc + (size_t)c * kAccWords;
             if (kMass) {
                 const float mi = pm[u];
-                atomicAdd(&asx[c], to_fixed(mi * vx[u]));
-                atomicAdd(&asy[c], to_fixed(mi * vy[u]));
-                atomicAdd(&asz[c], to_fixed(mi * vz[u]));
-                atomicAdd(&aw[c], to_fixed(mi));
-            } else {   // equal masses: aw counts particles
-                atomicAdd(&asx[c], to_fixed(vx[u]));
-                atomicAdd(&asy[c], to_fixed(vy[u]));
-                atomicAdd(&asz[c], to_fixed(vz[u]));
-                atomicAdd(&aw[c], 1ull);
+                atomicAdd(&r[0], to_fixed(mi * vx[u]));
+                atomicAdd(&r[1], to_fixed(mi * vy[u]));
+                atomicAdd(&r[2], to_fixed(mi * vz[u]));
+                atomicAdd(&r[3], to_fixed(mi));
+            } else {   // equal masses: r[3] counts particles
+                atomicAdd(&r[0], to_fixed(vx[u]));
+                atomicAdd(&r[1], to_fixed(vy[u]));
+                atomicAdd(&r[2], to_fixed(vz[u]));
+                atomicAdd(reinterpret_cast<uint32_t*>(&r[3]), 1u);
             }
         }
     }
@@ -383,10 +382,11 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
             const uint32_t gc = (uint32_t)(lox + lx) + L0 * (uint32_t)(loy + ly) + L01 * (uint32_t)(loz + lz);
             const CellAcc e = load_acc(esc + gc);
             if (e.w) {
-                asx[c] += e.sx;
-                asy[c] += e.sy;
-                asz[c] += e.sz;
-                aw[c] += kMass ? e.w : (e.w >> 32);   // escape weights are 2^32 m
+                unsigned long long* const r = acc + (size_t)c * kAccWords;
+                r[0] += e.sx;
+                r[1] += e.sy;
+                r[2] += e.sz;
+                r[3] += kMass ? e.w : (e.w >> 32);   // escape weights are 2^32 m
                 CellAcc z = {0ull, 0ull, 0ull, 0ull};
                 store_acc(esc + gc, z);
             }
@@ -396,27 +396,24 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
 
     // 2. cell velocity and axis
     for (int c = threadIdx.x; c < ncl; c += kT) {
-        const unsigned long long w = kMass ? aw[c] : (aw[c] << 32);
+        const unsigned long long* const r = acc + (size_t)c * kAccWords;
+        const unsigned long long w = kMass ? r[3] : ((r[3] & 0xffffffffull) << 32);
         if (w == 0) continue;
         const int lx = c % ex, ly = (c / ex) % ey, lz = c / (ex * ey);
         const uint32_t gc = (uint32_t)(lox + lx) + L0 * (uint32_t)(loy + ly) + L01 * (uint32_t)(loz + lz);
         CellUN u;
-        u.ux = fixed_mean(asx[c], w);
-        u.uy = fixed_mean(asy[c], w);
-        u.uz = fixed_mean(asz[c], w);
+        u.ux = fixed_mean(r[0], w);
+        u.uy = fixed_mean(r[1], w);
+        u.uz = fixed_mean(r[2], w);
         const float3 ax = cell_axis(b, k, gc);
         u.nx = ax.x;
         u.ny = ax.y;
         u.nz = ax.z;
         u.kappa = axis_kappa(ax);
         u.pad1 = 0.0f;
-        fu[c] = u.ux;
-        fu[ncl + c] = u.uy;
-        fu[2 * ncl + c] = u.uz;
-        fu[3 * ncl + c] = u.nx;
-        fu[4 * ncl + c] = u.ny;
-        fu[5 * ncl + c] = u.nz;
-        fu[6 * ncl + c] = u.kappa;
+        float4* const q = reinterpret_cast<float4*>(fu + (size_t)c * kUnWords);
+        q[0] = make_float4(u.ux, u.uy, u.uz, u.nx);
+        q[1] = make_float4(u.ny, u.nz, u.kappa, 0.0f);
         if (flagged) store_un(gp(b.un) + gc, u);   // read by the overflow particles
     }
     __syncthreads();
@@ -444,14 +441,16 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
             if (i < cnt) {
                 const uint32_t c = meta[u];
                 if (c != kNone) {
+                    const float4* const q = reinterpret_cast<const float4*>(fu + (size_t)c * kUnWords);
+                    const float4 q0 = q[0], q1 = q[1];
                     CellUN cu;
-                    cu.ux = fu[c];
-                    cu.uy = fu[ncl + c];
-                    cu.uz = fu[2 * ncl + c];
-                    cu.nx = fu[3 * ncl + c];
-                    cu.ny = fu[4 * ncl + c];
-                    cu.nz = fu[5 * ncl + c];
-                    cu.kappa = fu[6 * ncl + c];
+                    cu.ux = q0.x;
+                    cu.uy = q0.y;
+                    cu.uz = q0.z;
+                    cu.nx = q0.w;
+                    cu.ny = q1.x;
+                    cu.nz = q1.y;
+                    cu.kappa = q1.z;
                     const float3 v = rotate_about(cu, vx[u], vy[u], vz[u], ca, sa);
                     vx[u] = v.x;
                     vy[u] = v.y;
@@ -1245,7 +1244,7 @@ static void brick_step_run(const Tables& T, hipStream_t s)
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
         attr = true;
     }
-    const size_t lds = (size_t)T.max_bvol * kBrickCellBytes;
+    const size_t lds = (size_t)T.max_bvol * kBrickCellBytes + 16;
     hipLaunchKernelGGL((k_brick_step<kT, kS, kMass>), dim3(T.nbtiles), dim3(kT), lds, s, T.btiles, T.boxes,
                        T.state, T.dacc);
 }

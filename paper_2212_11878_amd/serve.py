@@ -23,7 +23,7 @@ import numpy as np
 class LibraryEngine:
     """Engine backed by libmpcd (one context, torch memory and stream)."""
 
-    def __init__(self, hbm_budget, binning=None, use_graph=False, max_slots=4096, vacf_stride=10):
+    def __init__(self, hbm_budget, binning=None, use_graph=True, max_slots=4096, vacf_stride=10):
         from . import mpcd
         self.m = mpcd
         self.vacf_stride = vacf_stride
