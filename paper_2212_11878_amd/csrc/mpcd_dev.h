@@ -49,13 +49,15 @@ struct alignas(32) CellAcc {
     unsigned long long w;
 };
 
-// Per-cell collision data: centre-of-mass velocity, rotation axis n (FP32,
-// |n| = 1 only to rounding) and kappa = 1/|n|^2 - 1 (from FP64), which lets
-// the rotation use the exactly normalised axis without a square root.
-struct alignas(32) CellUN {
-    float ux, uy, uz, nx, ny, nz, kappa, pad1;
+// Per-cell collision as an affine map of the velocity: v' = M v + t with
+// M = R(n, alpha) (Rodrigues: cos(a) I + sin(a) [n]x + (1 - cos(a)) n n^T,
+// n the cell's unit axis) and t = u - M u (u the cell's mass-weighted mean
+// velocity), so that v' = u + R (v - u).  Built per cell in FP64 and stored
+// in FP32 (48 bytes, three 16-byte pieces).
+struct alignas(16) CellRot {
+    float m[9];   // row-major M
+    float t[3];
 };
-
 // Read-only description of one box, resident in device memory.  Particle
 // arrays come in two buffers (ping-pong) of `nslot` slots; the buffer in use
 // is BoxState::parity.  Slots that hold no particle carry pid -1 once the
@@ -79,7 +81,7 @@ struct BoxDev {
     uint32_t* cell;        // sort key of each slot
     uint32_t* rank;        // rank of each slot inside its key (sort)
     uint32_t* cstart;      // counts, then exclusive starts, per key (C + 1)
-    CellUN* un;            // brick mode: u_c and axis of the cells of flagged bricks
+    CellRot* un;           // brick mode: collision map of the cells of flagged bricks
     CellAcc* esc[2];       // brick mode: per cell, sums of overflow particles (step parity)
     uint32_t* eflag;       // brick mode: per brick, k+1 when esc[k & 1] holds data for it
     uint32_t* bstart;      // brick mode: bucket starts (nbrick + 2)
@@ -145,24 +147,27 @@ __device__ __forceinline__ CellAcc load_acc(const MPCD_G CellAcc* p)
     return a;
 }
 
-__device__ __forceinline__ void store_un(MPCD_G CellUN* p, const CellUN& u)
+__device__ __forceinline__ void store_rot(MPCD_G CellRot* p, const CellRot& r)
 {
     MPCD_G f32x4* q = (MPCD_G f32x4*)p;
-    f32x4 a, b;
-    a.x = u.ux; a.y = u.uy; a.z = u.uz; a.w = u.nx;
-    b.x = u.ny; b.y = u.nz; b.z = u.kappa; b.w = u.pad1;
+    f32x4 a, b, c;
+    a.x = r.m[0]; a.y = r.m[1]; a.z = r.m[2]; a.w = r.m[3];
+    b.x = r.m[4]; b.y = r.m[5]; b.z = r.m[6]; b.w = r.m[7];
+    c.x = r.m[8]; c.y = r.t[0]; c.z = r.t[1]; c.w = r.t[2];
     q[0] = a;
     q[1] = b;
+    q[2] = c;
 }
 
-__device__ __forceinline__ CellUN load_un(const MPCD_G CellUN* p)
+__device__ __forceinline__ CellRot load_rot(const MPCD_G CellRot* p)
 {
     const MPCD_G f32x4* q = (const MPCD_G f32x4*)p;
-    const f32x4 a = q[0], b = q[1];
-    CellUN u;
-    u.ux = a.x; u.uy = a.y; u.uz = a.z; u.nx = a.w;
-    u.ny = b.x; u.nz = b.y; u.kappa = b.z; u.pad1 = b.w;
-    return u;
+    const f32x4 a = q[0], b = q[1], c = q[2];
+    CellRot r;
+    r.m[0] = a.x; r.m[1] = a.y; r.m[2] = a.z; r.m[3] = a.w;
+    r.m[4] = b.x; r.m[5] = b.y; r.m[6] = b.z; r.m[7] = b.w;
+    r.m[8] = c.x; r.t[0] = c.y; r.t[1] = c.z; r.t[2] = c.w;
+    return r;
 }
 
 // A contiguous range of one box's particles or cells.
@@ -246,9 +251,9 @@ __host__ __device__ __forceinline__ float fold(float x, float len)
 // outside [0, L) for non-finite x (callers range-check it); axis_cell clamps.
 __device__ __forceinline__ int axis_cell_raw(float x, float s, float inv_a, int L)
 {
-    int i = (int)floorf((x - s) * inv_a);
-    i = (i < 0) ? i + L : i;
-    return (i >= L) ? i - L : i;
+    unsigned i = (unsigned)(int)floorf((x - s) * inv_a);
+    i = min(i, i + (unsigned)L);   // -1 -> L - 1
+    return (int)min(i, i - (unsigned)L);   // L -> 0
 }
 __device__ __forceinline__ int axis_cell(float x, float s, float inv_a, int L)
 {
@@ -357,13 +362,17 @@ inline int64_t brick_slots(int64_t n, int64_t nbrick)
     return 2 * n + (n >> 3) + 4 * (root + nbrick) + 32 * nbrick;
 }
 
-// Velocity in 64-bit fixed point with quantum 2^-32 (exact for |v| >= 2^-9,
-// nearest multiple of 2^-32 below that).  Saturates far outside the valid
-// range |v| < 2^30 (such a box is flagged by the rotation's range check).
+// Velocity in 64-bit fixed point with quantum 2^-32: floor(v 2^32) as a
+// two's-complement integer (exact for |v| >= 2^-9).  Built from the exact
+// FP64 value v 2^32 as floor(v) (high word) and the remainder in [0, 2^32)
+// (low word).  Valid for |v| < 2^31; the steps flag velocities beyond the
+// smaller limit below.
 __device__ __forceinline__ unsigned long long to_fixed(float v)
 {
-    const float t = fminf(fmaxf(v * 4294967296.0f, -4.0e18f), 4.0e18f);
-    return (unsigned long long)(long long)rintf(t);
+    const double t = (double)v * 4294967296.0;
+    const double hi = fmin(fmax(floor(t * 2.3283064365386963e-10), -2147483648.0), 2147483647.0);
+    const double lo = fma(-hi, 4294967296.0, t);
+    return ((unsigned long long)(unsigned)(int)hi << 32) | (unsigned long long)(unsigned)lo;
 }
 
 // Largest speed component the fixed-point cell sums accept.
@@ -378,11 +387,11 @@ __device__ __forceinline__ double fixed_to_double(unsigned long long s)
     return hi * 4294967296.0 + lo;
 }
 
-// Mass-weighted mean velocity of a cell, sum(m v) / sum(m), from the exact
-// fixed-point sums; one division, rounded to FP32.
-__device__ __forceinline__ float fixed_mean(unsigned long long s, unsigned long long w)
+// Mass-weighted mean velocity component of a cell, sum(m v) / sum(m), from
+// the exact fixed-point sums, in FP64 (one division).
+__device__ __forceinline__ double fixed_mean(unsigned long long s, unsigned long long w)
 {
-    return (float)(fixed_to_double(s) / fixed_to_double(w));
+    return fixed_to_double(s) / fixed_to_double(w);
 }
 
 // mass of particle i (1 when the box has equal masses)
@@ -391,40 +400,47 @@ __device__ __forceinline__ float mass_of(const float* __restrict__ m, int64_t i)
     return m ? m[i] : 1.0f;
 }
 
-// 1/|n|^2 - 1 of an FP32 axis, from FP64 (a few 1e-8).
-__device__ __forceinline__ float axis_kappa(float3 n)
+// The collision map of a cell with mean velocity u (FP64) and axis n (FP32,
+// normalised here in FP64).  M is rounded to FP32 entry by entry; t is
+// formed from the rounded M, so that sum(m v') = M P + M_tot (u - M u) = P
+// holds to the rounding of the result.  The entry roundings are independent
+// from cell to cell, so they add no systematic change of the kinetic energy
+// (a rotation evaluated in FP32 with one cos(a), sin(a) pair for every cell
+// does: cos^2 + sin^2 != 1 by a fixed amount).
+__device__ __forceinline__ CellRot cell_rotation(double ux, double uy, double uz, float3 axis, double ca,
+                                                 double sa)
 {
-    const double nn = (double)n.x * n.x + (double)n.y * n.y + (double)n.z * n.z;
-    return (float)(1.0 / nn - 1.0);
+    double nx = axis.x, ny = axis.y, nz = axis.z;
+    const double inv = 1.0 / sqrt(nx * nx + ny * ny + nz * nz);
+    nx *= inv;
+    ny *= inv;
+    nz *= inv;
+    const double oc = 1.0 - ca;
+    CellRot r;
+    r.m[0] = (float)(ca + oc * nx * nx);
+    r.m[1] = (float)(oc * nx * ny - sa * nz);
+    r.m[2] = (float)(oc * nx * nz + sa * ny);
+    r.m[3] = (float)(oc * ny * nx + sa * nz);
+    r.m[4] = (float)(ca + oc * ny * ny);
+    r.m[5] = (float)(oc * ny * nz - sa * nx);
+    r.m[6] = (float)(oc * nz * nx - sa * ny);
+    r.m[7] = (float)(oc * nz * ny + sa * nx);
+    r.m[8] = (float)(ca + oc * nz * nz);
+    r.t[0] = (float)(ux - ((double)r.m[0] * ux + (double)r.m[1] * uy + (double)r.m[2] * uz));
+    r.t[1] = (float)(uy - ((double)r.m[3] * ux + (double)r.m[4] * uy + (double)r.m[5] * uz));
+    r.t[2] = (float)(uz - ((double)r.m[6] * ux + (double)r.m[7] * uy + (double)r.m[8] * uz));
+    return r;
 }
 
-// v' = u + (n.w) n + cos(a) (w - (n.w) n) + sin(a) (n x w), w = v - u, with
-// n the unit axis: the component along the axis is kept, the perpendicular
-// one turned by a.  Evaluated in FP64 from the FP32 inputs (the stored axis is
-// normalised through kappa: n n^T/|n|^2 = (1 + kappa) n n^T and
-// n/|n| = (1 + kappa/2) n to O(kappa^2) ~ 1e-15), then rounded once to FP32.
-// FP32 evaluation would leave a systematic kinetic-energy bias of a few 1e-8
-// per step (unit-norm and cos^2 + sin^2 rounding); the kernels are bound by
-// memory traffic, so the FP64 arithmetic costs no time.
-__device__ __forceinline__ float3 rotate_about(const CellUN& c, float vx, float vy, float vz,
-                                               double ca, double sa)
+// v' = M v + t (three fused multiply-adds per component, fixed order)
+__device__ __forceinline__ float3 apply_rotation(const CellRot& r, float vx, float vy, float vz)
 {
-    const double nx = c.nx, ny = c.ny, nz = c.nz;
-    const double kp = 1.0 + (double)c.kappa, kc = 1.0 + 0.5 * (double)c.kappa;
-    const double ux = c.ux, uy = c.uy, uz = c.uz;
-    const double wx = (double)vx - ux, wy = (double)vy - uy, wz = (double)vz - uz;
-    const double d = (nx * wx + ny * wy + nz * wz) * kp;
-    const double px = d * nx, py = d * ny, pz = d * nz;
-    const double s = sa * kc;
-    const double cx = ny * wz - nz * wy;
-    const double cy = nz * wx - nx * wz;
-    const double cz = nx * wy - ny * wx;
-    return make_float3((float)(ux + px + ca * (wx - px) + s * cx),
-                       (float)(uy + py + ca * (wy - py) + s * cy),
-                       (float)(uz + pz + ca * (wz - pz) + s * cz));
+    return make_float3(fmaf(r.m[0], vx, fmaf(r.m[1], vy, fmaf(r.m[2], vz, r.t[0]))),
+                       fmaf(r.m[3], vx, fmaf(r.m[4], vy, fmaf(r.m[5], vz, r.t[1]))),
+                       fmaf(r.m[6], vx, fmaf(r.m[7], vy, fmaf(r.m[8], vz, r.t[2]))));
 }
 
-// Rotated relative velocity R w in FP64 (same rule as rotate_about).
+// Rotated relative velocity R w in FP64 (Rodrigues, as cell_rotation).
 __device__ __forceinline__ void rotate_w(double nx, double ny, double nz, double ca, double sa,
                                          const double w[3], double out[3])
 {

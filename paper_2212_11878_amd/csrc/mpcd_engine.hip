@@ -153,7 +153,7 @@ Layout box_layout(int64_t nslot, int64_t ncell, bool vacf, int vacf_cap, bool br
     L.off_rank = o; o += pf;
     L.off_cstart = o; o += align256((size_t)(ncell + 1) * 4);
     const size_t nbk = brick ? (size_t)g.nbrick : 0;
-    L.off_un = o; o += brick ? align256((size_t)ncell * sizeof(CellUN)) : 0;
+    L.off_un = o; o += brick ? align256((size_t)ncell * sizeof(CellRot)) : 0;
     for (int b = 0; b < 2; ++b) { L.off_esc[b] = o; o += brick ? align256((size_t)ncell * sizeof(CellAcc)) : 0; }
     L.off_eflag = o; o += align256(2 * nbk * 4);
     L.off_bstart = o; o += align256((nbk + 2) * 4);
@@ -773,7 +773,7 @@ int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
     b.cell = (uint32_t*)(m + L.off_cell);
     b.rank = (uint32_t*)(m + L.off_rank);
     b.cstart = (uint32_t*)(m + L.off_cstart);
-    b.un = brick ? (CellUN*)(m + L.off_un) : nullptr;
+    b.un = brick ? (CellRot*)(m + L.off_un) : nullptr;
     for (int p = 0; p < 2; ++p) {
         b.esc[p] = brick ? (CellAcc*)(m + L.off_esc[p]) : nullptr;
         b.bsize[p] = brick ? (uint32_t*)(m + L.off_bsize[p]) : nullptr;
@@ -823,7 +823,7 @@ int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
     // zeroed cell accumulators and a defined particle state
     Slot& S = c->slots[s];
     if (brick) {
-        if (hipMemsetAsync(S.dev.un, 0, ncell * sizeof(CellUN), c->stream) != hipSuccess)
+        if (hipMemsetAsync(S.dev.un, 0, ncell * sizeof(CellRot), c->stream) != hipSuccess)
             return undo(MPCD_EDEVICE);
         rc = set_compact_layout(c, s, 0);
         if (rc) return undo(rc);

@@ -401,20 +401,13 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
         if (w == 0) continue;
         const int lx = c % ex, ly = (c / ex) % ey, lz = c / (ex * ey);
         const uint32_t gc = (uint32_t)(lox + lx) + L0 * (uint32_t)(loy + ly) + L01 * (uint32_t)(loz + lz);
-        CellUN u;
-        u.ux = fixed_mean(r[0], w);
-        u.uy = fixed_mean(r[1], w);
-        u.uz = fixed_mean(r[2], w);
-        const float3 ax = cell_axis(b, k, gc);
-        u.nx = ax.x;
-        u.ny = ax.y;
-        u.nz = ax.z;
-        u.kappa = axis_kappa(ax);
-        u.pad1 = 0.0f;
+        const CellRot cr = cell_rotation(fixed_mean(r[0], w), fixed_mean(r[1], w), fixed_mean(r[2], w),
+                                         cell_axis(b, k, gc), b.ca, b.sa);
         float4* const q = reinterpret_cast<float4*>(fu + (size_t)c * kUnWords);
-        q[0] = make_float4(u.ux, u.uy, u.uz, u.nx);
-        q[1] = make_float4(u.ny, u.nz, u.kappa, 0.0f);
-        if (flagged) store_un(gp(b.un) + gc, u);   // read by the overflow particles
+        q[0] = make_float4(cr.m[0], cr.m[1], cr.m[2], cr.m[3]);
+        q[1] = make_float4(cr.m[4], cr.m[5], cr.m[6], cr.m[7]);
+        q[2] = make_float4(cr.m[8], cr.t[0], cr.t[1], cr.t[2]);
+        if (flagged) store_rot(gp(b.un) + gc, cr);   // read by the overflow particles
     }
     __syncthreads();
 
@@ -442,16 +435,12 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
                 const uint32_t c = meta[u];
                 if (c != kNone) {
                     const float4* const q = reinterpret_cast<const float4*>(fu + (size_t)c * kUnWords);
-                    const float4 q0 = q[0], q1 = q[1];
-                    CellUN cu;
-                    cu.ux = q0.x;
-                    cu.uy = q0.y;
-                    cu.uz = q0.z;
-                    cu.nx = q0.w;
-                    cu.ny = q1.x;
-                    cu.nz = q1.y;
-                    cu.kappa = q1.z;
-                    const float3 v = rotate_about(cu, vx[u], vy[u], vz[u], ca, sa);
+                    const float4 q0 = q[0], q1 = q[1], q2 = q[2];
+                    CellRot cr;
+                    cr.m[0] = q0.x; cr.m[1] = q0.y; cr.m[2] = q0.z; cr.m[3] = q0.w;
+                    cr.m[4] = q1.x; cr.m[5] = q1.y; cr.m[6] = q1.z; cr.m[7] = q1.w;
+                    cr.m[8] = q2.x; cr.t[0] = q2.y; cr.t[1] = q2.z; cr.t[2] = q2.w;
+                    const float3 v = apply_rotation(cr, vx[u], vy[u], vz[u]);
                     vx[u] = v.x;
                     vy[u] = v.y;
                     vz[u] = v.z;
@@ -562,7 +551,7 @@ __device__ void overflow_step(const BoxDev& b, const BoxState& s, long long (&d)
         const float z = fold(fmaf(vz, b.dt, gp(b.p[src][2])[si]), b.len[2]);
         const float m = has_m ? gp(b.m[src])[si] : 1.0f;
         const uint32_t c = collision_cell(b, x, y, z, sh);
-        const float3 v = rotate_about(load_un(gp(b.un) + c), vx, vy, vz, b.ca, b.sa);
+        const float3 v = apply_rotation(load_rot(gp(b.un) + c), vx, vy, vz);
         diag_check(d, v);
         const int3 nc = next_cell(b, x, y, z, v, sh1);
         const int3 db = brick_of_cell(b, nc);
@@ -1011,17 +1000,10 @@ __global__ __launch_bounds__(kBlock) void k_cell_rotate(const Tile* __restrict__
             sz += to_fixed(mj * vz[j]);
             sw += to_fixed(mj);
         }
-        CellUN u;
-        u.ux = fixed_mean(sx, sw);
-        u.uy = fixed_mean(sy, sw);
-        u.uz = fixed_mean(sz, sw);
-        const float3 ax = cell_axis(b, s.k, (uint32_t)c);
-        u.nx = ax.x;
-        u.ny = ax.y;
-        u.nz = ax.z;
-        u.kappa = axis_kappa(ax);
+        const CellRot cr = cell_rotation(fixed_mean(sx, sw), fixed_mean(sy, sw), fixed_mean(sz, sw),
+                                         cell_axis(b, s.k, (uint32_t)c), ca, sa);
         for (uint32_t j = beg; j < end; ++j) {
-            const float3 v = rotate_about(u, vx[j], vy[j], vz[j], ca, sa);
+            const float3 v = apply_rotation(cr, vx[j], vy[j], vz[j]);
             vx[j] = v.x;
             vy[j] = v.y;
             vz[j] = v.z;
