@@ -235,6 +235,23 @@ __device__ __forceinline__ void put_particle(const BoxDev& b, int src, int dst, 
     }
 }
 
+// VACF term of one particle (v(0) from slot i of buffer src)
+__device__ __forceinline__ void vacf_term(const BoxDev& b, int src, uint32_t i, float3 v,
+                                                   long long (&d)[kNumDiag])
+{
+    const uint32_t o = i * 4u;
+    diag_vacf(d, v, ldg(gp(b.v0[src][0]), o), ldg(gp(b.v0[src][1]), o), ldg(gp(b.v0[src][2]), o));
+}
+
+// the VACF reference of slot i of buffer src goes to slot j of buffer dst
+__device__ __forceinline__ void copy_v0(const BoxDev& b, int src, int dst, uint32_t i, uint32_t j)
+{
+    const uint32_t oi = i * 4u, oj = j * 4u;
+    stg(gp(b.v0[dst][0]), oj, ldg(gp(b.v0[src][0]), oi));
+    stg(gp(b.v0[dst][1]), oj, ldg(gp(b.v0[src][1]), oi));
+    stg(gp(b.v0[dst][2]), oj, ldg(gp(b.v0[src][2]), oi));
+}
+
 // One SRD step of one brick (paper Sec. 2; the shifted grid of Sec. 3.1;
 // the mass-weighted cell velocity of Sec. 3.3).  The workgroup owns every
 // particle whose collision cell lies in its brick, so the whole step is one
@@ -413,6 +430,14 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
 
     // 3./4. rotate, route to the next step's buckets, store
     const float3 sh1 = grid_shift(b, k + 1);
+    MPCD_G float* const ox = gp(b.p[dst][0]);
+    MPCD_G float* const oy = gp(b.p[dst][1]);
+    MPCD_G float* const oz = gp(b.p[dst][2]);
+    MPCD_G float* const ovx = gp(b.p[dst][3]);
+    MPCD_G float* const ovy = gp(b.p[dst][4]);
+    MPCD_G float* const ovz = gp(b.p[dst][5]);
+    MPCD_G int32_t* const oid = gp(b.pid[dst]);
+    const MPCD_G int32_t* const iid = gp(b.pid[src]);
     const double ca = b.ca, sa = b.sa;
     const bool track = b.vacf_stride > 0;
     const bool has_m = kMass && b.m[src] != nullptr;
@@ -447,10 +472,7 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
                 }
                 const float3 v = make_float3(vx[u], vy[u], vz[u]);
                 diag_check(d, v);
-                if (vacf) {
-                    const uint32_t o = (beg + i) * 4u;
-                    diag_vacf(d, v, ldg(gp(b.v0[src][0]), o), ldg(gp(b.v0[src][1]), o), ldg(gp(b.v0[src][2]), o));
-                }
+                if (vacf) vacf_term(b, src, beg + i, v, d);
                 // brick of the next collision cell (a non-finite position
                 // lands far away and takes the clamped slow path below)
                 const int dbx = brick_of(axis_cell_raw(fold(fmaf(v.x, dt, px[u]), b.len[0]), sh1.x, inv_a, b.L[0]), b.bshift[0]);
@@ -479,7 +501,7 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
         for (int u = 0; u < kS; ++u) {
             if (u >= nu) break;
             const uint32_t i = (uint32_t)ch * kChunk + (uint32_t)(u * kT) + threadIdx.x;
-            id[u] = ldg(gp(b.pid[src]), (beg + (i < cnt ? i : 0u)) * 4u);
+            id[u] = ldg(iid, (beg + (i < cnt ? i : 0u)) * 4u);
         }
         __syncthreads();
         if (threadIdx.x < 27) {
@@ -522,7 +544,16 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
                 d[5] += 1;
                 continue;
             }
-            put_particle(b, src, dst, beg + i, j, px[u], py[u], pz[u], v, id[u], pm[u], has_m, track);
+            const uint32_t o = j * 4u;
+            stg(ox, o, px[u]);
+            stg(oy, o, py[u]);
+            stg(oz, o, pz[u]);
+            stg(ovx, o, v.x);
+            stg(ovy, o, v.y);
+            stg(ovz, o, v.z);
+            stg(oid, o, id[u]);
+            if (has_m) stg(gp(b.m[dst]), o, pm[u]);
+            if (track) copy_v0(b, src, dst, beg + i, j);
         }
         if (ch + 1 < nch) __syncthreads();
     }
