@@ -99,6 +99,11 @@ struct mpcd_ctx {
 
 namespace {
 
+// Registers a brick workgroup needs for buckets of `mean` particles on
+// average: the mean plus four Poisson standard deviations (larger buckets
+// run in a second chunk).
+int64_t bucket_need(double mean) { return (int64_t)std::ceil(mean + 4.0 * std::sqrt(mean) + 16.0); }
+
 void* ctx_alloc(mpcd_ctx* c, size_t bytes)
 {
     if (bytes == 0) bytes = 256;
@@ -233,9 +238,9 @@ int rebuild_tables(mpcd_ctx* c)
         } else {
             c->any_brick = true;
             max_bvol = std::max(max_bvol, b.bmax[0] * b.bmax[1] * b.bmax[2]);
-            // a bucket well above the mean (Poisson spread) still fits one chunk
-            const int64_t mean = b.nbrick > 0 ? (b.n + b.nbrick - 1) / b.nbrick : 0;
-            max_bucket = std::max<int64_t>(max_bucket, mean + mean / 4 + 64);
+            // a full brick's bucket, with a 4-sigma Poisson margin, fits one chunk
+            max_bucket = std::max<int64_t>(max_bucket, bucket_need((double)b.n * b.bmax[0] * b.bmax[1] * b.bmax[2] /
+                                                                   (double)b.ncell));
             brick_mass |= b.m[0] != nullptr;
         }
     }
@@ -569,11 +574,11 @@ constexpr int kNumRuleShapes = (int)(sizeof(kRuleShapes) / sizeof(kRuleShapes[0]
 
 static int rule_shape(double density)
 {
-    const double fit = (double)brick_shape_threads(1) * brick_shape_slots(1);   // 256 x 8
+    const int64_t fit = (int64_t)brick_shape_threads(1) * brick_shape_slots(1);   // 256 x 6
     int best = 0;
     for (int i = 0; i < kNumRuleShapes; ++i) {
         const double v = (double)kRuleShapes[i][0] * kRuleShapes[i][1] * kRuleShapes[i][2];
-        if (v * density * 1.25 + 64.0 <= fit) best = i;
+        if (bucket_need(v * density) <= fit) best = i;
     }
     return best;
 }

@@ -1276,6 +1276,7 @@ static const struct {
     void (*run)(const Tables&, hipStream_t);
 } kBrickShapes[] = {
     {128, 8, brick_step_at<128, 8>},
+    {256, 6, brick_step_at<256, 6>},   // fits 4 waves per SIMD
     {256, 8, brick_step_at<256, 8>},
     {512, 8, brick_step_at<512, 8>},
 };
