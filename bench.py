@@ -117,6 +117,10 @@ def main():
     ap.add_argument("--window", type=float, default=10.0, help="served: seconds of arrivals")
     ap.add_argument("--binning", default="auto", choices=["auto", "atomic", "sort"])
     ap.add_argument("--brick", type=int, nargs=3, default=[0, 0, 0])
+    ap.add_argument("--masses", action="store_true",
+                    help="every particle carries its own mass (all 1: the mass-weighted path)")
+    ap.add_argument("--conserve-l", action="store_true",
+                    help="angular-momentum-conserving collision (sort binning)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run device-to-device copies of MIB MiB (counter calibration)")
@@ -159,7 +163,8 @@ def main():
     print("[bench] workload %s: %d particles, admitting" % (args.workload, n), file=sys.stderr,
           flush=True)
     ctx = mpcd.Context(**opts)
-    slot = ctx.admit(mpcd.make_desc(L, n, dt=dt, alpha_deg=alpha, seed=seed, init="maxwell"))
+    slot = ctx.admit(mpcd.make_desc(L, n, dt=dt, alpha_deg=alpha, seed=seed, init="maxwell",
+                                    particle_mass=args.masses, conserve_l=args.conserve_l))
     ctx.step(args.warmup)
     ctx.synchronize()
     print("[bench] warmup done, timing %d steps" % args.steps, file=sys.stderr, flush=True)
@@ -211,7 +216,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "cells": list(L), "particles": n, "dt": dt,
                    "alpha_deg": alpha, "seed": seed, "binning": obs["binning"],
-                   "brick": list(obs["brick"])},
+                   "brick": list(obs["brick"]), "particle_masses": bool(args.masses),
+                   "conserve_angular_momentum": bool(args.conserve_l)},
         "useful_hbm_frac": round(value * STEP_ALGO_BYTES_PER_PARTICLE / 1e9 / HBM_PEAK_GBS, 4),
         "roofline": roofline,
         "kernels": kern,

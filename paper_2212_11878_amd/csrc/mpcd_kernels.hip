@@ -696,35 +696,59 @@ __global__ __launch_bounds__(kBlock) void k_count(const Tile* __restrict__ tiles
                                                    const BoxState* __restrict__ st)
 {
     const Tile tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];
-    const BoxState s = st[tl.box];
-    const BoxDev& b = boxes[tl.box];
+    const BoxState s = st[uniform(tl.box)];
+    const BoxDev& b = boxes[uniform(tl.box)];
     if (box_idle(s) || !sort_due(b, s)) return;
-    const float* __restrict__ x = b.p[s.parity][0];
-    const float* __restrict__ y = b.p[s.parity][1];
-    const float* __restrict__ z = b.p[s.parity][2];
-    const float* __restrict__ vx = b.p[s.parity][3];
-    const float* __restrict__ vy = b.p[s.parity][4];
-    const float* __restrict__ vz = b.p[s.parity][5];
-    const int32_t* __restrict__ pid = b.pid[s.parity];
+    const int par = uniform(s.parity);
+    const MPCD_G float* __restrict__ x = gp(b.p[par][0]);
+    const MPCD_G float* __restrict__ y = gp(b.p[par][1]);
+    const MPCD_G float* __restrict__ z = gp(b.p[par][2]);
+    const MPCD_G float* __restrict__ vx = gp(b.p[par][3]);
+    const MPCD_G float* __restrict__ vy = gp(b.p[par][4]);
+    const MPCD_G float* __restrict__ vz = gp(b.p[par][5]);
+    const MPCD_G int32_t* __restrict__ pid = gp(b.pid[par]);
+    MPCD_G uint32_t* __restrict__ cell = gp(b.cell);
+    MPCD_G uint32_t* __restrict__ rank = gp(b.rank);
     const bool by_brick = (b.binning == 1);
-    const float3 sh = grid_shift(b, s.k);
+    const float3 sh = grid_shift(b, uniform(s.k));
     const float dt = b.dt;
-    for (int64_t i = tl.begin + threadIdx.x; i < tl.end; i += kBlock) {
-        if (pid[i] < 0) continue;   // hole
-        const float px = fold(fmaf(vx[i], dt, x[i]), b.len[0]);
-        const float py = fold(fmaf(vy[i], dt, y[i]), b.len[1]);
-        const float pz = fold(fmaf(vz[i], dt, z[i]), b.len[2]);
-        uint32_t key;
-        if (by_brick) {   // the brick holding the collision cell of this step
-            const int3 c = make_int3(axis_cell(px, sh.x, b.inv_a, b.L[0]), axis_cell(py, sh.y, b.inv_a, b.L[1]),
-                                     axis_cell(pz, sh.z, b.inv_a, b.L[2]));
-            const int3 d = brick_of_cell(b, c);
-            key = (uint32_t)(d.x + b.nb[0] * (d.y + b.nb[1] * d.z));
-        } else {
-            key = collision_cell(b, px, py, pz, sh);
+    constexpr int kU = 4;   // particles per thread in flight
+    for (int64_t i0 = tl.begin + threadIdx.x; i0 < tl.end; i0 += (int64_t)kBlock * kU) {
+        float qx[kU], qy[kU], qz[kU], ux[kU], uy[kU], uz[kU];
+        int32_t id[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {   // issue every load first
+            const int64_t i = i0 + (int64_t)u * kBlock;
+            const int64_t j = i < tl.end ? i : tl.begin;
+            qx[u] = x[j];
+            qy[u] = y[j];
+            qz[u] = z[j];
+            ux[u] = vx[j];
+            uy[u] = vy[j];
+            uz[u] = vz[j];
+            id[u] = i < tl.end ? pid[j] : -1;
         }
-        b.cell[i] = key;
-        keys_rank(b.cstart, key, &b.rank[i]);
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int64_t i = i0 + (int64_t)u * kBlock;
+            if (id[u] < 0) continue;   // hole (or past the tile)
+            const float px = fold(fmaf(ux[u], dt, qx[u]), b.len[0]);
+            const float py = fold(fmaf(uy[u], dt, qy[u]), b.len[1]);
+            const float pz = fold(fmaf(uz[u], dt, qz[u]), b.len[2]);
+            uint32_t key;
+            if (by_brick) {   // the brick holding the collision cell of this step
+                const int3 c = make_int3(axis_cell(px, sh.x, b.inv_a, b.L[0]), axis_cell(py, sh.y, b.inv_a, b.L[1]),
+                                         axis_cell(pz, sh.z, b.inv_a, b.L[2]));
+                const int3 d = brick_of_cell(b, c);
+                key = (uint32_t)(d.x + b.nb[0] * (d.y + b.nb[1] * d.z));
+            } else {
+                key = collision_cell(b, px, py, pz, sh);
+            }
+            cell[i] = key;
+            uint32_t r = 0u;
+            keys_rank(b.cstart, key, &r);
+            rank[i] = r;
+        }
     }
 }
 
@@ -825,35 +849,74 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const Tile* __restrict__ til
                                                      const BoxState* __restrict__ st)
 {
     const Tile tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];
-    const BoxState s = st[tl.box];
-    const BoxDev& b = boxes[tl.box];
+    const BoxState s = st[uniform(tl.box)];
+    const BoxDev& b = boxes[uniform(tl.box)];
     if (box_idle(s) || !sort_due(b, s)) return;
-    const int src = s.parity, dst = s.parity ^ 1;
+    const int src = uniform(s.parity), dst = src ^ 1;
     const bool stream = (b.binning == 2);
     const bool vacf = b.vacf_stride > 0;
+    const bool has_m = b.m[src] != nullptr;
     const float dt = b.dt;
-    for (int64_t i = tl.begin + threadIdx.x; i < tl.end; i += kBlock) {
-        if (b.pid[src][i] < 0) continue;   // hole
-        const int64_t j = (int64_t)b.cstart[b.cell[i]] + b.rank[i];
-        const float vx = b.p[src][3][i], vy = b.p[src][4][i], vz = b.p[src][5][i];
-        float px = b.p[src][0][i], py = b.p[src][1][i], pz = b.p[src][2][i];
-        if (stream) {
-            px = fold(fmaf(vx, dt, px), b.len[0]);
-            py = fold(fmaf(vy, dt, py), b.len[1]);
-            pz = fold(fmaf(vz, dt, pz), b.len[2]);
+    const MPCD_G float* __restrict__ ix = gp(b.p[src][0]);
+    const MPCD_G float* __restrict__ iy = gp(b.p[src][1]);
+    const MPCD_G float* __restrict__ iz = gp(b.p[src][2]);
+    const MPCD_G float* __restrict__ ivx = gp(b.p[src][3]);
+    const MPCD_G float* __restrict__ ivy = gp(b.p[src][4]);
+    const MPCD_G float* __restrict__ ivz = gp(b.p[src][5]);
+    const MPCD_G int32_t* __restrict__ iid = gp(b.pid[src]);
+    MPCD_G float* __restrict__ ox = gp(b.p[dst][0]);
+    MPCD_G float* __restrict__ oy = gp(b.p[dst][1]);
+    MPCD_G float* __restrict__ oz = gp(b.p[dst][2]);
+    MPCD_G float* __restrict__ ovx = gp(b.p[dst][3]);
+    MPCD_G float* __restrict__ ovy = gp(b.p[dst][4]);
+    MPCD_G float* __restrict__ ovz = gp(b.p[dst][5]);
+    MPCD_G int32_t* __restrict__ oid = gp(b.pid[dst]);
+    const MPCD_G uint32_t* __restrict__ cell = gp(b.cell);
+    const MPCD_G uint32_t* __restrict__ rank = gp(b.rank);
+    const MPCD_G uint32_t* __restrict__ cstart = gp(b.cstart);
+    constexpr int kU = 4;   // particles per thread in flight
+    for (int64_t i0 = tl.begin + threadIdx.x; i0 < tl.end; i0 += (int64_t)kBlock * kU) {
+        float qx[kU], qy[kU], qz[kU], ux[kU], uy[kU], uz[kU];
+        int32_t id[kU];
+        uint32_t key[kU], rk[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {   // issue every load first
+            const int64_t i = i0 + (int64_t)u * kBlock;
+            const int64_t j = i < tl.end ? i : tl.begin;
+            id[u] = i < tl.end ? iid[j] : -1;
+            key[u] = cell[j];
+            rk[u] = rank[j];
+            qx[u] = ix[j];
+            qy[u] = iy[j];
+            qz[u] = iz[j];
+            ux[u] = ivx[j];
+            uy[u] = ivy[j];
+            uz[u] = ivz[j];
         }
-        b.p[dst][0][j] = px;
-        b.p[dst][1][j] = py;
-        b.p[dst][2][j] = pz;
-        b.p[dst][3][j] = vx;
-        b.p[dst][4][j] = vy;
-        b.p[dst][5][j] = vz;
-        b.pid[dst][j] = b.pid[src][i];
-        if (b.m[src]) b.m[dst][j] = b.m[src][i];
-        if (vacf) {
-            b.v0[dst][0][j] = b.v0[src][0][i];
-            b.v0[dst][1][j] = b.v0[src][1][i];
-            b.v0[dst][2][j] = b.v0[src][2][i];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            if (id[u] < 0) continue;   // hole (or past the tile)
+            const int64_t i = i0 + (int64_t)u * kBlock;
+            const int64_t j = (int64_t)cstart[key[u]] + rk[u];
+            float px = qx[u], py = qy[u], pz = qz[u];
+            if (stream) {
+                px = fold(fmaf(ux[u], dt, px), b.len[0]);
+                py = fold(fmaf(uy[u], dt, py), b.len[1]);
+                pz = fold(fmaf(uz[u], dt, pz), b.len[2]);
+            }
+            ox[j] = px;
+            oy[j] = py;
+            oz[j] = pz;
+            ovx[j] = ux[u];
+            ovy[j] = uy[u];
+            ovz[j] = uz[u];
+            oid[j] = id[u];
+            if (has_m) gp(b.m[dst])[j] = gp(b.m[src])[i];
+            if (vacf) {
+                gp(b.v0[dst][0])[j] = gp(b.v0[src][0])[i];
+                gp(b.v0[dst][1])[j] = gp(b.v0[src][1])[i];
+                gp(b.v0[dst][2])[j] = gp(b.v0[src][2])[i];
+            }
         }
     }
 }
