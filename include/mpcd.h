@@ -30,7 +30,7 @@
  *     unchanged (admission is all-or-nothing).
  *   - A context is not thread safe: use it from one host thread.
  *   - Device work is queued on the context's HIP stream; only mpcd_observe,
- *     mpcd_get_state, mpcd_set_state, mpcd_admit, mpcd_release and
+ *     mpcd_get_state, mpcd_set_state, mpcd_set_mass, mpcd_admit and
  *     mpcd_kernel_stats synchronise with it.
  *   - Pointers marked "host" are ordinary host memory owned by the caller
  *     and only read or written during the call.
@@ -104,7 +104,10 @@ typedef struct {
 } mpcd_box_desc;
 
 /* Device allocator supplied by the caller (e.g. backed by PyTorch).  Must
- * return device memory aligned to >= 256 bytes, or NULL. */
+ * return device memory aligned to >= 256 bytes, or NULL, and be ordered on
+ * the context stream: memory given back by the free callback may be handed
+ * out again only to work queued after it on that stream (PyTorch's caching
+ * allocator on the same stream is). */
 typedef void* (*mpcd_alloc_fn)(size_t bytes, void* user);
 typedef void (*mpcd_free_fn)(void* ptr, void* user);
 
@@ -198,7 +201,11 @@ int mpcd_set_state(mpcd_ctx* ctx, int32_t slot, const float* xyzv, int64_t step)
  * bad value (state unchanged).  Synchronises. */
 int mpcd_set_mass(mpcd_ctx* ctx, int32_t slot, const float* mass);
 
-/* Free a box's device state; the slot number may be reused.  Synchronises. */
+/* Free a box's device state; the slot number may be reused.  Does not wait
+ * for queued steps: the memory goes back through the context's allocator,
+ * which must be stream-ordered (work already queued on the context stream
+ * may still read it; hipFree, the default, waits for the device).  The box
+ * tables are rebuilt before the next step. */
 int mpcd_release(mpcd_ctx* ctx, int32_t slot);
 
 /* Turn per-kernel HIP-event timing on (1) or off (0); turning it on clears

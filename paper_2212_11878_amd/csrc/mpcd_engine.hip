@@ -270,13 +270,23 @@ int rebuild_tables(mpcd_ctx* c)
     c->T.brick_shape = brick_shape_for(max_bucket);
     c->T.brick_mass = brick_mass;
     c->T.host_flag = c->host_flag_dev;
-    if (!pt.empty()) HIPCHK(hipMemcpy(c->T.ptiles, pt.data(), pt.size() * sizeof(Tile), hipMemcpyHostToDevice));
-    if (!ct.empty()) HIPCHK(hipMemcpy(c->T.ctiles, ct.data(), ct.size() * sizeof(Tile), hipMemcpyHostToDevice));
-    if (!bt.empty()) HIPCHK(hipMemcpy(c->T.btiles, bt.data(), bt.size() * sizeof(Tile), hipMemcpyHostToDevice));
-    if (!active.empty())
-        HIPCHK(hipMemcpy(c->T.active, active.data(), active.size() * 4, hipMemcpyHostToDevice));
-    for (int32_t s : active)
-        HIPCHK(hipMemcpy(&c->T.boxes[s], &c->slots[s].dev, sizeof(BoxDev), hipMemcpyHostToDevice));
+    // one upload for the tile lists (laid out as on the device) and one for
+    // the box descriptors of every slot in use
+    const size_t tiles_bytes = (size_t)((char*)c->T.tilesum - base);
+    std::vector<char> host(tiles_bytes, 0);
+    auto put = [&](void* dev, const void* src, size_t bytes) {
+        if (bytes) memcpy(host.data() + ((char*)dev - base), src, bytes);
+    };
+    put(c->T.ptiles, pt.data(), pt.size() * sizeof(Tile));
+    put(c->T.ctiles, ct.data(), ct.size() * sizeof(Tile));
+    put(c->T.btiles, bt.data(), bt.size() * sizeof(Tile));
+    put(c->T.active, active.data(), active.size() * 4);
+    HIPCHK(hipMemcpy(base, host.data(), tiles_bytes, hipMemcpyHostToDevice));
+    if (!c->slots.empty()) {
+        std::vector<BoxDev> devs(c->slots.size());
+        for (size_t s = 0; s < c->slots.size(); ++s) devs[s] = c->slots[s].dev;
+        HIPCHK(hipMemcpy(c->T.boxes, devs.data(), devs.size() * sizeof(BoxDev), hipMemcpyHostToDevice));
+    }
     c->dirty = false;
     return MPCD_OK;
 }
@@ -1055,13 +1065,16 @@ int mpcd_release(mpcd_ctx* c, int32_t slot)
     if (!c) return MPCD_EINVAL;
     if (!sl) return MPCD_ENOTFOUND;
     HIPCHK(hipSetDevice(c->device));
-    HIPCHK(hipStreamSynchronize(c->stream));
+    // Steps already queued may still read this box: the caller's allocator
+    // is stream-ordered (its memory is reused only by later work on the
+    // stream) and hipFree waits for the device, so the memory can go now.
+    // The tables are rebuilt before the next step.
     ctx_free(c, sl->mem);
     c->used -= (int64_t)sl->bytes;
     sl->live = false;
     sl->mem = nullptr;
     c->dirty = true;
-    return rebuild_tables(c);
+    return MPCD_OK;
 }
 
 int mpcd_profile(mpcd_ctx* c, int32_t enable)

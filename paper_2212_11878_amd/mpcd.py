@@ -120,6 +120,12 @@ _SIGNATURES = {
 if not os.path.exists(LIB_PATH):
     raise ImportError("libmpcd.so is not built (%s); run `python -m paper_2212_11878_amd.csrc.build`"
                       % LIB_PATH)
+# PyTorch ships its own HIP runtime.  Loading it first makes the library's
+# libamdhip64 dependency resolve to that same copy (same soname); loading the
+# library first would map a second runtime, whose streams and device pointers
+# are not the ones PyTorch hands over.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 for _name, (_res, _args) in _SIGNATURES.items():
     _f = getattr(_lib, _name)
@@ -223,19 +229,23 @@ def mpcd_destroy(ctx):
 # convenience wrapper: torch memory and stream, exceptions on errors
 
 class _TorchAllocator:
-    """Device memory for the library from PyTorch's caching allocator."""
+    """Device memory for the library from PyTorch's caching allocator, in
+    the pool of the library's stream: a freed block is reused only by
+    allocations made for that stream, i.e. by work queued after the free."""
 
-    def __init__(self, device):
+    def __init__(self, device, stream):
         import torch
         self._torch = torch
         self.device = device
+        self.stream = stream
         self.blocks = {}
         self.c_alloc = mpcd_alloc_fn(self._alloc)
         self.c_free = mpcd_free_fn(self._free)
 
     def _alloc(self, nbytes, user):
         try:
-            t = self._torch.empty(int(nbytes), dtype=self._torch.uint8, device=self.device)
+            with self._torch.cuda.stream(self.stream):
+                t = self._torch.empty(int(nbytes), dtype=self._torch.uint8, device=self.device)
         except Exception:
             return None
         p = t.data_ptr()
@@ -287,7 +297,7 @@ class Context:
             raise RuntimeError("no GPU visible to PyTorch; libmpcd needs a HIP device")
         self.device = torch.device("cuda", device)
         self.stream = torch.cuda.Stream(device=self.device)
-        self.allocator = _TorchAllocator(self.device)
+        self.allocator = _TorchAllocator(self.device, self.stream)
         opt = mpcd_options()
         opt.binning = binning
         if isinstance(brick, int):

@@ -100,3 +100,14 @@ def test_brick_edges_must_be_powers_of_two(m):
             assert rc != m.MPCD_EINVAL, edges
         else:
             assert rc == m.MPCD_EINVAL, edges
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    """The binding and PyTorch share one HIP runtime in the process, also when
+    the binding is imported before torch."""
+    code = ("import paper_2212_11878_amd.mpcd\n"
+            "print(len(set(l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l)))\n")
+    out = subprocess.run([__import__("sys").executable, "-c", code], cwd=ROOT, capture_output=True,
+                         text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == "1"
