@@ -122,6 +122,7 @@ struct BoxState {
     long long overflow_steps;   // brick mode: steps in which a bucket was full
     long long rebuckets;        // brick mode: re-bucketings done
     double diag[4];        // sum m v (3), sum m v^2 of the last snapshot (exact sums, rounded once)
+    float adj[4];          // initial-state adjustment v <- (v - adj[0..2]) * adj[3]
 };
 
 // Record copies to and from global memory as native vectors (struct

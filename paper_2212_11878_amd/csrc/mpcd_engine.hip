@@ -46,8 +46,25 @@ struct Slot {
     size_t bytes = 0;
     BoxDev dev{};
     int64_t ptiles = 0, ctiles = 0;
-    int32_t part_tile = kPartTile;   // slots per tile
+    int32_t ntile = 0;               // particle tiles of kPartTile slots
+    long long* part = nullptr;       // ntile x kNumDiag partials of the per-box kernels
     double mass_total = 0.0;         // sum of the per-particle masses (MPCD_PARTICLE_MASS)
+};
+
+// Pinned staging buffer of an asynchronous upload; reusable once the copy
+// that reads it (recorded by `done`) has run.
+struct Upload {
+    void* p = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+};
+
+// A replaced step graph: destroyed once the launches queued before the
+// replacement (recorded by `done`) have run.
+struct Retired {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;
 };
 
 }  // namespace
@@ -83,6 +100,10 @@ struct mpcd_ctx {
     // graph of one step
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
+    std::vector<Retired> retired;
+
+    // host-to-device uploads are stream-ordered through pinned staging
+    std::vector<Upload> uploads;
 
     // profiling
     bool profiling = false;
@@ -122,19 +143,96 @@ void ctx_free(mpcd_ctx* c, void* p)
         (void)hipFree(p);
 }
 
-void drop_graph(mpcd_ctx* c)
+// Destroy the retired graphs whose queued launches have run (all of them
+// with `wait`, after the stream has drained).
+void purge_retired(mpcd_ctx* c, bool wait)
 {
-    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
-    if (c->graph) (void)hipGraphDestroy(c->graph);
-    c->graph_exec = nullptr;
+    size_t keep = 0;
+    for (size_t i = 0; i < c->retired.size(); ++i) {
+        Retired& r = c->retired[i];
+        if (wait || hipEventQuery(r.done) == hipSuccess) {
+            if (r.exec) (void)hipGraphExecDestroy(r.exec);
+            if (r.graph) (void)hipGraphDestroy(r.graph);
+            (void)hipEventDestroy(r.done);
+        } else {
+            c->retired[keep++] = r;
+        }
+    }
+    c->retired.resize(keep);
+}
+
+// Take the current step graph out of use.  Launches of it may still be
+// queued on the stream, so it is destroyed later (purge_retired).
+int drop_graph(mpcd_ctx* c)
+{
+    purge_retired(c, false);
+    if (!c->graph && !c->graph_exec) return MPCD_OK;
+    Retired r{c->graph, c->graph_exec, nullptr};
     c->graph = nullptr;
+    c->graph_exec = nullptr;
+    if (hipEventCreateWithFlags(&r.done, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(r.done, c->stream) != hipSuccess) {
+        // no event: wait for the stream instead
+        if (r.done) (void)hipEventDestroy(r.done);
+        (void)hipStreamSynchronize(c->stream);
+        if (r.exec) (void)hipGraphExecDestroy(r.exec);
+        if (r.graph) (void)hipGraphDestroy(r.graph);
+        return MPCD_EDEVICE;
+    }
+    c->retired.push_back(r);
+    return MPCD_OK;
+}
+
+// Copy `bytes` host bytes to device address `dst` in stream order: the
+// bytes are staged in pinned memory at once (the caller may reuse `src` on
+// return) and the copy runs after the work already queued on the stream.
+int upload(mpcd_ctx* c, void* dst, const void* src, size_t bytes)
+{
+    if (bytes == 0) return MPCD_OK;
+    constexpr size_t kMaxUploads = 1024;
+    Upload* u = nullptr;
+    for (Upload& x : c->uploads)
+        if (x.cap >= bytes && hipEventQuery(x.done) == hipSuccess) {
+            u = &x;
+            break;
+        }
+    if (!u && c->uploads.size() >= kMaxUploads) {
+        // all buffers busy or small: wait for the oldest copy, grow its buffer
+        u = &c->uploads.front();
+        for (Upload& x : c->uploads)
+            if (x.cap >= bytes) {
+                u = &x;
+                break;
+            }
+        HIPCHK(hipEventSynchronize(u->done));
+    }
+    if (!u) {
+        c->uploads.emplace_back();
+        u = &c->uploads.back();
+        HIPCHK(hipEventCreateWithFlags(&u->done, hipEventDisableTiming));
+    }
+    if (u->cap < bytes) {
+        if (u->p) HIPCHK(hipHostFree(u->p));
+        u->p = nullptr;
+        u->cap = 0;
+        size_t cap = 4096;
+        while (cap < bytes) cap *= 2;
+        HIPCHK(hipHostMalloc(&u->p, cap, hipHostMallocDefault));
+        u->cap = cap;
+    }
+    memcpy(u->p, src, bytes);
+    HIPCHK(hipMemcpyAsync(dst, u->p, bytes, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipEventRecord(u->done, c->stream));
+    return MPCD_OK;
 }
 
 // Layout of one box's device allocation.
 struct Layout {
     size_t off_p[2][6], off_v0[2][3], off_pid[2], off_m[2], off_cell, off_rank, off_cstart, off_un, off_esc[2],
-        off_eflag, off_bstart, off_bsize[2], off_vacf, total;
+        off_eflag, off_bstart, off_bsize[2], off_vacf, off_part, total;
 };
+
+int ntile_of(int64_t nslot) { return (int)std::max<int64_t>(1, (nslot + kPartTile - 1) / kPartTile); }
 
 Layout box_layout(int64_t nslot, int64_t ncell, bool vacf, int vacf_cap, bool brick, const BrickGeom& g,
                   bool masses)
@@ -164,6 +262,7 @@ Layout box_layout(int64_t nslot, int64_t ncell, bool vacf, int vacf_cap, bool br
     L.off_bstart = o; o += align256((nbk + 2) * 4);
     for (int b = 0; b < 2; ++b) { L.off_bsize[b] = o; o += align256((nbk + 1) * 4); }
     L.off_vacf = o; o += align256((size_t)std::max(vacf_cap, 1) * 8);
+    L.off_part = o; o += align256((size_t)ntile_of(nslot) * kNumDiag * 8);
     L.total = o;
     return L;
 }
@@ -205,11 +304,14 @@ int vacf_capacity(const mpcd_box_desc* d)
 }
 
 // Rebuild the device tables (tiles, active list, descriptors) for the live
-// slots.  Synchronises the stream first (old tables may still be in use).
+// slots.  The uploads are stream-ordered, so work already queued still reads
+// the old tables; the step graph is replaced.
 int rebuild_tables(mpcd_ctx* c)
 {
-    HIPCHK(hipStreamSynchronize(c->stream));
-    drop_graph(c);
+    {
+        int rc = drop_graph(c);
+        if (rc) return rc;
+    }
     std::vector<Tile> pt, ct, bt;
     std::vector<int32_t> active;
     c->any_brick = c->any_sort = false;
@@ -222,8 +324,8 @@ int rebuild_tables(mpcd_ctx* c)
         active.push_back(s);
         BoxDev& b = sl.dev;
         b.ptile0 = (int32_t)pt.size();
-        for (int64_t i = 0; i < b.nslot; i += sl.part_tile)
-            pt.push_back(Tile{s, 0, i, std::min<int64_t>(b.nslot, i + sl.part_tile)});
+        for (int64_t i = 0; i < b.nslot; i += kPartTile)
+            pt.push_back(Tile{s, 0, i, std::min<int64_t>(b.nslot, i + kPartTile)});
         b.ptile1 = (int32_t)pt.size();
         b.ctile0 = (int32_t)ct.size();
         for (int64_t i = 0; i < b.ncell; i += kCellTile)
@@ -246,7 +348,7 @@ int rebuild_tables(mpcd_ctx* c)
     }
     const size_t need = align256(pt.size() * sizeof(Tile) + 256) + align256(ct.size() * sizeof(Tile) + 256) +
                         align256(bt.size() * sizeof(Tile) + 256) + align256(active.size() * 4 + 256) +
-                        align256(pt.size() * kNumDiag * 8 + 256) + align256(ct.size() * 4 + 256);
+                        align256(ct.size() * 4 + 256);
     if (need > c->tile_cap) {
         void* m = ctx_alloc(c, need * 5 / 4);
         if (!m) return MPCD_ENOMEM;
@@ -260,7 +362,6 @@ int rebuild_tables(mpcd_ctx* c)
     c->T.ctiles = (Tile*)(base + o); o += align256(ct.size() * sizeof(Tile) + 256);
     c->T.btiles = (Tile*)(base + o); o += align256(bt.size() * sizeof(Tile) + 256);
     c->T.active = (int32_t*)(base + o); o += align256(active.size() * 4 + 256);
-    c->T.partials = (long long*)(base + o); o += align256(pt.size() * kNumDiag * 8 + 256);
     c->T.tilesum = (uint32_t*)(base + o);
     c->T.nptiles = (int)pt.size();
     c->T.nctiles = (int)ct.size();
@@ -281,11 +382,13 @@ int rebuild_tables(mpcd_ctx* c)
     put(c->T.ctiles, ct.data(), ct.size() * sizeof(Tile));
     put(c->T.btiles, bt.data(), bt.size() * sizeof(Tile));
     put(c->T.active, active.data(), active.size() * 4);
-    HIPCHK(hipMemcpy(base, host.data(), tiles_bytes, hipMemcpyHostToDevice));
+    int rc = upload(c, base, host.data(), tiles_bytes);
+    if (rc) return rc;
     if (!c->slots.empty()) {
         std::vector<BoxDev> devs(c->slots.size());
         for (size_t s = 0; s < c->slots.size(); ++s) devs[s] = c->slots[s].dev;
-        HIPCHK(hipMemcpy(c->T.boxes, devs.data(), devs.size() * sizeof(BoxDev), hipMemcpyHostToDevice));
+        rc = upload(c, c->T.boxes, devs.data(), devs.size() * sizeof(BoxDev));
+        if (rc) return rc;
     }
     c->dirty = false;
     return MPCD_OK;
@@ -368,7 +471,8 @@ int enqueue_step(mpcd_ctx* c, bool with_sort)
 
 int capture_graph(mpcd_ctx* c)
 {
-    drop_graph(c);
+    int rc0 = drop_graph(c);
+    if (rc0) return rc0;
     HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     int rc = enqueue_step(c, false);
     hipGraph_t g = nullptr;
@@ -389,57 +493,39 @@ Slot* live_slot(mpcd_ctx* c, int32_t slot)
     return &c->slots[slot];
 }
 
-// Exact sums of the fixed-point partials over one box's particle tiles
-// (host side, after a synchronising copy), rounded once to FP64.
-int read_box_partials(mpcd_ctx* c, const Slot& sl, double out[kNumDiag])
-{
-    const int n = sl.dev.ptile1 - sl.dev.ptile0;
-    std::vector<long long> h((size_t)n * kNumDiag);
-    if (n > 0)
-        HIPCHK(hipMemcpyAsync(h.data(), c->T.partials + (size_t)sl.dev.ptile0 * kNumDiag,
-                              h.size() * 8, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    for (int j = 0; j < kNumDiag; ++j) {
-        __int128 acc = 0;
-        for (int t = 0; t < n; ++t) acc += h[(size_t)t * kNumDiag + j];
-        out[j] = (j == 5) ? (double)acc : (double)acc * 2.3283064365386963e-10;   // 2^-32
-    }
-    return MPCD_OK;
-}
-
-// Mark the holes of brick box s's current buffer (pid -1), so that host-side
-// passes over all its slots see only particles.
+// Mark the holes of brick box s's current buffer (pid -1), so that passes
+// over all its slots see only particles.
 void mark_holes(mpcd_ctx* c, int32_t s)
 {
     const Slot& sl = c->slots[s];
     if (sl.dev.binning != MPCD_BIN_ATOMIC) return;
-    launch_mark_holes(c->T.ptiles + sl.dev.ptile0, sl.dev.ptile1 - sl.dev.ptile0, c->T, 1, c->stream);
+    launch_mark_holes_box(c->T, s, sl.ntile, c->stream);
 }
 
 // Bucket description of a brick box whose particles sit in slots [0, n) of
 // buffer `parity` in no particular order (all in bucket 0, the rest of the
 // buffer an empty overflow bucket), with no pending escape sums; the next
-// step re-buckets it.
+// step re-buckets it.  Stream-ordered.
 int set_compact_layout(mpcd_ctx* c, int32_t s, int parity)
 {
     const Slot& sl = c->slots[s];
     const BoxDev& b = sl.dev;
     if (b.binning != MPCD_BIN_ATOMIC) return MPCD_OK;
     const size_t nbk = (size_t)b.nbrick;
-    std::vector<uint32_t> start(nbk + 2, (uint32_t)b.n), size(nbk + 1, 0u), zero(nbk + 1, 0u);
+    std::vector<uint32_t> start(nbk + 2, (uint32_t)b.n), size(nbk + 1, 0u);
     start[0] = 0u;
     start[nbk + 1] = (uint32_t)b.nslot;
     size[0] = (uint32_t)b.n;
-    HIPCHK(hipStreamSynchronize(c->stream));
-    HIPCHK(hipMemcpy(b.bstart, start.data(), start.size() * 4, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(b.bsize[parity], size.data(), size.size() * 4, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(b.bsize[parity ^ 1], zero.data(), zero.size() * 4, hipMemcpyHostToDevice));
-    for (int k = 0; k < 2; ++k) HIPCHK(hipMemset(b.esc[k], 0, (size_t)b.ncell * sizeof(CellAcc)));
-    HIPCHK(hipMemset(b.eflag, 0, 2 * nbk * 4));
+    int rc = upload(c, b.bstart, start.data(), start.size() * 4);
+    if (!rc) rc = upload(c, b.bsize[parity], size.data(), size.size() * 4);
+    if (rc) return rc;
+    HIPCHK(hipMemsetAsync(b.bsize[parity ^ 1], 0, (nbk + 1) * 4, c->stream));
+    for (int k = 0; k < 2; ++k) HIPCHK(hipMemsetAsync(b.esc[k], 0, (size_t)b.ncell * sizeof(CellAcc), c->stream));
+    HIPCHK(hipMemsetAsync(b.eflag, 0, 2 * nbk * 4, c->stream));
     return MPCD_OK;
 }
 
-// Write a fresh BoxState for slot s.
+// Write a fresh BoxState for slot s (stream-ordered).
 int reset_state(mpcd_ctx* c, int32_t s, int64_t step, int parity)
 {
     Slot& sl = c->slots[s];
@@ -451,67 +537,38 @@ int reset_state(mpcd_ctx* c, int32_t s, int64_t step, int parity)
     st.vacf_len = 0;
     st.status = 0;
     st.rebucket = (sl.dev.binning == MPCD_BIN_ATOMIC) ? 1 : 0;
+    st.adj[3] = 1.0f;
     if (st.rebucket) c->pending_rebucket = true;
-    HIPCHK(hipStreamSynchronize(c->stream));
-    HIPCHK(hipMemcpy(&c->T.state[s], &st, sizeof(BoxState), hipMemcpyHostToDevice));
-    return MPCD_OK;
+    return upload(c, &c->T.state[s], &st, sizeof(BoxState));
 }
 
-// Diagnostics of the current state; with new_origin also v0 <- v (if
-// tracked) and VACF sample 0.
+// Diagnostics of the current state into the box state (exact sums, status);
+// with new_origin also v0 <- v (if tracked) and VACF sample 0.  Queued on
+// the stream; nothing is read back here.
 int take_snapshot(mpcd_ctx* c, int32_t s, bool new_origin = true)
 {
     Slot& sl = c->slots[s];
-    const Tile* tiles = c->T.ptiles + sl.dev.ptile0;
     mark_holes(c, s);
-    launch_snapshot(tiles, sl.dev.ptile1 - sl.dev.ptile0, c->T, new_origin ? 1 : 0, c->stream);
+    launch_snapshot(c->T, s, sl.ntile, new_origin ? 1 : 0, sl.part, c->stream);
+    launch_box_stats(c->T, s, sl.ntile, sl.part, kStatsSnapshot | (new_origin ? kStatsOrigin : 0), 0.0, 0.0,
+                     c->stream);
     HIPCHK(hipGetLastError());
-    double d[kNumDiag];
-    int rc = read_box_partials(c, sl, d);
-    if (rc) return rc;
-    BoxState st;
-    HIPCHK(hipMemcpy(&st, &c->T.state[s], sizeof(BoxState), hipMemcpyDeviceToHost));
-    st.diag[0] = d[0];
-    st.diag[1] = d[1];
-    st.diag[2] = d[2];
-    st.diag[3] = d[3];
-    if (new_origin) st.vacf_len = 0;
-    if (new_origin && sl.dev.vacf_stride > 0 && sl.dev.n > 0) {
-        const double c0 = d[4] / (double)sl.dev.n;
-        HIPCHK(hipMemcpy(sl.dev.vacf, &c0, 8, hipMemcpyHostToDevice));
-        st.vacf_len = 1;
-    }
-    st.status = (d[5] == 0.0 && d[3] < 1e300) ? 0 : MPCD_ESTATE;
-    HIPCHK(hipMemcpy(&c->T.state[s], &st, sizeof(BoxState), hipMemcpyHostToDevice));
     return MPCD_OK;
 }
 
+// Maxwell-Boltzmann initial state at temperature kT: uniform positions and
+// Gaussian velocities, then the mean velocity removed and the velocities
+// rescaled to the exact temperature.  All on the device.
 int init_maxwell(mpcd_ctx* c, int32_t s)
 {
     Slot& sl = c->slots[s];
-    const int64_t n = sl.dev.n;
-    const Tile* tiles = c->T.ptiles + sl.dev.ptile0;
-    const int nt = sl.dev.ptile1 - sl.dev.ptile0;
     const double vs = sqrt(sl.desc.kT / sl.desc.mass);
-    launch_init_maxwell(tiles, nt, c->T, (float)vs, c->stream);
+    launch_init_maxwell(c->T, s, sl.ntile, (float)vs, sl.part, c->stream);
+    launch_box_stats(c->T, s, sl.ntile, sl.part, kStatsCentre, sl.desc.kT, sl.desc.mass, c->stream);
+    launch_init_adjust(c->T, s, sl.ntile, sl.part, c->stream);
+    launch_box_stats(c->T, s, sl.ntile, sl.part, kStatsScale, sl.desc.kT, sl.desc.mass, c->stream);
+    launch_init_adjust(c->T, s, sl.ntile, sl.part, c->stream);
     HIPCHK(hipGetLastError());
-    double d[kNumDiag];
-    int rc = read_box_partials(c, sl, d);
-    if (rc) return rc;
-    if (n > 1) {
-        const double mx = d[0] / n, my = d[1] / n, mz = d[2] / n;
-        // centre, then measure
-        launch_init_adjust(tiles, nt, c->T, (float)mx, (float)my, (float)mz, 1.0f, c->stream);
-        HIPCHK(hipGetLastError());
-        rc = read_box_partials(c, sl, d);
-        if (rc) return rc;
-        const double m = sl.desc.mass;
-        const double P2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-        const double T = m * (d[3] - P2 / n) / (3.0 * (n - 1));
-        const double scale = T > 0 ? sqrt(sl.desc.kT / T) : 1.0;
-        launch_init_adjust(tiles, nt, c->T, 0.0f, 0.0f, 0.0f, (float)scale, c->stream);
-        HIPCHK(hipGetLastError());
-    }
     return MPCD_OK;
 }
 
@@ -777,6 +834,8 @@ int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
     sl.desc = *d;
     sl.mem = mem;
     sl.bytes = L.total;
+    sl.ntile = ntile_of(nslot);
+    sl.part = (long long*)((char*)mem + L.off_part);
     BoxDev& b = sl.dev;
     char* m = (char*)mem;
     for (int p = 0; p < 2; ++p) {
@@ -826,14 +885,16 @@ int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
     else
         c->slots[s] = sl;
 
+    // Everything below is queued on the stream (nothing waits for the steps
+    // in flight); the box joins the step tables at the next mpcd_step.  Only
+    // its own descriptor is needed by the per-box kernels now.
     auto undo = [&](int code) {
         c->slots[s].live = false;
         ctx_free(c, mem);
-        c->dirty = true;
-        (void)rebuild_tables(c);
         return code;
     };
-    rc = rebuild_tables(c);
+    c->dirty = true;
+    rc = upload(c, &c->T.boxes[s], &c->slots[s].dev, sizeof(BoxDev));
     if (rc) return undo(rc);
     // zeroed cell accumulators and a defined particle state
     Slot& S = c->slots[s];
@@ -860,7 +921,6 @@ int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
     if (rc) return undo(rc);
     rc = take_snapshot(c, s);
     if (rc) return undo(rc);
-    if (hipStreamSynchronize(c->stream) != hipSuccess) return undo(MPCD_EDEVICE);
     c->used += (int64_t)L.total;
     *slot = s;
     return MPCD_OK;
@@ -869,12 +929,13 @@ int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
 int mpcd_step(mpcd_ctx* c, int32_t n)
 {
     if (!c || n < 0) return MPCD_EINVAL;
-    if (n == 0 || c->T.nactive == 0) return MPCD_OK;
+    if (n == 0) return MPCD_OK;
     HIPCHK(hipSetDevice(c->device));
     if (c->dirty) {
         int rc = rebuild_tables(c);
         if (rc) return rc;
     }
+    if (c->T.nactive == 0) return MPCD_OK;
     // a bucket overflowed in an earlier step: the boxes concerned carry the
     // rebucket flag; re-bucket them in the next step
     if (__atomic_exchange_n(c->host_flag, 0, __ATOMIC_ACQ_REL) != 0) c->pending_rebucket = true;
@@ -910,10 +971,6 @@ int mpcd_observe(mpcd_ctx* c, int32_t slot, mpcd_observables* out)
     Slot* sl = live_slot(c, slot);
     if (!sl) return MPCD_ENOTFOUND;
     HIPCHK(hipSetDevice(c->device));
-    if (c->dirty) {
-        int rc = rebuild_tables(c);
-        if (rc) return rc;
-    }
     // momentum and energy of the current state (exact sums over the box)
     int rc = take_snapshot(c, slot, false);
     if (rc) return rc;
@@ -1119,7 +1176,12 @@ void mpcd_destroy(mpcd_ctx* c)
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     (void)harvest(c);
-    drop_graph(c);
+    (void)drop_graph(c);
+    purge_retired(c, true);
+    for (Upload& u : c->uploads) {
+        if (u.p) (void)hipHostFree(u.p);
+        if (u.done) (void)hipEventDestroy(u.done);
+    }
     for (auto& sl : c->slots)
         if (sl.live) ctx_free(c, sl.mem);
     ctx_free(c, c->tile_mem);

@@ -71,6 +71,14 @@ __device__ __forceinline__ long long wave_sum(long long v)
     return v;
 }
 
+// Particle tile blockIdx.x of one box (per-box launches): slots
+// [t kPartTile, (t + 1) kPartTile) clipped to the box's slot count.
+__device__ __forceinline__ Tile box_tile(const BoxDev* __restrict__ boxes, int box)
+{
+    const int64_t begin = (int64_t)blockIdx.x * kPartTile;
+    return Tile{box, 0, begin, min(boxes[box].nslot, begin + (int64_t)kPartTile)};
+}
+
 // Block sum of kNumDiag exact partials; threads 0..kNumDiag-1 write out[].
 template <int kT = kBlock>
 __device__ __forceinline__ void block_diag(long long (&d)[kNumDiag], long long* out)
@@ -604,9 +612,9 @@ __device__ void overflow_step(const BoxDev& b, const BoxState& s, long long (&d)
 // box's state (all = 1: whatever the rebucket flag).
 __global__ __launch_bounds__(kBlock) void k_mark_holes(const Tile* __restrict__ tiles,
                                                         const BoxDev* __restrict__ boxes,
-                                                        const BoxState* __restrict__ st, int all)
+                                                        const BoxState* __restrict__ st, int all, int box)
 {
-    const Tile tl = tiles[blockIdx.x];
+    const Tile tl = box >= 0 ? box_tile(boxes, box) : tiles[blockIdx.x];
     const BoxState s = st[tl.box];
     const BoxDev& b = boxes[tl.box];
     if (b.binning != 1) return;
@@ -1181,13 +1189,12 @@ __global__ __launch_bounds__(kBlock) void k_box_finish(const int32_t* __restrict
 // --------------------------------------------------------------------------
 // initial state on the device (not part of the step)
 
-__global__ __launch_bounds__(kBlock) void k_init_maxwell(const Tile* __restrict__ tiles,
-                                                          const BoxDev* __restrict__ boxes,
-                                                          const BoxState* __restrict__ st,
+__global__ __launch_bounds__(kBlock) void k_init_maxwell(const BoxDev* __restrict__ boxes,
+                                                          const BoxState* __restrict__ st, int box,
                                                           float vscale, long long* __restrict__ partials)
 {
     const int t = blockIdx.x;
-    const Tile tl = tiles[t];
+    const Tile tl = box_tile(boxes, box);
     const BoxDev& b = boxes[tl.box];
     const int par = st[tl.box].parity;
     long long d[kNumDiag] = {0, 0, 0, 0, 0, 0};
@@ -1217,17 +1224,18 @@ __global__ __launch_bounds__(kBlock) void k_init_maxwell(const Tile* __restrict_
     block_diag(d, partials + (size_t)t * kNumDiag);
 }
 
-// v <- (v - V) * scale; partial sums of v^2 before scaling and of v after
-__global__ __launch_bounds__(kBlock) void k_init_adjust(const Tile* __restrict__ tiles,
-                                                         const BoxDev* __restrict__ boxes,
-                                                         const BoxState* __restrict__ st,
-                                                         float mx, float my, float mz, float scale,
+// v <- (v - V) * scale with (V, scale) = the box state's adj[]; partial
+// sums of the adjusted velocities
+__global__ __launch_bounds__(kBlock) void k_init_adjust(const BoxDev* __restrict__ boxes,
+                                                         const BoxState* __restrict__ st, int box,
                                                          long long* __restrict__ partials)
 {
     const int t = blockIdx.x;
-    const Tile tl = tiles[t];
+    const Tile tl = box_tile(boxes, box);
     const BoxDev& b = boxes[tl.box];
     const int par = st[tl.box].parity;
+    const float mx = st[tl.box].adj[0], my = st[tl.box].adj[1], mz = st[tl.box].adj[2];
+    const float scale = st[tl.box].adj[3];
     long long d[kNumDiag] = {0, 0, 0, 0, 0, 0};
     for (int64_t i = tl.begin + threadIdx.x; i < tl.end; i += kBlock) {
         if (b.pid[par][i] < 0) continue;
@@ -1243,13 +1251,12 @@ __global__ __launch_bounds__(kBlock) void k_init_adjust(const Tile* __restrict__
 }
 
 // v0 <- v, and the FP64 partials of the current state (sum v, sum v^2, sum v.v0)
-__global__ __launch_bounds__(kBlock) void k_snapshot(const Tile* __restrict__ tiles,
-                                                      const BoxDev* __restrict__ boxes,
-                                                      const BoxState* __restrict__ st,
+__global__ __launch_bounds__(kBlock) void k_snapshot(const BoxDev* __restrict__ boxes,
+                                                      const BoxState* __restrict__ st, int box,
                                                       int set_v0, long long* __restrict__ partials)
 {
     const int t = blockIdx.x;
-    const Tile tl = tiles[t];
+    const Tile tl = box_tile(boxes, box);
     const BoxDev& b = boxes[tl.box];
     const int par = st[tl.box].parity;
     const bool has_v0 = b.vacf_stride > 0;
@@ -1266,6 +1273,63 @@ __global__ __launch_bounds__(kBlock) void k_snapshot(const Tile* __restrict__ ti
         if (has_v0) diag_vacf(d, make_float3(vx, vy, vz), b.v0[par][0][i], b.v0[par][1][i], b.v0[par][2][i]);
     }
     block_diag(d, partials + (size_t)t * kNumDiag);
+}
+
+// Exact sums of one box's per-tile partials (one workgroup; 128-bit
+// integer accumulation, so no order dependence), rounded once to FP64, and
+// the use made of them:
+//   kStatsCentre   adj = (mean velocity, 1): centres the initial velocities
+//   kStatsScale    adj = (0, sqrt(kT/T)): rescales them to temperature kT,
+//                  T = m (sum v^2 - |sum v|^2 / n) / (3 (n - 1))
+//   kStatsSnapshot diag = (sum m v, sum m v^2), status from the range marks;
+//                  with kStatsOrigin also VACF sample 0 = sum v.v0 / n
+// Boxes with fewer than two particles get the identity adjustment.
+__global__ __launch_bounds__(kBlock) void k_box_stats(const long long* __restrict__ partials, int ntiles,
+                                                       const BoxDev* __restrict__ box, BoxState* __restrict__ st,
+                                                       int mode, double kT, double mass)
+{
+#pragma clang fp contract(off)
+    __shared__ __int128 red[kBlock][kNumDiag];
+    __int128 acc[kNumDiag];
+#pragma unroll
+    for (int j = 0; j < kNumDiag; ++j) acc[j] = 0;
+    for (int t = threadIdx.x; t < ntiles; t += kBlock)
+#pragma unroll
+        for (int j = 0; j < kNumDiag; ++j) acc[j] += partials[(size_t)t * kNumDiag + j];
+#pragma unroll
+    for (int j = 0; j < kNumDiag; ++j) red[threadIdx.x][j] = acc[j];
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double d[kNumDiag];
+    for (int j = 0; j < kNumDiag; ++j) {
+        __int128 v = 0;
+        for (int i = 0; i < kBlock; ++i) v += red[i][j];
+        d[j] = (j == 5) ? (double)v : (double)v * 2.3283064365386963e-10;   // 2^-32
+    }
+    const long long n = box->n;
+    if (mode == kStatsCentre || mode == kStatsScale) {
+        float a[4] = {0.0f, 0.0f, 0.0f, 1.0f};
+        if (n > 1 && mode == kStatsCentre) {
+            a[0] = (float)(d[0] / (double)n);
+            a[1] = (float)(d[1] / (double)n);
+            a[2] = (float)(d[2] / (double)n);
+        } else if (n > 1) {
+            const double P2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            const double T = mass * (d[3] - P2 / (double)n) / (3.0 * (double)(n - 1));
+            a[3] = (float)(T > 0.0 ? sqrt(kT / T) : 1.0);
+        }
+        for (int k = 0; k < 4; ++k) st->adj[k] = a[k];
+        return;
+    }
+    for (int k = 0; k < 4; ++k) st->diag[k] = d[k];
+    if (mode & kStatsOrigin) {
+        st->vacf_len = 0;
+        if (box->vacf_stride > 0 && n > 0) {
+            box->vacf[0] = d[4] / (double)n;
+            st->vacf_len = 1;
+        }
+    }
+    st->status = (d[5] == 0.0 && d[3] < 1e300) ? 0 : -5;
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill_iota(int32_t* __restrict__ p, int64_t n)
@@ -1361,7 +1425,7 @@ void launch_brick_step(const Tables& T, hipStream_t s)
 }
 void launch_mark_holes(const Tile* tiles, int ntiles, const Tables& T, int all, hipStream_t s)
 {
-    MPCD_LAUNCH(k_mark_holes, ntiles, kBlock, s, tiles, T.boxes, T.state, all);
+    MPCD_LAUNCH(k_mark_holes, ntiles, kBlock, s, tiles, T.boxes, T.state, all, -1);
 }
 void launch_rebucket_clear(const Tables& T, hipStream_t s)
 {
@@ -1399,25 +1463,29 @@ void launch_cell_rotate(const Tables& T, hipStream_t s)
     MPCD_LAUNCH(k_cell_rotate, T.nctiles, kBlock, s, T.ctiles, T.boxes, T.state, T.dacc);
 }
 
-// The init/snapshot launchers take a sub-range of T.ptiles (one box); their
-// partials land at the same tile indices as the step's.
-static long long* partials_at(const Tile* tiles, const Tables& T)
+// Per-box launchers: one workgroup per particle tile of box `box` (ntile =
+// ceil(nslot / kPartTile)); `part` holds ntile x kNumDiag partials.
+void launch_init_maxwell(const Tables& T, int32_t box, int ntile, float vscale, long long* part, hipStream_t s)
 {
-    return T.partials + (size_t)(tiles - T.ptiles) * kNumDiag;
+    MPCD_LAUNCH(k_init_maxwell, ntile, kBlock, s, T.boxes, T.state, box, vscale, part);
 }
-void launch_init_maxwell(const Tile* tiles, int ntiles, const Tables& T, float vscale, hipStream_t s)
+void launch_init_adjust(const Tables& T, int32_t box, int ntile, long long* part, hipStream_t s)
 {
-    MPCD_LAUNCH(k_init_maxwell, ntiles, kBlock, s, tiles, T.boxes, T.state, vscale, partials_at(tiles, T));
+    MPCD_LAUNCH(k_init_adjust, ntile, kBlock, s, T.boxes, T.state, box, part);
 }
-void launch_init_adjust(const Tile* tiles, int ntiles, const Tables& T, float mx, float my, float mz,
-                        float scale, hipStream_t s)
+void launch_snapshot(const Tables& T, int32_t box, int ntile, int set_v0, long long* part, hipStream_t s)
 {
-    MPCD_LAUNCH(k_init_adjust, ntiles, kBlock, s, tiles, T.boxes, T.state, mx, my, mz, scale,
-                partials_at(tiles, T));
+    MPCD_LAUNCH(k_snapshot, ntile, kBlock, s, T.boxes, T.state, box, set_v0, part);
 }
-void launch_snapshot(const Tile* tiles, int ntiles, const Tables& T, int set_v0, hipStream_t s)
+void launch_box_stats(const Tables& T, int32_t box, int ntile, const long long* part, int mode, double kT,
+                      double mass, hipStream_t s)
 {
-    MPCD_LAUNCH(k_snapshot, ntiles, kBlock, s, tiles, T.boxes, T.state, set_v0, partials_at(tiles, T));
+    hipLaunchKernelGGL(k_box_stats, dim3(1), dim3(kBlock), 0, s, part, ntile, T.boxes + box, T.state + box, mode,
+                       kT, mass);
+}
+void launch_mark_holes_box(const Tables& T, int32_t box, int ntile, hipStream_t s)
+{
+    MPCD_LAUNCH(k_mark_holes, ntile, kBlock, s, nullptr, T.boxes, T.state, 1, box);
 }
 void launch_fill_iota(int32_t* p, int64_t n, hipStream_t s)
 {

@@ -18,7 +18,6 @@ struct Tables {
     Tile* ctiles = nullptr;      // cell tiles of all live boxes
     Tile* btiles = nullptr;      // brick tiles (begin = brick index) of brick boxes
     int32_t* active = nullptr;   // live slots
-    long long* partials = nullptr;    // kNumDiag per particle tile (initial state, snapshots)
     long long* dacc = nullptr;        // per slot: kAccLanes x (VACF high, VACF low, violations)
     uint32_t* tilesum = nullptr; // per cell tile
     int nptiles = 0, nctiles = 0, nbtiles = 0, nactive = 0;
@@ -42,10 +41,16 @@ void launch_scatter(const Tables& T, hipStream_t s);
 void launch_flip(const Tables& T, hipStream_t s);
 void launch_cell_rotate(const Tables& T, hipStream_t s);
 
-void launch_init_maxwell(const Tile* tiles, int ntiles, const Tables& T, float vscale, hipStream_t s);
-void launch_init_adjust(const Tile* tiles, int ntiles, const Tables& T, float mx, float my, float mz,
-                        float scale, hipStream_t s);
-void launch_snapshot(const Tile* tiles, int ntiles, const Tables& T, int set_v0, hipStream_t s);
+// per-box launches over ntile = ceil(nslot / kPartTile) particle tiles of
+// box `box`; `part` receives ntile x kNumDiag exact partials
+void launch_init_maxwell(const Tables& T, int32_t box, int ntile, float vscale, long long* part, hipStream_t s);
+void launch_init_adjust(const Tables& T, int32_t box, int ntile, long long* part, hipStream_t s);
+void launch_snapshot(const Tables& T, int32_t box, int ntile, int set_v0, long long* part, hipStream_t s);
+// modes of launch_box_stats
+enum { kStatsCentre = 0, kStatsScale = 1, kStatsSnapshot = 2, kStatsOrigin = 4 };
+void launch_box_stats(const Tables& T, int32_t box, int ntile, const long long* part, int mode, double kT,
+                      double mass, hipStream_t s);
+void launch_mark_holes_box(const Tables& T, int32_t box, int ntile, hipStream_t s);
 void launch_fill_iota(int32_t* p, int64_t n, hipStream_t s);
 void launch_fill_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
 void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);

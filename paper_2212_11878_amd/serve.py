@@ -5,9 +5,12 @@ arrive over time.  The server admits a request as soon as the device-memory
 budget and a slot allow it, keeps every admitted box resident on the GPU, and
 advances all of them together: each mpcd_step call is one batched launch
 sequence over every live box, so new arrivals join the running batch while
-others are mid-flight.  A box that reaches its step count is observed
-(temperature and velocity autocorrelation) and released, freeing memory for
-the queue.  Latency is completion time minus arrival time.
+others are mid-flight.  Each round queues one chunk of steps (the call
+returns at once), admits arrivals while the chunk runs, then observes
+(temperature and velocity autocorrelation) and releases the boxes that
+reached their step count, freeing memory for the queue; a box that finishes
+inside a chunk idles on the device until then.  Latency is completion time
+minus arrival time.
 
 The scheduler talks to an engine with four calls (admit / step / observe /
 release).  `LibraryEngine` drives libmpcd through its C ABI; tests can plug
@@ -77,6 +80,15 @@ class Server:
                 break
             while pending and pending[0]["arrival"] <= now:
                 queue.append(pending.popleft())
+            # queue the next chunk for the live boxes; the engine returns at
+            # once and a box that reaches its step count idles on the device
+            stepped = bool(live)
+            if stepped:
+                self.engine.step(self.chunk_steps)
+                for v in live.values():
+                    steps_done += v[0]["n"] * min(self.chunk_steps, v[1])
+                    v[1] -= self.chunk_steps
+            # admit while the chunk runs (a new box joins at the next chunk)
             while queue:
                 slot = self.engine.admit(queue[0])
                 if slot is None:
@@ -90,15 +102,7 @@ class Server:
                 req = queue.popleft()
                 live[slot] = [req, int(req["steps"]), now]
             max_live = max(max_live, len(live))
-            if not live:
-                if pending:
-                    self.sleep(max(0.0, min(0.01, pending[0]["arrival"] - (self.clock() - t0))))
-                continue
-            chunk = min(self.chunk_steps, min(v[1] for v in live.values()))
-            self.engine.step(chunk)
-            for v in live.values():
-                steps_done += v[0]["n"] * min(chunk, v[1])
-                v[1] -= chunk
+            # boxes done after this chunk: observe (waits for the chunk), release
             for slot in [s for s, v in live.items() if v[1] <= 0]:
                 req, _, t_admit = live.pop(slot)
                 obs = self.engine.observe(slot)
@@ -106,6 +110,8 @@ class Server:
                 t_done = self.clock() - t0
                 done.append(dict(req=req, latency=t_done - req["arrival"], queued=t_admit - req["arrival"],
                                  T=obs["T"], vacf=obs["vacf"], status=obs["status"], step=obs["step"]))
+            if not stepped and not live and pending:
+                self.sleep(max(0.0, min(0.01, pending[0]["arrival"] - (self.clock() - t0))))
         wall = self.clock() - t0
         lat = np.array([d["latency"] for d in done]) if done else np.zeros(0)
         summary = dict(
