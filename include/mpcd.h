@@ -30,8 +30,10 @@
  *     unchanged (admission is all-or-nothing).
  *   - A context is not thread safe: use it from one host thread.
  *   - Device work is queued on the context's HIP stream; only mpcd_observe,
- *     mpcd_get_state, mpcd_set_state, mpcd_set_mass, mpcd_admit and
- *     mpcd_kernel_stats synchronise with it.
+ *     mpcd_get_state, mpcd_set_state, mpcd_set_mass and mpcd_kernel_stats
+ *     synchronise with it, and mpcd_admit when it times autotuner trials
+ *     (MPCD_BIN_AUTO, a box of at least 2^21 cells of a shape class new to
+ *     the context).
  *   - Pointers marked "host" are ordinary host memory owned by the caller
  *     and only read or written during the call.
  */
@@ -115,7 +117,9 @@ typedef struct {
     int32_t binning;        /* MPCD_BIN_*                                    */
     int32_t brick[3];       /* ATOMIC: brick edge in cells per dimension,
                                each 0 (auto) or a power of two in [2, 64];
-                               at most 2048 cells per brick                  */
+                               a box whose brick (edges clipped to its own
+                               edges) exceeds 1024 cells is refused by
+                               mpcd_admit with MPCD_EINVAL                   */
     int32_t block;          /* reserved, must be 0                           */
     int32_t use_graph;      /* 1: replay steps from a captured hipGraph      */
     int64_t hbm_budget;     /* bytes all boxes may occupy; 0 = unlimited     */
@@ -164,8 +168,10 @@ int mpcd_create(const mpcd_options* options, mpcd_ctx** out);
  * on average n_particles / (L0 L1 L2) particles).  Allocates its device
  * state through the context allocator and, with MPCD_INIT_MAXWELL, draws the
  * initial state on the device (Philox counter (i_lo, i_hi, 0, 2) for
- * positions, (i_lo, i_hi, 0, 3) for Box-Muller velocities).  The box starts
- * at step 0.  *slot receives its index.
+ * positions, (i_lo, i_hi, 0, 3) for Box-Muller velocities; mean removed,
+ * rescaled to temperature kT).  The initial state is queued on the stream
+ * behind the steps already queued, and the box joins the next mpcd_step.
+ * The box starts at step 0.  *slot receives its index.
  * ENOMEM over budget, EBUSY no free slot, EINVAL bad descriptor. */
 int mpcd_admit(mpcd_ctx* ctx, const mpcd_box_desc* desc, int32_t* slot);
 

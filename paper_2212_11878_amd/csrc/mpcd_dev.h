@@ -75,7 +75,7 @@ struct alignas(16) CellRot {
 // every particle of its cells and nothing else.
 struct BoxDev {
     float* p[2][6];        // x, y, z, vx, vy, vz
-    float* v0[2][3];       // VACF reference velocities (null if untracked)
+    float4* v0;            // VACF reference velocity of each particle id (x, y, z, unused); null if untracked
     int32_t* pid[2];       // particle identity (admission order); -1 in holes
     float* m[2];           // per-particle masses (null: all particles equal)
     uint32_t* cell;        // sort key of each slot

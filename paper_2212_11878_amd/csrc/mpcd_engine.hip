@@ -228,13 +228,13 @@ int upload(mpcd_ctx* c, void* dst, const void* src, size_t bytes)
 
 // Layout of one box's device allocation.
 struct Layout {
-    size_t off_p[2][6], off_v0[2][3], off_pid[2], off_m[2], off_cell, off_rank, off_cstart, off_un, off_esc[2],
+    size_t off_p[2][6], off_v0, off_pid[2], off_m[2], off_cell, off_rank, off_cstart, off_un, off_esc[2],
         off_eflag, off_bstart, off_bsize[2], off_vacf, off_part, total;
 };
 
 int ntile_of(int64_t nslot) { return (int)std::max<int64_t>(1, (nslot + kPartTile - 1) / kPartTile); }
 
-Layout box_layout(int64_t nslot, int64_t ncell, bool vacf, int vacf_cap, bool brick, const BrickGeom& g,
+Layout box_layout(int64_t n, int64_t nslot, int64_t ncell, bool vacf, int vacf_cap, bool brick, const BrickGeom& g,
                   bool masses)
 {
     Layout L{};
@@ -242,11 +242,8 @@ Layout box_layout(int64_t nslot, int64_t ncell, bool vacf, int vacf_cap, bool br
     const size_t pf = align256((size_t)nslot * 4);
     for (int b = 0; b < 2; ++b)
         for (int d = 0; d < 6; ++d) { L.off_p[b][d] = o; o += pf; }
-    for (int b = 0; b < 2; ++b)
-        for (int d = 0; d < 3; ++d) {
-            L.off_v0[b][d] = o;
-            if (vacf) o += pf;
-        }
+    L.off_v0 = o;
+    if (vacf) o += align256((size_t)n * 16);
     for (int b = 0; b < 2; ++b) { L.off_pid[b] = o; o += pf; }
     for (int b = 0; b < 2; ++b) {
         L.off_m[b] = o;
@@ -823,7 +820,7 @@ int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
     const bool brick = binning == MPCD_BIN_ATOMIC;
     const int64_t nslot = brick ? brick_slots(d->n_particles, g.nbrick) : d->n_particles;
     const bool masses = (d->flags & MPCD_PARTICLE_MASS) != 0;
-    const Layout L = box_layout(nslot, ncell, vacf, cap, brick, g, masses);
+    const Layout L = box_layout(d->n_particles, nslot, ncell, vacf, cap, brick, g, masses);
     if (c->budget > 0 && c->used + (int64_t)L.total > c->budget) return MPCD_ENOMEM;
     HIPCHK(hipSetDevice(c->device));
     void* mem = ctx_alloc(c, L.total);
@@ -840,10 +837,10 @@ int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
     char* m = (char*)mem;
     for (int p = 0; p < 2; ++p) {
         for (int k = 0; k < 6; ++k) b.p[p][k] = (float*)(m + L.off_p[p][k]);
-        for (int k = 0; k < 3; ++k) b.v0[p][k] = vacf ? (float*)(m + L.off_v0[p][k]) : nullptr;
         b.pid[p] = (int32_t*)(m + L.off_pid[p]);
         b.m[p] = masses ? (float*)(m + L.off_m[p]) : nullptr;
     }
+    b.v0 = vacf ? (float4*)(m + L.off_v0) : nullptr;
     b.cell = (uint32_t*)(m + L.off_cell);
     b.rank = (uint32_t*)(m + L.off_rank);
     b.cstart = (uint32_t*)(m + L.off_cstart);

@@ -220,11 +220,9 @@ __device__ __forceinline__ bool place_overflow(const BoxDev& b, int dst, long lo
     return true;
 }
 
-// Store particle state at slot j of buffer dst (VACF reference copied from
-// slot i of buffer src); slots < 2^30.
-__device__ __forceinline__ void put_particle(const BoxDev& b, int src, int dst, uint32_t i, uint32_t j, float x,
-                                             float y, float z, float3 v, int32_t id, float m, bool has_m,
-                                             bool track)
+// Store particle state at slot j of buffer dst (slots < 2^30).
+__device__ __forceinline__ void put_particle(const BoxDev& b, int dst, uint32_t j, float x, float y, float z,
+                                             float3 v, int32_t id, float m, bool has_m)
 {
     const uint32_t o = j * 4u;
     stg(gp(b.p[dst][0]), o, x);
@@ -235,29 +233,16 @@ __device__ __forceinline__ void put_particle(const BoxDev& b, int src, int dst, 
     stg(gp(b.p[dst][5]), o, v.z);
     stg(gp(b.pid[dst]), o, id);
     if (has_m) stg(gp(b.m[dst]), o, m);
-    if (track) {
-        const uint32_t oi = i * 4u;
-        stg(gp(b.v0[dst][0]), o, ldg(gp(b.v0[src][0]), oi));
-        stg(gp(b.v0[dst][1]), o, ldg(gp(b.v0[src][1]), oi));
-        stg(gp(b.v0[dst][2]), o, ldg(gp(b.v0[src][2]), oi));
-    }
 }
 
-// VACF term of one particle (v(0) from slot i of buffer src)
-__device__ __forceinline__ void vacf_term(const BoxDev& b, int src, uint32_t i, float3 v,
-                                                   long long (&d)[kNumDiag])
+// VACF term of particle `id` with new velocity v.  The reference velocities
+// v(0) stay in particle-id order (one 16-byte record each), so particles can
+// move between slots without carrying them; they are read only on the steps
+// that take a sample.
+__device__ __forceinline__ void vacf_term(const BoxDev& b, int32_t id, float3 v, long long (&d)[kNumDiag])
 {
-    const uint32_t o = i * 4u;
-    diag_vacf(d, v, ldg(gp(b.v0[src][0]), o), ldg(gp(b.v0[src][1]), o), ldg(gp(b.v0[src][2]), o));
-}
-
-// the VACF reference of slot i of buffer src goes to slot j of buffer dst
-__device__ __forceinline__ void copy_v0(const BoxDev& b, int src, int dst, uint32_t i, uint32_t j)
-{
-    const uint32_t oi = i * 4u, oj = j * 4u;
-    stg(gp(b.v0[dst][0]), oj, ldg(gp(b.v0[src][0]), oi));
-    stg(gp(b.v0[dst][1]), oj, ldg(gp(b.v0[src][1]), oi));
-    stg(gp(b.v0[dst][2]), oj, ldg(gp(b.v0[src][2]), oi));
+    const f32x4 w = *((const MPCD_G f32x4*)gp(b.v0) + id);
+    diag_vacf(d, v, w.x, w.y, w.z);
 }
 
 // One SRD step of one brick (paper Sec. 2; the shifted grid of Sec. 3.1;
@@ -446,8 +431,6 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
     MPCD_G float* const ovz = gp(b.p[dst][5]);
     MPCD_G int32_t* const oid = gp(b.pid[dst]);
     const MPCD_G int32_t* const iid = gp(b.pid[src]);
-    const double ca = b.ca, sa = b.sa;
-    const bool track = b.vacf_stride > 0;
     const bool has_m = kMass && b.m[src] != nullptr;
     const int lane = threadIdx.x & (kWave - 1);
     const unsigned long long below = (1ull << lane) - 1ull;
@@ -480,7 +463,7 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
                 }
                 const float3 v = make_float3(vx[u], vy[u], vz[u]);
                 diag_check(d, v);
-                if (vacf) vacf_term(b, src, beg + i, v, d);
+                if (vacf) vacf_term(b, ldg(iid, (beg + i) * 4u), v, d);
                 // brick of the next collision cell (a non-finite position
                 // lands far away and takes the clamped slow path below)
                 const int dbx = brick_of(axis_cell_raw(fold(fmaf(v.x, dt, px[u]), b.len[0]), sh1.x, inv_a, b.L[0]), b.bshift[0]);
@@ -531,7 +514,6 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
             if (u >= nu) break;
             const uint32_t r = meta[u] >> 24;
             if (r >= 28u) continue;
-            const uint32_t i = (uint32_t)ch * kChunk + (uint32_t)(u * kT) + threadIdx.x;
             const float3 v = make_float3(vx[u], vy[u], vz[u]);
             uint32_t j = 0u;
             bool placed = false;
@@ -561,7 +543,6 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
             stg(ovz, o, v.z);
             stg(oid, o, id[u]);
             if (has_m) stg(gp(b.m[dst]), o, pm[u]);
-            if (track) copy_v0(b, src, dst, beg + i, j);
         }
         if (ch + 1 < nch) __syncthreads();
     }
@@ -580,7 +561,6 @@ __device__ void overflow_step(const BoxDev& b, const BoxState& s, long long (&d)
     if (cnt == 0) return;
     const float3 sh = grid_shift(b, s.k), sh1 = grid_shift(b, s.k + 1);
     const bool has_m = b.m[src] != nullptr;
-    const bool track = b.vacf_stride > 0;
     const bool vacf = vacf_due(b, s);
     for (uint32_t i = threadIdx.x; i < cnt; i += kBlock) {
         const uint32_t si = ob + i;
@@ -601,8 +581,9 @@ __device__ void overflow_step(const BoxDev& b, const BoxState& s, long long (&d)
             d[5] += 1;
             continue;
         }
-        if (vacf) diag_vacf(d, v, gp(b.v0[src][0])[si], gp(b.v0[src][1])[si], gp(b.v0[src][2])[si]);
-        put_particle(b, src, dst, si, j, x, y, z, v, gp(b.pid[src])[si], m, has_m, track);
+        const int32_t id = gp(b.pid[src])[si];
+        if (vacf) vacf_term(b, id, v, d);
+        put_particle(b, dst, j, x, y, z, v, id, m, has_m);
     }
 }
 
@@ -862,7 +843,6 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const Tile* __restrict__ til
     if (box_idle(s) || !sort_due(b, s)) return;
     const int src = uniform(s.parity), dst = src ^ 1;
     const bool stream = (b.binning == 2);
-    const bool vacf = b.vacf_stride > 0;
     const bool has_m = b.m[src] != nullptr;
     const float dt = b.dt;
     const MPCD_G float* __restrict__ ix = gp(b.p[src][0]);
@@ -920,11 +900,6 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const Tile* __restrict__ til
             ovz[j] = uz[u];
             oid[j] = id[u];
             if (has_m) gp(b.m[dst])[j] = gp(b.m[src])[i];
-            if (vacf) {
-                gp(b.v0[dst][0])[j] = gp(b.v0[src][0])[i];
-                gp(b.v0[dst][1])[j] = gp(b.v0[src][1])[i];
-                gp(b.v0[dst][2])[j] = gp(b.v0[src][2])[i];
-            }
         }
     }
 }
@@ -1052,7 +1027,7 @@ __device__ __forceinline__ void collide_cell_am(const BoxDev& b, int par, long l
         const float3 v = make_float3((float)(u[0] + rw[0] + (om[1] * rp[2] - om[2] * rp[1])),
                                      (float)(u[1] + rw[1] + (om[2] * rp[0] - om[0] * rp[2])),
                                      (float)(u[2] + rw[2] + (om[0] * rp[1] - om[1] * rp[0])));
-        if (vacf) diag_vacf(d, v, b.v0[par][0][j], b.v0[par][1][j], b.v0[par][2][j]);
+        if (vacf) vacf_term(b, b.pid[par][j], v, d);
         vx[j] = v.x;
         vy[j] = v.y;
         vz[j] = v.z;
@@ -1076,9 +1051,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_rotate(const Tile* __restrict__
     float* __restrict__ vy = b.p[s.parity][4];
     float* __restrict__ vz = b.p[s.parity][5];
     const bool vacf = vacf_due(b, s);
-    const float* __restrict__ w0x = b.v0[s.parity][0];
-    const float* __restrict__ w0y = b.v0[s.parity][1];
-    const float* __restrict__ w0z = b.v0[s.parity][2];
+    const int32_t* __restrict__ pid = b.pid[s.parity];
     const float* __restrict__ mp = b.m[s.parity];
     const double ca = b.ca, sa = b.sa;
     long long d[kNumDiag] = {0, 0, 0, 0, 0, 0};
@@ -1110,7 +1083,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_rotate(const Tile* __restrict__
             vy[j] = v.y;
             vz[j] = v.z;
             diag_check(d, v);
-            if (vacf) diag_vacf(d, v, w0x[j], w0y[j], w0z[j]);
+            if (vacf) vacf_term(b, pid[j], v, d);
         }
     }
     step_flush(d, vacf, dacc + (size_t)tl.box * kAccLanes * 3, blockIdx.x);
@@ -1264,13 +1237,10 @@ __global__ __launch_bounds__(kBlock) void k_snapshot(const BoxDev* __restrict__ 
     for (int64_t i = tl.begin + threadIdx.x; i < tl.end; i += kBlock) {
         if (b.pid[par][i] < 0) continue;
         const float vx = b.p[par][3][i], vy = b.p[par][4][i], vz = b.p[par][5][i];
-        if (has_v0 && set_v0) {
-            b.v0[par][0][i] = vx;
-            b.v0[par][1][i] = vy;
-            b.v0[par][2][i] = vz;
-        }
+        const int32_t id = b.pid[par][i];
+        if (has_v0 && set_v0) b.v0[id] = make_float4(vx, vy, vz, 0.0f);
         diag_particle(d, make_float3(vx, vy, vz), mass_of(b.m[par], i));
-        if (has_v0) diag_vacf(d, make_float3(vx, vy, vz), b.v0[par][0][i], b.v0[par][1][i], b.v0[par][2][i]);
+        if (has_v0) vacf_term(b, id, make_float3(vx, vy, vz), d);
     }
     block_diag(d, partials + (size_t)t * kNumDiag);
 }
