@@ -38,6 +38,12 @@ constexpr int kMaxBrickCells = 1024; // cells of one brick (LDS of its workgroup
 constexpr int kAccWords = 5;         // 64-bit words per brick cell's sums record (4 used)
 constexpr int kUnWords = 12;         // 32-bit words per brick cell's data record (7 used)
 constexpr int kBrickCellBytes = 8 * kAccWords + 4 * kUnWords;   // LDS per brick cell
+// Angular-momentum-conserving collision on bricks: per cell 18 64-bit LDS
+// words (first the 13 moment sums, then u, r_c, n, Q / omega in FP64 and the
+// 3 angular-momentum sums), and at most kMaxAmBrickCells cells per brick.
+constexpr int kAmWords = 18;
+constexpr int kAmCellBytes = 8 * kAmWords;
+constexpr int kMaxAmBrickCells = 512;
 constexpr int kAccLanes = 64;        // step accumulator lanes per box (spread the atomics)
 constexpr int kNumDiag = 6;          // per-tile exact partials: sum v (3), sum v^2, sum v.v0, range violations
 
@@ -57,6 +63,14 @@ struct alignas(32) CellAcc {
 struct alignas(16) CellRot {
     float m[9];   // row-major M
     float t[3];
+};
+
+// Per-cell data of the angular-momentum-conserving collision (FP64): mean
+// velocity u, centre of mass r_c (inside the shifted cell), unit axis n and
+// the rigid-rotation correction omega; v' = u + R(n, alpha)(v - u) +
+// omega x (r - r_c).
+struct CellAm {
+    double u[3], rc[3], n[3], om[3];
 };
 // Read-only description of one box, resident in device memory.  Particle
 // arrays come in two buffers (ping-pong) of `nslot` slots; the buffer in use
@@ -82,6 +96,7 @@ struct BoxDev {
     uint32_t* rank;        // rank of each slot inside its key (sort)
     uint32_t* cstart;      // counts, then exclusive starts, per key (C + 1)
     CellRot* un;           // brick mode: collision map of the cells of flagged bricks
+    CellAm* uam;           // brick mode with conserve_l: the same for the angular-momentum rule
     CellAcc* esc[2];       // brick mode: per cell, sums of overflow particles (step parity)
     uint32_t* eflag;       // brick mode: per brick, k+1 when esc[k & 1] holds data for it
     uint32_t* bstart;      // brick mode: bucket starts (nbrick + 2)
@@ -383,6 +398,7 @@ constexpr float kVelocityLimit = 1073741824.0f;   // 2^30
 // lo 32-bit halves are exact; their combination rounds once).
 __device__ __forceinline__ double fixed_to_double(unsigned long long s)
 {
+#pragma clang fp contract(off)
     const double hi = (double)(int)(unsigned)(s >> 32);
     const double lo = (double)(unsigned)(s & 0xffffffffu);
     return hi * 4294967296.0 + lo;
@@ -445,6 +461,7 @@ __device__ __forceinline__ float3 apply_rotation(const CellRot& r, float vx, flo
 __device__ __forceinline__ void rotate_w(double nx, double ny, double nz, double ca, double sa,
                                          const double w[3], double out[3])
 {
+#pragma clang fp contract(off)
     const double d = nx * w[0] + ny * w[1] + nz * w[2];
     const double px = d * nx, py = d * ny, pz = d * nz;
     out[0] = px + ca * (w[0] - px) + sa * (ny * w[2] - nz * w[1]);
@@ -456,6 +473,7 @@ __device__ __forceinline__ void rotate_w(double nx, double ny, double nz, double
 // Jacobi rotations (eigenvalues below tol times the largest count as zero).
 __device__ __forceinline__ void sym3_pinv(double a[3][3], double tol, double out[3][3])
 {
+#pragma clang fp contract(off)
     double v[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
     for (int sweep = 0; sweep < 12; ++sweep) {
         if (fabs(a[0][1]) + fabs(a[0][2]) + fabs(a[1][2]) < 1e-300) break;
@@ -502,6 +520,7 @@ __device__ __forceinline__ void sym3_pinv(double a[3][3], double tol, double out
 // so block and box sums do not depend on summation order.
 __device__ __forceinline__ long long fixed_term(double t)
 {
+#pragma clang fp contract(off)
     t = fmin(fmax(t * 4294967296.0, -4.0e18), 4.0e18);
     return (long long)rint(t);
 }
@@ -528,6 +547,138 @@ __device__ __forceinline__ void diag_vacf(long long (&d)[kNumDiag], float3 v, fl
                                           float w0z)
 {
     d[4] += fixed_term((double)v.x * w0x + (double)v.y * w0y + (double)v.z * w0z);
+}
+
+// --------------------------------------------------------------------------
+// Angular-momentum-conserving collision (the plain rotation followed by the
+// rigid-body velocity omega x r' that restores the cell's angular momentum
+// about its centre of mass, omega = -I^+ dL).  The same functions serve the
+// counting-sort path (one thread walks a cell) and the brick path (LDS sums
+// over a brick), so both give the same bits: every cell sum is an exact
+// fixed-point integer and the per-cell algebra is FP64.
+
+constexpr int kAmMoments = 13;   // m, m v (3), m r (3), m r r^T (6)
+
+// Position of a streamed particle inside its shifted cell (shift sh, edge a),
+// each component in [0, a).
+__device__ __forceinline__ void am_local(double a, float x, float y, float z, float3 sh, double r[3])
+{
+#pragma clang fp contract(off)
+    const double q[3] = {(double)x - sh.x, (double)y - sh.y, (double)z - sh.z};
+    if (a == 1.0) {   // unit cells: the same value without the divisions
+#pragma unroll
+        for (int e = 0; e < 3; ++e) r[e] = q[e] - floor(q[e]);
+        return;
+    }
+#pragma unroll
+    for (int e = 0; e < 3; ++e) r[e] = q[e] - a * floor(q[e] / a);
+}
+
+// One particle's exact terms of the first pass: mass, momentum, first and
+// second position moments.
+__device__ __forceinline__ void am_moments(double mj, float vx, float vy, float vz, const double r[3],
+                                           long long t[kAmMoments])
+{
+#pragma clang fp contract(off)
+    t[0] = fixed_term(mj);
+    t[1] = fixed_term(mj * vx);
+    t[2] = fixed_term(mj * vy);
+    t[3] = fixed_term(mj * vz);
+#pragma unroll
+    for (int e = 0; e < 3; ++e) t[4 + e] = fixed_term(mj * r[e]);
+    t[7] = fixed_term(mj * r[0] * r[0]);
+    t[8] = fixed_term(mj * r[0] * r[1]);
+    t[9] = fixed_term(mj * r[0] * r[2]);
+    t[10] = fixed_term(mj * r[1] * r[1]);
+    t[11] = fixed_term(mj * r[1] * r[2]);
+    t[12] = fixed_term(mj * r[2] * r[2]);
+}
+
+// Cell data from the first-pass sums: mean velocity u, centre of mass rc,
+// second moment Q (xx, xy, xz, yy, yz, zz) about rc, and the unit axis n of
+// canonical cell c at step k.
+__device__ __forceinline__ void am_cell(const BoxDev& b, long long k, uint32_t c, const long long s[kAmMoments],
+                                        double u[3], double rc[3], double Q[6], double n[3])
+{
+#pragma clang fp contract(off)
+    const double M = fixed_to_double((unsigned long long)s[0]);
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        u[e] = fixed_to_double((unsigned long long)s[1 + e]) / M;
+        rc[e] = fixed_to_double((unsigned long long)s[4 + e]) / M;
+    }
+    // sums are in units of 2^-32: Mt is the true mass; u and rc are ratios
+    const double k2 = 2.3283064365386963e-10;
+    const double Mt = M * k2;
+    Q[0] = fixed_to_double((unsigned long long)s[7]) * k2 - Mt * rc[0] * rc[0];
+    Q[1] = fixed_to_double((unsigned long long)s[8]) * k2 - Mt * rc[0] * rc[1];
+    Q[2] = fixed_to_double((unsigned long long)s[9]) * k2 - Mt * rc[0] * rc[2];
+    Q[3] = fixed_to_double((unsigned long long)s[10]) * k2 - Mt * rc[1] * rc[1];
+    Q[4] = fixed_to_double((unsigned long long)s[11]) * k2 - Mt * rc[1] * rc[2];
+    Q[5] = fixed_to_double((unsigned long long)s[12]) * k2 - Mt * rc[2] * rc[2];
+    const float3 ax = cell_axis(b, k, c);
+    const double nx = ax.x, ny = ax.y, nz = ax.z;
+    const double inv = 1.0 / sqrt(nx * nx + ny * ny + nz * nz);
+    n[0] = nx * inv;
+    n[1] = ny * inv;
+    n[2] = nz * inv;
+}
+
+// One particle's exact second-pass terms: the change of its angular momentum
+// about rc under the plain rotation, m r' x (R w - w), w = v - u.
+__device__ __forceinline__ void am_dl(double mj, float vx, float vy, float vz, const double r[3],
+                                      const double u[3], const double rc[3], const double n[3], double ca,
+                                      double sa, long long t[3])
+{
+#pragma clang fp contract(off)
+    double w[3], rw[3];
+    w[0] = (double)vx - u[0];
+    w[1] = (double)vy - u[1];
+    w[2] = (double)vz - u[2];
+    rotate_w(n[0], n[1], n[2], ca, sa, w, rw);
+    const double rp[3] = {r[0] - rc[0], r[1] - rc[1], r[2] - rc[2]};
+    const double dw[3] = {rw[0] - w[0], rw[1] - w[1], rw[2] - w[2]};
+    t[0] = fixed_term(mj * (rp[1] * dw[2] - rp[2] * dw[1]));
+    t[1] = fixed_term(mj * (rp[2] * dw[0] - rp[0] * dw[2]));
+    t[2] = fixed_term(mj * (rp[0] * dw[1] - rp[1] * dw[0]));
+}
+
+// omega = -I^+ dL with I = tr(Q) 1 - Q (pseudo-inverse: rank-deficient cells,
+// e.g. one or two particles, get no correction along the null directions).
+__device__ __forceinline__ void am_omega(const double Q6[6], const long long sl[3], double om[3])
+{
+#pragma clang fp contract(off)
+    const double k2 = 2.3283064365386963e-10;
+    const double dL[3] = {fixed_to_double((unsigned long long)sl[0]) * k2,
+                          fixed_to_double((unsigned long long)sl[1]) * k2,
+                          fixed_to_double((unsigned long long)sl[2]) * k2};
+    const double Q[3][3] = {{Q6[0], Q6[1], Q6[2]}, {Q6[1], Q6[3], Q6[4]}, {Q6[2], Q6[4], Q6[5]}};
+    double I[3][3], Ip[3][3];
+    const double tr = Q[0][0] + Q[1][1] + Q[2][2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) I[i][j] = (i == j ? tr : 0.0) - Q[i][j];
+    sym3_pinv(I, 1e-10, Ip);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) om[i] = -(Ip[i][0] * dL[0] + Ip[i][1] * dL[1] + Ip[i][2] * dL[2]);
+}
+
+// New velocity: u + R (v - u) + omega x (r - rc), rounded once to FP32.
+__device__ __forceinline__ float3 am_velocity(float vx, float vy, float vz, const double r[3], const double u[3],
+                                              const double rc[3], const double n[3], const double om[3],
+                                              double ca, double sa)
+{
+#pragma clang fp contract(off)
+    double w[3], rw[3];
+    w[0] = (double)vx - u[0];
+    w[1] = (double)vy - u[1];
+    w[2] = (double)vz - u[2];
+    rotate_w(n[0], n[1], n[2], ca, sa, w, rw);
+    const double rp[3] = {r[0] - rc[0], r[1] - rc[1], r[2] - rc[2]};
+    return make_float3((float)(u[0] + rw[0] + (om[1] * rp[2] - om[2] * rp[1])),
+                       (float)(u[1] + rw[1] + (om[2] * rp[0] - om[0] * rp[2])),
+                       (float)(u[2] + rw[2] + (om[0] * rp[1] - om[1] * rp[0])));
 }
 
 // Blocks are dealt round-robin to the 8 XCDs; renumber so that each XCD

@@ -228,14 +228,14 @@ int upload(mpcd_ctx* c, void* dst, const void* src, size_t bytes)
 
 // Layout of one box's device allocation.
 struct Layout {
-    size_t off_p[2][6], off_v0, off_pid[2], off_m[2], off_cell, off_rank, off_cstart, off_un, off_esc[2],
+    size_t off_p[2][6], off_v0, off_pid[2], off_m[2], off_cell, off_rank, off_cstart, off_un, off_uam, off_esc[2],
         off_eflag, off_bstart, off_bsize[2], off_vacf, off_part, total;
 };
 
 int ntile_of(int64_t nslot) { return (int)std::max<int64_t>(1, (nslot + kPartTile - 1) / kPartTile); }
 
 Layout box_layout(int64_t n, int64_t nslot, int64_t ncell, bool vacf, int vacf_cap, bool brick, const BrickGeom& g,
-                  bool masses)
+                  bool masses, bool am)
 {
     Layout L{};
     size_t o = 0;
@@ -254,6 +254,7 @@ Layout box_layout(int64_t n, int64_t nslot, int64_t ncell, bool vacf, int vacf_c
     L.off_cstart = o; o += align256((size_t)(ncell + 1) * 4);
     const size_t nbk = brick ? (size_t)g.nbrick : 0;
     L.off_un = o; o += brick ? align256((size_t)ncell * sizeof(CellRot)) : 0;
+    L.off_uam = o; o += brick && am ? align256((size_t)ncell * sizeof(CellAm)) : 0;
     for (int b = 0; b < 2; ++b) { L.off_esc[b] = o; o += brick ? align256((size_t)ncell * sizeof(CellAcc)) : 0; }
     L.off_eflag = o; o += align256(2 * nbk * 4);
     L.off_bstart = o; o += align256((nbk + 2) * 4);
@@ -313,6 +314,8 @@ int rebuild_tables(mpcd_ctx* c)
     std::vector<int32_t> active;
     c->any_brick = c->any_sort = false;
     int max_bvol = 0;
+    size_t brick_lds = 0;
+    bool brick_am = false;
     int64_t max_bucket = 0;
     bool brick_mass = false;
     for (int s = 0; s < (int)c->slots.size(); ++s) {
@@ -341,6 +344,9 @@ int rebuild_tables(mpcd_ctx* c)
             max_bucket = std::max<int64_t>(max_bucket, bucket_need((double)b.n * b.bmax[0] * b.bmax[1] * b.bmax[2] /
                                                                    (double)b.ncell));
             brick_mass |= b.m[0] != nullptr;
+            brick_am |= b.conserve_l != 0;
+            brick_lds = std::max(brick_lds, (size_t)b.bmax[0] * b.bmax[1] * b.bmax[2] *
+                                                (b.conserve_l ? kAmCellBytes : kBrickCellBytes));
         }
     }
     const size_t need = align256(pt.size() * sizeof(Tile) + 256) + align256(ct.size() * sizeof(Tile) + 256) +
@@ -367,6 +373,8 @@ int rebuild_tables(mpcd_ctx* c)
     c->T.max_bvol = max_bvol;
     c->T.brick_shape = brick_shape_for(max_bucket);
     c->T.brick_mass = brick_mass;
+    c->T.brick_am = brick_am;
+    c->T.brick_lds = brick_lds;
     c->T.host_flag = c->host_flag_dev;
     // one upload for the tile lists (laid out as on the device) and one for
     // the box descriptors of every slot in use
@@ -587,7 +595,8 @@ static uint64_t shape_class(const mpcd_box_desc* d)
     const int rho = (int)std::lround(std::min(255.0, std::max(0.0, 2.0 * std::log2(dens) + 20.0)));
     const double vth = d->kT > 0 ? std::sqrt(d->kT / d->mass) : 1.0;
     const int step = (int)std::min(15.0, std::floor(8.0 * d->dt * vth / d->a));   // free path / cell
-    return ((uint64_t)lc << 16) | ((uint64_t)rho << 4) | (uint64_t)step;
+    const uint64_t rule = (d->flags & MPCD_CONSERVE_L) ? 1 : 0;   // angular-momentum rule
+    return (rule << 32) | ((uint64_t)lc << 16) | ((uint64_t)rho << 4) | (uint64_t)step;
 }
 
 static int trial_ms(mpcd_ctx* parent, const mpcd_box_desc* proxy, int32_t binning, const int32_t brick[3],
@@ -636,14 +645,17 @@ static const int32_t kRuleShapes[][3] = {{2, 2, 2}, {4, 2, 2}, {4, 4, 2}, {4, 4,
                                          {8, 8, 4}, {8, 8, 8}, {16, 8, 8}};
 constexpr int kNumRuleShapes = (int)(sizeof(kRuleShapes) / sizeof(kRuleShapes[0]));
 
-static int rule_shape(double density)
+static int rule_volume(int i) { return kRuleShapes[i][0] * kRuleShapes[i][1] * kRuleShapes[i][2]; }
+
+// angular-momentum boxes: bricks of at most kMaxAmBrickCells cells
+static bool rule_allowed(int i, bool am) { return !am || rule_volume(i) <= kMaxAmBrickCells; }
+
+static int rule_shape(double density, bool am)
 {
     const int64_t fit = (int64_t)brick_shape_threads(1) * brick_shape_slots(1);   // 256 x 6
     int best = 0;
-    for (int i = 0; i < kNumRuleShapes; ++i) {
-        const double v = (double)kRuleShapes[i][0] * kRuleShapes[i][1] * kRuleShapes[i][2];
-        if (bucket_need(v * density) <= fit) best = i;
-    }
+    for (int i = 0; i < kNumRuleShapes; ++i)
+        if (rule_allowed(i, am) && bucket_need(rule_volume(i) * density) <= fit) best = i;
     return best;
 }
 
@@ -651,7 +663,8 @@ static int autotune(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* binning, int32
 {
     const double C = (double)d->L[0] * d->L[1] * d->L[2];
     const double density = (double)d->n_particles / C;
-    const int r = rule_shape(density);
+    const bool am = (d->flags & MPCD_CONSERVE_L) != 0;
+    const int r = rule_shape(density, am);
     // defaults, also used inside trial contexts, for empty and for small boxes
     *binning = MPCD_BIN_ATOMIC;
     for (int k = 0; k < 3; ++k) brick[k] = kRuleShapes[r][k];
@@ -672,7 +685,7 @@ static int autotune(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* binning, int32
         cells *= p.L[k];
     }
     p.n_particles = std::max<int64_t>(1, std::llround(density * cells));
-    p.flags = MPCD_INIT_MAXWELL;
+    p.flags = MPCD_INIT_MAXWELL | (d->flags & (MPCD_CONSERVE_L | MPCD_PARTICLE_MASS));
     if (!(p.kT > 0.0)) p.kT = 1.0;
     p.n_steps = 0;
     p.vacf_stride = 0;
@@ -680,6 +693,7 @@ static int autotune(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* binning, int32
     struct Cand { int32_t bin; int32_t b[3]; std::string name; };
     std::vector<Cand> cands;
     for (int i = std::max(0, r - 1); i <= std::min(kNumRuleShapes - 1, r + 1); ++i) {
+        if (!rule_allowed(i, am)) continue;
         const int32_t* sh = kRuleShapes[i];
         cands.push_back({MPCD_BIN_ATOMIC, {sh[0], sh[1], sh[2]},
                          "brick" + std::to_string(sh[0]) + "x" + std::to_string(sh[1]) + "x" + std::to_string(sh[2])});
@@ -806,21 +820,20 @@ int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
     const int cap = vacf_capacity(d);
     int32_t binning = c->binning;
     int32_t want[3] = {c->brick[0], c->brick[1], c->brick[2]};
-    if (d->flags & MPCD_CONSERVE_L) {
-        binning = MPCD_BIN_SORT;   // the per-cell moments need whole cells in one thread
-    } else if (binning == MPCD_BIN_AUTO) {
+    if (binning == MPCD_BIN_AUTO) {
         rc = autotune(c, d, &binning, want);
         if (rc) return rc;
     }
     BrickGeom g = brick_geometry(d->L, want);
-    if (binning == MPCD_BIN_ATOMIC && g.bvol > kMaxBrickCells) return MPCD_EINVAL;
+    const bool am = (d->flags & MPCD_CONSERVE_L) != 0;
+    if (binning == MPCD_BIN_ATOMIC && g.bvol > (am ? kMaxAmBrickCells : kMaxBrickCells)) return MPCD_EINVAL;
     // slot byte offsets are 32-bit: very large boxes use the counting sort
     if (binning == MPCD_BIN_ATOMIC && brick_slots(d->n_particles, g.nbrick) >= ((int64_t)1 << 30))
         binning = MPCD_BIN_SORT;
     const bool brick = binning == MPCD_BIN_ATOMIC;
     const int64_t nslot = brick ? brick_slots(d->n_particles, g.nbrick) : d->n_particles;
     const bool masses = (d->flags & MPCD_PARTICLE_MASS) != 0;
-    const Layout L = box_layout(d->n_particles, nslot, ncell, vacf, cap, brick, g, masses);
+    const Layout L = box_layout(d->n_particles, nslot, ncell, vacf, cap, brick, g, masses, am);
     if (c->budget > 0 && c->used + (int64_t)L.total > c->budget) return MPCD_ENOMEM;
     HIPCHK(hipSetDevice(c->device));
     void* mem = ctx_alloc(c, L.total);
@@ -845,6 +858,7 @@ int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
     b.rank = (uint32_t*)(m + L.off_rank);
     b.cstart = (uint32_t*)(m + L.off_cstart);
     b.un = brick ? (CellRot*)(m + L.off_un) : nullptr;
+    b.uam = brick && am ? (CellAm*)(m + L.off_uam) : nullptr;
     for (int p = 0; p < 2; ++p) {
         b.esc[p] = brick ? (CellAcc*)(m + L.off_esc[p]) : nullptr;
         b.bsize[p] = brick ? (uint32_t*)(m + L.off_bsize[p]) : nullptr;

@@ -259,7 +259,7 @@ __device__ __forceinline__ void vacf_term(const BoxDev& b, int32_t id, float3 v,
 //   4. one global reservation per group in the destination buckets, then
 //      stores.  Per step only the range check (and the VACF sum when a
 //      sample is due) is reduced; momentum and energy are summed on demand.
-template <int kT, int kS, bool kMass>
+template <int kT, int kS, bool kMass, bool kAM>
 __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tiles,
                                                     const BoxDev* __restrict__ boxes,
                                                     const BoxState* __restrict__ st,
@@ -268,7 +268,8 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
     // LDS, per cell of the brick: exact sums of m v (3 x 64 bit) and of m (64
     // bit, or a 32-bit count for equal masses) in 40-byte records, then u_c,
     // n_c and kappa in 48-byte records (two 16-byte reads); both strides
-    // spread neighbouring cells over the LDS banks
+    // spread neighbouring cells over the LDS banks.  Boxes with the
+    // angular-momentum rule (kAM instances only) use kAmWords per cell instead.
     extern __shared__ __align__(16) unsigned long long lds64[];
     __shared__ uint32_t gcnt[27], gpos[27], gbeg[27], gcap[27];
     __shared__ uint32_t s_cnt;
@@ -290,9 +291,10 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
     const int ey = min(1 << b.bshift[1], b.L[1] - loy);
     const int ez = min(1 << b.bshift[2], b.L[2] - loz);
     const int ncl = ex * ey * ez;
+    const bool am = kAM && b.conserve_l != 0;
     unsigned long long* const acc = lds64;   // [ncl][kAccWords]: sx, sy, sz, w
     float* const fu = reinterpret_cast<float*>(lds64 + ((kAccWords * ncl + 1) & ~1));   // [ncl][kUnWords]
-    for (int i = threadIdx.x; i < kAccWords * ncl; i += kT) lds64[i] = 0ull;
+    for (int i = threadIdx.x; i < (am ? kAmWords : kAccWords) * ncl; i += kT) lds64[i] = 0ull;
     const uint32_t beg = (uint32_t)uniform((int)gp(b.bstart)[brick]);
     if (threadIdx.x == 0) {
         const uint32_t cap = gp(b.bstart)[brick + 1] - beg;
@@ -309,7 +311,8 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
     const MPCD_G float* __restrict__ ivx = gp(b.p[src][3]);
     const MPCD_G float* __restrict__ ivy = gp(b.p[src][4]);
     const MPCD_G float* __restrict__ ivz = gp(b.p[src][5]);
-    const MPCD_G float* __restrict__ im = gp(kMass ? b.m[src] : (float*)nullptr);
+    const bool has_mass = kMass && b.m[src] != nullptr;   // uniform
+    const MPCD_G float* __restrict__ im = gp(has_mass ? b.m[src] : (float*)nullptr);
     const float3 sh = grid_shift(b, k);
     const float dt = b.dt;
     const float inv_a = b.inv_a;
@@ -338,7 +341,7 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
             vx[u] = ldg(ivx, o);
             vy[u] = ldg(ivy, o);
             vz[u] = ldg(ivz, o);
-            pm[u] = kMass ? ldg(im, o) : 1.0f;
+            pm[u] = has_mass ? ldg(im, o) : 1.0f;
         }
 #pragma unroll
         for (int u = 0; u < kS; ++u) {
@@ -366,6 +369,16 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
         for (int u = 0; u < kS; ++u) {
             const uint32_t c = meta[u];
             if (c == kNone) continue;
+            if (kAM && am) {   // moments of the angular-momentum rule
+                double rl[3];
+                long long tm[kAmMoments];
+                am_local(b.a, px[u], py[u], pz[u], sh, rl);
+                am_moments((double)pm[u], vx[u], vy[u], vz[u], rl, tm);
+                unsigned long long* const ra = acc + (size_t)c * kAmWords;
+#pragma unroll
+                for (int q = 0; q < kAmMoments; ++q) atomicAdd(&ra[q], (unsigned long long)tm[q]);
+                continue;
+            }
             unsigned long long* const r = acc + (size_t)c * kAccWords;
             if (kMass) {
                 const float mi = pm[u];
@@ -385,6 +398,41 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
     const uint32_t stamp = (uint32_t)(k + 1);
     const bool flagged = gp(b.eflag)[(size_t)(k & 1) * b.nbrick + brick] == stamp;
     const uint32_t L0 = (uint32_t)b.L[0], L01 = (uint32_t)b.L[0] * (uint32_t)b.L[1];
+    // Angular-momentum rule, flagged brick: the particles of this step's
+    // overflow bucket whose collision cell lies here are read directly (pass
+    // 1: moments, pass 2: angular-momentum change), as their escape sums
+    // carry no moments.
+    auto am_overflow = [&](int pass) {
+        const uint32_t nbk = (uint32_t)b.nbrick;
+        const uint32_t ob = gp(b.bstart)[nbk];
+        const uint32_t ocnt = min(gp(b.bsize[src])[nbk], gp(b.bstart)[nbk + 1] - ob);
+        for (uint32_t q = threadIdx.x; q < ocnt; q += kT) {
+            const uint32_t si = ob + q;
+            const float ux = gp(b.p[src][3])[si], uy = gp(b.p[src][4])[si], uz = gp(b.p[src][5])[si];
+            const float qx = fold(fmaf(ux, dt, gp(b.p[src][0])[si]), b.len[0]);
+            const float qy = fold(fmaf(uy, dt, gp(b.p[src][1])[si]), b.len[1]);
+            const float qz = fold(fmaf(uz, dt, gp(b.p[src][2])[si]), b.len[2]);
+            const int cx = axis_cell(qx, sh.x, inv_a, b.L[0]) - lox;
+            const int cy = axis_cell(qy, sh.y, inv_a, b.L[1]) - loy;
+            const int cz = axis_cell(qz, sh.z, inv_a, b.L[2]) - loz;
+            if ((unsigned)cx >= (unsigned)ex || (unsigned)cy >= (unsigned)ey || (unsigned)cz >= (unsigned)ez) continue;
+            const int c = cx + ex * (cy + ey * cz);
+            const double mj = has_mass ? (double)gp(b.m[src])[si] : 1.0;
+            double rl[3];
+            am_local(b.a, qx, qy, qz, sh, rl);
+            unsigned long long* const ra = acc + (size_t)c * kAmWords;
+            if (pass == 1) {
+                long long tm[kAmMoments];
+                am_moments(mj, ux, uy, uz, rl, tm);
+                for (int e = 0; e < kAmMoments; ++e) atomicAdd(&ra[e], (unsigned long long)tm[e]);
+            } else {
+                const double* const rec = reinterpret_cast<const double*>(ra);
+                long long tl3[3];
+                am_dl(mj, ux, uy, uz, rl, rec, rec + 3, rec + 6, b.ca, b.sa, tl3);
+                for (int e = 0; e < 3; ++e) atomicAdd(&ra[15 + e], (unsigned long long)tl3[e]);
+            }
+        }
+    };
     if (flagged) {   // overflow particles of this step whose cells lie here
         MPCD_G CellAcc* __restrict__ esc = gp(b.esc[k & 1]);
         for (int c = threadIdx.x; c < ncl; c += kT) {
@@ -392,34 +440,99 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
             const uint32_t gc = (uint32_t)(lox + lx) + L0 * (uint32_t)(loy + ly) + L01 * (uint32_t)(loz + lz);
             const CellAcc e = load_acc(esc + gc);
             if (e.w) {
-                unsigned long long* const r = acc + (size_t)c * kAccWords;
-                r[0] += e.sx;
-                r[1] += e.sy;
-                r[2] += e.sz;
-                r[3] += kMass ? e.w : (e.w >> 32);   // escape weights are 2^32 m
+                if (!(kAM && am)) {
+                    unsigned long long* const r = acc + (size_t)c * kAccWords;
+                    r[0] += e.sx;
+                    r[1] += e.sy;
+                    r[2] += e.sz;
+                    r[3] += kMass ? e.w : (e.w >> 32);   // escape weights are 2^32 m
+                }
                 CellAcc z = {0ull, 0ull, 0ull, 0ull};
                 store_acc(esc + gc, z);
             }
         }
+        if (kAM && am) am_overflow(1);
         __syncthreads();
     }
 
-    // 2. cell velocity and axis
-    for (int c = threadIdx.x; c < ncl; c += kT) {
-        const unsigned long long* const r = acc + (size_t)c * kAccWords;
-        const unsigned long long w = kMass ? r[3] : ((r[3] & 0xffffffffull) << 32);
-        if (w == 0) continue;
-        const int lx = c % ex, ly = (c / ex) % ey, lz = c / (ex * ey);
-        const uint32_t gc = (uint32_t)(lox + lx) + L0 * (uint32_t)(loy + ly) + L01 * (uint32_t)(loz + lz);
-        const CellRot cr = cell_rotation(fixed_mean(r[0], w), fixed_mean(r[1], w), fixed_mean(r[2], w),
-                                         cell_axis(b, k, gc), b.ca, b.sa);
-        float4* const q = reinterpret_cast<float4*>(fu + (size_t)c * kUnWords);
-        q[0] = make_float4(cr.m[0], cr.m[1], cr.m[2], cr.m[3]);
-        q[1] = make_float4(cr.m[4], cr.m[5], cr.m[6], cr.m[7]);
-        q[2] = make_float4(cr.m[8], cr.t[0], cr.t[1], cr.t[2]);
-        if (flagged) store_rot(gp(b.un) + gc, cr);   // read by the overflow particles
+    if (kAM && am) {
+        // 2a. per cell: u, r_c, axis n, second moment Q (FP64, in place of
+        // the moment sums; an empty cell keeps n = 0)
+        for (int c = threadIdx.x; c < ncl; c += kT) {
+            unsigned long long* const ra = acc + (size_t)c * kAmWords;
+            const long long* const sm = reinterpret_cast<const long long*>(ra);
+            if (sm[0] == 0) continue;
+            const int lx = c % ex, ly = (c / ex) % ey, lz = c / (ex * ey);
+            const uint32_t gc = (uint32_t)(lox + lx) + L0 * (uint32_t)(loy + ly) + L01 * (uint32_t)(loz + lz);
+            double uc[3], rc[3], Q[6], n[3];
+            am_cell(b, k, gc, sm, uc, rc, Q, n);
+            double* const rec = reinterpret_cast<double*>(ra);
+            for (int e = 0; e < 3; ++e) {
+                rec[e] = uc[e];
+                rec[3 + e] = rc[e];
+                rec[6 + e] = n[e];
+            }
+            for (int e = 0; e < 6; ++e) rec[9 + e] = Q[e];
+        }
+        __syncthreads();
+        // 2b. angular-momentum change of each particle under the plain rotation
+        for (int ch = nch - 1; ch >= 0; --ch) {
+            if (nch > 1) load(ch);
+#pragma unroll
+            for (int u = 0; u < kS; ++u) {
+                const uint32_t c = meta[u];
+                if (c == kNone) continue;
+                unsigned long long* const ra = acc + (size_t)c * kAmWords;
+                const double* const rec = reinterpret_cast<const double*>(ra);
+                double rl[3];
+                long long tl3[3];
+                am_local(b.a, px[u], py[u], pz[u], sh, rl);
+                am_dl((double)pm[u], vx[u], vy[u], vz[u], rl, rec, rec + 3, rec + 6, b.ca, b.sa, tl3);
+                for (int e = 0; e < 3; ++e) atomicAdd(&ra[15 + e], (unsigned long long)tl3[e]);
+            }
+        }
+        if (flagged) am_overflow(2);
+        __syncthreads();
+        // 2c. per cell: omega (in place of Q); flagged bricks publish the
+        // cell data for the overflow particles
+        for (int c = threadIdx.x; c < ncl; c += kT) {
+            unsigned long long* const ra = acc + (size_t)c * kAmWords;
+            double* const rec = reinterpret_cast<double*>(ra);
+            if (rec[6] == 0.0 && rec[7] == 0.0 && rec[8] == 0.0) continue;   // empty
+            double om[3];
+            am_omega(rec + 9, reinterpret_cast<const long long*>(ra + 15), om);
+            for (int e = 0; e < 3; ++e) rec[9 + e] = om[e];
+            if (flagged) {
+                const int lx = c % ex, ly = (c / ex) % ey, lz = c / (ex * ey);
+                const uint32_t gc = (uint32_t)(lox + lx) + L0 * (uint32_t)(loy + ly) + L01 * (uint32_t)(loz + lz);
+                CellAm* const g = b.uam + gc;
+                for (int e = 0; e < 3; ++e) {
+                    g->u[e] = rec[e];
+                    g->rc[e] = rec[3 + e];
+                    g->n[e] = rec[6 + e];
+                    g->om[e] = om[e];
+                }
+            }
+        }
+        __syncthreads();
+    } else {
+        // 2. cell velocity and axis
+        for (int c = threadIdx.x; c < ncl; c += kT) {
+            const unsigned long long* const r = acc + (size_t)c * kAccWords;
+            const unsigned long long w = kMass ? r[3] : ((r[3] & 0xffffffffull) << 32);
+            if (w == 0) continue;
+            const int lx = c % ex, ly = (c / ex) % ey, lz = c / (ex * ey);
+            const uint32_t gc = (uint32_t)(lox + lx) + L0 * (uint32_t)(loy + ly) + L01 * (uint32_t)(loz + lz);
+            const CellRot cr = cell_rotation(fixed_mean(r[0], w), fixed_mean(r[1], w), fixed_mean(r[2], w),
+                                             cell_axis(b, k, gc), b.ca, b.sa);
+            float4* const q = reinterpret_cast<float4*>(fu + (size_t)c * kUnWords);
+            q[0] = make_float4(cr.m[0], cr.m[1], cr.m[2], cr.m[3]);
+            q[1] = make_float4(cr.m[4], cr.m[5], cr.m[6], cr.m[7]);
+            q[2] = make_float4(cr.m[8], cr.t[0], cr.t[1], cr.t[2]);
+            if (flagged) store_rot(gp(b.un) + gc, cr);   // read by the overflow particles
+        }
+        __syncthreads();
     }
-    __syncthreads();
 
     // 3./4. rotate, route to the next step's buckets, store
     const float3 sh1 = grid_shift(b, k + 1);
@@ -449,7 +562,15 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
             uint32_t r = 28u;   // no particle
             if (i < cnt) {
                 const uint32_t c = meta[u];
-                if (c != kNone) {
+                if (kAM && am && c != kNone) {
+                    const double* const rec = reinterpret_cast<const double*>(acc + (size_t)c * kAmWords);
+                    double rl[3];
+                    am_local(b.a, px[u], py[u], pz[u], sh, rl);
+                    const float3 v = am_velocity(vx[u], vy[u], vz[u], rl, rec, rec + 3, rec + 6, rec + 9, b.ca, b.sa);
+                    vx[u] = v.x;
+                    vy[u] = v.y;
+                    vz[u] = v.z;
+                } else if (c != kNone) {
                     const float4* const q = reinterpret_cast<const float4*>(fu + (size_t)c * kUnWords);
                     const float4 q0 = q[0], q1 = q[1], q2 = q[2];
                     CellRot cr;
@@ -570,7 +691,15 @@ __device__ void overflow_step(const BoxDev& b, const BoxState& s, long long (&d)
         const float z = fold(fmaf(vz, b.dt, gp(b.p[src][2])[si]), b.len[2]);
         const float m = has_m ? gp(b.m[src])[si] : 1.0f;
         const uint32_t c = collision_cell(b, x, y, z, sh);
-        const float3 v = apply_rotation(load_rot(gp(b.un) + c), vx, vy, vz);
+        float3 v;
+        if (b.conserve_l && b.uam) {   // angular-momentum rule: cell data published as CellAm
+            const CellAm& g = b.uam[c];
+            double rl[3];
+            am_local(b.a, x, y, z, sh, rl);
+            v = am_velocity(vx, vy, vz, rl, g.u, g.rc, g.n, g.om, b.ca, b.sa);
+        } else {
+            v = apply_rotation(load_rot(gp(b.un) + c), vx, vy, vz);
+        }
         diag_check(d, v);
         const int3 nc = next_cell(b, x, y, z, v, sh1);
         const int3 db = brick_of_cell(b, nc);
@@ -918,11 +1047,9 @@ __global__ void k_flip(const int32_t* __restrict__ active, int nactive,
 }
 
 // Angular-momentum-conserving collision of one cell whose particles occupy
-// [beg, end) of the current buffer (streamed, SORT binning): the plain
-// rotation followed by the rigid-body velocity omega x r' that restores the
-// cell's angular momentum about its centre of mass, omega = -I^+ dL.  All
-// cell sums are exact fixed point (independent of particle order); the
-// per-cell algebra is FP64.
+// [beg, end) of the current buffer (streamed, SORT binning): three passes of
+// one thread over the cell (moments, angular-momentum change, new
+// velocities) with the shared am_* functions.
 __device__ __forceinline__ void collide_cell_am(const BoxDev& b, int par, long long k, uint32_t c,
                                                 uint32_t beg, uint32_t end, float3 sh, double ca,
                                                 double sa, long long (&d)[kNumDiag], bool vacf)
@@ -935,98 +1062,32 @@ __device__ __forceinline__ void collide_cell_am(const BoxDev& b, int par, long l
     float* __restrict__ vz = b.p[par][5];
     const float* __restrict__ mp = b.m[par];
     const double a = b.a;
-    // position inside the shifted cell, each component in [0, a)
-    auto local = [&](uint32_t j, double r[3]) {
-        const double q[3] = {(double)px[j] - sh.x, (double)py[j] - sh.y, (double)pz[j] - sh.z};
-#pragma unroll
-        for (int e = 0; e < 3; ++e) r[e] = q[e] - a * floor(q[e] / a);
-    };
-    // pass 1: mass, momentum, first and second position moments
-    long long sw = 0, sv[3] = {0, 0, 0}, s1[3] = {0, 0, 0}, s2[6] = {0, 0, 0, 0, 0, 0};
+    long long sm[kAmMoments] = {};
     for (uint32_t j = beg; j < end; ++j) {
-        const double mj = mass_of(mp, j);
         double r[3];
-        local(j, r);
-        sw += fixed_term(mj);
-        sv[0] += fixed_term(mj * vx[j]);
-        sv[1] += fixed_term(mj * vy[j]);
-        sv[2] += fixed_term(mj * vz[j]);
+        long long t[kAmMoments];
+        am_local(a, px[j], py[j], pz[j], sh, r);
+        am_moments(mass_of(mp, j), vx[j], vy[j], vz[j], r, t);
 #pragma unroll
-        for (int e = 0; e < 3; ++e) s1[e] += fixed_term(mj * r[e]);
-        s2[0] += fixed_term(mj * r[0] * r[0]);
-        s2[1] += fixed_term(mj * r[0] * r[1]);
-        s2[2] += fixed_term(mj * r[0] * r[2]);
-        s2[3] += fixed_term(mj * r[1] * r[1]);
-        s2[4] += fixed_term(mj * r[1] * r[2]);
-        s2[5] += fixed_term(mj * r[2] * r[2]);
+        for (int q = 0; q < kAmMoments; ++q) sm[q] += t[q];
     }
-    const double M = fixed_to_double((unsigned long long)sw);
-    double u[3], rc[3];
-#pragma unroll
-    for (int e = 0; e < 3; ++e) {
-        u[e] = fixed_to_double((unsigned long long)sv[e]) / M;
-        rc[e] = fixed_to_double((unsigned long long)s1[e]) / M;
-    }
-    // sums are in units of 2^-32: Mt is the true mass; u and rc are ratios
-    const double k2 = 2.3283064365386963e-10;
-    const double Mt = M * k2;
-    double Q[3][3];   // second moment of position about the centre of mass
-    Q[0][0] = fixed_to_double((unsigned long long)s2[0]) * k2 - Mt * rc[0] * rc[0];
-    Q[0][1] = fixed_to_double((unsigned long long)s2[1]) * k2 - Mt * rc[0] * rc[1];
-    Q[0][2] = fixed_to_double((unsigned long long)s2[2]) * k2 - Mt * rc[0] * rc[2];
-    Q[1][1] = fixed_to_double((unsigned long long)s2[3]) * k2 - Mt * rc[1] * rc[1];
-    Q[1][2] = fixed_to_double((unsigned long long)s2[4]) * k2 - Mt * rc[1] * rc[2];
-    Q[2][2] = fixed_to_double((unsigned long long)s2[5]) * k2 - Mt * rc[2] * rc[2];
-    Q[1][0] = Q[0][1];
-    Q[2][0] = Q[0][2];
-    Q[2][1] = Q[1][2];
-    const float3 ax = cell_axis(b, k, c);
-    double nx = ax.x, ny = ax.y, nz = ax.z;
-    const double inv = 1.0 / sqrt(nx * nx + ny * ny + nz * nz);
-    nx *= inv;
-    ny *= inv;
-    nz *= inv;
-    // pass 2: change of the cell's angular momentum under the plain rotation
+    double u[3], rc[3], Q[6], n[3], om[3];
+    am_cell(b, k, c, sm, u, rc, Q, n);
     long long sl[3] = {0, 0, 0};
     for (uint32_t j = beg; j < end; ++j) {
-        const double mj = mass_of(mp, j);
-        double r[3], w[3], rw[3];
-        local(j, r);
-        w[0] = (double)vx[j] - u[0];
-        w[1] = (double)vy[j] - u[1];
-        w[2] = (double)vz[j] - u[2];
-        rotate_w(nx, ny, nz, ca, sa, w, rw);
-        const double rp[3] = {r[0] - rc[0], r[1] - rc[1], r[2] - rc[2]};
-        const double dw[3] = {rw[0] - w[0], rw[1] - w[1], rw[2] - w[2]};
-        sl[0] += fixed_term(mj * (rp[1] * dw[2] - rp[2] * dw[1]));
-        sl[1] += fixed_term(mj * (rp[2] * dw[0] - rp[0] * dw[2]));
-        sl[2] += fixed_term(mj * (rp[0] * dw[1] - rp[1] * dw[0]));
+        double r[3];
+        long long t[3];
+        am_local(a, px[j], py[j], pz[j], sh, r);
+        am_dl(mass_of(mp, j), vx[j], vy[j], vz[j], r, u, rc, n, ca, sa, t);
+        sl[0] += t[0];
+        sl[1] += t[1];
+        sl[2] += t[2];
     }
-    const double dL[3] = {fixed_to_double((unsigned long long)sl[0]) * k2,
-                          fixed_to_double((unsigned long long)sl[1]) * k2,
-                          fixed_to_double((unsigned long long)sl[2]) * k2};
-    double I[3][3], Ip[3][3];
-    const double tr = Q[0][0] + Q[1][1] + Q[2][2];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) I[i][j] = (i == j ? tr : 0.0) - Q[i][j];
-    sym3_pinv(I, 1e-10, Ip);
-    double om[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) om[i] = -(Ip[i][0] * dL[0] + Ip[i][1] * dL[1] + Ip[i][2] * dL[2]);
-    // pass 3: rotated relative velocity plus the rigid-body correction
+    am_omega(Q, sl, om);
     for (uint32_t j = beg; j < end; ++j) {
-        double r[3], w[3], rw[3];
-        local(j, r);
-        w[0] = (double)vx[j] - u[0];
-        w[1] = (double)vy[j] - u[1];
-        w[2] = (double)vz[j] - u[2];
-        rotate_w(nx, ny, nz, ca, sa, w, rw);
-        const double rp[3] = {r[0] - rc[0], r[1] - rc[1], r[2] - rc[2]};
-        const float3 v = make_float3((float)(u[0] + rw[0] + (om[1] * rp[2] - om[2] * rp[1])),
-                                     (float)(u[1] + rw[1] + (om[2] * rp[0] - om[0] * rp[2])),
-                                     (float)(u[2] + rw[2] + (om[0] * rp[1] - om[1] * rp[0])));
+        double r[3];
+        am_local(a, px[j], py[j], pz[j], sh, r);
+        const float3 v = am_velocity(vx[j], vy[j], vz[j], r, u, rc, n, om, ca, sa);
         if (vacf) vacf_term(b, b.pid[par][j], v, d);
         vx[j] = v.x;
         vy[j] = v.y;
@@ -1345,24 +1406,24 @@ __global__ __launch_bounds__(kBlock) void k_fill_zero_u32(uint32_t* __restrict__
         if ((grid) > 0) hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, stream, __VA_ARGS__); \
     } while (0)
 
-template <int kT, int kS, bool kMass>
+template <int kT, int kS, bool kMass, bool kAM>
 static void brick_step_run(const Tables& T, hipStream_t s)
 {
     static bool attr = false;
-    if (!attr) {   // a brick of kMaxBrickCells cells plus the static arrays
-        (void)hipFuncSetAttribute((const void*)k_brick_step<kT, kS, kMass>,
+    if (!attr) {   // the largest brick record (kMaxBrickCells or kMaxAmBrickCells cells)
+        (void)hipFuncSetAttribute((const void*)k_brick_step<kT, kS, kMass, kAM>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
         attr = true;
     }
-    const size_t lds = (size_t)T.max_bvol * kBrickCellBytes + 16;
-    hipLaunchKernelGGL((k_brick_step<kT, kS, kMass>), dim3(T.nbtiles), dim3(kT), lds, s, T.btiles, T.boxes,
-                       T.state, T.dacc);
+    hipLaunchKernelGGL((k_brick_step<kT, kS, kMass, kAM>), dim3(T.nbtiles), dim3(kT), T.brick_lds + 16, s,
+                       T.btiles, T.boxes, T.state, T.dacc);
 }
 template <int kT, int kS>
 static void brick_step_at(const Tables& T, hipStream_t s)
 {
-    if (T.brick_mass) brick_step_run<kT, kS, true>(T, s);
-    else brick_step_run<kT, kS, false>(T, s);
+    if (T.brick_am) brick_step_run<kT, kS, true, true>(T, s);
+    else if (T.brick_mass) brick_step_run<kT, kS, true, false>(T, s);
+    else brick_step_run<kT, kS, false, false>(T, s);
 }
 
 // Launch shapes of the brick step (workgroup size, particles per thread),

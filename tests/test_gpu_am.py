@@ -43,16 +43,18 @@ def _ill_conditioned_cells(box, s, st, cells, limit=1e3):
     return bad
 
 
+@pytest.mark.parametrize("binning", ["atomic", "sort"])
 @pytest.mark.parametrize("case", [
     dict(L=(8, 8, 8), n=5120, alpha=130.0, k=0, mass=False),
     dict(L=(6, 9, 5), n=2700, alpha=90.0, k=7, mass=True),
 ])
-def test_one_step_parity_am(mp, case):
-    print("[case] am", case, flush=True)
+def test_one_step_parity_am(mp, case, binning):
+    print("[case] am", binning, case, flush=True)
     L, n = case["L"], case["n"]
     pos, vel = inputs.thermal_state(L, n, seed=41)
     mass = np.random.default_rng(41).uniform(0.5, 2.0, n).astype(np.float32) if case["mass"] else None
-    with mp.Context() as ctx:
+    bin_id = mp.MPCD_BIN_ATOMIC if binning == "atomic" else mp.MPCD_BIN_SORT
+    with mp.Context(binning=bin_id, brick=(4, 4, 4)) as ctx:
         s = ctx.admit(mp.make_desc(L, n, alpha_deg=case["alpha"], seed=41, init="external",
                                    conserve_l=True, particle_mass=case["mass"]))
         ctx.set_state(s, (pos, vel), step=case["k"])
@@ -73,12 +75,14 @@ def test_one_step_parity_am(mp, case):
     check_against(sub, sh, cells[keep], box, gp[:, keep], gv[:, keep])
 
 
-def test_am_sort_is_deterministic_alone_and_in_mix(mp):
-    print("[case] am-mix", flush=True)
+@pytest.mark.parametrize("binning", ["atomic", "sort"])
+def test_am_is_deterministic_alone_and_in_mix(mp, binning):
+    print("[case] am-mix", binning, flush=True)
     boxes = [((8, 8, 8), 5120, 3), ((5, 7, 6), 2100, 4)]
     states = {}
+    bin_id = mp.MPCD_BIN_ATOMIC if binning == "atomic" else mp.MPCD_BIN_SORT
     for mix in (False, True):
-        with mp.Context() as ctx:
+        with mp.Context(binning=bin_id) as ctx:
             slots = []
             for (L, n, seed) in (boxes if mix else boxes[:1]):
                 pos, vel = inputs.thermal_state(L, n, seed)
@@ -89,3 +93,79 @@ def test_am_sort_is_deterministic_alone_and_in_mix(mp):
             states[mix] = ctx.get_state(slots[0])
     assert np.array_equal(states[False][0], states[True][0])
     assert np.array_equal(states[False][1], states[True][1])
+
+
+def _slab(n, seed, drift):
+    """Particles in the slab x < 3 of a 16^3 box, drifting along +x."""
+    g = np.random.default_rng(seed)
+    pos = np.empty((3, n), np.float32)
+    pos[0] = g.uniform(0.0, 3.0, n)
+    pos[1] = g.uniform(0.0, 16.0, n)
+    pos[2] = g.uniform(0.0, 16.0, n)
+    vel = g.standard_normal((3, n)).astype(np.float32)
+    vel[0] += np.float32(drift)
+    return pos, vel
+
+
+@pytest.mark.parametrize("mass", [False, True])
+def test_am_bricks_match_sort_through_overflow(mp, mass):
+    """The brick form of the angular-momentum rule (moments and angular
+    momentum summed in LDS, overflow particles read directly by their flagged
+    bricks) gives the counting-sort form's trajectory bit for bit, also while
+    a dense drifting slab overflows buckets."""
+    print("[case] am-overflow mass=%s" % mass, flush=True)
+    L, n = (16, 16, 16), 20000
+    pos, vel = _slab(n, 33, 4.0)
+    m = np.random.default_rng(33).uniform(0.5, 2.0, n).astype(np.float32) if mass else None
+    out, obs = [], []
+    for binning in (mp.MPCD_BIN_ATOMIC, mp.MPCD_BIN_SORT):
+        with mp.Context(binning=binning, brick=(4, 4, 4)) as ctx:
+            s = ctx.admit(mp.make_desc(L, n, dt=0.1, seed=33, init="external", conserve_l=True,
+                                       particle_mass=mass))
+            ctx.set_state(s, (pos, vel))
+            if m is not None:
+                ctx.set_mass(s, m)
+            for _ in range(8):
+                ctx.step(3)
+            out.append(ctx.get_state(s))
+            obs.append(ctx.observe(s))
+    print("[am-overflow] binning %d/%d, steps with overflow %d, re-bucketings %d" % (
+        obs[0]["binning"], obs[1]["binning"], obs[0]["overflow_steps"], obs[0]["rebuckets"]), flush=True)
+    assert obs[0]["binning"] == mp.MPCD_BIN_ATOMIC and obs[1]["binning"] == mp.MPCD_BIN_SORT
+    assert obs[0]["overflow_steps"] > 0 and obs[0]["rebuckets"] >= 2
+    assert out[0][2] == out[1][2] == 24
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    assert obs[0]["E"] == obs[1]["E"] and np.array_equal(obs[0]["P"], obs[1]["P"])
+
+
+def test_am_and_plain_boxes_share_a_launch(mp):
+    """Brick boxes with the angular-momentum rule, with per-particle masses
+    and plain ones advance in one launch; each ends where it ends alone."""
+    print("[case] am-plain-mix", flush=True)
+    boxes = [dict(L=(8, 8, 8), n=5120, seed=5, am=True, mass=False),
+             dict(L=(12, 10, 8), n=9600, seed=6, am=False, mass=True),
+             dict(L=(9, 9, 9), n=7290, seed=7, am=False, mass=False),
+             dict(L=(10, 8, 6), n=4800, seed=8, am=True, mass=True)]
+
+    def run(sel):
+        res = []
+        with mp.Context(binning=mp.MPCD_BIN_ATOMIC, brick=(4, 4, 4)) as ctx:
+            slots = []
+            for bx in sel:
+                pos, vel = inputs.thermal_state(bx["L"], bx["n"], bx["seed"])
+                sl = ctx.admit(mp.make_desc(bx["L"], bx["n"], seed=bx["seed"], init="external",
+                                            conserve_l=bx["am"], particle_mass=bx["mass"]))
+                ctx.set_state(sl, (pos, vel))
+                if bx["mass"]:
+                    ctx.set_mass(sl, np.random.default_rng(bx["seed"]).uniform(0.5, 2.0, bx["n"]).astype(np.float32))
+                slots.append(sl)
+            ctx.step(15)
+            for sl in slots:
+                res.append(ctx.get_state(sl))
+        return res
+
+    together = run(boxes)
+    for i, bx in enumerate(boxes):
+        alone = run([bx])[0]
+        assert alone[2] == together[i][2] == 15
+        assert np.array_equal(alone[0], together[i][0]) and np.array_equal(alone[1], together[i][1]), i
