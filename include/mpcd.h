@@ -73,7 +73,9 @@ typedef enum {
                                     velocity w x r' that restores its angular
                                     momentum about its centre of mass,
                                     w = -I^+ dL; kinetic energy is then not
-                                    conserved.  Uses MPCD_BIN_SORT.         */
+                                    conserved.  Brick binning and counting-
+                                    sort binning give the same bits; bricks
+                                    of such a box hold at most 512 cells.  */
 #define MPCD_PARTICLE_MASS 0x8u  /* every particle carries its own mass
                                     (initially desc.mass; mpcd_set_mass);
                                     cell velocities are mass weighted       */
