@@ -315,3 +315,33 @@ def test_nonfinite_velocity_flags_only_its_box(mp):
         ob = ctx.observe(b)
     assert oa["status"] == mp.MPCD_ESTATE
     assert ob["status"] == mp.MPCD_OK and ob["step"] == 2
+
+
+def test_admission_and_release_while_steps_are_queued(mp):
+    """mpcd_admit queues a new box's initial state behind the steps already
+    queued (nothing waits) and mpcd_release frees a box whose steps may still
+    be queued: the other boxes' trajectories are unchanged, and the new box
+    starts from the same initial state as in an idle context."""
+    _say("queued-admission")
+    descs = [dict(L=(20, 20, 20), n=80000, seed=51), dict(L=(16, 12, 10), n=19200, seed=52),
+             dict(L=(10, 10, 10), n=10000, seed=53)]
+    d = [mp.make_desc(x["L"], x["n"], seed=x["seed"]) for x in descs]
+    with mp.Context() as ctx:
+        a = ctx.admit(d[0])
+        c = ctx.admit(d[2])
+        ctx.step(10)           # queued, not waited for
+        b = ctx.admit(d[1])    # joins at the next step
+        ctx.release(c)
+        ctx.step(10)
+        sa, sb = ctx.get_state(a), ctx.get_state(b)
+    with mp.Context() as ctx:
+        a = ctx.admit(d[0])
+        ctx.step(20)
+        ra = ctx.get_state(a)
+    with mp.Context() as ctx:
+        b = ctx.admit(d[1])
+        ctx.step(10)
+        rb = ctx.get_state(b)
+    assert sa[2] == ra[2] == 20 and sb[2] == rb[2] == 10
+    assert np.array_equal(sa[0], ra[0]) and np.array_equal(sa[1], ra[1])
+    assert np.array_equal(sb[0], rb[0]) and np.array_equal(sb[1], rb[1])
