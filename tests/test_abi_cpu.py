@@ -111,3 +111,26 @@ def test_one_hip_runtime_whatever_the_import_order():
                          text=True, timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip() == "1"
+
+
+def _build_c_client(out_dir):
+    """Compile tests/c_abi_client.c (C99, gcc) against include/mpcd.h and link
+    it to the built libmpcd.so."""
+    from paper_2212_11878_amd import mpcd
+    exe = os.path.join(str(out_dir), "c_abi_client")
+    libdir = os.path.dirname(mpcd.LIB_PATH)
+    subprocess.run(["gcc", "-std=c99", "-O2", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                    os.path.join(ROOT, "tests", "c_abi_client.c"), "-L", libdir, "-lmpcd",
+                    "-Wl,-rpath," + libdir, "-lm", "-o", exe], check=True)
+    return exe
+
+
+def test_c_client_compiles_and_links(tmp_path):
+    """The header is plain C99 and the library links from C alone; without a
+    device the client stops at mpcd_create with MPCD_EDEVICE."""
+    import torch
+    exe = _build_c_client(tmp_path)
+    if torch.cuda.is_available():
+        return
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 77 and out.stdout.strip() == "no device", (out.returncode, out.stdout)
