@@ -44,6 +44,14 @@ __device__ __forceinline__ long long uniform(long long v)
     const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)((unsigned long long)v >> 32));
     return (long long)(((unsigned long long)hi << 32) | lo);
 }
+// A box array's global address, made wavefront-uniform so that it stays in
+// scalar registers (the address of each access is then that base plus a
+// 32-bit lane offset, with no per-lane 64-bit add).
+template <class T>
+__device__ __forceinline__ MPCD_G T* ugp(T* p)
+{
+    return (MPCD_G T*)(uintptr_t)(unsigned long long)uniform((long long)(uintptr_t)p);
+}
 
 // The counting sort runs every step for SORT boxes, and once for brick
 // boxes whose particles are not bucketed yet (after admission / set_state).
@@ -305,14 +313,14 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
     const uint32_t cnt = (uint32_t)uniform((int)s_cnt);
     const int nch = (int)((cnt + kChunk - 1) / kChunk);
 
-    const MPCD_G float* __restrict__ ix = gp(b.p[src][0]);
-    const MPCD_G float* __restrict__ iy = gp(b.p[src][1]);
-    const MPCD_G float* __restrict__ iz = gp(b.p[src][2]);
-    const MPCD_G float* __restrict__ ivx = gp(b.p[src][3]);
-    const MPCD_G float* __restrict__ ivy = gp(b.p[src][4]);
-    const MPCD_G float* __restrict__ ivz = gp(b.p[src][5]);
+    const MPCD_G float* __restrict__ ix = ugp(b.p[src][0]);
+    const MPCD_G float* __restrict__ iy = ugp(b.p[src][1]);
+    const MPCD_G float* __restrict__ iz = ugp(b.p[src][2]);
+    const MPCD_G float* __restrict__ ivx = ugp(b.p[src][3]);
+    const MPCD_G float* __restrict__ ivy = ugp(b.p[src][4]);
+    const MPCD_G float* __restrict__ ivz = ugp(b.p[src][5]);
     const bool has_mass = kMass && b.m[src] != nullptr;   // uniform
-    const MPCD_G float* __restrict__ im = gp(has_mass ? b.m[src] : (float*)nullptr);
+    const MPCD_G float* __restrict__ im = ugp(has_mass ? b.m[src] : (float*)nullptr);
     const float3 sh = grid_shift(b, k);
     const float dt = b.dt;
     const float inv_a = b.inv_a;
@@ -536,14 +544,14 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
 
     // 3./4. rotate, route to the next step's buckets, store
     const float3 sh1 = grid_shift(b, k + 1);
-    MPCD_G float* const ox = gp(b.p[dst][0]);
-    MPCD_G float* const oy = gp(b.p[dst][1]);
-    MPCD_G float* const oz = gp(b.p[dst][2]);
-    MPCD_G float* const ovx = gp(b.p[dst][3]);
-    MPCD_G float* const ovy = gp(b.p[dst][4]);
-    MPCD_G float* const ovz = gp(b.p[dst][5]);
-    MPCD_G int32_t* const oid = gp(b.pid[dst]);
-    const MPCD_G int32_t* const iid = gp(b.pid[src]);
+    MPCD_G float* const ox = ugp(b.p[dst][0]);
+    MPCD_G float* const oy = ugp(b.p[dst][1]);
+    MPCD_G float* const oz = ugp(b.p[dst][2]);
+    MPCD_G float* const ovx = ugp(b.p[dst][3]);
+    MPCD_G float* const ovy = ugp(b.p[dst][4]);
+    MPCD_G float* const ovz = ugp(b.p[dst][5]);
+    MPCD_G int32_t* const oid = ugp(b.pid[dst]);
+    const MPCD_G int32_t* const iid = ugp(b.pid[src]);
     const bool has_m = kMass && b.m[src] != nullptr;
     const int lane = threadIdx.x & (kWave - 1);
     const unsigned long long below = (1ull << lane) - 1ull;
@@ -974,12 +982,12 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const Tile* __restrict__ til
     const bool stream = (b.binning == 2);
     const bool has_m = b.m[src] != nullptr;
     const float dt = b.dt;
-    const MPCD_G float* __restrict__ ix = gp(b.p[src][0]);
-    const MPCD_G float* __restrict__ iy = gp(b.p[src][1]);
-    const MPCD_G float* __restrict__ iz = gp(b.p[src][2]);
-    const MPCD_G float* __restrict__ ivx = gp(b.p[src][3]);
-    const MPCD_G float* __restrict__ ivy = gp(b.p[src][4]);
-    const MPCD_G float* __restrict__ ivz = gp(b.p[src][5]);
+    const MPCD_G float* __restrict__ ix = ugp(b.p[src][0]);
+    const MPCD_G float* __restrict__ iy = ugp(b.p[src][1]);
+    const MPCD_G float* __restrict__ iz = ugp(b.p[src][2]);
+    const MPCD_G float* __restrict__ ivx = ugp(b.p[src][3]);
+    const MPCD_G float* __restrict__ ivy = ugp(b.p[src][4]);
+    const MPCD_G float* __restrict__ ivz = ugp(b.p[src][5]);
     const MPCD_G int32_t* __restrict__ iid = gp(b.pid[src]);
     MPCD_G float* __restrict__ ox = gp(b.p[dst][0]);
     MPCD_G float* __restrict__ oy = gp(b.p[dst][1]);
