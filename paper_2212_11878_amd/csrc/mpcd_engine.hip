@@ -315,7 +315,7 @@ int rebuild_tables(mpcd_ctx* c)
     c->any_brick = c->any_sort = false;
     int max_bvol = 0;
     size_t brick_lds = 0;
-    bool brick_am = false;
+    bool brick_am = false, brick_wide = false;
     int64_t max_bucket = 0;
     bool brick_mass = false;
     for (int s = 0; s < (int)c->slots.size(); ++s) {
@@ -345,6 +345,7 @@ int rebuild_tables(mpcd_ctx* c)
                                                                    (double)b.ncell));
             brick_mass |= b.m[0] != nullptr;
             brick_am |= b.conserve_l != 0;
+            brick_wide |= b.nslot >= ((int64_t)1 << 30);   // byte offsets beyond 32 bits
             brick_lds = std::max(brick_lds, (size_t)b.bmax[0] * b.bmax[1] * b.bmax[2] *
                                                 (b.conserve_l ? kAmCellBytes : kBrickCellBytes));
         }
@@ -374,6 +375,7 @@ int rebuild_tables(mpcd_ctx* c)
     c->T.brick_shape = brick_shape_for(max_bucket);
     c->T.brick_mass = brick_mass;
     c->T.brick_am = brick_am;
+    c->T.brick_wide = brick_wide;
     c->T.brick_lds = brick_lds;
     c->T.host_flag = c->host_flag_dev;
     // one upload for the tile lists (laid out as on the device) and one for
@@ -841,8 +843,8 @@ int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
     BrickGeom g = brick_geometry(d->L, want);
     const bool am = (d->flags & MPCD_CONSERVE_L) != 0;
     if (binning == MPCD_BIN_ATOMIC && g.bvol > (am ? kMaxAmBrickCells : kMaxBrickCells)) return MPCD_EINVAL;
-    // slot byte offsets are 32-bit: very large boxes use the counting sort
-    if (binning == MPCD_BIN_ATOMIC && brick_slots(d->n_particles, g.nbrick) >= ((int64_t)1 << 30))
+    // bucket starts are 32-bit: beyond 2^32 slots the box uses the counting sort
+    if (binning == MPCD_BIN_ATOMIC && brick_slots(d->n_particles, g.nbrick) >= ((int64_t)1 << 32))
         binning = MPCD_BIN_SORT;
     const bool brick = binning == MPCD_BIN_ATOMIC;
     const int64_t nslot = brick ? brick_slots(d->n_particles, g.nbrick) : d->n_particles;

@@ -24,6 +24,8 @@
 // they produce bit-identical velocities whatever the order of the atomics.
 // All kernels grid over "tiles" (contiguous slot, cell or brick ranges of one
 // box), which lets one launch advance many boxes of different sizes.
+#include <type_traits>
+
 #include "mpcd_dev.h"
 #include "mpcd_launch.h"
 
@@ -173,6 +175,12 @@ __device__ __forceinline__ void stg(MPCD_G T* p, uint32_t o, T v)
 {
     *(MPCD_G T*)((MPCD_G char*)p + o) = v;
 }
+// the same with a 64-bit byte offset (buffers of 2^30 slots or more)
+template <class T>
+__device__ __forceinline__ void stg(MPCD_G T* p, unsigned long long o, T v)
+{
+    *(MPCD_G T*)((MPCD_G char*)p + o) = v;
+}
 
 // Collision cell, at step k+1, of a particle at (x, y, z) that leaves step k
 // with velocity v: the stream of step k+1 and its shifted grid (the same
@@ -228,11 +236,11 @@ __device__ __forceinline__ bool place_overflow(const BoxDev& b, int dst, long lo
     return true;
 }
 
-// Store particle state at slot j of buffer dst (slots < 2^30).
+// Store particle state at slot j of buffer dst.
 __device__ __forceinline__ void put_particle(const BoxDev& b, int dst, uint32_t j, float x, float y, float z,
                                              float3 v, int32_t id, float m, bool has_m)
 {
-    const uint32_t o = j * 4u;
+    const unsigned long long o = (unsigned long long)j * 4u;
     stg(gp(b.p[dst][0]), o, x);
     stg(gp(b.p[dst][1]), o, y);
     stg(gp(b.p[dst][2]), o, z);
@@ -267,7 +275,7 @@ __device__ __forceinline__ void vacf_term(const BoxDev& b, int32_t id, float3 v,
 //   4. one global reservation per group in the destination buckets, then
 //      stores.  Per step only the range check (and the VACF sum when a
 //      sample is due) is reduced; momentum and energy are summed on demand.
-template <int kT, int kS, bool kMass, bool kAM>
+template <int kT, int kS, bool kMass, bool kAM, bool kWide>
 __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tiles,
                                                     const BoxDev* __restrict__ boxes,
                                                     const BoxState* __restrict__ st,
@@ -313,14 +321,15 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
     const uint32_t cnt = (uint32_t)uniform((int)s_cnt);
     const int nch = (int)((cnt + kChunk - 1) / kChunk);
 
-    const MPCD_G float* __restrict__ ix = ugp(b.p[src][0]);
-    const MPCD_G float* __restrict__ iy = ugp(b.p[src][1]);
-    const MPCD_G float* __restrict__ iz = ugp(b.p[src][2]);
-    const MPCD_G float* __restrict__ ivx = ugp(b.p[src][3]);
-    const MPCD_G float* __restrict__ ivy = ugp(b.p[src][4]);
-    const MPCD_G float* __restrict__ ivz = ugp(b.p[src][5]);
+    // bucket-relative bases (uniform): a lane's offset is its index in the bucket
+    const MPCD_G float* __restrict__ ix = ugp(b.p[src][0]) + beg;
+    const MPCD_G float* __restrict__ iy = ugp(b.p[src][1]) + beg;
+    const MPCD_G float* __restrict__ iz = ugp(b.p[src][2]) + beg;
+    const MPCD_G float* __restrict__ ivx = ugp(b.p[src][3]) + beg;
+    const MPCD_G float* __restrict__ ivy = ugp(b.p[src][4]) + beg;
+    const MPCD_G float* __restrict__ ivz = ugp(b.p[src][5]) + beg;
     const bool has_mass = kMass && b.m[src] != nullptr;   // uniform
-    const MPCD_G float* __restrict__ im = ugp(has_mass ? b.m[src] : (float*)nullptr);
+    const MPCD_G float* __restrict__ im = has_mass ? ugp(b.m[src]) + beg : nullptr;
     const float3 sh = grid_shift(b, k);
     const float dt = b.dt;
     const float inv_a = b.inv_a;
@@ -342,7 +351,7 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
         for (int u = 0; u < kS; ++u) {   // issue every load first
             if (u >= nu) break;
             const uint32_t i = (uint32_t)ch * kChunk + (uint32_t)(u * kT) + threadIdx.x;
-            const uint32_t o = (beg + (i < cnt ? i : 0u)) * 4u;   // byte offset (slots < 2^30)
+            const uint32_t o = (i < cnt ? i : 0u) * 4u;   // byte offset inside the bucket
             px[u] = ldg(ix, o);
             py[u] = ldg(iy, o);
             pz[u] = ldg(iz, o);
@@ -551,7 +560,7 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
     MPCD_G float* const ovy = ugp(b.p[dst][4]);
     MPCD_G float* const ovz = ugp(b.p[dst][5]);
     MPCD_G int32_t* const oid = ugp(b.pid[dst]);
-    const MPCD_G int32_t* const iid = ugp(b.pid[src]);
+    const MPCD_G int32_t* const iid = ugp(b.pid[src]) + beg;   // bucket-relative
     const bool has_m = kMass && b.m[src] != nullptr;
     const int lane = threadIdx.x & (kWave - 1);
     const unsigned long long below = (1ull << lane) - 1ull;
@@ -592,7 +601,7 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
                 }
                 const float3 v = make_float3(vx[u], vy[u], vz[u]);
                 diag_check(d, v);
-                if (vacf) vacf_term(b, ldg(iid, (beg + i) * 4u), v, d);
+                if (vacf) vacf_term(b, ldg(iid, i * 4u), v, d);
                 // brick of the next collision cell (a non-finite position
                 // lands far away and takes the clamped slow path below)
                 const int dbx = brick_of(axis_cell_raw(fold(fmaf(v.x, dt, px[u]), b.len[0]), sh1.x, inv_a, b.L[0]), b.bshift[0]);
@@ -621,7 +630,7 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
         for (int u = 0; u < kS; ++u) {
             if (u >= nu) break;
             const uint32_t i = (uint32_t)ch * kChunk + (uint32_t)(u * kT) + threadIdx.x;
-            id[u] = ldg(iid, (beg + (i < cnt ? i : 0u)) * 4u);
+            id[u] = ldg(iid, (i < cnt ? i : 0u) * 4u);
         }
         __syncthreads();
         if (threadIdx.x < 27) {
@@ -663,7 +672,9 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
                 d[5] += 1;
                 continue;
             }
-            const uint32_t o = j * 4u;
+            // byte offset of destination slot j (64-bit for buffers of 2^30 slots or more)
+            typedef typename std::conditional<kWide, unsigned long long, uint32_t>::type Off;
+            const Off o = (Off)j * 4u;
             stg(ox, o, px[u]);
             stg(oy, o, py[u]);
             stg(oz, o, pz[u]);
@@ -1414,24 +1425,29 @@ __global__ __launch_bounds__(kBlock) void k_fill_zero_u32(uint32_t* __restrict__
         if ((grid) > 0) hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, stream, __VA_ARGS__); \
     } while (0)
 
-template <int kT, int kS, bool kMass, bool kAM>
+template <int kT, int kS, bool kMass, bool kAM, bool kWide>
 static void brick_step_run(const Tables& T, hipStream_t s)
 {
     static bool attr = false;
     if (!attr) {   // the largest brick record (kMaxBrickCells or kMaxAmBrickCells cells)
-        (void)hipFuncSetAttribute((const void*)k_brick_step<kT, kS, kMass, kAM>,
+        (void)hipFuncSetAttribute((const void*)k_brick_step<kT, kS, kMass, kAM, kWide>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
         attr = true;
     }
-    hipLaunchKernelGGL((k_brick_step<kT, kS, kMass, kAM>), dim3(T.nbtiles), dim3(kT), T.brick_lds + 16, s,
+    hipLaunchKernelGGL((k_brick_step<kT, kS, kMass, kAM, kWide>), dim3(T.nbtiles), dim3(kT), T.brick_lds + 16, s,
                        T.btiles, T.boxes, T.state, T.dacc);
 }
+// Instances: plain and per-particle masses with 32-bit store offsets (every
+// brick buffer below 2^30 slots), masses with 64-bit offsets, and the
+// angular-momentum rule (64-bit offsets; compute bound).  The masses
+// instances also serve boxes without masses.
 template <int kT, int kS>
 static void brick_step_at(const Tables& T, hipStream_t s)
 {
-    if (T.brick_am) brick_step_run<kT, kS, true, true>(T, s);
-    else if (T.brick_mass) brick_step_run<kT, kS, true, false>(T, s);
-    else brick_step_run<kT, kS, false, false>(T, s);
+    if (T.brick_am) brick_step_run<kT, kS, true, true, true>(T, s);
+    else if (T.brick_wide) brick_step_run<kT, kS, true, false, true>(T, s);
+    else if (T.brick_mass) brick_step_run<kT, kS, true, false, false>(T, s);
+    else brick_step_run<kT, kS, false, false, false>(T, s);
 }
 
 // Launch shapes of the brick step (workgroup size, particles per thread),

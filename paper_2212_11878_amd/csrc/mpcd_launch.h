@@ -25,6 +25,7 @@ struct Tables {
     int brick_shape = 0;           // launch shape of the brick step (brick_shape_for)
     bool brick_mass = false;       // some brick box carries per-particle masses
     bool brick_am = false;         // some brick box uses the angular-momentum rule
+    bool brick_wide = false;       // some brick box has buffers of 2^30 slots or more
     size_t brick_lds = 0;          // LDS bytes of the largest brick record
     int* host_flag = nullptr;      // host-visible: a brick box asks for re-bucketing
 };

@@ -64,3 +64,31 @@ def test_full_size_one_step_sampled_cells():
     E0, E1 = 0.5 * np.sum(v0 * v0), 0.5 * np.sum(v1 * v1)
     assert np.all(np.abs(P1 - P0) < 1e-3 * math.sqrt(n))
     assert abs(E1 - E0) < 1e-6 * E0
+
+
+@pytest.mark.timeout(600)
+def test_brick_buffers_beyond_32bit_offsets():
+    """A box whose brick buffers hold more than 2^30 slots (byte offsets past
+    32 bits: 4.95e8 particles, 1.1e9 slots per buffer) runs on bricks with
+    64-bit store offsets, and after a few steps its exact momentum and energy
+    sums equal those of counting-sort binning bit for bit."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2212_11878_amd import mpcd
+    L, seed = (384, 384, 336), 17
+    n = 10 * L[0] * L[1] * L[2]
+    obs = []
+    for binning in (mpcd.MPCD_BIN_ATOMIC, mpcd.MPCD_BIN_SORT):
+        print("[case] wide offsets, binning %d" % binning, flush=True)
+        with mpcd.Context(binning=binning, brick=(8, 4, 4)) as ctx:
+            slot = ctx.admit(mpcd.make_desc(L, n, dt=0.1, alpha_deg=130.0, seed=seed))
+            ctx.step(5)
+            obs.append(ctx.observe(slot))
+        torch.cuda.empty_cache()
+    a, b = obs
+    print("[case] wide offsets: E %.17g / %.17g, overflow steps %d" % (a["E"], b["E"], a["overflow_steps"]),
+          flush=True)
+    assert a["binning"] == mpcd.MPCD_BIN_ATOMIC and b["binning"] == mpcd.MPCD_BIN_SORT
+    assert a["step"] == b["step"] == 5 and a["status"] == b["status"] == 0
+    assert a["E"] == b["E"] and np.array_equal(a["P"], b["P"])
