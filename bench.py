@@ -28,6 +28,7 @@ WORKLOADS = {
     # name: (L, particles per cell, dt, alpha_deg, seed)
     "srd_256cube_10ppc": ((256, 256, 256), 10, 0.1, 130.0, 3),
     "srd_100cube_10ppc": ((100, 100, 100), 10, 0.1, 130.0, 2),
+    "srd_512cube_10ppc": ((512, 512, 512), 10, 0.1, 130.0, 5),   # the paper's largest system
 }
 DEFAULT_WORKLOAD = "srd_256cube_10ppc"
 ENSEMBLE = "ensemble_512_boxes"      # 512 boxes, edges U{8..48}, densities U[5,20]

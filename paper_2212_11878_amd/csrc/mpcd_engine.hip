@@ -583,11 +583,12 @@ int init_maxwell(mpcd_ctx* c, int32_t s)
 
 // ==========================================================================
 // Autotuner: picks the binning (brick or sort) and the brick shape.  Boxes
-// below 2^21 cells take the shape the density rule gives; for larger ones a
-// class of boxes is timed once on short trial runs of a proxy box of the same
-// density and time step (at most 128^3 cells) in a private context on the
-// same stream.  Results do not depend on the choice (cell sums are exact),
-// only the speed does.
+// below 2^21 cells, and boxes whose buffers reach 2^30 slots, take the shape
+// the density rule gives; for the others a class of boxes is timed once on
+// short trial runs of a proxy box of the same density and time step (at most
+// 128^3 cells) in a private context on the same stream, and a candidate
+// replaces the rule's shape only when clearly faster.  Results do not depend
+// on the choice (cell sums are exact), only the speed does.
 
 static uint64_t shape_class(const mpcd_box_desc* d)
 {
@@ -672,6 +673,9 @@ static int autotune(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* binning, int32
     *binning = MPCD_BIN_ATOMIC;
     for (int k = 0; k < 3; ++k) brick[k] = kRuleShapes[r][k];
     if (c->tuning || d->n_particles == 0 || C < (double)(1 << 21)) return MPCD_OK;
+    // boxes whose buffers need 64-bit offsets run a different instance than
+    // any proxy: the rule decides
+    if (brick_slots(d->n_particles, brick_geometry(d->L, brick).nbrick) >= ((int64_t)1 << 30)) return MPCD_OK;
     const uint64_t key = shape_class(d);
     auto it = c->tuned.find(key);
     if (it != c->tuned.end()) {
@@ -703,8 +707,9 @@ static int autotune(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* binning, int32
     }
     cands.push_back({MPCD_BIN_SORT, {0, 0, 0}, "sort"});
     c->tune_log.clear();
-    // the rule's shape stays unless another candidate is at least 3% faster
-    // (trial timings on the proxy carry a little noise)
+    // the rule's shape stays unless another candidate is at least 10% faster
+    // on the proxy (trial timings carry noise, and the proxy's ranking of
+    // close candidates does not always carry over to the full box)
     double best = 1e300, rule_ms = 1e300;
     std::vector<double> ms_of(cands.size(), 1e300);
     for (size_t i = 0; i < cands.size(); ++i) {
@@ -721,7 +726,7 @@ static int autotune(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* binning, int32
     }
     for (size_t i = 0; i < cands.size(); ++i)
         best = std::min(best, ms_of[i]);
-    if (best * 1.03 >= rule_ms) best = rule_ms;   // keep the rule (already in *binning / brick)
+    if (best * 1.10 >= rule_ms) best = rule_ms;   // keep the rule (already in *binning / brick)
     else
         for (size_t i = 0; i < cands.size(); ++i)
             if (ms_of[i] == best) {
