@@ -128,8 +128,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py measures one GPU: the SRD box runs on a single device here "
-              "(multi-GPU halo decomposition is not part of this build); use --gpus 1",
+        print("bench.py measures one GPU: the library runs each box on one device "
+              "(a multi-GPU halo decomposition is not implemented); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 
