@@ -85,7 +85,9 @@ typedef enum {
 #define MPCD_BIN_ATOMIC 1  /* particles kept in buckets by the brick of cells
                               holding their next collision cell; one pass
                               per brick: LDS-atomic cell sums, rotation, and
-                              the store into the next step's bucket        */
+                              the store into the next step's bucket.  A box
+                              whose two buffers would need 2^32 slots or more
+                              (about 1.9e9 particles) uses MPCD_BIN_SORT   */
 #define MPCD_BIN_SORT 2    /* counting-sort particles by collision cell every
                               step, then reduce each cell's contiguous run   */
 
