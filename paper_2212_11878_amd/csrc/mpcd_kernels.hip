@@ -1325,37 +1325,29 @@ __global__ __launch_bounds__(kBlock) void k_snapshot(const BoxDev* __restrict__ 
     block_diag(d, partials + (size_t)t * kNumDiag);
 }
 
-// Exact sums of one box's per-tile partials (one workgroup; 128-bit
-// integer accumulation, so no order dependence), rounded once to FP64, and
-// the use made of them:
-//   kStatsCentre   adj = (mean velocity, 1): centres the initial velocities
-//   kStatsScale    adj = (0, sqrt(kT/T)): rescales them to temperature kT,
-//                  T = m (sum v^2 - |sum v|^2 / n) / (3 (n - 1))
-//   kStatsSnapshot diag = (sum m v, sum m v^2), status from the range marks;
-//                  with kStatsOrigin also VACF sample 0 = sum v.v0 / n
-// Boxes with fewer than two particles get the identity adjustment.
-__global__ __launch_bounds__(kBlock) void k_box_stats(const long long* __restrict__ partials, int ntiles,
-                                                       const BoxDev* __restrict__ box, BoxState* __restrict__ st,
-                                                       int mode, double kT, double mass)
+// Block sum of one int128 per thread and component; thread 0 gets the totals.
+__device__ __forceinline__ void block_sum128(__int128 (&acc)[kNumDiag], __int128 (&tot)[kNumDiag])
 {
-#pragma clang fp contract(off)
     __shared__ __int128 red[kBlock][kNumDiag];
-    __int128 acc[kNumDiag];
-#pragma unroll
-    for (int j = 0; j < kNumDiag; ++j) acc[j] = 0;
-    for (int t = threadIdx.x; t < ntiles; t += kBlock)
-#pragma unroll
-        for (int j = 0; j < kNumDiag; ++j) acc[j] += partials[(size_t)t * kNumDiag + j];
 #pragma unroll
     for (int j = 0; j < kNumDiag; ++j) red[threadIdx.x][j] = acc[j];
     __syncthreads();
     if (threadIdx.x != 0) return;
-    double d[kNumDiag];
     for (int j = 0; j < kNumDiag; ++j) {
         __int128 v = 0;
         for (int i = 0; i < kBlock; ++i) v += red[i][j];
-        d[j] = (j == 5) ? (double)v : (double)v * 2.3283064365386963e-10;   // 2^-32
+        tot[j] = v;
     }
+}
+
+// What the exact box sums are used for (thread 0; see k_box_stats).
+__device__ void box_stats_finish(const __int128 (&tot)[kNumDiag], const BoxDev* __restrict__ box,
+                                 BoxState* __restrict__ st, int mode, double kT, double mass)
+{
+#pragma clang fp contract(off)
+    double d[kNumDiag];
+    for (int j = 0; j < kNumDiag; ++j)
+        d[j] = (j == 5) ? (double)tot[j] : (double)tot[j] * 2.3283064365386963e-10;   // 2^-32
     const long long n = box->n;
     if (mode == kStatsCentre || mode == kStatsScale) {
         float a[4] = {0.0f, 0.0f, 0.0f, 1.0f};
@@ -1380,6 +1372,61 @@ __global__ __launch_bounds__(kBlock) void k_box_stats(const long long* __restric
         }
     }
     st->status = (d[5] == 0.0 && d[3] < 1e300) ? 0 : -5;
+}
+
+// Exact sums of one box's per-tile partials, rounded once to FP64, and the
+// use made of them:
+//   kStatsCentre   adj = (mean velocity, 1): centres the initial velocities
+//   kStatsScale    adj = (0, sqrt(kT/T)): rescales them to temperature kT,
+//                  T = m (sum v^2 - |sum v|^2 / n) / (3 (n - 1))
+//   kStatsSnapshot diag = (sum m v, sum m v^2), status from the range marks;
+//                  with kStatsOrigin also VACF sample 0 = sum v.v0 / n
+// Boxes with fewer than two particles get the identity adjustment.  128-bit
+// integer accumulation, so the order of the partials does not matter.  One
+// workgroup over all tiles, or (many tiles) k_box_stats_tiles first folds
+// runs of `per` tiles into one 128-bit partial each, kept in the first two
+// tiles' slots of the run, and this kernel reads those (packed = 1).
+__global__ __launch_bounds__(kBlock) void k_box_stats(const long long* __restrict__ partials, int nitems,
+                                                       int per, int packed, const BoxDev* __restrict__ box,
+                                                       BoxState* __restrict__ st, int mode, double kT,
+                                                       double mass)
+{
+    __int128 acc[kNumDiag], tot[kNumDiag];
+#pragma unroll
+    for (int j = 0; j < kNumDiag; ++j) acc[j] = 0;
+    for (int t = threadIdx.x; t < nitems; t += kBlock) {
+        if (packed) {
+            const __int128* q = reinterpret_cast<const __int128*>(partials + (size_t)t * per * kNumDiag);
+#pragma unroll
+            for (int j = 0; j < kNumDiag; ++j) acc[j] += q[j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < kNumDiag; ++j) acc[j] += partials[(size_t)t * kNumDiag + j];
+        }
+    }
+    block_sum128(acc, tot);
+    if (threadIdx.x == 0) box_stats_finish(tot, box, st, mode, kT, mass);
+}
+
+// First level of k_box_stats for boxes with many tiles: workgroup g sums the
+// partials of tiles [g per, (g + 1) per) and stores the 128-bit totals over
+// the first two tiles of its run (per >= 2; each workgroup reads and writes
+// only its own run).
+__global__ __launch_bounds__(kBlock) void k_box_stats_tiles(long long* __restrict__ partials, int ntiles, int per)
+{
+    const int t0 = blockIdx.x * per, t1 = min(ntiles, t0 + per);
+    __int128 acc[kNumDiag], tot[kNumDiag];
+#pragma unroll
+    for (int j = 0; j < kNumDiag; ++j) acc[j] = 0;
+    for (int t = t0 + threadIdx.x; t < t1; t += kBlock)
+#pragma unroll
+        for (int j = 0; j < kNumDiag; ++j) acc[j] += partials[(size_t)t * kNumDiag + j];
+    block_sum128(acc, tot);
+    __syncthreads();   // every thread has read its tiles before thread 0 overwrites the first two
+    if (threadIdx.x == 0) {
+        __int128* q = reinterpret_cast<__int128*>(partials + (size_t)t0 * kNumDiag);
+        for (int j = 0; j < kNumDiag; ++j) q[j] = tot[j];
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill_iota(int32_t* __restrict__ p, int64_t n)
@@ -1532,11 +1579,19 @@ void launch_snapshot(const Tables& T, int32_t box, int ntile, int set_v0, long l
 {
     MPCD_LAUNCH(k_snapshot, ntile, kBlock, s, T.boxes, T.state, box, set_v0, part);
 }
-void launch_box_stats(const Tables& T, int32_t box, int ntile, const long long* part, int mode, double kT,
+void launch_box_stats(const Tables& T, int32_t box, int ntile, long long* part, int mode, double kT,
                       double mass, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_box_stats, dim3(1), dim3(kBlock), 0, s, part, ntile, T.boxes + box, T.state + box, mode,
-                       kT, mass);
+    if (ntile <= 4 * kBlock) {
+        hipLaunchKernelGGL(k_box_stats, dim3(1), dim3(kBlock), 0, s, part, ntile, 1, 0, T.boxes + box,
+                           T.state + box, mode, kT, mass);
+        return;
+    }
+    const int per = (ntile + kBlock - 1) / kBlock;   // >= 5, so each run holds two tiles' slots
+    const int groups = (ntile + per - 1) / per;
+    hipLaunchKernelGGL(k_box_stats_tiles, dim3(groups), dim3(kBlock), 0, s, part, ntile, per);
+    hipLaunchKernelGGL(k_box_stats, dim3(1), dim3(kBlock), 0, s, part, groups, per, 1, T.boxes + box,
+                       T.state + box, mode, kT, mass);
 }
 void launch_mark_holes_box(const Tables& T, int32_t box, int ntile, hipStream_t s)
 {

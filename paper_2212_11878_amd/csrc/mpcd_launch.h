@@ -51,8 +51,8 @@ void launch_init_adjust(const Tables& T, int32_t box, int ntile, long long* part
 void launch_snapshot(const Tables& T, int32_t box, int ntile, int set_v0, long long* part, hipStream_t s);
 // modes of launch_box_stats
 enum { kStatsCentre = 0, kStatsScale = 1, kStatsSnapshot = 2, kStatsOrigin = 4 };
-void launch_box_stats(const Tables& T, int32_t box, int ntile, const long long* part, int mode, double kT,
-                      double mass, hipStream_t s);
+void launch_box_stats(const Tables& T, int32_t box, int ntile, long long* part, int mode, double kT,
+                      double mass, hipStream_t s);   // consumes the partials
 void launch_mark_holes_box(const Tables& T, int32_t box, int ntile, hipStream_t s);
 void launch_fill_iota(int32_t* p, int64_t n, hipStream_t s);
 void launch_fill_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
