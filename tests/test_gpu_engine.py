@@ -345,3 +345,41 @@ def test_admission_and_release_while_steps_are_queued(mp):
     assert sa[2] == ra[2] == 20 and sb[2] == rb[2] == 10
     assert np.array_equal(sa[0], ra[0]) and np.array_equal(sa[1], ra[1])
     assert np.array_equal(sb[0], rb[0]) and np.array_equal(sb[1], rb[1])
+
+
+def test_random_box_mixes_match_sort(mp):
+    """Seeded random batches of boxes (edges 1..40 per dimension, 0..20
+    particles per cell, dt, alpha, per-particle masses, the angular-momentum
+    rule, VACF) stepped together on bricks, with a box released and another
+    admitted mid-run, end bit for bit where counting-sort binning ends."""
+    _say("random-mixes")
+    g = np.random.default_rng(2024)
+    for trial in range(3):
+        boxes = []
+        for _ in range(6):
+            L = tuple(int(x) for x in g.integers(1, 41, 3))
+            n = int(g.integers(0, 21) * L[0] * L[1] * L[2] // 1 + g.integers(0, 5))
+            boxes.append(dict(L=L, n=n, dt=float(g.uniform(0.05, 0.6)), alpha=float(g.uniform(30, 170)),
+                              seed=int(g.integers(1, 1 << 40)), mass=bool(g.integers(0, 2)),
+                              am=bool(g.integers(0, 4) == 0), vacf=bool(g.integers(0, 2))))
+        res = {}
+        for binning in (mp.MPCD_BIN_ATOMIC, mp.MPCD_BIN_SORT):
+            with mp.Context(binning=binning) as ctx:
+                slots = []
+                for bx in boxes[:5]:
+                    d = mp.make_desc(bx["L"], bx["n"], dt=bx["dt"], alpha_deg=bx["alpha"], seed=bx["seed"],
+                                     particle_mass=bx["mass"], conserve_l=bx["am"],
+                                     vacf_stride=3 if bx["vacf"] else 0)
+                    slots.append(ctx.admit(d))
+                ctx.step(4)
+                ctx.release(slots[1])
+                bx = boxes[5]
+                slots[1] = ctx.admit(mp.make_desc(bx["L"], bx["n"], dt=bx["dt"], alpha_deg=bx["alpha"],
+                                                  seed=bx["seed"], particle_mass=bx["mass"], conserve_l=bx["am"]))
+                ctx.step(5)
+                res[binning] = [(ctx.get_state(s), ctx.observe(s)) for s in slots]
+        for i, ((sa, oa), (sb, ob)) in enumerate(zip(res[mp.MPCD_BIN_ATOMIC], res[mp.MPCD_BIN_SORT])):
+            assert oa["status"] == ob["status"] == 0, (trial, i)
+            assert sa[2] == sb[2], (trial, i)
+            assert np.array_equal(sa[0], sb[0]) and np.array_equal(sa[1], sb[1]), (trial, i, boxes[i])
+            assert np.array_equal(oa["vacf"], ob["vacf"]), (trial, i)
