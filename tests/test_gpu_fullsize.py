@@ -92,3 +92,30 @@ def test_brick_buffers_beyond_32bit_offsets():
     assert a["binning"] == mpcd.MPCD_BIN_ATOMIC and b["binning"] == mpcd.MPCD_BIN_SORT
     assert a["step"] == b["step"] == 5 and a["status"] == b["status"] == 0
     assert a["E"] == b["E"] and np.array_equal(a["P"], b["P"])
+
+
+@pytest.mark.timeout(600)
+def test_full_size_drift_over_500_steps():
+    """256^3 cells, 1.68e8 particles, 500 steps in the benchmark's launch
+    configuration: SRD conserves momentum and kinetic energy exactly (the
+    FP64 oracle holds them to its rounding), so the GPU's drift measures its
+    own rounding: relative energy drift below 1e-6 and momentum drift below
+    1e-8 N sqrt(kT/m)."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2212_11878_amd import mpcd
+    import bench
+    L, n, seed = (256, 256, 256), 167772160, 3
+    print("[case] full-size drift", flush=True)
+    with mpcd.Context(**bench.context_options()) as ctx:
+        slot = ctx.admit(mpcd.make_desc(L, n, dt=0.1, alpha_deg=130.0, seed=seed))
+        o0 = ctx.observe(slot)
+        ctx.step(500)
+        o1 = ctx.observe(slot)
+    print("[case] full-size drift: E0 %.15e E500 %.15e rel %.3e, |P0| %.3e |P500 - P0| %.3e" % (
+        o0["E"], o1["E"], (o1["E"] - o0["E"]) / o0["E"], np.abs(o0["P"]).max(),
+        np.abs(o1["P"] - o0["P"]).max()), flush=True)
+    assert o1["step"] == 500 and o1["status"] == 0
+    assert abs(o1["E"] - o0["E"]) / o0["E"] < 1e-6
+    assert np.all(np.abs(o1["P"] - o0["P"]) < 1e-8 * n)
