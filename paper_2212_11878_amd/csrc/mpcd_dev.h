@@ -113,7 +113,7 @@ struct BoxDev {
     int32_t vacf_stride;   // 0 = untracked
     int32_t vacf_cap;
     int32_t binning;       // MPCD_BIN_ATOMIC (bricks) or MPCD_BIN_SORT
-    int32_t conserve_l;    // 1: angular-momentum-conserving rule (SORT binning only)
+    int32_t conserve_l;    // 1: angular-momentum-conserving rule
     int32_t ptile0, ptile1;   // slot tiles [ptile0, ptile1)
     int32_t ctile0, ctile1;   // cell tiles [ctile0, ctile1)
     int32_t btile0, btile1;   // brick tiles [btile0, btile1)

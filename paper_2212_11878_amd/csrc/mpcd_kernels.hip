@@ -8,7 +8,10 @@
 //                         u_c = sum(m v)/sum(m) and axis n_c from Philox,
 //                         v <- u_c + R(n_c, alpha)(v - u_c), then the particle
 //                         goes straight into the bucket of the brick holding
-//                         its next-step collision cell; FP64 diagnostics
+//                         its next-step collision cell; range check and VACF
+//                         terms.  Instances: per-particle masses (kMass), the
+//                         angular-momentum rule (kAM: moment, angular-momentum
+//                         and omega passes), 64-bit store offsets (kWide)
 //     k_box_finish        per box: particles of the overflow bucket (rare),
 //                         reduce diagnostics, VACF sample, k++
 //   Re-bucketing (after admission / set_state, or when a bucket overflowed):
@@ -19,6 +22,10 @@
 //     zero, k_count (streamed collision cell + rank), scan, k_scatter (streams
 //     while moving), flip, k_cell_rotate (one thread per cell over its
 //     contiguous run), k_box_finish
+//
+// Per box, outside the step: k_init_maxwell / k_init_adjust (initial state),
+// k_snapshot (exact momentum and energy on demand), k_box_stats(_tiles)
+// (exact 128-bit reduction of their per-tile partials on the device).
 //
 // Both paths sum the momentum of a cell exactly (64-bit fixed point), so
 // they produce bit-identical velocities whatever the order of the atomics.
