@@ -309,7 +309,8 @@ def bench_served(args):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
            "data": "synthetic",
            "config": {"workload": SERVED, "edges": "U{8..64}", "density": "U[5,20]", "dt": "U[0.05,0.2]",
-                      "alpha_deg": "U[90,150]", "steps": "U{200..2000}", "window_s": args.window},
+                      "alpha_deg": "U[90,150]", "steps": "U{200..2000}", "window_s": args.window,
+                      "rate_hz": head["rate_hz"], "vacf_stride": 10, "chunk_steps": 50},
            "p50_latency_s": head["p50_latency_s"], "p99_latency_s": head["p99_latency_s"],
            "sweep": sweep}
     print(json.dumps(out), flush=True)
