@@ -119,3 +119,30 @@ def test_full_size_drift_over_500_steps():
     assert o1["step"] == 500 and o1["status"] == 0
     assert abs(o1["E"] - o0["E"]) / o0["E"] < 1e-6
     assert np.all(np.abs(o1["P"] - o0["P"]) < 1e-8 * n)
+
+
+@pytest.mark.timeout(600)
+def test_100cube_one_step_every_particle():
+    """100^3 cells, 10^7 particles (the 100^3 workload) in the benchmark's
+    launch configuration: one step from a seeded state against the oracle,
+    for every particle (face-band exemptions as in the small cases)."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2212_11878_amd import mpcd
+    from gpu_util import compare_step
+    import bench
+    L, n, seed, k = (100, 100, 100), 10_000_000, 2, 3
+    print("[case] 100^3 inputs", flush=True)
+    pos, vel = inputs.thermal_state(L, n, seed)
+    with mpcd.Context(**bench.context_options()) as ctx:
+        slot = ctx.admit(mpcd.make_desc(L, n, dt=0.1, alpha_deg=130.0, seed=seed, init="external"))
+        ctx.set_state(slot, (pos, vel), step=k)
+        ctx.step(1)
+        gp, gv, step = ctx.get_state(slot)
+    assert step == k + 1
+    print("[case] 100^3 oracle step", flush=True)
+    box = orc.make_box(L, dt=0.1, alpha_deg=130.0, seed=seed)
+    band, err = compare_step(pos, vel, gp, gv, box, k)
+    print("[case] 100^3: %d particles, %d in face band, max rel err %.2e" % (n, band, err), flush=True)
+    assert band < n // 1000
