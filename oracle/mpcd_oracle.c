@@ -247,48 +247,130 @@ void oracle_cell_local(const oracle_box* b, const double s[3], double x, double 
     }
 }
 
-/* Cyclic Jacobi rotations diagonalise the symmetric matrix: A = V diag(e) V^T. */
+/* Determinant of a 3x3 matrix (row major), cofactor expansion on row 0. */
+static double det3(const double A[9])
+{
+    return A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+           A[2] * (A[3] * A[7] - A[4] * A[6]);
+}
+
+/* Eigenvalues of a symmetric 3x3 matrix in closed form, largest first
+ * (O. K. Smith, "Eigenvalues of a symmetric 3 x 3 matrix", Comm. ACM 4
+ * (1961) 168): with q = tr(A)/3 and p = sqrt(|A - q I|_F^2 / 6), the matrix
+ * B = (A - q I)/p has the eigenvalues 2 cos(phi + 2 pi j/3), j = 0, 1, 2,
+ * where cos(3 phi) = det(B)/2.  A degenerate pair comes out to about
+ * sqrt(machine epsilon) only, but the isolated eigenvalue and the sum of
+ * the pair stay accurate, which is all the pseudo-inverse below uses. */
+static void sym3_eigenvalues(const double A[9], double e[3])
+{
+    const double off = A[1] * A[1] + A[2] * A[2] + A[5] * A[5];
+    if (off == 0.0) {   /* diagonal */
+        double d[3] = { A[0], A[4], A[8] };
+        for (int i = 0; i < 3; ++i)
+            for (int j = i + 1; j < 3; ++j)
+                if (d[j] > d[i]) { double t = d[i]; d[i] = d[j]; d[j] = t; }
+        e[0] = d[0]; e[1] = d[1]; e[2] = d[2];
+        return;
+    }
+    const double q = (A[0] + A[4] + A[8]) / 3.0;
+    const double f = (A[0] - q) * (A[0] - q) + (A[4] - q) * (A[4] - q) + (A[8] - q) * (A[8] - q) + 2.0 * off;
+    const double p = sqrt(f / 6.0);
+    double B[9];
+    for (int i = 0; i < 9; ++i) B[i] = (A[i] - ((i % 4) == 0 ? q : 0.0)) / p;
+    double r = det3(B) / 2.0;
+    if (r < -1.0) r = -1.0;
+    if (r > 1.0) r = 1.0;
+    const double phi = acos(r) / 3.0;
+    const double two_pi_3 = 2.0943951023931954923;   /* 2 pi / 3 */
+    e[0] = q + 2.0 * p * cos(phi);
+    e[2] = q + 2.0 * p * cos(phi + two_pi_3);
+    e[1] = 3.0 * q - e[0] - e[2];
+}
+
+static void cross3(const double a[3], const double b[3], double out[3]);
+
+static double dot3(const double a[3], const double b[3])
+{
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+/* y = A x for a 3x3 row-major A */
+static void matvec3(const double A[9], const double x[3], double y[3])
+{
+    for (int i = 0; i < 3; ++i) y[i] = A[3 * i] * x[0] + A[3 * i + 1] * x[1] + A[3 * i + 2] * x[2];
+}
+
+/* Moore-Penrose pseudo-inverse of a symmetric 3x3 matrix from an analytic
+ * eigen-decomposition (no iteration):
+ *   1. eigenvalues in closed form (sym3_eigenvalues);
+ *   2. the isolated eigenvalue (the one farther from the middle eigenvalue,
+ *      which the closed form gives to full accuracy) and its eigenvector as
+ *      the longest cross product of two rows of A - l I (those rows span the
+ *      plane orthogonal to the eigenvector);
+ *   3. the other two eigenpairs from the 2x2 matrix A takes in that plane,
+ *      diagonalised by the rotation angle t with tan(2t) = 2 b / (a - c);
+ *   4. A^+ = sum of e e^T / l over the eigenpairs (l, e) with |l| > tol
+ *      times the largest |l|; the others count as zero.
+ * (Eigenvalues: O. K. Smith, Comm. ACM 4 (1961) 168; eigenvectors by cross
+ * products as in J. Kopp, Int. J. Mod. Phys. C 19 (2008) 523.) */
 void oracle_sym3_pinv(const double A[9], double tol, double out[9])
 {
-    double a[3][3], v[3][3] = { { 1, 0, 0 }, { 0, 1, 0 }, { 0, 0, 1 } };
+    double e[3];
+    sym3_eigenvalues(A, e);
+    for (int i = 0; i < 9; ++i) out[i] = 0.0;
+    /* eigenvector of the isolated eigenvalue */
+    const int iso = (e[0] - e[1] >= e[1] - e[2]) ? 0 : 2;
+    double r[3][3];
     for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) a[i][j] = A[3 * i + j];
-    for (int sweep = 0; sweep < 50; ++sweep) {
-        double off = fabs(a[0][1]) + fabs(a[0][2]) + fabs(a[1][2]);
-        if (off < 1e-300) break;
-        for (int p = 0; p < 2; ++p)
-            for (int q = p + 1; q < 3; ++q) {
-                if (fabs(a[p][q]) < 1e-300) continue;
-                double theta = (a[q][q] - a[p][p]) / (2.0 * a[p][q]);
-                double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-                double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
-                for (int k = 0; k < 3; ++k) {   /* A <- A J */
-                    double akp = a[k][p], akq = a[k][q];
-                    a[k][p] = c * akp - sn * akq;
-                    a[k][q] = sn * akp + c * akq;
-                }
-                for (int k = 0; k < 3; ++k) {   /* A <- J^T A */
-                    double apk = a[p][k], aqk = a[q][k];
-                    a[p][k] = c * apk - sn * aqk;
-                    a[q][k] = sn * apk + c * aqk;
-                }
-                for (int k = 0; k < 3; ++k) {   /* V <- V J */
-                    double vkp = v[k][p], vkq = v[k][q];
-                    v[k][p] = c * vkp - sn * vkq;
-                    v[k][q] = sn * vkp + c * vkq;
-                }
-            }
-    }
-    double e[3] = { a[0][0], a[1][1], a[2][2] };
-    double emax = fmax(fabs(e[0]), fmax(fabs(e[1]), fabs(e[2])));
-    double inv[3];
-    for (int i = 0; i < 3; ++i) inv[i] = (emax > 0 && fabs(e[i]) > tol * emax) ? 1.0 / e[i] : 0.0;
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-            double acc = 0;
-            for (int k = 0; k < 3; ++k) acc += v[i][k] * inv[k] * v[j][k];
-            out[3 * i + j] = acc;
+        for (int j = 0; j < 3; ++j) r[i][j] = A[3 * i + j] - (i == j ? e[iso] : 0.0);
+    double v[3] = { 1.0, 0.0, 0.0 }, best = 0.0;
+    const int pairs[3][2] = { { 0, 1 }, { 0, 2 }, { 1, 2 } };
+    for (int k = 0; k < 3; ++k) {
+        double c[3];
+        cross3(r[pairs[k][0]], r[pairs[k][1]], c);
+        const double nn = dot3(c, c);
+        if (nn > best) {
+            best = nn;
+            for (int d = 0; d < 3; ++d) v[d] = c[d];
         }
+    }
+    if (best > 0.0) {   /* otherwise A = l I: any unit vector will do */
+        const double inv = 1.0 / sqrt(best);
+        for (int d = 0; d < 3; ++d) v[d] *= inv;
+    }
+    /* orthonormal basis (u, w) of the plane orthogonal to v */
+    int ax = 0;
+    for (int d = 1; d < 3; ++d)
+        if (fabs(v[d]) < fabs(v[ax])) ax = d;
+    double ek[3] = { 0.0, 0.0, 0.0 }, u[3], w[3];
+    ek[ax] = 1.0;
+    cross3(v, ek, u);
+    const double un = 1.0 / sqrt(dot3(u, u));
+    for (int d = 0; d < 3; ++d) u[d] *= un;
+    cross3(v, u, w);
+    /* the 2x2 block [[a, b], [b, c]] of A in the plane, and its eigenpairs */
+    double Au[3], Aw[3], Av[3];
+    matvec3(A, u, Au);
+    matvec3(A, w, Aw);
+    matvec3(A, v, Av);
+    const double a = dot3(u, Au), b = dot3(u, Aw), c = dot3(w, Aw);
+    const double t = 0.5 * atan2(2.0 * b, a - c);
+    const double ct = cos(t), st = sin(t);
+    double vec[3][3], lam[3];
+    for (int d = 0; d < 3; ++d) {
+        vec[0][d] = v[d];
+        vec[1][d] = ct * u[d] + st * w[d];
+        vec[2][d] = -st * u[d] + ct * w[d];
+    }
+    lam[0] = dot3(v, Av);
+    lam[1] = a * ct * ct + 2.0 * b * ct * st + c * st * st;
+    lam[2] = a * st * st - 2.0 * b * ct * st + c * ct * ct;
+    const double lmax = fmax(fabs(lam[0]), fmax(fabs(lam[1]), fabs(lam[2])));
+    for (int k = 0; k < 3; ++k) {
+        if (!(lmax > 0.0) || !(fabs(lam[k]) > tol * lmax)) continue;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) out[3 * i + j] += vec[k][i] * vec[k][j] / lam[k];
+    }
 }
 
 static void cross3(const double a[3], const double b[3], double out[3])

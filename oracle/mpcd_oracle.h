@@ -122,8 +122,11 @@ int oracle_collide_am_given(const oracle_box* b, const double s[3], const double
 void oracle_cell_local(const oracle_box* b, const double s[3], double x, double y, double z,
                        double r[3]);
 
-/* Moore-Penrose pseudo-inverse of a symmetric 3x3 matrix (row major), by
- * Jacobi eigen-decomposition; eigenvalues below tol * (largest) count as 0. */
+/* Moore-Penrose pseudo-inverse of a symmetric 3x3 matrix (row major) from
+ * an analytic eigen-decomposition: eigenvalues in closed form (Smith 1961),
+ * the isolated eigenvalue's eigenvector from a cross product of two rows of
+ * A - l I, the other two from the 2x2 block in the orthogonal plane;
+ * eigenvalues of magnitude at most tol * (largest) count as 0. */
 void oracle_sym3_pinv(const double A[9], double tol, double out[9]);
 
 /* One full step k: streaming, then collision. */

@@ -25,18 +25,82 @@ def test_worked_pair(orc):
 
 
 def test_pseudo_inverse_matches_numpy(orc):
+    """The closed-form pseudo-inverse against numpy's SVD-based pinv (same
+    cut: singular values at most 1e-10 of the largest count as zero) on
+    random symmetric matrices of every rank, positive semi-definite and
+    indefinite, over several scales."""
     g = np.random.default_rng(4)
-    for rank in (3, 2, 1, 0):
+    for trial in range(200):
+        rank = trial % 4
         B = g.standard_normal((3, rank))
+        D = np.diag(g.choice([-1.0, 1.0], rank)) if trial % 8 >= 4 else np.eye(rank)
+        A = (B @ D @ B.T) * 10.0 ** g.uniform(-3, 3)
+        ref = np.linalg.pinv(A, rcond=1e-10, hermitian=True)
+        got = orc.sym3_pinv(A)
+        scale = max(1.0, np.abs(ref).max())
+        assert np.allclose(got, ref, rtol=1e-7, atol=1e-8 * scale), (trial, rank, A, got, ref)
+
+
+def test_pseudo_inverse_closed_forms(orc):
+    """Cases with a known answer: the inertia tensor of a collinear cell,
+    I = q (1 - d d^T), has I^+ = (1 - d d^T)/q (rank 2 with a degenerate kept
+    pair); an isotropic tensor c 1 inverts to 1/c (triple eigenvalue); a
+    diagonal matrix inverts entry by entry; the Moore-Penrose identities
+    A A^+ A = A and A^+ A A^+ = A^+ hold with A A^+ symmetric."""
+    g = np.random.default_rng(5)
+    for _ in range(50):
+        d = g.standard_normal(3)
+        d /= np.linalg.norm(d)
+        q = 10.0 ** g.uniform(-2, 2)
+        P = np.eye(3) - np.outer(d, d)
+        assert np.allclose(orc.sym3_pinv(q * P), P / q, rtol=1e-9, atol=1e-9 / q)
+        c = 10.0 ** g.uniform(-2, 2)
+        assert np.allclose(orc.sym3_pinv(c * np.eye(3)), np.eye(3) / c, rtol=1e-12)
+        e = g.uniform(0.1, 5.0, 3)
+        assert np.allclose(orc.sym3_pinv(np.diag(e)), np.diag(1.0 / e), rtol=1e-12)
+        B = g.standard_normal((3, 3))
         A = B @ B.T
-        assert np.allclose(orc.sym3_pinv(A), np.linalg.pinv(A, rcond=1e-10, hermitian=True), atol=1e-9)
+        Ap = orc.sym3_pinv(A)
+        assert np.allclose(A @ Ap @ A, A, atol=1e-9 * np.abs(A).max())
+        assert np.allclose(Ap @ A @ Ap, Ap, atol=1e-9 * np.abs(Ap).max())
+        assert np.allclose(A @ Ap, (A @ Ap).T, atol=1e-9)
+    assert np.all(orc.sym3_pinv(np.zeros((3, 3))) == 0.0)
+
+
+def test_cell_local_against_brute_force(orc):
+    """Position inside the shifted collision cell at nonzero shifts and
+    a != 1: the test finds the cell by a point-in-shifted-cube search over
+    every periodic image, independently of the oracle, and expects
+    r_d = x_d - s_d - a i_d for the image that contains the particle."""
+    g = np.random.default_rng(12)
+    for trial in range(300):
+        L = tuple(int(v) for v in g.integers(1, 5, 3))
+        a = float(g.choice([1.0, 0.5, 1.75]))
+        box = orc.make_box(L, a=a)
+        s = g.uniform(-a / 2, a / 2, 3)
+        x = g.uniform(0, 1, 3) * np.array(L) * a
+        want = np.zeros(3)
+        for d in range(3):
+            hits = [x[d] + m * L[d] * a - s[d] - a * i
+                    for m in (-1, 0, 1) for i in range(L[d])
+                    if a * i + s[d] <= x[d] + m * L[d] * a < a * (i + 1) + s[d]]
+            assert len(hits) == 1, (trial, d, hits)
+            want[d] = hits[0]
+        got = orc.cell_local(box, s, *x)
+        assert np.all(got >= 0) and np.all(got < a)
+        assert np.allclose(got, want, atol=1e-12), (trial, L, a, s, x, got, want)
 
 
 def _cell_moments(orc, box, s, st, cells):
-    """Per-cell momentum and angular momentum about the cell's centre of mass."""
+    """Per-cell momentum and angular momentum about the cell's centre of mass.
+    Positions inside the shifted cells are computed here with numpy (the
+    shifted coordinate folded into the box, minus the cell's lower corner),
+    not with the oracle's own cell_local."""
     C = orc.n_cells(box)
     m = st.mass if st.mass is not None else np.ones(st.n)
-    r = np.array([orc.cell_local(box, s, *st.pos[:, i]) for i in range(st.n)]).T
+    Lvec = np.array([box.L[d] for d in range(3)], dtype=np.float64) * box.a
+    q = np.mod(st.pos - np.asarray(s)[:, None], Lvec[:, None])
+    r = q - box.a * np.floor(q / box.a)
     M = np.bincount(cells, weights=m, minlength=C)
     rcm = np.stack([np.bincount(cells, weights=m * r[d], minlength=C) for d in range(3)]) / np.maximum(M, 1e-300)
     rp = r - rcm[:, cells]
