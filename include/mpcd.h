@@ -21,17 +21,26 @@
  * which other boxes share the device.
  *
  * Precision: positions and velocities are FP32.  Per-cell momentum sums are
- * exact two's-complement 64-bit fixed point (velocity quantum 2^-32), so the
- * sum is independent of summation order; global momentum / energy
- * diagnostics are accumulated in FP64.
+ * exact two's-complement 64-bit fixed point (velocity quantum 2^-32, each
+ * term truncated toward zero, exact for |v| >= 2^-9), so the sum is
+ * independent of summation order; global momentum / energy diagnostics are
+ * exact fixed-point sums rounded once to FP64.
+ *
+ * Range of the exact sums: every velocity component must stay below 256 in
+ * magnitude (units of a per unit time: choose units with kT/m of order 1, as
+ * the method's reduced units do), every per-particle mass in [2^-8, 2^8],
+ * and every collision cell below 4096 particles.  A step that meets a
+ * velocity or a cell outside this range, or a non-finite velocity, marks the
+ * box MPCD_ESTATE (mpcd_observe); no sum ever wraps silently.
  *
  * General conventions
  *   - Every call returns an mpcd_status; a failing call leaves the context
  *     unchanged (admission is all-or-nothing).
  *   - A context is not thread safe: use it from one host thread.
  *   - Device work is queued on the context's HIP stream; only mpcd_observe,
- *     mpcd_get_state, mpcd_set_state, mpcd_set_mass and mpcd_kernel_stats
- *     synchronise with it, and mpcd_admit when it times autotuner trials
+ *     mpcd_get_state, mpcd_set_state, mpcd_set_mass, mpcd_get_mass,
+ *     mpcd_get_vacf, mpcd_set_vacf and mpcd_kernel_stats synchronise with
+ *     it, and mpcd_admit when it times autotuner trials
  *     (MPCD_BIN_AUTO, a box of at least 2^21 cells of a shape class new to
  *     the context).
  *   - Pointers marked "host" are ordinary host memory owned by the caller
@@ -47,7 +56,7 @@
 extern "C" {
 #endif
 
-#define MPCD_ABI_VERSION 2
+#define MPCD_ABI_VERSION 3
 
 typedef enum {
     MPCD_OK = 0,
@@ -78,7 +87,17 @@ typedef enum {
                                     of such a box hold at most 512 cells.  */
 #define MPCD_PARTICLE_MASS 0x8u  /* every particle carries its own mass
                                     (initially desc.mass; mpcd_set_mass);
-                                    cell velocities are mass weighted       */
+                                    cell velocities are mass weighted
+                                    (Sec. 3.3, Listing 4)                   */
+#define MPCD_UNORDERED 0x20u     /* particle identity is not kept: the steps
+                                    move x and v only (48 instead of 56 bytes
+                                    per particle-step on bricks), and
+                                    mpcd_get_state returns the particles in
+                                    storage order.  The SRD result is the
+                                    same set of particles (the collision
+                                    never depends on storage order).  Not
+                                    with MPCD_TRACK_VACF or
+                                    MPCD_PARTICLE_MASS (EINVAL)             */
 
 /* mpcd_options.binning */
 #define MPCD_BIN_AUTO 0    /* autotuner chooses per box-shape class         */
@@ -94,16 +113,20 @@ typedef enum {
 /* One periodic box (a "slot" once admitted). */
 typedef struct {
     int32_t L[3];          /* cells per edge, each in [1, 4096]; L0*L1*L2 < 2^31 */
-    double a;              /* cell edge, > 0                                 */
+    double a;              /* cell edge, > 0 (at most 16 with MPCD_CONSERVE_L) */
     int64_t n_particles;   /* >= 0                                           */
     double dt;             /* streaming time step, > 0                       */
     double alpha;          /* rotation angle in radians, finite              */
-    double kT;             /* initial temperature (MPCD_INIT_MAXWELL), > 0   */
-    double mass;           /* particle mass, > 0 (all particles, or the
-                              initial one with MPCD_PARTICLE_MASS)          */
+    double kT;             /* initial temperature (MPCD_INIT_MAXWELL), > 0,
+                              with kT / mass <= 256 (thermal speed <= 16)   */
+    double mass;           /* particle mass, > 0 (all particles), or the
+                              initial one with MPCD_PARTICLE_MASS, then in
+                              [2^-8, 2^8]                                   */
     uint64_t seed;         /* Philox key                                     */
     int64_t n_steps;       /* steps this box runs, then idles; 0 = unbounded */
-    uint32_t flags;        /* MPCD_INIT_* | MPCD_TRACK_VACF                   */
+    uint32_t flags;        /* one MPCD_INIT_* | MPCD_TRACK_VACF |
+                              MPCD_PARTICLE_MASS | MPCD_CONSERVE_L |
+                              MPCD_UNORDERED                                 */
     int32_t vacf_stride;   /* steps between VACF samples, >= 1 when tracked  */
     int32_t vacf_capacity; /* max VACF samples kept; 0 = n_steps/stride + 1
                               (1024 if n_steps == 0)                        */
@@ -163,9 +186,12 @@ typedef struct {
 
 typedef struct mpcd_ctx mpcd_ctx;   /* opaque, owned by the library */
 
-/* Create a context on options->device (options may be NULL: defaults).
- * *out receives the handle.  EINVAL for bad options, EDEVICE if the device
- * cannot be used. */
+/* Create a context on options->device (options may be NULL: defaults): the
+ * device tables that let one launch sequence advance many independent boxes
+ * (the paper's small systems under-fill a GPU, Sec. 4; batching them is this
+ * library's answer).  *out receives the handle.  EINVAL for bad options,
+ * EDEVICE if the device cannot be used, ENOMEM if the tables cannot be
+ * allocated. */
 int mpcd_create(const mpcd_options* options, mpcd_ctx** out);
 
 /* Admit one box (Sec. 4 workload: cubic periodic box of unit cells holding
@@ -179,54 +205,89 @@ int mpcd_create(const mpcd_options* options, mpcd_ctx** out);
  * ENOMEM over budget, EBUSY no free slot, EINVAL bad descriptor. */
 int mpcd_admit(mpcd_ctx* ctx, const mpcd_box_desc* desc, int32_t* slot);
 
-/* Queue n_steps SRD steps (Sec. 2) for every live box whose step budget is
- * not exhausted; boxes that reach desc.n_steps stop advancing.  Asynchronous
- * on the context stream. */
+/* Queue n_steps SRD steps (Sec. 2: streaming, random grid shift, cell
+ * velocity, rotation about a random axis) for every live box whose step
+ * budget is not exhausted; boxes that reach desc.n_steps stop advancing.
+ * Asynchronous on the context stream.  EINVAL for n_steps < 0. */
 int mpcd_step(mpcd_ctx* ctx, int32_t n_steps);
 
-/* Synchronise and read a box's diagnostics: momentum, kinetic energy and
- * temperature are summed exactly over the current state by one pass on the
- * device (the steps themselves only check the velocity range and, on
- * sampled steps, accumulate the VACF).  out->vacf stays valid until the next
+/* Synchronise and read a box's diagnostics: total momentum and kinetic
+ * energy, which the collision conserves (Sec. 2), and the temperature, each
+ * summed exactly over the current state by one pass on the device (the
+ * steps themselves only check the range and, on sampled steps, accumulate
+ * the VACF).  out (host) is filled; out->vacf stays valid until the next
  * call on ctx.  Returns MPCD_ESTATE (and fills *out) if a velocity became
- * NaN, Inf or too large for the exact cell sums. */
+ * non-finite or left the range of the exact sums; ENOTFOUND for a slot not
+ * live. */
 int mpcd_observe(mpcd_ctx* ctx, int32_t slot, mpcd_observables* out);
 
-/* Copy a box's state to host memory xyzv (6 N floats, SoA: x[N], y[N], z[N],
- * vx[N], vy[N], vz[N]) in the particle order given at admission / the last
- * mpcd_set_state; *step receives the steps completed.  Synchronises. */
+/* Copy a box's state -- the particle positions and velocities that the
+ * method advances (Sec. 2) -- to host memory xyzv (6 N floats, SoA: x[N],
+ * y[N], z[N], vx[N], vy[N], vz[N]) in the particle order given at admission
+ * / the last mpcd_set_state (MPCD_UNORDERED boxes: storage order); *step
+ * (host, may be NULL) receives the steps completed.  Synchronises.
+ * ESTATE if the device copy is inconsistent; ENOTFOUND for a slot not
+ * live. */
 int mpcd_get_state(mpcd_ctx* ctx, int32_t slot, float* xyzv, int64_t* step);
 
-/* Replace a box's state with host xyzv (layout as mpcd_get_state; positions
- * must lie in [0, L_d a)) and set its step counter; the velocities become
- * the VACF reference v(0).  EINVAL if a position is out of range or not
- * finite (state unchanged).  Synchronises. */
+/* Replace a box's state (Sec. 2: positions and velocities) with host xyzv
+ * (layout as mpcd_get_state; positions must lie in [0, L_d a)) and set its
+ * step counter, which keys the random shift and axes of the following
+ * steps; the velocities become the VACF reference v(0), starting a new
+ * series (mpcd_set_vacf restores an old one).  EINVAL if a position is out
+ * of range or not finite (state unchanged).  Synchronises. */
 int mpcd_set_state(mpcd_ctx* ctx, int32_t slot, const float* xyzv, int64_t step);
 
 /* Per-particle masses (box admitted with MPCD_PARTICLE_MASS): host mass[N],
- * indexed like mpcd_set_state's particles, each finite and > 0.  The cell
+ * indexed like mpcd_set_state's particles, each in [2^-8, 2^8].  The cell
  * velocity becomes sum(m v) / sum(m) (Sec. 3.3, Listing 4) and the
  * diagnostics are mass weighted.  Masses travel with their particles and
  * survive mpcd_set_state.  EINVAL for a box without per-particle masses or a
  * bad value (state unchanged).  Synchronises. */
 int mpcd_set_mass(mpcd_ctx* ctx, int32_t slot, const float* mass);
 
+/* Copy a box's per-particle masses (Sec. 3.3, Listing 4) to host mass[N] in
+ * particle order, as mpcd_set_mass takes them.  EINVAL for a box without
+ * per-particle masses.  Synchronises. */
+int mpcd_get_mass(mpcd_ctx* ctx, int32_t slot, float* mass);
+
+/* Read a box's VACF record (MPCD_TRACK_VACF): host v0 (3 N floats SoA,
+ * particle order; may be NULL) receives the reference velocities, *origin
+ * (may be NULL) the step at which they were taken, samples (host) up to max
+ * of the samples so far (sample j = (1/N) sum_i v_i(origin + j stride) .
+ * v0_i), *len (may be NULL) their number.  With mpcd_get_state,
+ * mpcd_get_mass and mpcd_set_vacf it checkpoints a box so that a resumed run
+ * continues bit for bit.  EINVAL for a box without VACF.  Synchronises. */
+int mpcd_get_vacf(mpcd_ctx* ctx, int32_t slot, float* v0, int64_t* origin, double* samples, int32_t max,
+                  int32_t* len);
+
+/* Restore a VACF record after mpcd_set_state: host v0 (3 N floats SoA,
+ * particle order, finite), the origin step and the len samples taken so
+ * far, which must be exactly those of steps origin, origin + stride, ... up
+ * to the box's current step (EINVAL otherwise, or if len exceeds the
+ * capacity).  Synchronises. */
+int mpcd_set_vacf(mpcd_ctx* ctx, int32_t slot, const float* v0, int64_t origin, const double* samples,
+                  int32_t len);
+
 /* Free a box's device state; the slot number may be reused.  Does not wait
  * for queued steps: the memory goes back through the context's allocator,
  * which must be stream-ordered (work already queued on the context stream
  * may still read it; hipFree, the default, waits for the device).  The box
- * tables are rebuilt before the next step. */
+ * tables are rebuilt before the next step.  ENOTFOUND for a slot not live.
+ * (Slots are this library's unit of batching; the paper has none.) */
 int mpcd_release(mpcd_ctx* ctx, int32_t slot);
 
 /* Turn per-kernel HIP-event timing on (1) or off (0); turning it on clears
- * the statistics. */
+ * the statistics.  While it is on, steps are launched eagerly (not from the
+ * captured graph) with an event pair around every kernel. */
 int mpcd_profile(mpcd_ctx* ctx, int32_t enable);
 
-/* Synchronise and copy up to max entries of per-kernel timing into out;
- * *count receives the number of kernels with statistics. */
+/* Synchronise and copy up to max entries of per-kernel timing into out
+ * (host); *count receives the number of kernels with statistics. */
 int mpcd_kernel_stats(mpcd_ctx* ctx, mpcd_kernel_stat* out, int32_t max, int32_t* count);
 
-/* Release every box and the context itself.  NULL is ignored. */
+/* Release every box and the context itself (waits for the stream).  NULL is
+ * ignored. */
 void mpcd_destroy(mpcd_ctx* ctx);
 
 /* Static description of a status code. */
@@ -234,6 +295,14 @@ const char* mpcd_strerror(int status);
 
 /* MPCD_ABI_VERSION of the loaded library. */
 int mpcd_abi_version(void);
+
+/* Measurement only (not part of the method): copy `bytes` bytes from device
+ * src to device dst with the library's streaming copy kernel (16-byte loads
+ * and stores, `blocks` workgroups of 256 threads, 0 = 4096) on HIP stream
+ * `stream` (NULL = the null stream), asynchronously.  Its rate is the
+ * practical HBM ceiling the SRD kernels are compared with.  EINVAL unless
+ * both pointers are 16-byte aligned and bytes is a multiple of 16. */
+int mpcd_hbm_copy(const void* src, void* dst, size_t bytes, int32_t blocks, void* stream);
 
 #ifdef __cplusplus
 }

@@ -45,7 +45,8 @@ constexpr int kAmWords = 18;
 constexpr int kAmCellBytes = 8 * kAmWords;
 constexpr int kMaxAmBrickCells = 512;
 constexpr int kAccLanes = 64;        // step accumulator lanes per box (spread the atomics)
-constexpr int kNumDiag = 6;          // per-tile exact partials: sum v (3), sum v^2, sum v.v0, range violations
+constexpr int kNumDiag = 7;          // per-tile exact partials: sum v (3), sum v^2 (high words), sum v.v0,
+                                     // range violations, sum v^2 (low words)
 
 // Per-cell accumulator: exact 64-bit fixed-point sums (quantum 2^-32) of the
 // momentum m v and of the mass m (equal masses count as m = 1, so w is
@@ -90,7 +91,8 @@ struct CellAm {
 struct BoxDev {
     float* p[2][6];        // x, y, z, vx, vy, vz
     float4* v0;            // VACF reference velocity of each particle id (x, y, z, unused); null if untracked
-    int32_t* pid[2];       // particle identity (admission order); -1 in holes
+    int32_t* pid[2];       // particle identity (admission order); -1 in holes.  Null for boxes
+                           // without particle ids (MPCD_UNORDERED): their holes carry x = -1
     float* m[2];           // per-particle masses (null: all particles equal)
     uint32_t* cell;        // sort key of each slot
     uint32_t* rank;        // rank of each slot inside its key (sort)
@@ -98,6 +100,7 @@ struct BoxDev {
     CellRot* un;           // brick mode: collision map of the cells of flagged bricks
     CellAm* uam;           // brick mode with conserve_l: the same for the angular-momentum rule
     CellAcc* esc[2];       // brick mode: per cell, sums of overflow particles (step parity)
+    uint32_t* ecnt[2];     // brick mode with per-particle masses: per cell, overflow particles counted
     uint32_t* eflag;       // brick mode: per brick, k+1 when esc[k & 1] holds data for it
     uint32_t* bstart;      // brick mode: bucket starts (nbrick + 2)
     uint32_t* bsize[2];    // brick mode: particles in each bucket of each buffer (nbrick + 1)
@@ -378,21 +381,34 @@ inline int64_t brick_slots(int64_t n, int64_t nbrick)
     return 2 * n + (n >> 3) + 4 * (root + nbrick) + 32 * nbrick;
 }
 
-// Velocity in 64-bit fixed point with quantum 2^-32: floor(v 2^32) as a
-// two's-complement integer (exact for |v| >= 2^-9).  Built from the exact
-// FP64 value v 2^32 as floor(v) (high word) and the remainder in [0, 2^32)
-// (low word).  Valid for |v| < 2^31; the steps flag velocities beyond the
-// smaller limit below.
-__device__ __forceinline__ unsigned long long to_fixed(float v)
+// Velocity in 64-bit fixed point with quantum 2^-32: v 2^32 truncated toward
+// zero, as a two's-complement integer, taken from the bits of v (exact for
+// |v| >= 2^-9; smaller magnitudes lose less than one quantum).  With the
+// 24-bit significand m (implicit bit set) and biased exponent e,
+// |v| 2^32 = m 2^(e - 118) = (m 2^39) >> (157 - e); exponents of 2^-33 and
+// below shift everything out (the shift is capped at 63), and so do
+// |v| >= 2^31, zero, subnormal and non-finite values (the range check of the
+// steps flags every velocity from kVelocityLimit up).
+__host__ __device__ __forceinline__ unsigned long long to_fixed(float v)
 {
-    const double t = (double)v * 4294967296.0;
-    const double hi = fmin(fmax(floor(t * 2.3283064365386963e-10), -2147483648.0), 2147483647.0);
-    const double lo = fma(-hi, 4294967296.0, t);
-    return ((unsigned long long)(unsigned)(int)hi << 32) | (unsigned long long)(unsigned)lo;
+    const uint32_t u = __builtin_bit_cast(uint32_t, v);
+    const uint32_t e = (u >> 23) & 0xffu;
+    const uint32_t sh = (e == 0u || e > 157u) ? 63u : (157u - e < 63u ? 157u - e : 63u);
+    const unsigned long long mag = ((unsigned long long)((u & 0x7fffffu) | 0x800000u) << 39) >> sh;
+    return (u >> 31) ? 0ull - mag : mag;
 }
 
-// Largest speed component the fixed-point cell sums accept.
-constexpr float kVelocityLimit = 1073741824.0f;   // 2^30
+// Range of the exact sums.  Every velocity component stays below
+// kVelocityLimit and every mass in [kMassMin, kMassMax], so a term m v 2^32
+// of a cell sum is below 2^48; a cell of fewer than kMaxCellCount particles
+// then sums to less than 2^60, and a box tile of kPartTile particles too, so
+// no 64-bit sum can wrap.  The steps count a violation (the box's status
+// becomes MPCD_ESTATE) for every velocity beyond the limit and every cell
+// holding kMaxCellCount particles or more.
+constexpr float kVelocityLimit = 256.0f;    // 2^8
+constexpr float kMassMin = 0.00390625f;     // 2^-8
+constexpr float kMassMax = 256.0f;          // 2^8
+constexpr uint32_t kMaxCellCount = 4096u;   // 2^12
 
 // Exact value of a two's-complement 64-bit fixed-point sum as FP64 (hi and
 // lo 32-bit halves are exact; their combination rounds once).
@@ -404,11 +420,29 @@ __device__ __forceinline__ double fixed_to_double(unsigned long long s)
     return hi * 4294967296.0 + lo;
 }
 
-// Mass-weighted mean velocity component of a cell, sum(m v) / sum(m), from
-// the exact fixed-point sums, in FP64 (one division).
-__device__ __forceinline__ double fixed_mean(unsigned long long s, unsigned long long w)
+// Mass-weighted mean velocity of a cell, sum(m v) / sum(m), from the exact
+// fixed-point sums, in FP64: one reciprocal of the mass sum, three products.
+__device__ __forceinline__ void fixed_mean3(unsigned long long sx, unsigned long long sy, unsigned long long sz,
+                                            unsigned long long w, double u[3])
 {
-    return fixed_to_double(s) / fixed_to_double(w);
+#pragma clang fp contract(off)
+    const double inv = 1.0 / fixed_to_double(w);
+    u[0] = fixed_to_double(sx) * inv;
+    u[1] = fixed_to_double(sy) * inv;
+    u[2] = fixed_to_double(sz) * inv;
+}
+
+// Slot i of buffer par holds a particle: holes carry pid -1, or x = -1 in
+// boxes without particle ids (a non-finite position still counts as a
+// particle; valid positions are never negative).
+__device__ __forceinline__ bool slot_live(const BoxDev& b, int par, int64_t i)
+{
+    return b.pid[par] ? b.pid[par][i] >= 0 : !(b.p[par][0][i] < 0.0f);
+}
+__device__ __forceinline__ void mark_hole(const BoxDev& b, int par, int64_t i)
+{
+    if (b.pid[par]) b.pid[par][i] = -1;
+    else b.p[par][0][i] = -1.0f;
 }
 
 // mass of particle i (1 when the box has equal masses)
@@ -516,6 +550,13 @@ __device__ __forceinline__ void sym3_pinv(double a[3][3], double tol, double out
             out[i][j] = v[i][0] * i0 * v[j][0] + v[i][1] * i1 * v[j][1] + v[i][2] * i2 * v[j][2];
 }
 
+// Every component finite and below kVelocityLimit in magnitude (written with
+// comparisons only: a maximum would drop a NaN component).
+__host__ __device__ __forceinline__ bool in_range(float3 v)
+{
+    return fabsf(v.x) < kVelocityLimit && fabsf(v.y) < kVelocityLimit && fabsf(v.z) < kVelocityLimit;
+}
+
 // Exact diagnostics: per-particle terms in 64-bit fixed point (quantum 2^-32)
 // so block and box sums do not depend on summation order.
 __device__ __forceinline__ long long fixed_term(double t)
@@ -525,24 +566,29 @@ __device__ __forceinline__ long long fixed_term(double t)
     return (long long)rint(t);
 }
 
-// momentum m v and twice the kinetic energy m v^2 of one particle
+// Momentum m v and twice the kinetic energy m v^2 of one particle (the energy
+// term, below 2^60, is summed as high and low 32-bit words so that a tile of
+// kPartTile particles cannot wrap), and the range check of its velocity and
+// mass.
 __device__ __forceinline__ void diag_particle(long long (&d)[kNumDiag], float3 v, float m)
 {
     d[0] += fixed_term((double)m * v.x);
     d[1] += fixed_term((double)m * v.y);
     d[2] += fixed_term((double)m * v.z);
-    d[3] += fixed_term((double)m * ((double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z));
-    const float vm = fmaxf(fabsf(v.x), fmaxf(fabsf(v.y), fabsf(v.z)));
-    if (!(vm < kVelocityLimit)) d[5] += 1;
+    const long long e = fixed_term((double)m * ((double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z));
+    d[3] += e >> 32;
+    d[6] += e & 0xffffffffll;
+    if (!in_range(v) || !(m >= kMassMin && m <= kMassMax)) d[5] += 1;
 }
 
-// range check of a new velocity (non-finite or beyond the fixed-point range)
-__device__ __forceinline__ void diag_check(long long (&d)[kNumDiag], float3 v)
+// range check of a new velocity (non-finite or beyond the exact-sum range)
+__host__ __device__ __forceinline__ void diag_check(long long (&d)[kNumDiag], float3 v)
 {
-    const float vm = fmaxf(fabsf(v.x), fmaxf(fabsf(v.y), fabsf(v.z)));
-    if (!(vm < kVelocityLimit)) d[5] += 1;
+    if (!in_range(v)) d[5] += 1;
 }
 
+// VACF term v . v0, below 3 2^48 in fixed point, so a workgroup's sum of at
+// most 4096 terms stays below 2^62
 __device__ __forceinline__ void diag_vacf(long long (&d)[kNumDiag], float3 v, float w0x, float w0y,
                                           float w0z)
 {
@@ -625,8 +671,10 @@ __device__ __forceinline__ void am_cell(const BoxDev& b, long long k, uint32_t c
 }
 
 // One particle's exact second-pass terms: the change of its angular momentum
-// about rc under the plain rotation, m r' x (R w - w), w = v - u.
-__device__ __forceinline__ void am_dl(double mj, float vx, float vy, float vz, const double r[3],
+// about rc under the plain rotation, m r' x (R w - w), w = v - u.  Returns
+// false when a term reaches 2^48 in fixed point (a cell of fewer than
+// kMaxCellCount such terms cannot wrap its 64-bit sum).
+__device__ __forceinline__ bool am_dl(double mj, float vx, float vy, float vz, const double r[3],
                                       const double u[3], const double rc[3], const double n[3], double ca,
                                       double sa, long long t[3])
 {
@@ -641,6 +689,8 @@ __device__ __forceinline__ void am_dl(double mj, float vx, float vy, float vz, c
     t[0] = fixed_term(mj * (rp[1] * dw[2] - rp[2] * dw[1]));
     t[1] = fixed_term(mj * (rp[2] * dw[0] - rp[0] * dw[2]));
     t[2] = fixed_term(mj * (rp[0] * dw[1] - rp[1] * dw[0]));
+    constexpr long long kLim = 1ll << 48;
+    return t[0] > -kLim && t[0] < kLim && t[1] > -kLim && t[1] < kLim && t[2] > -kLim && t[2] < kLim;
 }
 
 // omega = -I^+ dL with I = tr(Q) 1 - Q (pseudo-inverse: rank-deficient cells,

@@ -229,13 +229,13 @@ int upload(mpcd_ctx* c, void* dst, const void* src, size_t bytes)
 // Layout of one box's device allocation.
 struct Layout {
     size_t off_p[2][6], off_v0, off_pid[2], off_m[2], off_cell, off_rank, off_cstart, off_un, off_uam, off_esc[2],
-        off_eflag, off_bstart, off_bsize[2], off_vacf, off_part, total;
+        off_ecnt[2], off_eflag, off_bstart, off_bsize[2], off_vacf, off_part, total;
 };
 
 int ntile_of(int64_t nslot) { return (int)std::max<int64_t>(1, (nslot + kPartTile - 1) / kPartTile); }
 
 Layout box_layout(int64_t n, int64_t nslot, int64_t ncell, bool vacf, int vacf_cap, bool brick, const BrickGeom& g,
-                  bool masses, bool am)
+                  bool masses, bool am, bool ids)
 {
     Layout L{};
     size_t o = 0;
@@ -244,7 +244,10 @@ Layout box_layout(int64_t n, int64_t nslot, int64_t ncell, bool vacf, int vacf_c
         for (int d = 0; d < 6; ++d) { L.off_p[b][d] = o; o += pf; }
     L.off_v0 = o;
     if (vacf) o += align256((size_t)n * 16);
-    for (int b = 0; b < 2; ++b) { L.off_pid[b] = o; o += pf; }
+    for (int b = 0; b < 2; ++b) {
+        L.off_pid[b] = o;
+        if (ids) o += pf;
+    }
     for (int b = 0; b < 2; ++b) {
         L.off_m[b] = o;
         if (masses) o += pf;
@@ -256,6 +259,7 @@ Layout box_layout(int64_t n, int64_t nslot, int64_t ncell, bool vacf, int vacf_c
     L.off_un = o; o += brick ? align256((size_t)ncell * sizeof(CellRot)) : 0;
     L.off_uam = o; o += brick && am ? align256((size_t)ncell * sizeof(CellAm)) : 0;
     for (int b = 0; b < 2; ++b) { L.off_esc[b] = o; o += brick ? align256((size_t)ncell * sizeof(CellAcc)) : 0; }
+    for (int b = 0; b < 2; ++b) { L.off_ecnt[b] = o; o += brick && masses ? align256((size_t)ncell * 4) : 0; }
     L.off_eflag = o; o += align256(2 * nbk * 4);
     L.off_bstart = o; o += align256((nbk + 2) * 4);
     for (int b = 0; b < 2; ++b) { L.off_bsize[b] = o; o += align256((nbk + 1) * 4); }
@@ -281,11 +285,21 @@ int validate_desc(const mpcd_box_desc* d)
     if (!(d->mass > 0.0) || !isfinite(d->mass)) return MPCD_EINVAL;
     if (d->n_steps < 0) return MPCD_EINVAL;
     if (d->flags & ~(MPCD_INIT_MAXWELL | MPCD_INIT_EXTERNAL | MPCD_TRACK_VACF | MPCD_PARTICLE_MASS |
-                     MPCD_CONSERVE_L))
+                     MPCD_CONSERVE_L | MPCD_UNORDERED))
         return MPCD_EINVAL;
+    // boxes without particle ids can neither follow a particle's VACF nor
+    // take masses indexed by particle
+    if ((d->flags & MPCD_UNORDERED) && (d->flags & (MPCD_TRACK_VACF | MPCD_PARTICLE_MASS))) return MPCD_EINVAL;
+    // range of the exact fixed-point sums (velocity limit kVelocityLimit,
+    // masses in [kMassMin, kMassMax], cells of the angular-momentum rule at
+    // most 16 long so that its position moments stay in range)
+    if ((d->flags & MPCD_PARTICLE_MASS) && !(d->mass >= kMassMin && d->mass <= kMassMax)) return MPCD_EINVAL;
+    if ((d->flags & MPCD_CONSERVE_L) && !(d->a <= 16.0)) return MPCD_EINVAL;
     const uint32_t init = d->flags & (MPCD_INIT_MAXWELL | MPCD_INIT_EXTERNAL);
     if (init != MPCD_INIT_MAXWELL && init != MPCD_INIT_EXTERNAL) return MPCD_EINVAL;
     if ((d->flags & MPCD_INIT_MAXWELL) && (!(d->kT > 0.0) || !isfinite(d->kT))) return MPCD_EINVAL;
+    // Maxwellian draws stay far inside the velocity limit: thermal speed <= 16
+    if ((d->flags & MPCD_INIT_MAXWELL) && !(d->kT / d->mass <= 256.0)) return MPCD_EINVAL;
     if ((d->flags & MPCD_TRACK_VACF) && d->vacf_stride < 1) return MPCD_EINVAL;
     if (d->vacf_capacity < 0) return MPCD_EINVAL;
     for (int i = 0; i < 3; ++i)
@@ -528,6 +542,8 @@ int set_compact_layout(mpcd_ctx* c, int32_t s, int parity)
     if (rc) return rc;
     HIPCHK(hipMemsetAsync(b.bsize[parity ^ 1], 0, (nbk + 1) * 4, c->stream));
     for (int k = 0; k < 2; ++k) HIPCHK(hipMemsetAsync(b.esc[k], 0, (size_t)b.ncell * sizeof(CellAcc), c->stream));
+    for (int k = 0; k < 2; ++k)
+        if (b.ecnt[k]) HIPCHK(hipMemsetAsync(b.ecnt[k], 0, (size_t)b.ncell * 4, c->stream));
     HIPCHK(hipMemsetAsync(b.eflag, 0, 2 * nbk * 4, c->stream));
     return MPCD_OK;
 }
@@ -599,7 +615,8 @@ static uint64_t shape_class(const mpcd_box_desc* d)
     const double vth = d->kT > 0 ? std::sqrt(d->kT / d->mass) : 1.0;
     const int step = (int)std::min(15.0, std::floor(8.0 * d->dt * vth / d->a));   // free path / cell
     const uint64_t rule = (d->flags & MPCD_CONSERVE_L) ? 1 : 0;   // angular-momentum rule
-    return (rule << 32) | ((uint64_t)lc << 16) | ((uint64_t)rho << 4) | (uint64_t)step;
+    const uint64_t ids = (d->flags & MPCD_UNORDERED) ? 0 : 1;     // particle ids travel
+    return (ids << 33) | (rule << 32) | ((uint64_t)lc << 16) | ((uint64_t)rho << 4) | (uint64_t)step;
 }
 
 static int trial_ms(mpcd_ctx* parent, const mpcd_box_desc* proxy, int32_t binning, const int32_t brick[3],
@@ -698,8 +715,8 @@ static int autotune(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* binning, int32
         cells *= p.L[k];
     }
     p.n_particles = std::max<int64_t>(1, std::llround(density * cells));
-    p.flags = MPCD_INIT_MAXWELL | (d->flags & (MPCD_CONSERVE_L | MPCD_PARTICLE_MASS));
-    if (!(p.kT > 0.0)) p.kT = 1.0;
+    p.flags = MPCD_INIT_MAXWELL | (d->flags & (MPCD_CONSERVE_L | MPCD_PARTICLE_MASS | MPCD_UNORDERED));
+    if (!(p.kT > 0.0) || !(p.kT / p.mass <= 256.0)) p.kT = p.mass;   // thermal speed 1
     p.n_steps = 0;
     p.vacf_stride = 0;
     p.vacf_capacity = 0;
@@ -860,7 +877,8 @@ int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
     const bool brick = binning == MPCD_BIN_ATOMIC;
     const int64_t nslot = brick ? brick_slots(d->n_particles, g.nbrick) : d->n_particles;
     const bool masses = (d->flags & MPCD_PARTICLE_MASS) != 0;
-    const Layout L = box_layout(d->n_particles, nslot, ncell, vacf, cap, brick, g, masses, am);
+    const bool ids = (d->flags & MPCD_UNORDERED) == 0;
+    const Layout L = box_layout(d->n_particles, nslot, ncell, vacf, cap, brick, g, masses, am, ids);
     if (c->budget > 0 && c->used + (int64_t)L.total > c->budget) return MPCD_ENOMEM;
     HIPCHK(hipSetDevice(c->device));
     void* mem = ctx_alloc(c, L.total);
@@ -877,7 +895,7 @@ int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
     char* m = (char*)mem;
     for (int p = 0; p < 2; ++p) {
         for (int k = 0; k < 6; ++k) b.p[p][k] = (float*)(m + L.off_p[p][k]);
-        b.pid[p] = (int32_t*)(m + L.off_pid[p]);
+        b.pid[p] = ids ? (int32_t*)(m + L.off_pid[p]) : nullptr;
         b.m[p] = masses ? (float*)(m + L.off_m[p]) : nullptr;
     }
     b.v0 = vacf ? (float4*)(m + L.off_v0) : nullptr;
@@ -888,6 +906,7 @@ int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
     b.uam = brick && am ? (CellAm*)(m + L.off_uam) : nullptr;
     for (int p = 0; p < 2; ++p) {
         b.esc[p] = brick ? (CellAcc*)(m + L.off_esc[p]) : nullptr;
+        b.ecnt[p] = brick && masses ? (uint32_t*)(m + L.off_ecnt[p]) : nullptr;
         b.bsize[p] = brick ? (uint32_t*)(m + L.off_bsize[p]) : nullptr;
     }
     b.eflag = brick ? (uint32_t*)(m + L.off_eflag) : nullptr;
@@ -954,7 +973,7 @@ int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
         for (int k = 0; k < 6; ++k)
             if (hipMemsetAsync(S.dev.p[0][k], 0, (size_t)S.dev.nslot * 4, c->stream) != hipSuccess)
                 return undo(MPCD_EDEVICE);
-        launch_fill_iota(S.dev.pid[0], S.dev.n, c->stream);
+        if (S.dev.pid[0]) launch_fill_iota(S.dev.pid[0], S.dev.n, c->stream);
     }
     if (rc) return undo(rc);
     rc = take_snapshot(c, s);
@@ -1057,7 +1076,7 @@ int mpcd_get_state(mpcd_ctx* c, int32_t slot, float* xyzv, int64_t* step)
     HIPCHK(hipStreamSynchronize(c->stream));
     c->stage.resize((size_t)ns);
     c->stage_pid.resize((size_t)ns);
-    if (n > 0) {
+    if (n > 0 && sl->dev.pid[st.parity]) {   // particle-id order
         HIPCHK(hipMemcpy(c->stage_pid.data(), sl->dev.pid[st.parity], (size_t)ns * 4, hipMemcpyDeviceToHost));
         int64_t seen = 0;
         for (int64_t i = 0; i < ns; ++i) {
@@ -1073,6 +1092,19 @@ int mpcd_get_state(mpcd_ctx* c, int32_t slot, float* xyzv, int64_t* step)
                 const int32_t id = c->stage_pid[i];
                 if (id >= 0) dst[id] = c->stage[i];
             }
+        }
+    } else if (n > 0) {   // no ids: storage order, holes (x = -1) left out
+        std::vector<int64_t> live;
+        live.reserve((size_t)n);
+        HIPCHK(hipMemcpy(c->stage.data(), sl->dev.p[st.parity][0], (size_t)ns * 4, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < ns; ++i)
+            if (!(c->stage[i] < 0.0f)) live.push_back(i);
+        if ((int64_t)live.size() != n) return MPCD_ESTATE;
+        for (int d = 0; d < 6; ++d) {
+            if (d > 0)
+                HIPCHK(hipMemcpy(c->stage.data(), sl->dev.p[st.parity][d], (size_t)ns * 4, hipMemcpyDeviceToHost));
+            float* dst = xyzv + (size_t)d * n;
+            for (int64_t j = 0; j < n; ++j) dst[j] = c->stage[live[j]];
         }
     }
     if (step) *step = st.k;
@@ -1108,7 +1140,7 @@ int mpcd_set_state(mpcd_ctx* c, int32_t slot, const float* xyzv, int64_t step)
     if (n > 0) {
         for (int d = 0; d < 6; ++d)
             HIPCHK(hipMemcpy(sl->dev.p[0][d], xyzv + (size_t)d * n, (size_t)n * 4, hipMemcpyHostToDevice));
-        launch_fill_iota(sl->dev.pid[0], n, c->stream);
+        if (sl->dev.pid[0]) launch_fill_iota(sl->dev.pid[0], n, c->stream);
         HIPCHK(hipGetLastError());
     }
     {
@@ -1132,7 +1164,7 @@ int mpcd_set_mass(mpcd_ctx* c, int32_t slot, const float* mass)
     const int64_t n = sl->dev.n;
     double total = 0.0;
     for (int64_t i = 0; i < n; ++i) {
-        if (!(mass[i] > 0.0f) || !isfinite(mass[i])) return MPCD_EINVAL;
+        if (!(mass[i] >= kMassMin && mass[i] <= kMassMax)) return MPCD_EINVAL;
         total += mass[i];
     }
     HIPCHK(hipSetDevice(c->device));
@@ -1151,6 +1183,102 @@ int mpcd_set_mass(mpcd_ctx* c, int32_t slot, const float* mass)
     int rc = take_snapshot(c, slot, false);
     if (rc) return rc;
     HIPCHK(hipStreamSynchronize(c->stream));
+    return MPCD_OK;
+}
+
+int mpcd_get_mass(mpcd_ctx* c, int32_t slot, float* mass)
+{
+    Slot* sl = live_slot(c, slot);
+    if (!c || !mass) return MPCD_EINVAL;
+    if (!sl) return MPCD_ENOTFOUND;
+    if (!sl->dev.m[0]) return MPCD_EINVAL;
+    HIPCHK(hipSetDevice(c->device));
+    BoxState st;
+    HIPCHK(hipMemcpyAsync(&st, &c->T.state[slot], sizeof(BoxState), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const int64_t n = sl->dev.n, ns = sl->dev.nslot;
+    if (n == 0) return MPCD_OK;
+    mark_holes(c, slot);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->stage.resize((size_t)ns);
+    c->stage_pid.resize((size_t)ns);
+    HIPCHK(hipMemcpy(c->stage_pid.data(), sl->dev.pid[st.parity], (size_t)ns * 4, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(c->stage.data(), sl->dev.m[st.parity], (size_t)ns * 4, hipMemcpyDeviceToHost));
+    int64_t seen = 0;
+    for (int64_t i = 0; i < ns; ++i) {
+        const int32_t id = c->stage_pid[i];
+        if (id >= n) return MPCD_ESTATE;
+        if (id >= 0) {
+            mass[id] = c->stage[i];
+            ++seen;
+        }
+    }
+    return seen == n ? MPCD_OK : MPCD_ESTATE;
+}
+
+int mpcd_get_vacf(mpcd_ctx* c, int32_t slot, float* v0, int64_t* origin, double* samples, int32_t max,
+                  int32_t* len)
+{
+    Slot* sl = live_slot(c, slot);
+    if (!c || max < 0 || (max > 0 && !samples)) return MPCD_EINVAL;
+    if (!sl) return MPCD_ENOTFOUND;
+    if (sl->dev.vacf_stride <= 0) return MPCD_EINVAL;
+    HIPCHK(hipSetDevice(c->device));
+    BoxState st;
+    HIPCHK(hipMemcpyAsync(&st, &c->T.state[slot], sizeof(BoxState), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const int64_t n = sl->dev.n;
+    if (v0 && n > 0) {
+        std::vector<float> rec((size_t)n * 4);
+        HIPCHK(hipMemcpy(rec.data(), sl->dev.v0, (size_t)n * 16, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < n; ++i)
+            for (int d = 0; d < 3; ++d) v0[(size_t)d * n + i] = rec[(size_t)i * 4 + d];
+    }
+    const int32_t k = std::min<int32_t>(std::max(st.vacf_len, 0), max);
+    if (k > 0) HIPCHK(hipMemcpy(samples, sl->dev.vacf, (size_t)k * 8, hipMemcpyDeviceToHost));
+    if (origin) *origin = st.vacf_origin;
+    if (len) *len = st.vacf_len;
+    return MPCD_OK;
+}
+
+int mpcd_set_vacf(mpcd_ctx* c, int32_t slot, const float* v0, int64_t origin, const double* samples, int32_t len)
+{
+    Slot* sl = live_slot(c, slot);
+    if (!c || !v0 || !samples) return MPCD_EINVAL;
+    if (!sl) return MPCD_ENOTFOUND;
+    const BoxDev& b = sl->dev;
+    if (b.vacf_stride <= 0 || len < 1 || len > b.vacf_cap || origin < 0) return MPCD_EINVAL;
+    HIPCHK(hipSetDevice(c->device));
+    BoxState st;
+    HIPCHK(hipMemcpyAsync(&st, &c->T.state[slot], sizeof(BoxState), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    // sample j belongs to step origin + j stride: a series that reaches the
+    // box's current step holds exactly this many samples
+    if (origin > st.k || (st.k - origin) / b.vacf_stride + 1 != len) return MPCD_EINVAL;
+    const int64_t n = b.n;
+    for (int64_t i = 0; i < 3 * n; ++i)
+        if (!isfinite(v0[i])) return MPCD_EINVAL;
+    for (int32_t j = 0; j < len; ++j)
+        if (!isfinite(samples[j])) return MPCD_EINVAL;
+    if (n > 0) {
+        std::vector<float> rec((size_t)n * 4, 0.0f);
+        for (int64_t i = 0; i < n; ++i)
+            for (int d = 0; d < 3; ++d) rec[(size_t)i * 4 + d] = v0[(size_t)d * n + i];
+        HIPCHK(hipMemcpy(b.v0, rec.data(), (size_t)n * 16, hipMemcpyHostToDevice));
+    }
+    HIPCHK(hipMemcpy(b.vacf, samples, (size_t)len * 8, hipMemcpyHostToDevice));
+    st.vacf_origin = origin;
+    st.vacf_len = len;
+    HIPCHK(hipMemcpy(&c->T.state[slot], &st, sizeof(BoxState), hipMemcpyHostToDevice));
+    return MPCD_OK;
+}
+
+int mpcd_hbm_copy(const void* src, void* dst, size_t bytes, int32_t blocks, void* stream)
+{
+    if (!src || !dst || blocks < 0 || (bytes & 15) || (((uintptr_t)src | (uintptr_t)dst) & 15)) return MPCD_EINVAL;
+    if (bytes == 0) return MPCD_OK;
+    launch_hbm_copy(src, dst, (int64_t)(bytes / 16), blocks > 0 ? blocks : 4096, (hipStream_t)stream);
+    HIPCHK(hipGetLastError());
     return MPCD_OK;
 }
 

@@ -238,6 +238,7 @@ __device__ __forceinline__ bool place_overflow(const BoxDev& b, int dst, long lo
     gatomic_add(&e->sy, to_fixed(m * v.y));
     gatomic_add(&e->sz, to_fixed(m * v.z));
     gatomic_add(&e->w, to_fixed(m));
+    if (b.ecnt[0]) gatomic_add(gp(b.ecnt[(k + 1) & 1]) + c, 1u);   // masses: w is no count
     const int3 br = brick_of_cell(b, nc);
     gp(b.eflag)[(size_t)((k + 1) & 1) * b.nbrick + br.x + b.nb[0] * (br.y + b.nb[1] * br.z)] = (uint32_t)(k + 2);
     return true;
@@ -254,7 +255,7 @@ __device__ __forceinline__ void put_particle(const BoxDev& b, int dst, uint32_t 
     stg(gp(b.p[dst][3]), o, v.x);
     stg(gp(b.p[dst][4]), o, v.y);
     stg(gp(b.p[dst][5]), o, v.z);
-    stg(gp(b.pid[dst]), o, id);
+    if (b.pid[dst]) stg(gp(b.pid[dst]), o, id);
     if (has_m) stg(gp(b.m[dst]), o, m);
 }
 
@@ -343,7 +344,7 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
 
     float px[kS], py[kS], pz[kS], vx[kS], vy[kS], vz[kS], pm[kS];
     uint32_t meta[kS];   // cell in the brick after loading; destination group << 24 | rank later
-    long long d[kNumDiag] = {0, 0, 0, 0, 0, 0};
+    long long d[kNumDiag] = {};
     // load and stream chunk ch; meta <- cell inside the brick, kNone past the
     // end of the bucket or for a particle in the wrong bucket (never happens:
     // both sides use the same arithmetic; flagged if it does)
@@ -401,6 +402,7 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
                 unsigned long long* const ra = acc + (size_t)c * kAmWords;
 #pragma unroll
                 for (int q = 0; q < kAmMoments; ++q) atomicAdd(&ra[q], (unsigned long long)tm[q]);
+                atomicAdd(&ra[kAmMoments], 1ull);   // particle count (free until pass 2a)
                 continue;
             }
             unsigned long long* const r = acc + (size_t)c * kAccWords;
@@ -410,6 +412,7 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
                 atomicAdd(&r[1], to_fixed(mi * vy[u]));
                 atomicAdd(&r[2], to_fixed(mi * vz[u]));
                 atomicAdd(&r[3], to_fixed(mi));
+                atomicAdd(reinterpret_cast<uint32_t*>(&r[4]), 1u);   // particle count
             } else {   // equal masses: r[3] counts particles
                 atomicAdd(&r[0], to_fixed(vx[u]));
                 atomicAdd(&r[1], to_fixed(vy[u]));
@@ -449,10 +452,11 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
                 long long tm[kAmMoments];
                 am_moments(mj, ux, uy, uz, rl, tm);
                 for (int e = 0; e < kAmMoments; ++e) atomicAdd(&ra[e], (unsigned long long)tm[e]);
+                atomicAdd(&ra[kAmMoments], 1ull);
             } else {
                 const double* const rec = reinterpret_cast<const double*>(ra);
                 long long tl3[3];
-                am_dl(mj, ux, uy, uz, rl, rec, rec + 3, rec + 6, b.ca, b.sa, tl3);
+                if (!am_dl(mj, ux, uy, uz, rl, rec, rec + 3, rec + 6, b.ca, b.sa, tl3)) d[5] += 1;
                 for (int e = 0; e < 3; ++e) atomicAdd(&ra[15 + e], (unsigned long long)tl3[e]);
             }
         }
@@ -470,6 +474,11 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
                     r[1] += e.sy;
                     r[2] += e.sz;
                     r[3] += kMass ? e.w : (e.w >> 32);   // escape weights are 2^32 m
+                    if (kMass && has_mass) {   // and their count
+                        MPCD_G uint32_t* const ec = gp(b.ecnt[k & 1]) + gc;
+                        *reinterpret_cast<uint32_t*>(&r[4]) += *ec;
+                        *ec = 0u;
+                    }
                 }
                 CellAcc z = {0ull, 0ull, 0ull, 0ull};
                 store_acc(esc + gc, z);
@@ -486,6 +495,7 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
             unsigned long long* const ra = acc + (size_t)c * kAmWords;
             const long long* const sm = reinterpret_cast<const long long*>(ra);
             if (sm[0] == 0) continue;
+            if (ra[kAmMoments] >= kMaxCellCount) d[5] += 1;   // the cell's sums may have wrapped
             const int lx = c % ex, ly = (c / ex) % ey, lz = c / (ex * ey);
             const uint32_t gc = (uint32_t)(lox + lx) + L0 * (uint32_t)(loy + ly) + L01 * (uint32_t)(loz + lz);
             double uc[3], rc[3], Q[6], n[3];
@@ -511,7 +521,7 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
                 double rl[3];
                 long long tl3[3];
                 am_local(b.a, px[u], py[u], pz[u], sh, rl);
-                am_dl((double)pm[u], vx[u], vy[u], vz[u], rl, rec, rec + 3, rec + 6, b.ca, b.sa, tl3);
+                if (!am_dl((double)pm[u], vx[u], vy[u], vz[u], rl, rec, rec + 3, rec + 6, b.ca, b.sa, tl3)) d[5] += 1;
                 for (int e = 0; e < 3; ++e) atomicAdd(&ra[15 + e], (unsigned long long)tl3[e]);
             }
         }
@@ -545,10 +555,13 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
             const unsigned long long* const r = acc + (size_t)c * kAccWords;
             const unsigned long long w = kMass ? r[3] : ((r[3] & 0xffffffffull) << 32);
             if (w == 0) continue;
+            const uint32_t count = kMass ? (uint32_t)r[4] : (uint32_t)r[3];
+            if (count >= kMaxCellCount) d[5] += 1;   // the cell's sums may have wrapped
             const int lx = c % ex, ly = (c / ex) % ey, lz = c / (ex * ey);
             const uint32_t gc = (uint32_t)(lox + lx) + L0 * (uint32_t)(loy + ly) + L01 * (uint32_t)(loz + lz);
-            const CellRot cr = cell_rotation(fixed_mean(r[0], w), fixed_mean(r[1], w), fixed_mean(r[2], w),
-                                             cell_axis(b, k, gc), b.ca, b.sa);
+            double uc[3];
+            fixed_mean3(r[0], r[1], r[2], w, uc);
+            const CellRot cr = cell_rotation(uc[0], uc[1], uc[2], cell_axis(b, k, gc), b.ca, b.sa);
             float4* const q = reinterpret_cast<float4*>(fu + (size_t)c * kUnWords);
             q[0] = make_float4(cr.m[0], cr.m[1], cr.m[2], cr.m[3]);
             q[1] = make_float4(cr.m[4], cr.m[5], cr.m[6], cr.m[7]);
@@ -566,8 +579,9 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
     MPCD_G float* const ovx = ugp(b.p[dst][3]);
     MPCD_G float* const ovy = ugp(b.p[dst][4]);
     MPCD_G float* const ovz = ugp(b.p[dst][5]);
-    MPCD_G int32_t* const oid = ugp(b.pid[dst]);
-    const MPCD_G int32_t* const iid = ugp(b.pid[src]) + beg;   // bucket-relative
+    const bool has_id = b.pid[src] != nullptr;   // uniform
+    MPCD_G int32_t* const oid = has_id ? ugp(b.pid[dst]) : nullptr;
+    const MPCD_G int32_t* const iid = has_id ? ugp(b.pid[src]) + beg : nullptr;   // bucket-relative
     const bool has_m = kMass && b.m[src] != nullptr;
     const int lane = threadIdx.x & (kWave - 1);
     const unsigned long long below = (1ull << lane) - 1ull;
@@ -635,7 +649,7 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
         int32_t id[kS];
 #pragma unroll
         for (int u = 0; u < kS; ++u) {
-            if (u >= nu) break;
+            if (u >= nu || !has_id) break;
             const uint32_t i = (uint32_t)ch * kChunk + (uint32_t)(u * kT) + threadIdx.x;
             id[u] = ldg(iid, (i < cnt ? i : 0u) * 4u);
         }
@@ -688,7 +702,7 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
             stg(ovx, o, v.x);
             stg(ovy, o, v.y);
             stg(ovz, o, v.z);
-            stg(oid, o, id[u]);
+            if (has_id) stg(oid, o, id[u]);
             if (has_m) stg(gp(b.m[dst]), o, pm[u]);
         }
         if (ch + 1 < nch) __syncthreads();
@@ -736,7 +750,7 @@ __device__ void overflow_step(const BoxDev& b, const BoxState& s, long long (&d)
             d[5] += 1;
             continue;
         }
-        const int32_t id = gp(b.pid[src])[si];
+        const int32_t id = b.pid[src] ? gp(b.pid[src])[si] : 0;
         if (vacf) vacf_term(b, id, v, d);
         put_particle(b, dst, j, x, y, z, v, id, m, has_m);
     }
@@ -761,7 +775,7 @@ __global__ __launch_bounds__(kBlock) void k_mark_holes(const Tile* __restrict__ 
     for (int64_t i = tl.begin + threadIdx.x; i < tl.end; i += kBlock) {
         const int lo = bucket_of_slot(bs, nbk, i);
         const uint32_t fill = min(sz[lo], bs[lo + 1] - bs[lo]);
-        if ((uint32_t)(i - bs[lo]) >= fill) b.pid[s.parity][i] = -1;
+        if ((uint32_t)(i - bs[lo]) >= fill) mark_hole(b, s.parity, i);
     }
 }
 
@@ -790,6 +804,7 @@ __global__ __launch_bounds__(kBlock) void k_rebucket_clear(const Tile* __restric
         const uint32_t gc = (uint32_t)(lox + lx) + L0 * (uint32_t)(loy + ly) + L01 * (uint32_t)(loz + lz);
         CellAcc z = {0ull, 0ull, 0ull, 0ull};
         store_acc(gp(b.esc[s.k & 1]) + gc, z);
+        if (b.ecnt[0]) b.ecnt[s.k & 1][gc] = 0u;
     }
     __syncthreads();
     if (threadIdx.x == 0) *flag = 0u;
@@ -850,7 +865,7 @@ __global__ __launch_bounds__(kBlock) void k_count(const Tile* __restrict__ tiles
     const MPCD_G float* __restrict__ vx = gp(b.p[par][3]);
     const MPCD_G float* __restrict__ vy = gp(b.p[par][4]);
     const MPCD_G float* __restrict__ vz = gp(b.p[par][5]);
-    const MPCD_G int32_t* __restrict__ pid = gp(b.pid[par]);
+    const MPCD_G int32_t* __restrict__ pid = b.pid[par] ? gp(b.pid[par]) : nullptr;
     MPCD_G uint32_t* __restrict__ cell = gp(b.cell);
     MPCD_G uint32_t* __restrict__ rank = gp(b.rank);
     const bool by_brick = (b.binning == 1);
@@ -859,7 +874,7 @@ __global__ __launch_bounds__(kBlock) void k_count(const Tile* __restrict__ tiles
     constexpr int kU = 4;   // particles per thread in flight
     for (int64_t i0 = tl.begin + threadIdx.x; i0 < tl.end; i0 += (int64_t)kBlock * kU) {
         float qx[kU], qy[kU], qz[kU], ux[kU], uy[kU], uz[kU];
-        int32_t id[kU];
+        bool live[kU];
 #pragma unroll
         for (int u = 0; u < kU; ++u) {   // issue every load first
             const int64_t i = i0 + (int64_t)u * kBlock;
@@ -870,12 +885,12 @@ __global__ __launch_bounds__(kBlock) void k_count(const Tile* __restrict__ tiles
             ux[u] = vx[j];
             uy[u] = vy[j];
             uz[u] = vz[j];
-            id[u] = i < tl.end ? pid[j] : -1;
+            live[u] = i < tl.end && (pid ? pid[j] >= 0 : !(qx[u] < 0.0f));
         }
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
             const int64_t i = i0 + (int64_t)u * kBlock;
-            if (id[u] < 0) continue;   // hole (or past the tile)
+            if (!live[u]) continue;   // hole (or past the tile)
             const float px = fold(fmaf(ux[u], dt, qx[u]), b.len[0]);
             const float py = fold(fmaf(uy[u], dt, qy[u]), b.len[1]);
             const float pz = fold(fmaf(uz[u], dt, qz[u]), b.len[2]);
@@ -1006,14 +1021,14 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const Tile* __restrict__ til
     const MPCD_G float* __restrict__ ivx = ugp(b.p[src][3]);
     const MPCD_G float* __restrict__ ivy = ugp(b.p[src][4]);
     const MPCD_G float* __restrict__ ivz = ugp(b.p[src][5]);
-    const MPCD_G int32_t* __restrict__ iid = gp(b.pid[src]);
+    const MPCD_G int32_t* __restrict__ iid = b.pid[src] ? gp(b.pid[src]) : nullptr;
     MPCD_G float* __restrict__ ox = gp(b.p[dst][0]);
     MPCD_G float* __restrict__ oy = gp(b.p[dst][1]);
     MPCD_G float* __restrict__ oz = gp(b.p[dst][2]);
     MPCD_G float* __restrict__ ovx = gp(b.p[dst][3]);
     MPCD_G float* __restrict__ ovy = gp(b.p[dst][4]);
     MPCD_G float* __restrict__ ovz = gp(b.p[dst][5]);
-    MPCD_G int32_t* __restrict__ oid = gp(b.pid[dst]);
+    MPCD_G int32_t* __restrict__ oid = b.pid[dst] ? gp(b.pid[dst]) : nullptr;
     const MPCD_G uint32_t* __restrict__ cell = gp(b.cell);
     const MPCD_G uint32_t* __restrict__ rank = gp(b.rank);
     const MPCD_G uint32_t* __restrict__ cstart = gp(b.cstart);
@@ -1026,7 +1041,6 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const Tile* __restrict__ til
         for (int u = 0; u < kU; ++u) {   // issue every load first
             const int64_t i = i0 + (int64_t)u * kBlock;
             const int64_t j = i < tl.end ? i : tl.begin;
-            id[u] = i < tl.end ? iid[j] : -1;
             key[u] = cell[j];
             rk[u] = rank[j];
             qx[u] = ix[j];
@@ -1035,10 +1049,12 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const Tile* __restrict__ til
             ux[u] = ivx[j];
             uy[u] = ivy[j];
             uz[u] = ivz[j];
+            id[u] = iid ? iid[j] : 0;
+            if (i >= tl.end || (iid ? id[u] < 0 : qx[u] < 0.0f)) id[u] = -1;   // hole (or past the tile)
         }
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
-            if (id[u] < 0) continue;   // hole (or past the tile)
+            if (id[u] < 0) continue;
             const int64_t i = i0 + (int64_t)u * kBlock;
             const int64_t j = (int64_t)cstart[key[u]] + rk[u];
             float px = qx[u], py = qy[u], pz = qz[u];
@@ -1053,7 +1069,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const Tile* __restrict__ til
             ovx[j] = ux[u];
             ovy[j] = uy[u];
             ovz[j] = uz[u];
-            oid[j] = id[u];
+            if (oid) oid[j] = id[u];
             if (has_m) gp(b.m[dst])[j] = gp(b.m[src])[i];
         }
     }
@@ -1089,6 +1105,7 @@ __device__ __forceinline__ void collide_cell_am(const BoxDev& b, int par, long l
     const float* __restrict__ mp = b.m[par];
     const double a = b.a;
     long long sm[kAmMoments] = {};
+    if (end - beg >= kMaxCellCount) d[5] += 1;   // the cell's sums may have wrapped
     for (uint32_t j = beg; j < end; ++j) {
         double r[3];
         long long t[kAmMoments];
@@ -1104,7 +1121,7 @@ __device__ __forceinline__ void collide_cell_am(const BoxDev& b, int par, long l
         double r[3];
         long long t[3];
         am_local(a, px[j], py[j], pz[j], sh, r);
-        am_dl(mass_of(mp, j), vx[j], vy[j], vz[j], r, u, rc, n, ca, sa, t);
+        if (!am_dl(mass_of(mp, j), vx[j], vy[j], vz[j], r, u, rc, n, ca, sa, t)) d[5] += 1;
         sl[0] += t[0];
         sl[1] += t[1];
         sl[2] += t[2];
@@ -1141,7 +1158,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_rotate(const Tile* __restrict__
     const int32_t* __restrict__ pid = b.pid[s.parity];
     const float* __restrict__ mp = b.m[s.parity];
     const double ca = b.ca, sa = b.sa;
-    long long d[kNumDiag] = {0, 0, 0, 0, 0, 0};
+    long long d[kNumDiag] = {};
     if (b.conserve_l) {
         const float3 sh = grid_shift(b, s.k);
         for (int64_t c = tl.begin + threadIdx.x; c < tl.end; c += kBlock) {
@@ -1154,6 +1171,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_rotate(const Tile* __restrict__
     for (int64_t c = tl.begin + threadIdx.x; c < tl.end; c += kBlock) {
         const uint32_t beg = b.cstart[c], end = b.cstart[c + 1];
         if (beg == end) continue;
+        if (end - beg >= kMaxCellCount) d[5] += 1;   // the cell's sums may have wrapped
         unsigned long long sx = 0, sy = 0, sz = 0, sw = 0;
         for (uint32_t j = beg; j < end; ++j) {
             const float mj = mass_of(mp, j);
@@ -1162,8 +1180,9 @@ __global__ __launch_bounds__(kBlock) void k_cell_rotate(const Tile* __restrict__
             sz += to_fixed(mj * vz[j]);
             sw += to_fixed(mj);
         }
-        const CellRot cr = cell_rotation(fixed_mean(sx, sw), fixed_mean(sy, sw), fixed_mean(sz, sw),
-                                         cell_axis(b, s.k, (uint32_t)c), ca, sa);
+        double uc[3];
+        fixed_mean3(sx, sy, sz, sw, uc);
+        const CellRot cr = cell_rotation(uc[0], uc[1], uc[2], cell_axis(b, s.k, (uint32_t)c), ca, sa);
         for (uint32_t j = beg; j < end; ++j) {
             const float3 v = apply_rotation(cr, vx[j], vy[j], vz[j]);
             vx[j] = v.x;
@@ -1191,7 +1210,7 @@ __global__ __launch_bounds__(kBlock) void k_box_finish(const int32_t* __restrict
     if (box_idle(*sp)) return;
     const BoxDev& b = boxes[bx];
     const bool by_cell = (b.binning == 2);
-    long long d[kNumDiag] = {0, 0, 0, 0, 0, 0};
+    long long d[kNumDiag] = {};
     if (!by_cell) overflow_step(b, *sp, d);
     // this thread's share of the exact sums: its particles plus, for the
     // first kAccLanes threads, one accumulator lane (then cleared)
@@ -1257,10 +1276,10 @@ __global__ __launch_bounds__(kBlock) void k_init_maxwell(const BoxDev* __restric
     const Tile tl = box_tile(boxes, box);
     const BoxDev& b = boxes[tl.box];
     const int par = st[tl.box].parity;
-    long long d[kNumDiag] = {0, 0, 0, 0, 0, 0};
+    long long d[kNumDiag] = {};
     for (int64_t i = tl.begin + threadIdx.x; i < tl.end; i += kBlock) {
         if (i >= b.n) {   // spare slot of a brick box
-            b.pid[par][i] = -1;
+            mark_hole(b, par, i);
             continue;
         }
         const uint32_t lo = (uint32_t)i, hi = (uint32_t)((uint64_t)i >> 32);
@@ -1278,7 +1297,7 @@ __global__ __launch_bounds__(kBlock) void k_init_maxwell(const BoxDev* __restric
         b.p[par][3][i] = vx;
         b.p[par][4][i] = vy;
         b.p[par][5][i] = vz;
-        b.pid[par][i] = (int32_t)i;
+        if (b.pid[par]) b.pid[par][i] = (int32_t)i;
         diag_particle(d, make_float3(vx, vy, vz), 1.0f);
     }
     block_diag(d, partials + (size_t)t * kNumDiag);
@@ -1296,9 +1315,9 @@ __global__ __launch_bounds__(kBlock) void k_init_adjust(const BoxDev* __restrict
     const int par = st[tl.box].parity;
     const float mx = st[tl.box].adj[0], my = st[tl.box].adj[1], mz = st[tl.box].adj[2];
     const float scale = st[tl.box].adj[3];
-    long long d[kNumDiag] = {0, 0, 0, 0, 0, 0};
+    long long d[kNumDiag] = {};
     for (int64_t i = tl.begin + threadIdx.x; i < tl.end; i += kBlock) {
-        if (b.pid[par][i] < 0) continue;
+        if (!slot_live(b, par, i)) continue;
         const float vx = (b.p[par][3][i] - mx) * scale;
         const float vy = (b.p[par][4][i] - my) * scale;
         const float vz = (b.p[par][5][i] - mz) * scale;
@@ -1320,11 +1339,11 @@ __global__ __launch_bounds__(kBlock) void k_snapshot(const BoxDev* __restrict__ 
     const BoxDev& b = boxes[tl.box];
     const int par = st[tl.box].parity;
     const bool has_v0 = b.vacf_stride > 0;
-    long long d[kNumDiag] = {0, 0, 0, 0, 0, 0};
+    long long d[kNumDiag] = {};
     for (int64_t i = tl.begin + threadIdx.x; i < tl.end; i += kBlock) {
-        if (b.pid[par][i] < 0) continue;
+        if (!slot_live(b, par, i)) continue;
         const float vx = b.p[par][3][i], vy = b.p[par][4][i], vz = b.p[par][5][i];
-        const int32_t id = b.pid[par][i];
+        const int32_t id = b.pid[par] ? b.pid[par][i] : 0;
         if (has_v0 && set_v0) b.v0[id] = make_float4(vx, vy, vz, 0.0f);
         diag_particle(d, make_float3(vx, vy, vz), mass_of(b.m[par], i));
         if (has_v0) vacf_term(b, id, make_float3(vx, vy, vz), d);
@@ -1355,6 +1374,7 @@ __device__ void box_stats_finish(const __int128 (&tot)[kNumDiag], const BoxDev* 
     double d[kNumDiag];
     for (int j = 0; j < kNumDiag; ++j)
         d[j] = (j == 5) ? (double)tot[j] : (double)tot[j] * 2.3283064365386963e-10;   // 2^-32
+    d[3] = (double)((tot[3] << 32) + tot[6]) * 2.3283064365386963e-10;   // energy: high and low words
     const long long n = box->n;
     if (mode == kStatsCentre || mode == kStatsScale) {
         float a[4] = {0.0f, 0.0f, 0.0f, 1.0f};
@@ -1469,6 +1489,25 @@ __global__ __launch_bounds__(kBlock) void k_fill_zero_u32(uint32_t* __restrict__
 {
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
         p[i] = 0u;
+}
+
+// Streaming copy of n16 16-byte words (each thread moves kU words per trip,
+// all loads issued before the stores): the practical HBM ceiling that the
+// step kernels are compared with.
+__global__ __launch_bounds__(kBlock) void k_hbm_copy(const f32x4* __restrict__ src, f32x4* __restrict__ dst,
+                                                      int64_t n16)
+{
+    constexpr int kU = 4;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    for (; i + (kU - 1) * stride < n16; i += kU * stride) {
+        f32x4 t[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) t[u] = src[i + u * stride];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) dst[i + u * stride] = t[u];
+    }
+    for (; i < n16; i += stride) dst[i] = src[i];
 }
 
 // --------------------------------------------------------------------------
@@ -1619,6 +1658,10 @@ void launch_permute_f32(float* dst, const float* src, const int32_t* pid, int64_
 {
     const int64_t g = (nslot + kBlock - 1) / kBlock;
     MPCD_LAUNCH(k_permute_f32, (int)(g < 65536 ? g : 65536), kBlock, s, dst, src, pid, nslot, n, scatter);
+}
+void launch_hbm_copy(const void* src, void* dst, int64_t n16, int blocks, hipStream_t s)
+{
+    MPCD_LAUNCH(k_hbm_copy, blocks, kBlock, s, (const f32x4*)src, (f32x4*)dst, n16);
 }
 void launch_fill_zero_u32(uint32_t* p, int64_t n, hipStream_t s)
 {

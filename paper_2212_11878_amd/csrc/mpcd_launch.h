@@ -56,6 +56,7 @@ void launch_box_stats(const Tables& T, int32_t box, int ntile, long long* part, 
 void launch_mark_holes_box(const Tables& T, int32_t box, int ntile, hipStream_t s);
 void launch_fill_iota(int32_t* p, int64_t n, hipStream_t s);
 void launch_fill_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
+void launch_hbm_copy(const void* src, void* dst, int64_t n16, int blocks, hipStream_t s);
 void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 void launch_permute_f32(float* dst, const float* src, const int32_t* pid, int64_t nslot, int64_t n, int scatter,
                         hipStream_t s);

@@ -27,6 +27,7 @@ MPCD_INIT_EXTERNAL = 0x2
 MPCD_TRACK_VACF = 0x4
 MPCD_PARTICLE_MASS = 0x8
 MPCD_CONSERVE_L = 0x10
+MPCD_UNORDERED = 0x20
 
 MPCD_BIN_AUTO = 0
 MPCD_BIN_ATOMIC = 1
@@ -108,6 +109,14 @@ _SIGNATURES = {
     "mpcd_set_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_float),
                                       ctypes.c_int64]),
     "mpcd_set_mass": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_float)]),
+    "mpcd_get_mass": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_float)]),
+    "mpcd_get_vacf": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_float),
+                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
+                                     ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "mpcd_set_vacf": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_float),
+                                     ctypes.c_int64, ctypes.POINTER(ctypes.c_double), ctypes.c_int32]),
+    "mpcd_hbm_copy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32,
+                                     ctypes.c_void_p]),
     "mpcd_release": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "mpcd_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "mpcd_kernel_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(mpcd_kernel_stat), ctypes.c_int32,
@@ -133,7 +142,7 @@ for _name, (_res, _args) in _SIGNATURES.items():
     _f.argtypes = _args
 
 # layout of the structs above (include/mpcd.h, MPCD_ABI_VERSION)
-ABI_VERSION = 2
+ABI_VERSION = 3
 if _lib.mpcd_abi_version() != ABI_VERSION:
     raise ImportError("libmpcd.so has ABI version %d, this binding expects %d; rebuild it"
                       % (_lib.mpcd_abi_version(), ABI_VERSION))
@@ -203,6 +212,35 @@ def mpcd_set_mass(ctx, slot, mass):
     return _lib.mpcd_set_mass(ctx, int(slot), buf.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
 
 
+def mpcd_get_mass(ctx, slot, n):
+    buf = np.empty(int(n), dtype=np.float32)
+    rc = _lib.mpcd_get_mass(ctx, int(slot), buf.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+    return rc, buf
+
+
+def mpcd_get_vacf(ctx, slot, n, max_samples):
+    v0 = np.empty(3 * int(n), dtype=np.float32)
+    samples = np.empty(max(1, int(max_samples)), dtype=np.float64)
+    origin = ctypes.c_int64(0)
+    length = ctypes.c_int32(0)
+    rc = _lib.mpcd_get_vacf(ctx, int(slot), v0.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                            ctypes.byref(origin), samples.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                            int(max_samples), ctypes.byref(length))
+    return rc, v0.reshape(3, -1), origin.value, samples[:min(length.value, int(max_samples))].copy()
+
+
+def mpcd_set_vacf(ctx, slot, v0, origin, samples):
+    v = np.ascontiguousarray(v0, dtype=np.float32).reshape(-1)
+    smp = np.ascontiguousarray(samples, dtype=np.float64).reshape(-1)
+    return _lib.mpcd_set_vacf(ctx, int(slot), v.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), int(origin),
+                              smp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(smp))
+
+
+def mpcd_hbm_copy(src_ptr, dst_ptr, nbytes, blocks=0, stream=None):
+    return _lib.mpcd_hbm_copy(ctypes.c_void_p(src_ptr), ctypes.c_void_p(dst_ptr), int(nbytes), int(blocks),
+                              ctypes.c_void_p(stream) if stream else None)
+
+
 def mpcd_release(ctx, slot):
     return _lib.mpcd_release(ctx, int(slot))
 
@@ -261,7 +299,7 @@ class _TorchAllocator:
 
 def make_desc(L, n_particles, dt=0.1, alpha_deg=130.0, seed=1, a=1.0, kT=1.0, mass=1.0,
               n_steps=0, init="maxwell", vacf_stride=0, vacf_capacity=0, alpha_rad=None,
-              particle_mass=False, conserve_l=False):
+              particle_mass=False, conserve_l=False, unordered=False):
     d = mpcd_box_desc()
     if isinstance(L, int):
         L = (L, L, L)
@@ -280,6 +318,8 @@ def make_desc(L, n_particles, dt=0.1, alpha_deg=130.0, seed=1, a=1.0, kT=1.0, ma
         d.flags |= MPCD_PARTICLE_MASS
     if conserve_l:
         d.flags |= MPCD_CONSERVE_L
+    if unordered:
+        d.flags |= MPCD_UNORDERED
     if vacf_stride:
         d.flags |= MPCD_TRACK_VACF
         d.vacf_stride = int(vacf_stride)
@@ -344,6 +384,20 @@ class Context:
 
     def set_mass(self, slot, mass):
         _check(mpcd_set_mass(self.handle, slot, mass), "mpcd_set_mass")
+
+    def get_mass(self, slot):
+        rc, m = mpcd_get_mass(self.handle, slot, self.n[slot])
+        _check(rc, "mpcd_get_mass")
+        return m
+
+    def get_vacf(self, slot, max_samples=1 << 16):
+        """(v0 [3, N], origin step, samples so far)"""
+        rc, v0, origin, samples = mpcd_get_vacf(self.handle, slot, self.n[slot], max_samples)
+        _check(rc, "mpcd_get_vacf")
+        return v0, origin, samples
+
+    def set_vacf(self, slot, v0, origin, samples):
+        _check(mpcd_set_vacf(self.handle, slot, v0, origin, samples), "mpcd_set_vacf")
 
     def get_state(self, slot):
         rc, buf, step = mpcd_get_state(self.handle, slot, self.n[slot])

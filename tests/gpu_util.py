@@ -116,3 +116,33 @@ def compare_step(pos32, vel32, gpu_pos, gpu_vel, box, k, kT=1.0, mass=1.0, mass3
     number of face-band particles and the largest kept velocity error."""
     st, s, cells = oracle_one_step(pos32, vel32, box, k, mass32)
     return check_against(st, s, cells, box, gpu_pos, gpu_vel, kT, mass)
+
+
+def match_unordered(ref_pos, gpu_pos, gpu_vel, L, a=1.0):
+    """Boxes without particle ids return their particles in storage order.
+    Match every reference particle (oracle FP64 positions after the step's
+    streaming, which the collision leaves unchanged) with the GPU particle at
+    the same place on the torus (within the FP32 position tolerance, each GPU
+    particle used once) and return the GPU positions and velocities in the
+    reference order."""
+    from scipy.spatial import cKDTree
+    edge = np.array([L[d] * a for d in range(3)], dtype=np.float64)
+    tol = 2.0 * max(ulp_top(x) for x in edge)
+    g = np.mod(gpu_pos.astype(np.float64).T, edge)
+    r = np.mod(np.asarray(ref_pos, dtype=np.float64).T, edge)
+    tree = cKDTree(g, boxsize=edge)
+    dist, idx = tree.query(r, k=1)
+    assert np.all(dist <= tol), ("unmatched particle", float(dist.max()), tol)
+    assert len(np.unique(idx)) == len(idx), "two reference particles matched one GPU particle"
+    return gpu_pos[:, idx], gpu_vel[:, idx]
+
+
+def same_particle_set(pa, va, pb, vb):
+    """The two states hold the same particles bit for bit (any order)."""
+    A = np.concatenate([pa, va]).view(np.uint32)
+    B = np.concatenate([pb, vb]).view(np.uint32)
+    if A.shape != B.shape:
+        return False
+    oa = np.lexsort(A[::-1])
+    ob = np.lexsort(B[::-1])
+    return bool(np.array_equal(A[:, oa], B[:, ob]))

@@ -58,7 +58,7 @@ def test_struct_layout_matches_header(m, tmp_path):
 
 
 def test_status_strings_and_version(m):
-    assert m.mpcd_abi_version() == m.ABI_VERSION == 2
+    assert m.mpcd_abi_version() == m.ABI_VERSION == 3
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert m.mpcd_strerror(code) and m.mpcd_strerror(code) != "unknown status"
     assert m.mpcd_strerror(12345) == "unknown status"
@@ -70,6 +70,14 @@ def test_null_arguments_rejected(m):
     assert lib.mpcd_step(None, 1) == m.MPCD_EINVAL
     assert lib.mpcd_release(None, 0) == m.MPCD_EINVAL
     assert lib.mpcd_observe(None, 0, None) == m.MPCD_EINVAL
+    assert lib.mpcd_get_mass(None, 0, None) == m.MPCD_EINVAL
+    assert lib.mpcd_get_vacf(None, 0, None, None, None, 0, None) == m.MPCD_EINVAL
+    assert lib.mpcd_set_vacf(None, 0, None, 0, None, 0) == m.MPCD_EINVAL
+    # the measurement copy checks its arguments before touching a device
+    assert lib.mpcd_hbm_copy(None, None, 16, 0, None) == m.MPCD_EINVAL
+    assert lib.mpcd_hbm_copy(ctypes.c_void_p(16), ctypes.c_void_p(32), 15, 0, None) == m.MPCD_EINVAL
+    assert lib.mpcd_hbm_copy(ctypes.c_void_p(8), ctypes.c_void_p(32), 16, 0, None) == m.MPCD_EINVAL
+    assert lib.mpcd_hbm_copy(ctypes.c_void_p(16), ctypes.c_void_p(32), 0, 0, None) == m.MPCD_OK
     lib.mpcd_destroy(None)
 
 

@@ -1,8 +1,9 @@
 """Parity at the benchmark's full size: 256^3 cells, 10 particles per cell
-(167,772,160 particles), the launch configuration bench.py times.  The
-oracle recomputes complete sample cells one by one: it streams every particle,
-bins them, and collides only the particles of three whole slabs of
-collision cells (about 5 million particles)."""
+(167,772,160 particles), in the launch configuration bench.py times (no
+particle ids, graph replay).  The box first routes itself through three
+steps; then the oracle takes step 3 from the GPU's own state and recomputes
+three whole slabs of collision cells (about 2 million particles), matched
+with the GPU's particles by position."""
 import math
 
 import numpy as np
@@ -11,33 +12,40 @@ import pytest
 from oracle import oracle as orc
 from paper_2212_11878_amd import inputs
 
-from gpu_util import check_against
+from gpu_util import check_against, face_band_mask, match_unordered
 
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.timeout(600)
-def test_full_size_one_step_sampled_cells():
+@pytest.mark.timeout(900)
+def test_full_size_step_after_self_routing_sampled_cells():
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2212_11878_amd import mpcd
     import bench
 
-    L, n, seed, k = (256, 256, 256), 167772160, 3, 0
+    L, n, seed, k = (256, 256, 256), 167772160, 3, 3
     print("[case] full-size inputs", flush=True)
     pos, vel = inputs.thermal_state(L, n, seed)
-    print("[case] full-size gpu step", flush=True)
+    print("[case] full-size gpu steps", flush=True)
     with mpcd.Context(**bench.context_options()) as ctx:
-        slot = ctx.admit(mpcd.make_desc(L, n, dt=0.1, alpha_deg=130.0, seed=seed, init="external"))
+        slot = ctx.admit(mpcd.make_desc(L, n, dt=0.1, alpha_deg=130.0, seed=seed, init="external",
+                                        unordered=True))
         ctx.set_state(slot, (pos, vel))
+        del pos, vel
+        ctx.step(k)
+        p3, v3, step = ctx.get_state(slot)
+        assert step == k
         ctx.step(1)
         gp, gv, step = ctx.get_state(slot)
-    assert step == 1
+        obs = ctx.observe(slot)
+    assert step == k + 1 and obs["status"] == 0
     print("[case] full-size oracle sample", flush=True)
     box = orc.make_box(L, dt=0.1, alpha_deg=130.0, seed=seed)
-    st = orc.State(pos, vel)
-    del pos
+    st = orc.State(p3, v3)
+    v3_64 = v3.astype(np.float64)
+    del p3, v3
     orc.stream(box, st)
     s = orc.shift(seed, k, 1.0)
     cells = orc.cells(box, s, st)
@@ -46,22 +54,25 @@ def test_full_size_one_step_sampled_cells():
     pick = np.nonzero((iz == 0) | (iz == 255) | (iy == 131))[0]
     sub = orc.State(st.pos[:, pick], st.vel[:, pick])
     # face-band particles anywhere may move into a sampled cell on the FP32 path
-    from gpu_util import face_band_mask
     near = face_band_mask(st.pos, s, box)
     band_pos, band_cells = st.pos[:, near].copy(), cells[near].copy()
     del st
     orc.collide(box, k, sub)
-    band, err = check_against(sub, s, cells[pick], box, gp[:, pick], gv[:, pick],
-                              band_from=(band_pos, band_cells))
-    print("[case] full-size sample: %d particles, %d in face band, max rel err %.2e"
-          % (len(pick), band, err), flush=True)
+    # the GPU's particles of the same slabs (with a margin of one cell layer)
+    gq = gp.astype(np.float64)
+    gi = [np.floor((gq[d] - s[d])).astype(np.int64) % 256 for d in range(3)]
+    cand = np.nonzero((gi[2] <= 1) | (gi[2] >= 254) | (np.abs(gi[1] - 131) <= 1))[0]
+    del gq, gi
+    mpos, mvel = match_unordered(sub.pos, gp[:, cand], gv[:, cand], L)
+    band, err = check_against(sub, s, cells[pick], box, mpos, mvel, band_from=(band_pos, band_cells))
+    print("[case] full-size sample after %d routed steps: %d particles, %d in face band, max rel err %.2e"
+          % (k, len(pick), band, err), flush=True)
     assert len(pick) > 1_900_000
     # whole-box invariants of the GPU result
     assert gp.min() >= 0 and gp.max() < 256
-    v0 = vel.astype(np.float64)
     v1 = gv.astype(np.float64)
-    P0, P1 = v0.sum(axis=1), v1.sum(axis=1)
-    E0, E1 = 0.5 * np.sum(v0 * v0), 0.5 * np.sum(v1 * v1)
+    P0, P1 = v3_64.sum(axis=1), v1.sum(axis=1)
+    E0, E1 = 0.5 * np.sum(v3_64 * v3_64), 0.5 * np.sum(v1 * v1)
     assert np.all(np.abs(P1 - P0) < 1e-3 * math.sqrt(n))
     assert abs(E1 - E0) < 1e-6 * E0
 
@@ -109,7 +120,7 @@ def test_full_size_drift_over_500_steps():
     L, n, seed = (256, 256, 256), 167772160, 3
     print("[case] full-size drift", flush=True)
     with mpcd.Context(**bench.context_options()) as ctx:
-        slot = ctx.admit(mpcd.make_desc(L, n, dt=0.1, alpha_deg=130.0, seed=seed))
+        slot = ctx.admit(mpcd.make_desc(L, n, dt=0.1, alpha_deg=130.0, seed=seed, unordered=True))
         o0 = ctx.observe(slot)
         ctx.step(500)
         o1 = ctx.observe(slot)
@@ -122,27 +133,34 @@ def test_full_size_drift_over_500_steps():
 
 
 @pytest.mark.timeout(600)
-def test_100cube_one_step_every_particle():
+@pytest.mark.parametrize("ids", [True, False])
+def test_100cube_one_step_every_particle(ids):
     """100^3 cells, 10^7 particles (the 100^3 workload) in the benchmark's
-    launch configuration: one step from a seeded state against the oracle,
-    for every particle (face-band exemptions as in the small cases)."""
+    launch configuration, with and without particle ids: one step from a
+    seeded state against the oracle, for every particle (face-band
+    exemptions as in the small cases; without ids the particles are matched
+    by position)."""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2212_11878_amd import mpcd
-    from gpu_util import compare_step
+    from gpu_util import oracle_one_step
     import bench
     L, n, seed, k = (100, 100, 100), 10_000_000, 2, 3
-    print("[case] 100^3 inputs", flush=True)
+    print("[case] 100^3 inputs, ids=%s" % ids, flush=True)
     pos, vel = inputs.thermal_state(L, n, seed)
     with mpcd.Context(**bench.context_options()) as ctx:
-        slot = ctx.admit(mpcd.make_desc(L, n, dt=0.1, alpha_deg=130.0, seed=seed, init="external"))
+        slot = ctx.admit(mpcd.make_desc(L, n, dt=0.1, alpha_deg=130.0, seed=seed, init="external",
+                                        unordered=not ids))
         ctx.set_state(slot, (pos, vel), step=k)
         ctx.step(1)
         gp, gv, step = ctx.get_state(slot)
     assert step == k + 1
     print("[case] 100^3 oracle step", flush=True)
     box = orc.make_box(L, dt=0.1, alpha_deg=130.0, seed=seed)
-    band, err = compare_step(pos, vel, gp, gv, box, k)
+    st, s, cells = oracle_one_step(pos, vel, box, k)
+    if not ids:
+        gp, gv = match_unordered(st.pos, gp, gv, L)
+    band, err = check_against(st, s, cells, box, gp, gv)
     print("[case] 100^3: %d particles, %d in face band, max rel err %.2e" % (n, band, err), flush=True)
     assert band < n // 1000
