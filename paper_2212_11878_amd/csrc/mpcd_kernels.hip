@@ -814,30 +814,6 @@ __global__ __launch_bounds__(kBlock) void k_rebucket_clear(const Tile* __restric
 // counting sort: by collision cell every step (SORT), or by brick once to
 // bucket a brick box's particles (after admission / set_state)
 
-// rank of this lane's particle among those with the same key: lanes of a
-// wave that share a key (sorted input: most of them) take one atomic
-__device__ __forceinline__ void keys_rank(uint32_t* counts, uint32_t key, uint32_t* rank)
-{
-    const int lane = threadIdx.x & (kWave - 1);
-    const unsigned long long below = (1ull << lane) - 1ull;
-    bool pending = true;
-    while (true) {
-        const unsigned long long act = __ballot(pending);
-        if (!act) break;
-        const int leader = __ffsll((long long)act) - 1;
-        const uint32_t k0 = (uint32_t)__builtin_amdgcn_readlane((int)key, leader);
-        const bool mine = pending && key == k0;
-        const unsigned long long same = __ballot(mine);
-        uint32_t base = 0u;
-        if (lane == leader) base = atomicAdd(&counts[k0], (uint32_t)__popcll(same));
-        base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
-        if (mine) {
-            *rank = base + (uint32_t)__popcll(same & below);
-            pending = false;
-        }
-    }
-}
-
 __global__ __launch_bounds__(kBlock) void k_zero_counts(const Tile* __restrict__ tiles,
                                                          const BoxDev* __restrict__ boxes,
                                                          const BoxState* __restrict__ st)
@@ -850,10 +826,29 @@ __global__ __launch_bounds__(kBlock) void k_zero_counts(const Tile* __restrict__
     if (tl.end == b.ncell && threadIdx.x == 0) b.cstart[b.ncell] = 0u;
 }
 
+// Rank of every live slot among the slots with the same key (SORT: its
+// collision cell; re-bucketing: the brick of that cell), and the per-key
+// counts in cstart.  The tile is taken in halves of kCountHalf slots; each
+// half gathers its keys in an LDS hash table (open addressing, load factor at
+// most 1/2), so a key takes one global atomic per half-tile, and the atomics
+// of all distinct keys are issued together rather than one after another.
+constexpr int kCountHalf = kPartTile / 2;
+constexpr int kCountPer = kCountHalf / kBlock;    // slots per thread per half
+constexpr int kHashSlots = 2 * kCountHalf;
+constexpr uint32_t kHashEmpty = 0xffffffffu;
+
+__device__ __forceinline__ uint32_t hash_slot(uint32_t key)
+{
+    return (key * 0x9E3779B1u) >> (32 - 12);   // Fibonacci hashing onto kHashSlots = 4096
+}
+static_assert(kHashSlots == 4096, "hash_slot maps onto 4096 slots");
+
 __global__ __launch_bounds__(kBlock) void k_count(const Tile* __restrict__ tiles,
                                                    const BoxDev* __restrict__ boxes,
                                                    const BoxState* __restrict__ st)
 {
+    __shared__ uint32_t hkey[kHashSlots];
+    __shared__ uint32_t hval[kHashSlots];   // count of the key in this half, then its global base
     const Tile tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     const BoxState s = st[uniform(tl.box)];
     const BoxDev& b = boxes[uniform(tl.box)];
@@ -868,16 +863,22 @@ __global__ __launch_bounds__(kBlock) void k_count(const Tile* __restrict__ tiles
     const MPCD_G int32_t* __restrict__ pid = b.pid[par] ? gp(b.pid[par]) : nullptr;
     MPCD_G uint32_t* __restrict__ cell = gp(b.cell);
     MPCD_G uint32_t* __restrict__ rank = gp(b.rank);
+    MPCD_G uint32_t* __restrict__ counts = gp(b.cstart);
     const bool by_brick = (b.binning == 1);
     const float3 sh = grid_shift(b, uniform(s.k));
     const float dt = b.dt;
-    constexpr int kU = 4;   // particles per thread in flight
-    for (int64_t i0 = tl.begin + threadIdx.x; i0 < tl.end; i0 += (int64_t)kBlock * kU) {
-        float qx[kU], qy[kU], qz[kU], ux[kU], uy[kU], uz[kU];
-        bool live[kU];
+    for (int64_t h0 = tl.begin; h0 < tl.end; h0 += kCountHalf) {
+        for (int q = threadIdx.x; q < kHashSlots; q += kBlock) {
+            hkey[q] = kHashEmpty;
+            hval[q] = 0u;
+        }
+        __syncthreads();
+        uint32_t slot_rank[kCountPer];   // hash slot << 16 | rank inside the half; kHashEmpty: none
+        float qx[kCountPer], qy[kCountPer], qz[kCountPer], ux[kCountPer], uy[kCountPer], uz[kCountPer];
+        bool live[kCountPer];
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {   // issue every load first
-            const int64_t i = i0 + (int64_t)u * kBlock;
+        for (int u = 0; u < kCountPer; ++u) {   // issue every load first
+            const int64_t i = h0 + (int64_t)u * kBlock + threadIdx.x;
             const int64_t j = i < tl.end ? i : tl.begin;
             qx[u] = x[j];
             qy[u] = y[j];
@@ -888,9 +889,10 @@ __global__ __launch_bounds__(kBlock) void k_count(const Tile* __restrict__ tiles
             live[u] = i < tl.end && (pid ? pid[j] >= 0 : !(qx[u] < 0.0f));
         }
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int64_t i = i0 + (int64_t)u * kBlock;
+        for (int u = 0; u < kCountPer; ++u) {
+            slot_rank[u] = kHashEmpty;
             if (!live[u]) continue;   // hole (or past the tile)
+            const int64_t i = h0 + (int64_t)u * kBlock + threadIdx.x;
             const float px = fold(fmaf(ux[u], dt, qx[u]), b.len[0]);
             const float py = fold(fmaf(uy[u], dt, qy[u]), b.len[1]);
             const float pz = fold(fmaf(uz[u], dt, qz[u]), b.len[2]);
@@ -904,10 +906,28 @@ __global__ __launch_bounds__(kBlock) void k_count(const Tile* __restrict__ tiles
                 key = collision_cell(b, px, py, pz, sh);
             }
             cell[i] = key;
-            uint32_t r = 0u;
-            keys_rank(b.cstart, key, &r);
-            rank[i] = r;
+            uint32_t hs = hash_slot(key);
+            while (true) {   // at most kCountHalf keys in kHashSlots slots: a free slot exists
+                const uint32_t old = atomicCAS(&hkey[hs], kHashEmpty, key);
+                if (old == kHashEmpty || old == key) break;
+                hs = (hs + 1u) & (kHashSlots - 1);
+            }
+            slot_rank[u] = (hs << 16) | atomicAdd(&hval[hs], 1u);
         }
+        __syncthreads();
+        // one global atomic per distinct key of the half: its base among all tiles
+        for (int q = threadIdx.x; q < kHashSlots; q += kBlock) {
+            const uint32_t key = hkey[q];
+            if (key != kHashEmpty) hval[q] = gatomic_add(counts + key, hval[q]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kCountPer; ++u) {
+            if (slot_rank[u] == kHashEmpty) continue;
+            const int64_t i = h0 + (int64_t)u * kBlock + threadIdx.x;
+            rank[i] = hval[slot_rank[u] >> 16] + (slot_rank[u] & 0xffffu);
+        }
+        __syncthreads();   // the table is reset for the next half
     }
 }
 
@@ -1037,6 +1057,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const Tile* __restrict__ til
         float qx[kU], qy[kU], qz[kU], ux[kU], uy[kU], uz[kU];
         int32_t id[kU];
         uint32_t key[kU], rk[kU];
+        bool live[kU];
 #pragma unroll
         for (int u = 0; u < kU; ++u) {   // issue every load first
             const int64_t i = i0 + (int64_t)u * kBlock;
@@ -1050,11 +1071,12 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const Tile* __restrict__ til
             uy[u] = ivy[j];
             uz[u] = ivz[j];
             id[u] = iid ? iid[j] : 0;
-            if (i >= tl.end || (iid ? id[u] < 0 : qx[u] < 0.0f)) id[u] = -1;   // hole (or past the tile)
+            // the same predicate as k_count: a hole (or past the tile) is skipped
+            live[u] = i < tl.end && (iid ? id[u] >= 0 : !(qx[u] < 0.0f));
         }
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
-            if (id[u] < 0) continue;
+            if (!live[u]) continue;
             const int64_t i = i0 + (int64_t)u * kBlock;
             const int64_t j = (int64_t)cstart[key[u]] + rk[u];
             float px = qx[u], py = qy[u], pz = qz[u];
@@ -1139,58 +1161,158 @@ __device__ __forceinline__ void collide_cell_am(const BoxDev& b, int par, long l
     }
 }
 
-// SORT path: particles of cell c occupy [cstart[c], cstart[c+1]) in the
-// current buffer, already streamed.  One thread per cell.
+// Plain collision of one cell whose particles occupy [beg, end) of the
+// current buffer, by one thread straight from global memory (SORT path, a
+// cell too large for the staging area of k_cell_rotate).
+__device__ void collide_cell_serial(const BoxDev& b, int par, long long k, uint32_t c, uint32_t beg, uint32_t end,
+                                    long long (&d)[kNumDiag], bool vacf)
+{
+    float* __restrict__ vx = b.p[par][3];
+    float* __restrict__ vy = b.p[par][4];
+    float* __restrict__ vz = b.p[par][5];
+    const float* __restrict__ mp = b.m[par];
+    if (end - beg >= kMaxCellCount) d[5] += 1;   // the cell's sums may have wrapped
+    unsigned long long sx = 0, sy = 0, sz = 0, sw = 0;
+    for (uint32_t j = beg; j < end; ++j) {
+        const float mj = mass_of(mp, j);
+        sx += to_fixed(mj * vx[j]);
+        sy += to_fixed(mj * vy[j]);
+        sz += to_fixed(mj * vz[j]);
+        sw += to_fixed(mj);
+    }
+    double uc[3];
+    fixed_mean3(sx, sy, sz, sw, uc);
+    const CellRot cr = cell_rotation(uc[0], uc[1], uc[2], cell_axis(b, k, c), b.ca, b.sa);
+    for (uint32_t j = beg; j < end; ++j) {
+        const float3 v = apply_rotation(cr, vx[j], vy[j], vz[j]);
+        vx[j] = v.x;
+        vy[j] = v.y;
+        vz[j] = v.z;
+        diag_check(d, v);
+        if (vacf) vacf_term(b, b.pid[par][j], v, d);
+    }
+}
+
+// SORT path: the particles of cell c occupy [cstart[c], cstart[c+1]) of the
+// current buffer, already streamed.  A workgroup takes its cell tile in runs
+// of at most kRotCells cells holding at most kRotCap particles: it stages the
+// run's velocities (and masses) in LDS with coalesced loads, one thread per
+// cell sums its particles from LDS (exact fixed point, the same terms as the
+// brick step) and builds the cell's collision map, then every thread applies
+// the maps to its particles and stores them coalesced.  A cell larger than
+// the staging area is walked by one thread in global memory.  The
+// angular-momentum rule walks each cell with one thread (three passes).
+constexpr int kRotCap = 1024;
+constexpr int kRotCells = 128;
+
 __global__ __launch_bounds__(kBlock) void k_cell_rotate(const Tile* __restrict__ tiles,
                                                          const BoxDev* __restrict__ boxes,
                                                          const BoxState* __restrict__ st,
                                                          long long* __restrict__ dacc)
 {
+    __shared__ uint32_t cs[kCellTile + 1];     // cstart of the tile's cells
+    __shared__ float sv[3][kRotCap];
+    __shared__ float sm[kRotCap];
+    __shared__ uint8_t seg[kRotCap];           // run-local cell of each staged particle
+    __shared__ f32x4 rot[kRotCells][3];
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const Tile tl = tiles[t];
-    const BoxState s = st[tl.box];
-    const BoxDev& b = boxes[tl.box];
+    const BoxState s = st[uniform(tl.box)];
+    const BoxDev& b = boxes[uniform(tl.box)];
     if (box_idle(s) || b.binning != 2) return;
-    float* __restrict__ vx = b.p[s.parity][3];
-    float* __restrict__ vy = b.p[s.parity][4];
-    float* __restrict__ vz = b.p[s.parity][5];
+    const int par = uniform(s.parity);
+    const long long k = uniform(s.k);
     const bool vacf = vacf_due(b, s);
-    const int32_t* __restrict__ pid = b.pid[s.parity];
-    const float* __restrict__ mp = b.m[s.parity];
-    const double ca = b.ca, sa = b.sa;
     long long d[kNumDiag] = {};
     if (b.conserve_l) {
-        const float3 sh = grid_shift(b, s.k);
+        const float3 sh = grid_shift(b, k);
         for (int64_t c = tl.begin + threadIdx.x; c < tl.end; c += kBlock) {
             const uint32_t beg = b.cstart[c], end = b.cstart[c + 1];
-            if (beg != end) collide_cell_am(b, s.parity, s.k, (uint32_t)c, beg, end, sh, ca, sa, d, vacf);
+            if (beg != end) collide_cell_am(b, par, k, (uint32_t)c, beg, end, sh, b.ca, b.sa, d, vacf);
         }
         step_flush(d, vacf, dacc + (size_t)tl.box * kAccLanes * 3, blockIdx.x);
         return;
     }
-    for (int64_t c = tl.begin + threadIdx.x; c < tl.end; c += kBlock) {
-        const uint32_t beg = b.cstart[c], end = b.cstart[c + 1];
-        if (beg == end) continue;
-        if (end - beg >= kMaxCellCount) d[5] += 1;   // the cell's sums may have wrapped
-        unsigned long long sx = 0, sy = 0, sz = 0, sw = 0;
-        for (uint32_t j = beg; j < end; ++j) {
-            const float mj = mass_of(mp, j);
-            sx += to_fixed(mj * vx[j]);
-            sy += to_fixed(mj * vy[j]);
-            sz += to_fixed(mj * vz[j]);
-            sw += to_fixed(mj);
+    MPCD_G float* const vx = ugp(b.p[par][3]);
+    MPCD_G float* const vy = ugp(b.p[par][4]);
+    MPCD_G float* const vz = ugp(b.p[par][5]);
+    const MPCD_G float* const mp = b.m[par] ? ugp(b.m[par]) : nullptr;
+    const MPCD_G int32_t* const pid = b.pid[par] ? ugp(b.pid[par]) : nullptr;
+    const int nc = (int)(tl.end - tl.begin);
+    for (int i = threadIdx.x; i <= nc; i += kBlock) cs[i] = gp(b.cstart)[tl.begin + i];
+    __syncthreads();
+    int c = 0;
+    while (c < nc) {
+        // the run [c, e): as many cells as fit (uniform binary search on cs)
+        int e = c + 1;
+        const uint32_t base = cs[c];
+        if (cs[e] - base <= (uint32_t)kRotCap) {
+            int lo = e, hi = min(nc, c + kRotCells);
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (cs[mid] - base <= (uint32_t)kRotCap) lo = mid;
+                else hi = mid - 1;
+            }
+            e = lo;
         }
-        double uc[3];
-        fixed_mean3(sx, sy, sz, sw, uc);
-        const CellRot cr = cell_rotation(uc[0], uc[1], uc[2], cell_axis(b, s.k, (uint32_t)c), ca, sa);
-        for (uint32_t j = beg; j < end; ++j) {
-            const float3 v = apply_rotation(cr, vx[j], vy[j], vz[j]);
-            vx[j] = v.x;
-            vy[j] = v.y;
-            vz[j] = v.z;
+        const uint32_t np = cs[e] - base;
+        if (np > (uint32_t)kRotCap) {   // one cell larger than the staging area
+            if (threadIdx.x == 0)
+                collide_cell_serial(b, par, k, (uint32_t)(tl.begin + c), base, cs[e], d, vacf);
+            c = e;
+            continue;
+        }
+        for (uint32_t j = threadIdx.x; j < np; j += kBlock) {
+            sv[0][j] = vx[base + j];
+            sv[1][j] = vy[base + j];
+            sv[2][j] = vz[base + j];
+            sm[j] = mp ? mp[base + j] : 1.0f;
+        }
+        __syncthreads();
+        if (threadIdx.x < e - c) {
+            const int q = threadIdx.x;
+            const uint32_t rb = cs[c + q] - base, re = cs[c + q + 1] - base;
+            if (rb != re) {
+                if (re - rb >= kMaxCellCount) d[5] += 1;   // the cell's sums may have wrapped
+                unsigned long long sx = 0, sy = 0, sz = 0, sw = 0;
+                for (uint32_t j = rb; j < re; ++j) {
+                    const float mj = sm[j];
+                    sx += to_fixed(mj * sv[0][j]);
+                    sy += to_fixed(mj * sv[1][j]);
+                    sz += to_fixed(mj * sv[2][j]);
+                    sw += to_fixed(mj);
+                    seg[j] = (uint8_t)q;
+                }
+                double uc[3];
+                fixed_mean3(sx, sy, sz, sw, uc);
+                const CellRot cr = cell_rotation(uc[0], uc[1], uc[2],
+                                                 cell_axis(b, k, (uint32_t)(tl.begin + c + q)), b.ca, b.sa);
+                f32x4 r0, r1, r2;
+                r0.x = cr.m[0]; r0.y = cr.m[1]; r0.z = cr.m[2]; r0.w = cr.m[3];
+                r1.x = cr.m[4]; r1.y = cr.m[5]; r1.z = cr.m[6]; r1.w = cr.m[7];
+                r2.x = cr.m[8]; r2.y = cr.t[0]; r2.z = cr.t[1]; r2.w = cr.t[2];
+                rot[q][0] = r0;
+                rot[q][1] = r1;
+                rot[q][2] = r2;
+            }
+        }
+        __syncthreads();
+        for (uint32_t j = threadIdx.x; j < np; j += kBlock) {
+            const int q = seg[j];
+            const f32x4 r0 = rot[q][0], r1 = rot[q][1], r2 = rot[q][2];
+            CellRot cr;
+            cr.m[0] = r0.x; cr.m[1] = r0.y; cr.m[2] = r0.z; cr.m[3] = r0.w;
+            cr.m[4] = r1.x; cr.m[5] = r1.y; cr.m[6] = r1.z; cr.m[7] = r1.w;
+            cr.m[8] = r2.x; cr.t[0] = r2.y; cr.t[1] = r2.z; cr.t[2] = r2.w;
+            const float3 v = apply_rotation(cr, sv[0][j], sv[1][j], sv[2][j]);
+            vx[base + j] = v.x;
+            vy[base + j] = v.y;
+            vz[base + j] = v.z;
             diag_check(d, v);
-            if (vacf) vacf_term(b, pid[j], v, d);
+            if (vacf) vacf_term(b, pid[base + j], v, d);
         }
+        __syncthreads();   // the staging area is refilled by the next run
+        c = e;
     }
     step_flush(d, vacf, dacc + (size_t)tl.box * kAccLanes * 3, blockIdx.x);
 }
@@ -1398,7 +1520,12 @@ __device__ void box_stats_finish(const __int128 (&tot)[kNumDiag], const BoxDev* 
             st->vacf_len = 1;
         }
     }
-    st->status = (d[5] == 0.0 && d[3] < 1e300) ? 0 : -5;
+    // a new state (admission, mpcd_set_state) is judged on its own; a
+    // snapshot on demand only adds flags, so a box marked by a step (or by
+    // its initial state) stays marked
+    const bool ok = d[5] == 0.0 && d[3] < 1e300;
+    if (mode & kStatsOrigin) st->status = ok ? 0 : -5;
+    else if (!ok) st->status = -5;
 }
 
 // Exact sums of one box's per-tile partials, rounded once to FP64, and the

@@ -6,7 +6,7 @@ import pytest
 from oracle import oracle as orc
 from paper_2212_11878_amd import inputs
 
-from gpu_util import check_against
+from gpu_util import check_against, ulp_top
 
 pytestmark = pytest.mark.gpu
 
@@ -20,10 +20,16 @@ def mp():
     return mpcd
 
 
-def _ill_conditioned_cells(box, s, st, cells, limit=1e3):
-    """Cells whose inertia tensor is nearly singular but not exactly (three or
-    more almost collinear particles): there I^+ amplifies the FP32 rounding of
-    positions, so they are exempt from the 1e-5 velocity check."""
+def _ill_conditioned_cells(box, s, st, cells, limit=1e4):
+    """Cells whose inertia tensor I (about the centre of mass) has a condition
+    number above `limit` (three or more almost collinear particles).  The GPU
+    sums the position moments as fixed-point terms rounded to 2^-32 (relative
+    error about 1e-9 of I and of the angular-momentum change dL), and
+    omega = -I^+ dL amplifies a relative error of I or dL by up to cond(I), so
+    the rigid-rotation velocity omega x r' is held to 1e-5 only where
+    cond(I) 1e-9 stays below 1e-5: cond(I) <= 1e4.  Rank-deficient cells
+    (one or two particles, exactly collinear) are not exempt: their
+    pseudo-inverse drops the null direction on both sides."""
     bad = set()
     order = np.argsort(cells, kind="stable")
     cs = cells[order]
@@ -49,6 +55,12 @@ def _ill_conditioned_cells(box, s, st, cells, limit=1e3):
     dict(L=(6, 9, 5), n=2700, alpha=90.0, k=7, mass=True),
 ])
 def test_one_step_parity_am(mp, case, binning):
+    """One step of the angular-momentum rule.  Streaming is checked on its own
+    (GPU positions within 1 ulp of the oracle's streamed FP64 positions); the
+    collision is then checked with the oracle colliding at the GPU's streamed
+    positions, so that an ill-conditioned inertia tensor does not amplify the
+    FP32 rounding of the positions (only of the exact sums; see
+    _ill_conditioned_cells)."""
     print("[case] am", binning, case, flush=True)
     L, n = case["L"], case["n"]
     pos, vel = inputs.thermal_state(L, n, seed=41)
@@ -63,14 +75,23 @@ def test_one_step_parity_am(mp, case, binning):
         ctx.step(1)
         gp, gv, _ = ctx.get_state(s)
     box = orc.make_box(L, alpha_deg=case["alpha"], seed=41)
-    st = orc.State(pos, vel, None if mass is None else mass.astype(np.float64))
-    orc.stream(box, st)
+    m64 = None if mass is None else mass.astype(np.float64)
+    # streaming: the GPU's positions against the oracle's
+    ref = orc.State(pos, vel, m64)
+    orc.stream(box, ref)
+    edge = np.array(L, dtype=np.float64)[:, None]
+    dpos = gp.astype(np.float64) - ref.pos
+    dpos -= np.round(dpos / edge) * edge
+    assert np.max(np.abs(dpos)) <= ulp_top(max(L))
+    # collision at the GPU's streamed positions
+    st = orc.State(gp.astype(np.float64), vel.astype(np.float64), m64)
     sh = orc.shift(41, case["k"], 1.0)
     cells = orc.cells(box, sh, st)
     orc.collide_am(box, case["k"], st)
     bad = _ill_conditioned_cells(box, sh, st, cells)
     keep = ~np.isin(cells, np.fromiter(bad, dtype=np.int64, count=len(bad)))
-    assert keep.sum() > 0.97 * n
+    print("[case] am: %d of %d particles in cells with cond(I) > 1e4" % (n - keep.sum(), n), flush=True)
+    assert keep.sum() > 0.995 * n
     sub = orc.State(st.pos[:, keep], st.vel[:, keep])
     check_against(sub, sh, cells[keep], box, gp[:, keep], gv[:, keep])
 
