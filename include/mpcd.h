@@ -296,9 +296,24 @@ const char* mpcd_strerror(int status);
 /* MPCD_ABI_VERSION of the loaded library. */
 int mpcd_abi_version(void);
 
+/* Exact total momentum and twice the kinetic energy of n particles held in
+ * caller device arrays -- the quantities the collision conserves (Sec. 2),
+ * summed as mpcd_observe sums them (exact 64-bit fixed-point terms, 128-bit
+ * totals, each result rounded once to FP64): vx, vy, vz (device, n floats
+ * each), mass (device, n floats, or NULL for unit masses).  out (device, 5
+ * doubles) receives sum m v (3), sum m v^2 and the number of particles
+ * outside the range of the exact sums (velocity component >= 256 or not
+ * finite, mass outside [2^-8, 2^8]).  Works on HIP stream `stream` (NULL =
+ * the null stream) with a workspace of ceil(n / 4096) x 56 bytes that it
+ * allocates, and waits for the stream before it frees it.  EINVAL for bad
+ * arguments, EDEVICE if the allocation or a launch fails. */
+int mpcd_moments(const float* vx, const float* vy, const float* vz, const float* mass, int64_t n, double* out,
+                 void* stream);
+
 /* Measurement only (not part of the method): copy `bytes` bytes from device
  * src to device dst with the library's streaming copy kernel (16-byte loads
- * and stores, `blocks` workgroups of 256 threads, 0 = 4096) on HIP stream
+ * and stores, `blocks` workgroups of 256 threads each copying a contiguous
+ * chunk, 0 = 8192) on HIP stream
  * `stream` (NULL = the null stream), asynchronously.  Its rate is the
  * practical HBM ceiling the SRD kernels are compared with.  EINVAL unless
  * both pointers are 16-byte aligned and bytes is a multiple of 16. */

@@ -329,7 +329,7 @@ int rebuild_tables(mpcd_ctx* c)
     c->any_brick = c->any_sort = false;
     int max_bvol = 0;
     size_t brick_lds = 0;
-    bool brick_am = false, brick_wide = false;
+    bool brick_am = false, brick_wide = false, brick_ids = false;
     int64_t max_bucket = 0;
     bool brick_mass = false;
     for (int s = 0; s < (int)c->slots.size(); ++s) {
@@ -360,6 +360,7 @@ int rebuild_tables(mpcd_ctx* c)
             brick_mass |= b.m[0] != nullptr;
             brick_am |= b.conserve_l != 0;
             brick_wide |= b.nslot >= ((int64_t)1 << 30);   // byte offsets beyond 32 bits
+            brick_ids |= b.pid[0] != nullptr;
             brick_lds = std::max(brick_lds, (size_t)b.bmax[0] * b.bmax[1] * b.bmax[2] *
                                                 (b.conserve_l ? kAmCellBytes : kBrickCellBytes));
         }
@@ -390,6 +391,7 @@ int rebuild_tables(mpcd_ctx* c)
     c->T.brick_mass = brick_mass;
     c->T.brick_am = brick_am;
     c->T.brick_wide = brick_wide;
+    c->T.brick_ids = brick_ids;
     c->T.brick_lds = brick_lds;
     c->T.host_flag = c->host_flag_dev;
     // one upload for the tile lists (laid out as on the device) and one for
@@ -1273,11 +1275,28 @@ int mpcd_set_vacf(mpcd_ctx* c, int32_t slot, const float* v0, int64_t origin, co
     return MPCD_OK;
 }
 
+int mpcd_moments(const float* vx, const float* vy, const float* vz, const float* mass, int64_t n, double* out,
+                 void* stream)
+{
+    if (!out || n < 0 || (n > 0 && (!vx || !vy || !vz))) return MPCD_EINVAL;
+    if (n > ((int64_t)INT32_MAX) * kPartTile) return MPCD_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t ntile = std::max<int64_t>(1, (n + kPartTile - 1) / kPartTile);
+    long long* part = nullptr;
+    HIPCHK(hipMalloc((void**)&part, (size_t)ntile * kNumDiag * sizeof(long long)));
+    launch_moments(vx, vy, vz, mass, n, part, out, s);
+    const hipError_t e1 = hipGetLastError();
+    const hipError_t e2 = hipStreamSynchronize(s);   // the workspace is freed once the kernels have run
+    (void)hipFree(part);
+    if (e1 != hipSuccess || e2 != hipSuccess) return MPCD_EDEVICE;
+    return MPCD_OK;
+}
+
 int mpcd_hbm_copy(const void* src, void* dst, size_t bytes, int32_t blocks, void* stream)
 {
     if (!src || !dst || blocks < 0 || (bytes & 15) || (((uintptr_t)src | (uintptr_t)dst) & 15)) return MPCD_EINVAL;
     if (bytes == 0) return MPCD_OK;
-    launch_hbm_copy(src, dst, (int64_t)(bytes / 16), blocks > 0 ? blocks : 4096, (hipStream_t)stream);
+    launch_hbm_copy(src, dst, (int64_t)(bytes / 16), blocks > 0 ? blocks : 8192, (hipStream_t)stream);
     HIPCHK(hipGetLastError());
     return MPCD_OK;
 }

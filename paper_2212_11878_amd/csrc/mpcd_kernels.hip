@@ -283,7 +283,7 @@ __device__ __forceinline__ void vacf_term(const BoxDev& b, int32_t id, float3 v,
 //   4. one global reservation per group in the destination buckets, then
 //      stores.  Per step only the range check (and the VACF sum when a
 //      sample is due) is reduced; momentum and energy are summed on demand.
-template <int kT, int kS, bool kMass, bool kAM, bool kWide>
+template <int kT, int kS, bool kMass, bool kAM, bool kWide, bool kIds>
 __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tiles,
                                                     const BoxDev* __restrict__ boxes,
                                                     const BoxState* __restrict__ st,
@@ -579,7 +579,7 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
     MPCD_G float* const ovx = ugp(b.p[dst][3]);
     MPCD_G float* const ovy = ugp(b.p[dst][4]);
     MPCD_G float* const ovz = ugp(b.p[dst][5]);
-    const bool has_id = b.pid[src] != nullptr;   // uniform
+    const bool has_id = kIds && b.pid[src] != nullptr;   // uniform
     MPCD_G int32_t* const oid = has_id ? ugp(b.pid[dst]) : nullptr;
     const MPCD_G int32_t* const iid = has_id ? ugp(b.pid[src]) + beg : nullptr;   // bucket-relative
     const bool has_m = kMass && b.m[src] != nullptr;
@@ -1618,23 +1618,61 @@ __global__ __launch_bounds__(kBlock) void k_fill_zero_u32(uint32_t* __restrict__
         p[i] = 0u;
 }
 
-// Streaming copy of n16 16-byte words (each thread moves kU words per trip,
-// all loads issued before the stores): the practical HBM ceiling that the
-// step kernels are compared with.
+// Exact momentum and kinetic energy of n particles in caller arrays (the
+// diagnostics of k_snapshot without a box): workgroup t sums particles
+// [t kPartTile, (t + 1) kPartTile) into kNumDiag exact partials, then one
+// workgroup adds the partials in 128-bit integers and writes
+// out = (sum m v (3), sum m v^2, range violations), each rounded once.
+__global__ __launch_bounds__(kBlock) void k_moments_tiles(const float* __restrict__ vx, const float* __restrict__ vy,
+                                                           const float* __restrict__ vz, const float* __restrict__ m,
+                                                           int64_t n, long long* __restrict__ partials)
+{
+    const int64_t begin = (int64_t)blockIdx.x * kPartTile, end = min(n, begin + (int64_t)kPartTile);
+    long long d[kNumDiag] = {};
+    for (int64_t i = begin + threadIdx.x; i < end; i += kBlock)
+        diag_particle(d, make_float3(vx[i], vy[i], vz[i]), m ? m[i] : 1.0f);
+    block_diag(d, partials + (size_t)blockIdx.x * kNumDiag);
+}
+
+__global__ __launch_bounds__(kBlock) void k_moments_finish(const long long* __restrict__ partials, int ntile,
+                                                            double* __restrict__ out)
+{
+    __int128 acc[kNumDiag], tot[kNumDiag];
+#pragma unroll
+    for (int j = 0; j < kNumDiag; ++j) acc[j] = 0;
+    for (int t = threadIdx.x; t < ntile; t += kBlock)
+#pragma unroll
+        for (int j = 0; j < kNumDiag; ++j) acc[j] += partials[(size_t)t * kNumDiag + j];
+    block_sum128(acc, tot);
+    if (threadIdx.x == 0) {
+#pragma clang fp contract(off)
+        for (int j = 0; j < 3; ++j) out[j] = (double)tot[j] * 2.3283064365386963e-10;   // 2^-32
+        out[3] = (double)((tot[3] << 32) + tot[6]) * 2.3283064365386963e-10;
+        out[4] = (double)tot[5];
+    }
+}
+
+// Streaming copy of n16 16-byte words: workgroup g copies its own contiguous
+// chunk, each thread moving kU words per trip with every load issued before
+// the stores (the fastest of the copy forms measured on this GPU: grid-stride
+// with and without non-temporal hints, one to eight words per trip, 1024 to
+// 65536 workgroups).  It measures the practical HBM ceiling that the step
+// kernels are compared with.
 __global__ __launch_bounds__(kBlock) void k_hbm_copy(const f32x4* __restrict__ src, f32x4* __restrict__ dst,
                                                       int64_t n16)
 {
     constexpr int kU = 4;
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    for (; i + (kU - 1) * stride < n16; i += kU * stride) {
+    const int64_t per = (n16 + gridDim.x - 1) / gridDim.x;
+    const int64_t b0 = (int64_t)blockIdx.x * per, b1 = min(n16, b0 + per);
+    int64_t i = b0 + threadIdx.x;
+    for (; i + (kU - 1) * kBlock < b1; i += kU * kBlock) {
         f32x4 t[kU];
 #pragma unroll
-        for (int u = 0; u < kU; ++u) t[u] = src[i + u * stride];
+        for (int u = 0; u < kU; ++u) t[u] = src[i + u * kBlock];
 #pragma unroll
-        for (int u = 0; u < kU; ++u) dst[i + u * stride] = t[u];
+        for (int u = 0; u < kU; ++u) dst[i + u * kBlock] = t[u];
     }
-    for (; i < n16; i += stride) dst[i] = src[i];
+    for (; i < b1; i += kBlock) dst[i] = src[i];
 }
 
 // --------------------------------------------------------------------------
@@ -1645,29 +1683,31 @@ __global__ __launch_bounds__(kBlock) void k_hbm_copy(const f32x4* __restrict__ s
         if ((grid) > 0) hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, stream, __VA_ARGS__); \
     } while (0)
 
-template <int kT, int kS, bool kMass, bool kAM, bool kWide>
+template <int kT, int kS, bool kMass, bool kAM, bool kWide, bool kIds>
 static void brick_step_run(const Tables& T, hipStream_t s)
 {
     static bool attr = false;
     if (!attr) {   // the largest brick record (kMaxBrickCells or kMaxAmBrickCells cells)
-        (void)hipFuncSetAttribute((const void*)k_brick_step<kT, kS, kMass, kAM, kWide>,
+        (void)hipFuncSetAttribute((const void*)k_brick_step<kT, kS, kMass, kAM, kWide, kIds>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
         attr = true;
     }
-    hipLaunchKernelGGL((k_brick_step<kT, kS, kMass, kAM, kWide>), dim3(T.nbtiles), dim3(kT), T.brick_lds + 16, s,
-                       T.btiles, T.boxes, T.state, T.dacc);
+    hipLaunchKernelGGL((k_brick_step<kT, kS, kMass, kAM, kWide, kIds>), dim3(T.nbtiles), dim3(kT), T.brick_lds + 16,
+                       s, T.btiles, T.boxes, T.state, T.dacc);
 }
-// Instances: plain and per-particle masses with 32-bit store offsets (every
-// brick buffer below 2^30 slots), masses with 64-bit offsets, and the
-// angular-momentum rule (64-bit offsets; compute bound).  The masses
-// instances also serve boxes without masses.
+// Instances: plain without particle ids, plain and per-particle masses with
+// 32-bit store offsets (every brick buffer below 2^30 slots), masses with
+// 64-bit offsets, and the angular-momentum rule (64-bit offsets; compute
+// bound).  The masses instances also serve boxes without masses, and every
+// instance but the first serves boxes with and without ids.
 template <int kT, int kS>
 static void brick_step_at(const Tables& T, hipStream_t s)
 {
-    if (T.brick_am) brick_step_run<kT, kS, true, true, true>(T, s);
-    else if (T.brick_wide) brick_step_run<kT, kS, true, false, true>(T, s);
-    else if (T.brick_mass) brick_step_run<kT, kS, true, false, false>(T, s);
-    else brick_step_run<kT, kS, false, false, false>(T, s);
+    if (T.brick_am) brick_step_run<kT, kS, true, true, true, true>(T, s);
+    else if (T.brick_wide) brick_step_run<kT, kS, true, false, true, true>(T, s);
+    else if (T.brick_mass) brick_step_run<kT, kS, true, false, false, true>(T, s);
+    else if (T.brick_ids) brick_step_run<kT, kS, false, false, false, true>(T, s);
+    else brick_step_run<kT, kS, false, false, false, false>(T, s);
 }
 
 // Launch shapes of the brick step (workgroup size, particles per thread),
@@ -1785,6 +1825,13 @@ void launch_permute_f32(float* dst, const float* src, const int32_t* pid, int64_
 {
     const int64_t g = (nslot + kBlock - 1) / kBlock;
     MPCD_LAUNCH(k_permute_f32, (int)(g < 65536 ? g : 65536), kBlock, s, dst, src, pid, nslot, n, scatter);
+}
+void launch_moments(const float* vx, const float* vy, const float* vz, const float* m, int64_t n,
+                    long long* partials, double* out, hipStream_t s)
+{
+    const int ntile = (int)((n + kPartTile - 1) / kPartTile);
+    MPCD_LAUNCH(k_moments_tiles, ntile, kBlock, s, vx, vy, vz, m, n, partials);
+    hipLaunchKernelGGL(k_moments_finish, dim3(1), dim3(kBlock), 0, s, partials, ntile, out);
 }
 void launch_hbm_copy(const void* src, void* dst, int64_t n16, int blocks, hipStream_t s)
 {

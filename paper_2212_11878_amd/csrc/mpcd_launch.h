@@ -26,6 +26,7 @@ struct Tables {
     bool brick_mass = false;       // some brick box carries per-particle masses
     bool brick_am = false;         // some brick box uses the angular-momentum rule
     bool brick_wide = false;       // some brick box has buffers of 2^30 slots or more
+    bool brick_ids = false;        // some brick box keeps particle ids
     size_t brick_lds = 0;          // LDS bytes of the largest brick record
     int* host_flag = nullptr;      // host-visible: a brick box asks for re-bucketing
 };
@@ -57,6 +58,10 @@ void launch_mark_holes_box(const Tables& T, int32_t box, int ntile, hipStream_t 
 void launch_fill_iota(int32_t* p, int64_t n, hipStream_t s);
 void launch_fill_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
 void launch_hbm_copy(const void* src, void* dst, int64_t n16, int blocks, hipStream_t s);
+// exact momentum and energy of caller arrays: ceil(n / kPartTile) x kNumDiag
+// partials in `partials` (scratch), the five results in out (device)
+void launch_moments(const float* vx, const float* vy, const float* vz, const float* m, int64_t n,
+                    long long* partials, double* out, hipStream_t s);
 void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 void launch_permute_f32(float* dst, const float* src, const int32_t* pid, int64_t nslot, int64_t n, int scatter,
                         hipStream_t s);
