@@ -310,6 +310,18 @@ int mpcd_abi_version(void);
 int mpcd_moments(const float* vx, const float* vy, const float* vz, const float* mass, int64_t n, double* out,
                  void* stream);
 
+/* mpcd_moments for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, the same results bit for bit, but the workspace is a
+ * static device array of the library (3.5 MiB per GPU, kept until the process
+ * ends), so n may be at most 2^28 particles (EINVAL beyond), nothing is
+ * allocated or freed, and the call returns without waiting (out is written
+ * in stream order).  Every call on a GPU shares that GPU's workspace: calls
+ * whose work overlaps on one GPU (different streams, or host threads) race;
+ * calls ordered on one stream do not. */
+int mpcd_moments_noalloc(const float* vx, const float* vy, const float* vz, const float* mass, int64_t n,
+                         double* out, void* stream);
+
 /* Measurement only (not part of the method): copy `bytes` bytes from device
  * src to device dst with the library's streaming copy kernel (16-byte loads
  * and stores, `blocks` workgroups of 256 threads each copying a contiguous

@@ -10,6 +10,7 @@
 #include <string>
 #include <chrono>
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include "mpcd.h"
@@ -1289,6 +1290,50 @@ int mpcd_moments(const float* vx, const float* vy, const float* vz, const float*
     const hipError_t e2 = hipStreamSynchronize(s);   // the workspace is freed once the kernels have run
     (void)hipFree(part);
     if (e1 != hipSuccess || e2 != hipSuccess) return MPCD_EDEVICE;
+    return MPCD_OK;
+}
+
+// Workspace of mpcd_moments_noalloc: the partials of at most
+// kMomentsMaxTiles particle tiles (n <= 2^28 particles; 3.5 MiB), one copy
+// per GPU, held until the process ends.  Host code never uses the array's
+// name as an address: each device's address comes from hipGetSymbolAddress,
+// taken once per device with that device current.
+constexpr int64_t kMomentsMaxTiles = 65536;
+static __device__ __align__(256) long long scratch[kMomentsMaxTiles * kNumDiag];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mutex;
+long long* scratch_ptr[kMaxDevices] = {};
+
+// scratch's address on the current device (looked up on its first use there)
+int scratch_address(long long** out)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return MPCD_EDEVICE;
+    std::lock_guard<std::mutex> lock(scratch_mutex);
+    if (!scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return MPCD_EDEVICE;
+        scratch_ptr[dev] = (long long*)p;
+    }
+    *out = scratch_ptr[dev];
+    return MPCD_OK;
+}
+}  // namespace
+
+int mpcd_moments_noalloc(const float* vx, const float* vy, const float* vz, const float* mass, int64_t n,
+                         double* out, void* stream)
+{
+    if (!out || n < 0 || (n > 0 && (!vx || !vy || !vz))) return MPCD_EINVAL;
+    if (n > kMomentsMaxTiles * kPartTile) return MPCD_EINVAL;
+    long long* part = nullptr;
+    const int rc = scratch_address(&part);
+    if (rc) return rc;
+    launch_moments(vx, vy, vz, mass, n, part, out, (hipStream_t)stream);
+    HIPCHK(hipGetLastError());
     return MPCD_OK;
 }
 

@@ -119,6 +119,8 @@ _SIGNATURES = {
                                      ctypes.c_void_p]),
     "mpcd_moments": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
+    "mpcd_moments_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
     "mpcd_release": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "mpcd_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "mpcd_kernel_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(mpcd_kernel_stat), ctypes.c_int32,
@@ -247,6 +249,12 @@ def mpcd_moments(vx_ptr, vy_ptr, vz_ptr, mass_ptr, n, out_ptr, stream=None):
     return _lib.mpcd_moments(ctypes.c_void_p(vx_ptr), ctypes.c_void_p(vy_ptr), ctypes.c_void_p(vz_ptr),
                              ctypes.c_void_p(mass_ptr) if mass_ptr else None, int(n), ctypes.c_void_p(out_ptr),
                              ctypes.c_void_p(stream) if stream else None)
+
+
+def mpcd_moments_noalloc(vx_ptr, vy_ptr, vz_ptr, mass_ptr, n, out_ptr, stream=None):
+    return _lib.mpcd_moments_noalloc(ctypes.c_void_p(vx_ptr), ctypes.c_void_p(vy_ptr), ctypes.c_void_p(vz_ptr),
+                                     ctypes.c_void_p(mass_ptr) if mass_ptr else None, int(n),
+                                     ctypes.c_void_p(out_ptr), ctypes.c_void_p(stream) if stream else None)
 
 
 def mpcd_release(ctx, slot):
