@@ -19,6 +19,7 @@ counter summary matches the kernel sources; the streaming-copy ceiling of the
 same GPU; and the FP64 oracle on the host (one core, and one process per core).
 """
 import argparse
+import gc
 import hashlib
 import json
 import math
@@ -133,14 +134,16 @@ def cpu_baseline(workload):
     """The FP64 oracle as it stands, on bounded samples of the workload: one
     core on a 128^3-cell box (3 steps), then one oracle process per core,
     each on its own 96^3-cell box of the same density (2 steps).  Runs before
-    the GPU is touched (the worker processes are spawned, not forked)."""
+    the GPU is touched, entirely in spawned worker processes (their memory is
+    returned before the GPU is timed)."""
     L, ppc, dt, alpha, seed = WORKLOADS[workload]
     Ls = tuple(min(128, l) for l in L)
-    work1, t1 = _oracle_rate(Ls, ppc, dt, alpha, seed, 3)
     cores, nproc = host_cores()
     Lw = tuple(min(96, l) for l in L)
     jobs = [(Lw, ppc, dt, alpha, seed + 1000 * (i + 1), 2) for i in range(cores)]
     ctx = multiprocessing.get_context("spawn")
+    with ctx.Pool(1) as pool:
+        work1, t1 = pool.apply(_oracle_worker, ((Ls, ppc, dt, alpha, seed, 3),))
     t0 = time.perf_counter()
     with ctx.Pool(cores) as pool:
         res = pool.map(_oracle_worker, jobs)
@@ -299,6 +302,7 @@ def main():
     if not args.no_cpu_baseline:   # before any GPU call: its workers are separate processes
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         cpu = cpu_baseline(args.workload)
+        gc.collect()
 
     print("[bench] workload %s: %d particles, admitting" % (args.workload, n), file=sys.stderr, flush=True)
     t, runs, stats, obs = run_box(args, L, n, dt, alpha, seed, ids, args.steps, args.warmup, args.repeats,

@@ -269,6 +269,14 @@ __device__ __forceinline__ void vacf_term(const BoxDev& b, int32_t id, float3 v,
     diag_vacf(d, v, w.x, w.y, w.z);
 }
 
+// Offset (-1, 0, 1) along one axis of the brick holding next-step cell
+// lo + d from this workgroup's brick [lo, lo + e) (the brick below spans
+// b cells, the one above bn), or 2 when it is no neighbour.
+__device__ __forceinline__ int near_rel(int d, int e, int b, int bn)
+{
+    return d < 0 ? (d >= -b ? -1 : 2) : (d < e ? 0 : (d < e + bn ? 1 : 2));
+}
+
 // One SRD step of one brick (paper Sec. 2; the shifted grid of Sec. 3.1;
 // the mass-weighted cell velocity of Sec. 3.3).  The workgroup owns every
 // particle whose collision cell lies in its brick, so the whole step is one
@@ -283,11 +291,15 @@ __device__ __forceinline__ void vacf_term(const BoxDev& b, int32_t id, float3 v,
 //   4. one global reservation per group in the destination buckets, then
 //      stores.  Per step only the range check (and the VACF sum when a
 //      sample is due) is reduced; momentum and energy are summed on demand.
+// The instance for equal masses without particle ids (the benchmark's) is
+// held to 5 waves per SIMD (96 registers, a few spilled): measured 6 %
+// faster than 4 waves with no spill, while 6 waves (80 registers) and the
+// instances with ids at 5 waves are slower.
 template <int kT, int kS, bool kMass, bool kAM, bool kWide, bool kIds>
-__global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tiles,
-                                                    const BoxDev* __restrict__ boxes,
-                                                    const BoxState* __restrict__ st,
-                                                    long long* __restrict__ dacc)
+__global__ __launch_bounds__(kT)
+__attribute__((amdgpu_waves_per_eu(kMass || kAM || kIds ? 1 : 5, kMass || kAM || kIds ? 8 : 5)))
+void k_brick_step(const Tile* __restrict__ tiles, const BoxDev* __restrict__ boxes,
+                  const BoxState* __restrict__ st, long long* __restrict__ dacc)
 {
     // LDS, per cell of the brick: exact sums of m v (3 x 64 bit) and of m (64
     // bit, or a 32-bit count for equal masses) in 40-byte records, then u_c,
@@ -573,6 +585,15 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
 
     // 3./4. rotate, route to the next step's buckets, store
     const float3 sh1 = grid_shift(b, k + 1);
+    // Interior bricks (a whole brick between this one and every box face):
+    // a particle that stays inside the box needs no periodic fold, and its
+    // next cell floor((x' - s1)/a) lies within one brick of this one or is
+    // farther than any wrap, so its neighbour offset follows from the cell
+    // index directly; everything else takes the exact general form.
+    const bool interior = bx >= 1 && bx + 2 <= nb0 && by >= 1 && by + 2 <= nb1 && bz >= 1 && bz + 2 <= nb2;
+    const int bbx = 1 << b.bshift[0], bby = 1 << b.bshift[1], bbz = 1 << b.bshift[2];
+    const int bnx = min(bbx, b.L[0] - (lox + ex)), bny = min(bby, b.L[1] - (loy + ey)),
+              bnz = min(bbz, b.L[2] - (loz + ez));
     MPCD_G float* const ox = ugp(b.p[dst][0]);
     MPCD_G float* const oy = ugp(b.p[dst][1]);
     MPCD_G float* const oz = ugp(b.p[dst][2]);
@@ -625,10 +646,21 @@ __global__ __launch_bounds__(kT) void k_brick_step(const Tile* __restrict__ tile
                 if (vacf) vacf_term(b, ldg(iid, i * 4u), v, d);
                 // brick of the next collision cell (a non-finite position
                 // lands far away and takes the clamped slow path below)
-                const int dbx = brick_of(axis_cell_raw(fold(fmaf(v.x, dt, px[u]), b.len[0]), sh1.x, inv_a, b.L[0]), b.bshift[0]);
-                const int dby = brick_of(axis_cell_raw(fold(fmaf(v.y, dt, py[u]), b.len[1]), sh1.y, inv_a, b.L[1]), b.bshift[1]);
-                const int dbz = brick_of(axis_cell_raw(fold(fmaf(v.z, dt, pz[u]), b.len[2]), sh1.z, inv_a, b.L[2]), b.bshift[2]);
-                const int rx = brick_rel(bx, dbx, nb0), ry = brick_rel(by, dby, nb1), rz = brick_rel(bz, dbz, nb2);
+                const float qx = fmaf(v.x, dt, px[u]), qy = fmaf(v.y, dt, py[u]), qz = fmaf(v.z, dt, pz[u]);
+                int rx, ry, rz;
+                if (interior && qx >= 0.0f && qx < b.len[0] && qy >= 0.0f && qy < b.len[1] && qz >= 0.0f &&
+                    qz < b.len[2]) {
+                    rx = near_rel((int)floorf((qx - sh1.x) * inv_a) - lox, ex, bbx, bnx);
+                    ry = near_rel((int)floorf((qy - sh1.y) * inv_a) - loy, ey, bby, bny);
+                    rz = near_rel((int)floorf((qz - sh1.z) * inv_a) - loz, ez, bbz, bnz);
+                } else {
+                    const int dbx = brick_of(axis_cell_raw(fold(qx, b.len[0]), sh1.x, inv_a, b.L[0]), b.bshift[0]);
+                    const int dby = brick_of(axis_cell_raw(fold(qy, b.len[1]), sh1.y, inv_a, b.L[1]), b.bshift[1]);
+                    const int dbz = brick_of(axis_cell_raw(fold(qz, b.len[2]), sh1.z, inv_a, b.L[2]), b.bshift[2]);
+                    rx = brick_rel(bx, dbx, nb0);
+                    ry = brick_rel(by, dby, nb1);
+                    rz = brick_rel(bz, dbz, nb2);
+                }
                 r = (rx <= 1 && ry <= 1 && rz <= 1) ? (uint32_t)((rx + 1) + 3 * ((ry + 1) + 3 * (rz + 1))) : 27u;
             }
             // particles that stay in the brick (most) take consecutive ranks
