@@ -74,8 +74,10 @@ def context_options():
 
 
 def kernel_sources_sha():
+    """Hash of the sources that decide a step's memory traffic (kernels, and
+    the engine's bucket layout and launch order)."""
     h = hashlib.sha256()
-    for f in ("mpcd_dev.h", "mpcd_kernels.hip"):
+    for f in ("mpcd_dev.h", "mpcd_kernels.hip", "mpcd_engine.hip"):
         with open(os.path.join(ROOT, "paper_2212_11878_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -252,6 +254,8 @@ def main():
     ap.add_argument("--rate", type=float, nargs="+", default=[200.0],
                     help="served: arrival rates (req/s) to sweep")
     ap.add_argument("--window", type=float, default=60.0, help="served: seconds of arrivals")
+    ap.add_argument("--compare-serial", action="store_true",
+                    help="served: also serve the same requests one box at a time")
     ap.add_argument("--binning", default="auto", choices=["auto", "atomic", "sort"])
     ap.add_argument("--brick", type=int, nargs=3, default=[0, 0, 0])
     ap.add_argument("--masses", action="store_true",
@@ -432,20 +436,35 @@ def bench_ensemble(args):
 
 
 def bench_served(args):
-    """Continuous batching of Poisson-arriving single-box requests; p50/p99
-    latency and sustained throughput per arrival rate."""
+    """Continuous batching of Poisson-arriving single-box requests: p50/p99
+    latency and sustained throughput per arrival rate over a fixed window of
+    arrivals; with --compare-serial the same requests also go through the
+    same server one box at a time."""
     from paper_2212_11878_amd import inputs, serve
+
+    def served(reqs, max_live, label):
+        eng = serve.LibraryEngine(hbm_budget=64 << 30)
+
+        def report(p):
+            print("[bench] %s: t %.0f s, %d done, %d live, %d queued, %d not yet arrived"
+                  % (label, p["t"], p["completed"], p["live"], p["queued"], p["pending"]),
+                  file=sys.stderr, flush=True)
+        summary, _ = serve.Server(eng, chunk_steps=50, max_live=max_live).run(
+            reqs, max_wall_s=args.window * 2, progress=report)
+        eng.close()
+        summary["offered_particle_steps_per_s"] = sum(r["n"] * r["steps"] for r in reqs) / args.window
+        print("[bench] %s: %r" % (label, summary), file=sys.stderr, flush=True)
+        return summary
+
     sweep = []
     for rate in args.rate:
         reqs = inputs.served_requests(rate_hz=rate, window_s=args.window, seed=5)
-        eng = serve.LibraryEngine(hbm_budget=64 << 30)
         print("[bench] served: %g req/s, %d requests" % (rate, len(reqs)), file=sys.stderr, flush=True)
-        summary, done = serve.Server(eng, chunk_steps=50).run(reqs, max_wall_s=args.window * 3)
-        eng.close()
+        summary = served(reqs, None, "served %g req/s" % rate)
         summary["rate_hz"] = rate
-        summary["offered_particle_steps_per_s"] = sum(r["n"] * r["steps"] for r in reqs) / args.window
+        if args.compare_serial:
+            summary["one_at_a_time"] = served([dict(r) for r in reqs], 1, "one at a time %g req/s" % rate)
         sweep.append(summary)
-        print("[bench] served %g req/s: %r" % (rate, summary), file=sys.stderr, flush=True)
     head = sweep[-1]
     out = {"metric": "p50/p99 request latency and particle-steps/s", "value": head["particle_steps_per_s"],
            "unit": "particle-steps/s", "n_gpus": 1, "steps": None, "warmup": None, "ms_per_step": None,
@@ -453,7 +472,8 @@ def bench_served(args):
            "data": "synthetic",
            "config": {"workload": SERVED, "edges": "U{8..64}", "density": "U[5,20]", "dt": "U[0.05,0.2]",
                       "alpha_deg": "U[90,150]", "steps": "U{200..2000}", "window_s": args.window,
-                      "rate_hz": head["rate_hz"], "vacf_stride": 10, "chunk_steps": 50},
+                      "max_wall_s": args.window * 2, "rate_hz": head["rate_hz"], "vacf_stride": 10,
+                      "chunk_steps": 50},
            "p50_latency_s": head["p50_latency_s"], "p99_latency_s": head["p99_latency_s"],
            "sweep": sweep}
     print(json.dumps(out), flush=True)

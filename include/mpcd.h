@@ -274,6 +274,8 @@ int mpcd_set_vacf(mpcd_ctx* ctx, int32_t slot, const float* v0, int64_t origin, 
  * which must be stream-ordered (work already queued on the context stream
  * may still read it; hipFree, the default, waits for the device).  The box
  * tables are rebuilt before the next step.  ENOTFOUND for a slot not live.
+ * This is also how a request is cancelled in flight: released with steps of
+ * it still queued, the box stops there and the other boxes go on unchanged.
  * (Slots are this library's unit of batching; the paper has none.) */
 int mpcd_release(mpcd_ctx* ctx, int32_t slot);
 

@@ -53,3 +53,41 @@ def test_budget_admission_queues_requests(serve):
     eng.close()
     assert summary["completed"] == len(reqs)
     assert max(d["queued"] for d in done) > 0.0     # some waited for memory
+
+
+def test_cancel_in_flight_leaves_the_others_unchanged(serve):
+    """One request is cancelled while its box is live, with steps of it still
+    queued on the device: its memory is released at once, and every other
+    request's temperature and VACF equal those of the uncancelled mix bit for
+    bit."""
+    print("[case] serve cancel", flush=True)
+    reqs = _small_requests()
+    victim = max(reqs, key=lambda r: r["steps"])
+    eng = serve.LibraryEngine(hbm_budget=1 << 30, vacf_stride=5)
+    _, full = serve.Server(eng, chunk_steps=16).run([dict(r) for r in reqs])
+    eng.close()
+
+    eng = serve.LibraryEngine(hbm_budget=1 << 30, vacf_stride=5)
+    srv = serve.Server(eng, chunk_steps=16)
+    calls = [0]
+    real_step = eng.step
+
+    def step(n):       # cancel after the third chunk is queued (no sync in between)
+        real_step(n)
+        calls[0] += 1
+        if calls[0] == 3:
+            srv.cancel(victim["seed"])
+    eng.step = step
+    summary, part = srv.run([dict(r) for r in reqs])
+    eng.close()
+    assert summary["cancelled"] == 1 and summary["completed"] == len(reqs) - 1
+    a = {d["req"]["seed"]: d for d in full}
+    b = {d["req"]["seed"]: d for d in part}
+    assert b[victim["seed"]]["status"] == "cancelled"
+    assert 0 < b[victim["seed"]]["step"] < victim["steps"]
+    for r in reqs:
+        if r["seed"] == victim["seed"]:
+            continue
+        assert b[r["seed"]]["step"] == a[r["seed"]]["step"] == r["steps"]
+        assert b[r["seed"]]["T"] == a[r["seed"]]["T"]
+        assert np.array_equal(b[r["seed"]]["vacf"], a[r["seed"]]["vacf"])
