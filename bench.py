@@ -52,12 +52,13 @@ SERVED = "served_poisson"            # Poisson arrivals of single-box requests
 #                write x, v (24 B); the cell sums live and die in LDS   -> 48 P
 #   cell_rotate: read v, write v                                      -> 24 P
 #   scatter    : read x, v (24 B), write them (24 B)                  -> 48 P
-#   count      : read x (12 B), write the key (4 B)                   -> 16 P
+#   count      : read x, v (24 B: the key is the streamed position's
+#                cell), write the key (4 B)                           -> 28 P
 ALGO_BYTES = {
     "brick_step": (48, 0),
     "cell_rotate": (24, 0),
     "scatter": (48, 0),
-    "count": (16, 0),
+    "count": (28, 0),
 }
 # the whole step: every particle's x and v read once and written once
 STEP_ALGO_BYTES_PER_PARTICLE = 48
@@ -254,6 +255,8 @@ def main():
     ap.add_argument("--rate", type=float, nargs="+", default=[200.0],
                     help="served: arrival rates (req/s) to sweep")
     ap.add_argument("--window", type=float, default=60.0, help="served: seconds of arrivals")
+    ap.add_argument("--hybrid", action="store_true",
+                    help="ensemble: also split the boxes between the GPU and the host's cores")
     ap.add_argument("--compare-serial", action="store_true",
                     help="served: also serve the same requests one box at a time")
     ap.add_argument("--binning", default="auto", choices=["auto", "atomic", "sort"])
@@ -421,6 +424,7 @@ def bench_ensemble(args):
     solo.close()
     value = total * args.steps / t_batch
     one = total * args.steps / t_one
+    hybrid = bench_hybrid(args, boxes, value) if args.hybrid else None
     out = {"metric": "particle-steps/s", "value": value, "unit": "particle-steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1000 * t_batch / args.steps,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -432,7 +436,36 @@ def bench_ensemble(args):
            "nonfinite_boxes": len(bad),
            "kernels": {k: {"launches": v[0], "avg_ms": round(v[1] / max(1, v[0]), 4)}
                        for k, v in stats.items()}}
+    if hybrid is not None:
+        out["hybrid_cpu_gpu"] = hybrid
     print(json.dumps(out), flush=True)
+
+
+def bench_hybrid(args, boxes, gpu_rate):
+    """The same boxes split between the GPU and the host's cores (the CPU leg,
+    one box per worker thread), in the proportion of the two measured rates,
+    both advancing at once."""
+    from paper_2212_11878_amd import hybrid
+    workers = hybrid.host_workers()
+    print("[bench] hybrid: host rate on %d workers" % workers, file=sys.stderr, flush=True)
+    cpu_rate = hybrid.host_rate(boxes, workers)
+    frac = cpu_rate / (cpu_rate + gpu_rate)
+    host_idx = hybrid.split(boxes, frac)
+    ens = hybrid.HybridEnsemble(boxes, host_idx, workers=workers, **context_options())
+    total = sum(b["n"] for b in boxes)
+    ens.step(args.warmup)
+    print("[bench] hybrid: %d boxes on the host (%.3f of the particles), %d on the GPU"
+          % (len(host_idx), sum(boxes[i]["n"] for i in host_idx) / total, len(ens.gpu_idx)),
+          file=sys.stderr, flush=True)
+    wall, t_gpu, t_host = ens.step(args.steps)
+    obs = ens.observe()
+    ens.close()
+    rate = total * args.steps / wall
+    return {"value": rate, "ms_per_step": 1000 * wall / args.steps, "over_gpu_only": rate / gpu_rate,
+            "host_workers": workers, "host_rate_measured": cpu_rate, "host_boxes": len(host_idx),
+            "host_particle_fraction": sum(boxes[i]["n"] for i in host_idx) / total,
+            "host_side_ms_per_step": 1000 * t_host / args.steps,
+            "bad_status_boxes": sum(1 for o in obs if o["status"] != 0)}
 
 
 def bench_served(args):

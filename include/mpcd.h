@@ -56,7 +56,7 @@
 extern "C" {
 #endif
 
-#define MPCD_ABI_VERSION 3
+#define MPCD_ABI_VERSION 4
 
 typedef enum {
     MPCD_OK = 0,
@@ -323,6 +323,32 @@ int mpcd_moments(const float* vx, const float* vy, const float* vz, const float*
  * calls ordered on one stream do not. */
 int mpcd_moments_noalloc(const float* vx, const float* vy, const float* vz, const float* mass, int64_t n,
                          double* out, void* stream);
+
+/* The CPU leg of hybrid CPU+GPU execution (Sec. 3.2 and Sec. 4, Fig. 2f: part
+ * of a run's work on the host's cores next to the GPU).  Advances one box
+ * held in host memory by n_steps SRD steps, steps step .. step + n_steps - 1,
+ * on `threads` host threads (0 = every core), with the GPU path's method and
+ * random streams: streaming with the periodic fold (Sec. 2), the grid shift
+ * of Sec. 3.1 and the per-cell axes drawn from Philox4x32-10 keyed by
+ * desc->seed, exact fixed-point cell sums (the mass-weighted mean of Sec. 3.3
+ * with MPCD_PARTICLE_MASS), the cell's collision map built in FP64 and
+ * applied in FP32; binning is a counting sort by collision cell every step.
+ * Results match the GPU's within the parity tolerance (the host's sinf/cosf
+ * can move an axis by one unit in the last place).
+ *   xyzv: host, 6 n floats SoA (x, y, z, vx, vy, vz), positions in [0, L a),
+ *         updated in place; on return the particles are in the cell order of
+ *         the last step;
+ *   mass: host, n floats in [2^-8, 2^8] with MPCD_PARTICLE_MASS, else NULL;
+ *   pid:  host, n int32 or NULL, any values (e.g. particle ids);
+ * mass and pid travel with their particles.  The caller owns every buffer;
+ * the call allocates host memory of about 40 bytes per particle and 8 per
+ * cell for its duration, and returns when the steps are done.  EINVAL for a
+ * descriptor mpcd_admit refuses, MPCD_CONSERVE_L (GPU only), a position
+ * outside the box or a non-finite velocity (the state is then untouched);
+ * ESTATE when a velocity leaves the range of the exact sums or a cell holds
+ * 4096 particles or more (the state then holds the steps' results). */
+int mpcd_host_step(const mpcd_box_desc* desc, float* xyzv, float* mass, int32_t* pid, int64_t step,
+                   int32_t n_steps, int32_t threads);
 
 /* Measurement only (not part of the method): copy `bytes` bytes from device
  * src to device dst with the library's streaming copy kernel (16-byte loads

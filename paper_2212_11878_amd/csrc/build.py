@@ -11,7 +11,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 LIB_PATH = os.path.join(PKG, "libmpcd.so")
-SOURCES = ["mpcd_kernels.hip", "mpcd_engine.hip"]
+SOURCES = ["mpcd_kernels.hip", "mpcd_engine.hip", "mpcd_host.hip"]
+# host code of the CPU leg: fused multiply-add and AVX2 (x86-64-v3; every
+# EPYC and every Xeon since Haswell), so fmaf is one instruction
+EXTRA_FLAGS = {"mpcd_host.hip": ["-Xarch_host", "-mfma", "-Xarch_host", "-mavx2"]}
 HEADERS = ["mpcd_dev.h", "mpcd_launch.h"]
 ARCH = os.environ.get("MPCD_OFFLOAD_ARCH", "gfx950")
 
@@ -31,7 +34,7 @@ def build(verbose=False, jobs=2):
     objs, procs = [], []
     for src in SOURCES:
         obj = os.path.join(bdir, src.replace(".hip", ".o"))
-        cmd = [_hipcc()] + flags + ["-c", os.path.join(HERE, src), "-o", obj]
+        cmd = [_hipcc()] + flags + EXTRA_FLAGS.get(src, []) + ["-c", os.path.join(HERE, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))

@@ -35,6 +35,7 @@ constexpr int kBlock = 256;          // threads per workgroup of the particle ke
 constexpr int kPartTile = 4096;      // particles per particle tile (16 per thread)
 constexpr int kCellTile = 2048;      // cells per cell tile
 constexpr int kMaxBrickCells = 1024; // cells of one brick (LDS of its workgroup)
+constexpr int kSortBlockShift = 4;    // the counting sort orders cells in blocks of 16^3
 constexpr int kAccWords = 5;         // 64-bit words per brick cell's sums record (4 used)
 constexpr int kUnWords = 12;         // 32-bit words per brick cell's data record (7 used)
 constexpr int kBrickCellBytes = 8 * kAccWords + 4 * kUnWords;   // LDS per brick cell
@@ -112,6 +113,7 @@ struct BoxDev {
     int32_t nb[3];         // bricks per dimension
     int32_t bshift[3];     // brick edge 2^bshift cells per dimension
     int32_t bmax[3];       // largest brick extent per dimension
+    int32_t sshift[3];     // block edge 2^sshift cells of the counting sort's cell order
     int32_t nbrick;
     int32_t vacf_stride;   // 0 = untracked
     int32_t vacf_cap;
@@ -200,13 +202,18 @@ struct Tile {
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64-bit
 // products whose halves are exchanged with the odd words and the round key;
 // the key advances by the Weyl increments after every round.
-__device__ __forceinline__ uint4 philox4x32_10(uint4 ctr, uint32_t k0, uint32_t k1)
+__host__ __device__ __forceinline__ uint32_t mulhi32(uint32_t a, uint32_t b)
+{
+    return (uint32_t)(((uint64_t)a * b) >> 32);
+}
+
+__host__ __device__ __forceinline__ uint4 philox4x32_10(uint4 ctr, uint32_t k0, uint32_t k1)
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint32_t a = ctr.x, b = ctr.z;
-        const uint32_t lo_a = a * 0xD2511F53u, hi_a = __umulhi(a, 0xD2511F53u);
-        const uint32_t lo_b = b * 0xCD9E8D57u, hi_b = __umulhi(b, 0xCD9E8D57u);
+        const uint32_t lo_a = a * 0xD2511F53u, hi_a = mulhi32(a, 0xD2511F53u);
+        const uint32_t lo_b = b * 0xCD9E8D57u, hi_b = mulhi32(b, 0xCD9E8D57u);
         ctr = make_uint4(hi_b ^ ctr.y ^ k0, lo_b, hi_a ^ ctr.w ^ k1, lo_a);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
@@ -215,13 +222,13 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 ctr, uint32_t k0, uint32_t 
 }
 
 // top 24 bits as a float in [0, 1); exact
-__device__ __forceinline__ float unit24(uint32_t r)
+__host__ __device__ __forceinline__ float unit24(uint32_t r)
 {
     return (float)(r >> 8) * 5.9604644775390625e-8f;   // 2^-24
 }
 
 // Grid shift of step k: s_d = a (u_d - 1/2), stream 0.
-__device__ __forceinline__ float3 grid_shift(const BoxDev& b, long long k)
+__host__ __device__ __forceinline__ float3 grid_shift(const BoxDev& b, long long k)
 {
     const uint4 r = philox4x32_10(
         make_uint4((uint32_t)k, 0u, (uint32_t)((unsigned long long)k >> 32), 0u), b.key0, b.key1);
@@ -268,15 +275,18 @@ __host__ __device__ __forceinline__ float fold(float x, float len)
 // folded periodically: for x in [0, L a) and |s| <= a/2 the floor lies in
 // [-1, L], so one add or subtract wraps it.  axis_cell_raw may return values
 // outside [0, L) for non-finite x (callers range-check it); axis_cell clamps.
-__device__ __forceinline__ int axis_cell_raw(float x, float s, float inv_a, int L)
+__host__ __device__ __forceinline__ int axis_cell_raw(float x, float s, float inv_a, int L)
 {
     unsigned i = (unsigned)(int)floorf((x - s) * inv_a);
-    i = min(i, i + (unsigned)L);   // -1 -> L - 1
-    return (int)min(i, i - (unsigned)L);   // L -> 0
+    const unsigned up = i + (unsigned)L;
+    i = up < i ? up : i;   // -1 -> L - 1
+    const unsigned dn = i - (unsigned)L;
+    return (int)(dn < i ? dn : i);   // L -> 0
 }
-__device__ __forceinline__ int axis_cell(float x, float s, float inv_a, int L)
+__host__ __device__ __forceinline__ int axis_cell(float x, float s, float inv_a, int L)
 {
-    return min(max(axis_cell_raw(x, s, inv_a, L), 0), L - 1);
+    const int c = axis_cell_raw(x, s, inv_a, L);
+    return c < 0 ? 0 : (c > L - 1 ? L - 1 : c);
 }
 
 __device__ __forceinline__ uint32_t collision_cell(const BoxDev& b, float x, float y, float z,
@@ -292,6 +302,65 @@ __device__ __forceinline__ uint32_t collision_cell(const BoxDev& b, float x, flo
 // [i 2^shift, min((i+1) 2^shift, L)).
 __host__ __device__ __forceinline__ int brick_lo(int i, int shift) { return i << shift; }
 __host__ __device__ __forceinline__ int brick_of(int c, int shift) { return c >> shift; }
+
+// Cell order of the counting sort (SORT binning): cells are numbered block by
+// block, in blocks of 2^sh[d] cells per dimension (blocks in x-fastest order,
+// cells x-fastest inside a block; the last block of a dimension may be
+// shorter, and the numbering stays dense over [0, L0 L1 L2)).  A particle
+// moves at most one cell per step, so in this order its new place in the
+// sorted buffer lies close to its old one and the scatter's writes stay
+// local.  sort_key maps cell (ix, iy, iz) to its position; cell_of_key maps
+// a position back to the cell index ix + L0 (iy + L1 iz).
+__host__ __device__ __forceinline__ uint32_t sort_key(const int32_t L[3], const int32_t sh[3], int ix, int iy, int iz)
+{
+    const uint64_t Lx = (uint64_t)L[0], Ly = (uint64_t)L[1], Lz = (uint64_t)L[2];
+    const uint64_t lox = (uint64_t)((ix >> sh[0]) << sh[0]), loy = (uint64_t)((iy >> sh[1]) << sh[1]),
+                   loz = (uint64_t)((iz >> sh[2]) << sh[2]);
+    const uint64_t bx = (uint64_t)1 << sh[0], by = (uint64_t)1 << sh[1], bz = (uint64_t)1 << sh[2];
+    const uint64_t ex = Lx - lox < bx ? Lx - lox : bx;
+    const uint64_t ey = Ly - loy < by ? Ly - loy : by;
+    const uint64_t ez = Lz - loz < bz ? Lz - loz : bz;
+    const uint64_t base = loz * Lx * Ly + ez * (loy * Lx + ey * lox);
+    return (uint32_t)(base + ((uint64_t)ix - lox) + ex * (((uint64_t)iy - loy) + ey * ((uint64_t)iz - loz)));
+}
+
+__host__ __device__ __forceinline__ uint32_t cell_of_key(const int32_t L[3], const int32_t sh[3], uint32_t key)
+{
+    // 32-bit arithmetic: with block edges clipped to the box, every product
+    // below is at most the number of cells (< 2^32)
+    const uint32_t Lx = (uint32_t)L[0], Ly = (uint32_t)L[1], Lz = (uint32_t)L[2];
+    const uint32_t bx = (1u << sh[0]) < Lx ? (1u << sh[0]) : Lx;
+    const uint32_t by = (1u << sh[1]) < Ly ? (1u << sh[1]) : Ly;
+    const uint32_t bz = (1u << sh[2]) < Lz ? (1u << sh[2]) : Lz;
+    uint32_t r = key;
+    // block layer along z (the last one may be thinner)
+    const uint32_t nz = (Lz + bz - 1) / bz;
+    uint32_t iz = r / (Lx * Ly * bz);
+    iz = iz < nz - 1 ? iz : nz - 1;
+    const uint32_t loz = iz * bz, ez = Lz - loz < bz ? Lz - loz : bz;
+    r -= loz * Lx * Ly;
+    // block row along y inside the layer
+    const uint32_t ny = (Ly + by - 1) / by;
+    uint32_t iy = r / (Lx * ez * by);
+    iy = iy < ny - 1 ? iy : ny - 1;
+    const uint32_t loy = iy * by, ey = Ly - loy < by ? Ly - loy : by;
+    r -= loy * Lx * ez;
+    // block along x inside the row
+    const uint32_t nx = (Lx + bx - 1) / bx;
+    uint32_t ix = r / (ey * ez * bx);
+    ix = ix < nx - 1 ? ix : nx - 1;
+    const uint32_t lox = ix * bx, ex = Lx - lox < bx ? Lx - lox : bx;
+    r -= lox * ey * ez;
+    const uint32_t cx = lox + r % ex, cy = loy + (r / ex) % ey, cz = loz + r / (ex * ey);
+    return cx + Lx * (cy + Ly * cz);
+}
+
+// Sort key of the collision cell of streamed position (x, y, z) under shift s.
+__device__ __forceinline__ uint32_t sort_cell(const BoxDev& b, float x, float y, float z, float3 s)
+{
+    return sort_key(b.L, b.sshift, axis_cell(x, s.x, b.inv_a, b.L[0]), axis_cell(y, s.y, b.inv_a, b.L[1]),
+                    axis_cell(z, s.z, b.inv_a, b.L[2]));
+}
 
 // Neighbour of brick b at offset r (-1, 0, 1) along a dimension with nb
 // bricks (periodic), or -1 when there is none (nb <= 2 and b + r outside).
@@ -412,7 +481,7 @@ constexpr uint32_t kMaxCellCount = 4096u;   // 2^12
 
 // Exact value of a two's-complement 64-bit fixed-point sum as FP64 (hi and
 // lo 32-bit halves are exact; their combination rounds once).
-__device__ __forceinline__ double fixed_to_double(unsigned long long s)
+__host__ __device__ __forceinline__ double fixed_to_double(unsigned long long s)
 {
 #pragma clang fp contract(off)
     const double hi = (double)(int)(unsigned)(s >> 32);
@@ -422,7 +491,7 @@ __device__ __forceinline__ double fixed_to_double(unsigned long long s)
 
 // Mass-weighted mean velocity of a cell, sum(m v) / sum(m), from the exact
 // fixed-point sums, in FP64: one reciprocal of the mass sum, three products.
-__device__ __forceinline__ void fixed_mean3(unsigned long long sx, unsigned long long sy, unsigned long long sz,
+__host__ __device__ __forceinline__ void fixed_mean3(unsigned long long sx, unsigned long long sy, unsigned long long sz,
                                             unsigned long long w, double u[3])
 {
 #pragma clang fp contract(off)
@@ -458,7 +527,7 @@ __device__ __forceinline__ float mass_of(const float* __restrict__ m, int64_t i)
 // from cell to cell, so they add no systematic change of the kinetic energy
 // (a rotation evaluated in FP32 with one cos(a), sin(a) pair for every cell
 // does: cos^2 + sin^2 != 1 by a fixed amount).
-__device__ __forceinline__ CellRot cell_rotation(double ux, double uy, double uz, float3 axis, double ca,
+__host__ __device__ __forceinline__ CellRot cell_rotation(double ux, double uy, double uz, float3 axis, double ca,
                                                  double sa)
 {
     double nx = axis.x, ny = axis.y, nz = axis.z;
@@ -484,7 +553,7 @@ __device__ __forceinline__ CellRot cell_rotation(double ux, double uy, double uz
 }
 
 // v' = M v + t (three fused multiply-adds per component, fixed order)
-__device__ __forceinline__ float3 apply_rotation(const CellRot& r, float vx, float vy, float vz)
+__host__ __device__ __forceinline__ float3 apply_rotation(const CellRot& r, float vx, float vy, float vz)
 {
     return make_float3(fmaf(r.m[0], vx, fmaf(r.m[1], vy, fmaf(r.m[2], vz, r.t[0]))),
                        fmaf(r.m[3], vx, fmaf(r.m[4], vy, fmaf(r.m[5], vz, r.t[1]))),

@@ -600,6 +600,9 @@ int init_maxwell(mpcd_ctx* c, int32_t s)
 
 }  // namespace
 
+// the descriptor check, for the host leg (mpcd_host.hip)
+int mpcd::validate_box_desc(const mpcd_box_desc* d) { return validate_desc(d); }
+
 // ==========================================================================
 // Autotuner: picks the binning (brick or sort) and the brick shape.  Boxes
 // below 2^21 cells, and boxes whose buffers reach 2^30 slots, take the shape
@@ -918,6 +921,7 @@ int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
         b.nb[k] = brick ? g.nb[k] : 1;
         b.bshift[k] = brick ? g.shift[k] : 0;
         b.bmax[k] = brick ? g.bmax[k] : d->L[k];
+        b.sshift[k] = kSortBlockShift;
     }
     b.nbrick = brick ? g.nbrick : 0;
     b.nslot = nslot;

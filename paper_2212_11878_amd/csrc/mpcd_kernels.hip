@@ -297,7 +297,7 @@ __device__ __forceinline__ int near_rel(int d, int e, int b, int bn)
 // instances with ids at 5 waves are slower.
 template <int kT, int kS, bool kMass, bool kAM, bool kWide, bool kIds>
 __global__ __launch_bounds__(kT)
-__attribute__((amdgpu_waves_per_eu(kMass || kAM || kIds ? 1 : 5, kMass || kAM || kIds ? 8 : 5)))
+__attribute__((amdgpu_waves_per_eu(kMass || kAM ? 1 : (kIds || kS > 6 ? 4 : 5), kMass || kAM || kIds || kS > 6 ? 8 : 5)))
 void k_brick_step(const Tile* __restrict__ tiles, const BoxDev* __restrict__ boxes,
                   const BoxState* __restrict__ st, long long* __restrict__ dacc)
 {
@@ -859,7 +859,8 @@ __global__ __launch_bounds__(kBlock) void k_zero_counts(const Tile* __restrict__
 }
 
 // Rank of every live slot among the slots with the same key (SORT: its
-// collision cell; re-bucketing: the brick of that cell), and the per-key
+// collision cell, numbered in the blocked order of sort_key; re-bucketing:
+// the brick of that cell), and the per-key
 // counts in cstart.  The tile is taken in halves of kCountHalf slots; each
 // half gathers its keys in an LDS hash table (open addressing, load factor at
 // most 1/2), so a key takes one global atomic per half-tile, and the atomics
@@ -934,8 +935,8 @@ __global__ __launch_bounds__(kBlock) void k_count(const Tile* __restrict__ tiles
                                          axis_cell(pz, sh.z, b.inv_a, b.L[2]));
                 const int3 d = brick_of_cell(b, c);
                 key = (uint32_t)(d.x + b.nb[0] * (d.y + b.nb[1] * d.z));
-            } else {
-                key = collision_cell(b, px, py, pz, sh);
+            } else {   // the position of its collision cell in the sort's cell order
+                key = sort_cell(b, px, py, pz, sh);
             }
             cell[i] = key;
             uint32_t hs = hash_slot(key);
@@ -1225,8 +1226,8 @@ __device__ void collide_cell_serial(const BoxDev& b, int par, long long k, uint3
     }
 }
 
-// SORT path: the particles of cell c occupy [cstart[c], cstart[c+1]) of the
-// current buffer, already streamed.  A workgroup takes its cell tile in runs
+// SORT path: the particles of the cell with sort key c (sort_key) occupy
+// [cstart[c], cstart[c+1]) of the current buffer, already streamed.  A workgroup takes its cell tile in runs
 // of at most kRotCells cells holding at most kRotCap particles: it stages the
 // run's velocities (and masses) in LDS with coalesced loads, one thread per
 // cell sums its particles from LDS (exact fixed point, the same terms as the
@@ -1260,7 +1261,8 @@ __global__ __launch_bounds__(kBlock) void k_cell_rotate(const Tile* __restrict__
         const float3 sh = grid_shift(b, k);
         for (int64_t c = tl.begin + threadIdx.x; c < tl.end; c += kBlock) {
             const uint32_t beg = b.cstart[c], end = b.cstart[c + 1];
-            if (beg != end) collide_cell_am(b, par, k, (uint32_t)c, beg, end, sh, b.ca, b.sa, d, vacf);
+            if (beg != end)
+                collide_cell_am(b, par, k, cell_of_key(b.L, b.sshift, (uint32_t)c), beg, end, sh, b.ca, b.sa, d, vacf);
         }
         step_flush(d, vacf, dacc + (size_t)tl.box * kAccLanes * 3, blockIdx.x);
         return;
@@ -1290,7 +1292,8 @@ __global__ __launch_bounds__(kBlock) void k_cell_rotate(const Tile* __restrict__
         const uint32_t np = cs[e] - base;
         if (np > (uint32_t)kRotCap) {   // one cell larger than the staging area
             if (threadIdx.x == 0)
-                collide_cell_serial(b, par, k, (uint32_t)(tl.begin + c), base, cs[e], d, vacf);
+                collide_cell_serial(b, par, k, cell_of_key(b.L, b.sshift, (uint32_t)(tl.begin + c)), base, cs[e], d,
+                                    vacf);
             c = e;
             continue;
         }
@@ -1317,8 +1320,8 @@ __global__ __launch_bounds__(kBlock) void k_cell_rotate(const Tile* __restrict__
                 }
                 double uc[3];
                 fixed_mean3(sx, sy, sz, sw, uc);
-                const CellRot cr = cell_rotation(uc[0], uc[1], uc[2],
-                                                 cell_axis(b, k, (uint32_t)(tl.begin + c + q)), b.ca, b.sa);
+                const uint32_t cell = cell_of_key(b.L, b.sshift, (uint32_t)(tl.begin + c + q));
+                const CellRot cr = cell_rotation(uc[0], uc[1], uc[2], cell_axis(b, k, cell), b.ca, b.sa);
                 f32x4 r0, r1, r2;
                 r0.x = cr.m[0]; r0.y = cr.m[1]; r0.z = cr.m[2]; r0.w = cr.m[3];
                 r1.x = cr.m[4]; r1.y = cr.m[5]; r1.z = cr.m[6]; r1.w = cr.m[7];

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "mpcd.h"
 #include "mpcd_dev.h"
 
 namespace mpcd {
@@ -58,6 +59,9 @@ void launch_mark_holes_box(const Tables& T, int32_t box, int ntile, hipStream_t 
 void launch_fill_iota(int32_t* p, int64_t n, hipStream_t s);
 void launch_fill_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
 void launch_hbm_copy(const void* src, void* dst, int64_t n16, int blocks, hipStream_t s);
+
+// mpcd_admit's check of a box descriptor (MPCD_OK or MPCD_EINVAL)
+int validate_box_desc(const mpcd_box_desc* d);
 // exact momentum and energy of caller arrays: ceil(n / kPartTile) x kNumDiag
 // partials in `partials` (scratch), the five results in out (device)
 void launch_moments(const float* vx, const float* vy, const float* vz, const float* m, int64_t n,

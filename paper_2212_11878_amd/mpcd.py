@@ -121,6 +121,9 @@ _SIGNATURES = {
                                     ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
     "mpcd_moments_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                             ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
+    "mpcd_host_step": (ctypes.c_int, [ctypes.POINTER(mpcd_box_desc), ctypes.POINTER(ctypes.c_float),
+                                      ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]),
     "mpcd_release": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "mpcd_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "mpcd_kernel_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(mpcd_kernel_stat), ctypes.c_int32,
@@ -146,7 +149,7 @@ for _name, (_res, _args) in _SIGNATURES.items():
     _f.argtypes = _args
 
 # layout of the structs above (include/mpcd.h, MPCD_ABI_VERSION)
-ABI_VERSION = 3
+ABI_VERSION = 4
 if _lib.mpcd_abi_version() != ABI_VERSION:
     raise ImportError("libmpcd.so has ABI version %d, this binding expects %d; rebuild it"
                       % (_lib.mpcd_abi_version(), ABI_VERSION))
@@ -255,6 +258,22 @@ def mpcd_moments_noalloc(vx_ptr, vy_ptr, vz_ptr, mass_ptr, n, out_ptr, stream=No
     return _lib.mpcd_moments_noalloc(ctypes.c_void_p(vx_ptr), ctypes.c_void_p(vy_ptr), ctypes.c_void_p(vz_ptr),
                                      ctypes.c_void_p(mass_ptr) if mass_ptr else None, int(n),
                                      ctypes.c_void_p(out_ptr), ctypes.c_void_p(stream) if stream else None)
+
+
+def mpcd_host_step(desc, xyzv, mass, pid, step, n_steps, threads=0):
+    """xyzv: float32 array of shape (6, n), C-contiguous, updated in place;
+    mass (float32, n) and pid (int32, n) likewise, or None.  The call runs
+    without the interpreter lock."""
+    def ptr(a, dtype, shape, ctype):
+        if a is None:
+            return None
+        if not (isinstance(a, np.ndarray) and a.dtype == dtype and a.flags.c_contiguous and a.shape == shape):
+            raise ValueError("expected a C-contiguous %s array of shape %s" % (np.dtype(dtype).name, shape))
+        return a.ctypes.data_as(ctypes.POINTER(ctype))
+    n = int(desc.n_particles)
+    return _lib.mpcd_host_step(ctypes.byref(desc), ptr(xyzv, np.float32, (6, n), ctypes.c_float),
+                               ptr(mass, np.float32, (n,), ctypes.c_float), ptr(pid, np.int32, (n,), ctypes.c_int32),
+                               int(step), int(n_steps), int(threads))
 
 
 def mpcd_release(ctx, slot):

@@ -4,7 +4,9 @@
 // group of a destination brick (brick_rel) maps back to it (brick_nbr) and is
 // unique per source; bucket capacities with slack leave an overflow bucket
 // that can take every particle; bucket_of_slot finds the bucket of every slot
-// when some buckets are empty.  Prints "ok" or the first mismatch.  Built
+// when some buckets are empty; the counting sort's blocked cell order
+// (sort_key) is a bijection that cell_of_key inverts.  Prints "ok" or the
+// first mismatch.  Built
 // with hipcc as host code.
 #include <cstdio>
 #include <cstdlib>
@@ -121,6 +123,41 @@ int main()
                     return 1;
                 }
             }
+    }
+    // the counting sort's blocked cell order: a bijection of the cells onto
+    // [0, L0 L1 L2) that cell_of_key inverts (every cell of small boxes,
+    // random cells of large ones, blocks from 1 to 32 cells per edge)
+    for (int trial = 0; trial < 300; ++trial) {
+        int32_t L[3], sh[3];
+        for (int d = 0; d < 3; ++d) {
+            L[d] = trial < 200 ? rnd(1, 40) : rnd(1, 1200);
+            sh[d] = rnd(0, 5);
+        }
+        const uint64_t nc = (uint64_t)L[0] * L[1] * L[2];
+        if (trial < 200) {
+            std::vector<char> seen(nc, 0);
+            for (int iz = 0; iz < L[2]; ++iz)
+                for (int iy = 0; iy < L[1]; ++iy)
+                    for (int ix = 0; ix < L[0]; ++ix) {
+                        const uint32_t key = sort_key(L, sh, ix, iy, iz);
+                        const uint32_t c = (uint32_t)(ix + L[0] * (iy + L[1] * iz));
+                        if (key >= nc || seen[key] || cell_of_key(L, sh, key) != c) {
+                            printf("sort_key L=%d,%d,%d sh=%d,%d,%d cell %d,%d,%d -> %u\n", L[0], L[1], L[2], sh[0],
+                                   sh[1], sh[2], ix, iy, iz, key);
+                            return 1;
+                        }
+                        seen[key] = 1;
+                    }
+        } else {
+            for (int q = 0; q < 20000; ++q) {
+                const int ix = rnd(0, L[0] - 1), iy = rnd(0, L[1] - 1), iz = rnd(0, L[2] - 1);
+                const uint32_t key = sort_key(L, sh, ix, iy, iz);
+                if (key >= nc || cell_of_key(L, sh, key) != (uint32_t)(ix + L[0] * (iy + L[1] * iz))) {
+                    printf("sort_key (large) L=%d,%d,%d cell %d,%d,%d -> %u\n", L[0], L[1], L[2], ix, iy, iz, key);
+                    return 1;
+                }
+            }
+        }
     }
     printf("ok\n");
     return 0;

@@ -58,7 +58,7 @@ def test_struct_layout_matches_header(m, tmp_path):
 
 
 def test_status_strings_and_version(m):
-    assert m.mpcd_abi_version() == m.ABI_VERSION == 3
+    assert m.mpcd_abi_version() == m.ABI_VERSION == 4
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert m.mpcd_strerror(code) and m.mpcd_strerror(code) != "unknown status"
     assert m.mpcd_strerror(12345) == "unknown status"

@@ -1,0 +1,120 @@
+"""The CPU leg of hybrid execution (mpcd_host_step): SRD steps of a box in
+host memory on the host's cores, checked against the FP64 oracle with the
+tolerances of the GPU parity tests (positions to 1 ulp of the box edge,
+collision cells bit-exact away from cell faces, velocities to 1e-5), on the
+CPU.  Particle ids travel with the particles, so the oracle's order is
+restored from them."""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2212_11878_amd import inputs
+
+from gpu_util import check_against, oracle_one_step
+
+
+@pytest.fixture(scope="module")
+def m():
+    from paper_2212_11878_amd import mpcd
+    return mpcd
+
+
+def _host_steps(m, L, pos, vel, k, n_steps, seed, mass=None, threads=0, **kw):
+    n = pos.shape[1]
+    d = m.make_desc(L, n, dt=kw.get("dt", 0.1), alpha_deg=kw.get("alpha_deg", 130.0), seed=seed,
+                    a=kw.get("a", 1.0), init="external", particle_mass=mass is not None)
+    xyzv = np.ascontiguousarray(np.concatenate([pos, vel]).astype(np.float32))
+    pid = np.arange(n, dtype=np.int32)
+    mm = None if mass is None else np.array(mass, dtype=np.float32, copy=True)
+    rc = m.mpcd_host_step(d, xyzv, mm, pid, k, n_steps, threads)
+    order = np.argsort(pid)
+    out = xyzv[:, order]
+    return rc, out[:3], out[3:], (None if mm is None else mm[order]), pid[order]
+
+
+@pytest.mark.parametrize("L,n,k,a", [((10, 10, 10), 10000, 0, 1.0), ((7, 12, 5), 4000, 37, 1.0),
+                                     ((9, 9, 9), 7000, (1 << 32) + 5, 1.0), ((6, 8, 10), 5000, 3, 0.75)])
+def test_one_step_matches_the_oracle(m, L, n, k, a):
+    pos, vel = inputs.thermal_state(L, n, seed=11, a=a)
+    rc, gp, gv, _, pid = _host_steps(m, L, pos, vel, k, 1, seed=11, a=a)
+    assert rc == m.MPCD_OK and np.array_equal(pid, np.arange(n))
+    box = orc.make_box(L, dt=0.1, alpha_deg=130.0, seed=11, a=a)
+    st, s, cells = oracle_one_step(pos.astype(np.float32), vel.astype(np.float32), box, k)
+    band, err = check_against(st, s, cells, box, gp, gv)
+    assert band < n // 100 + 5
+
+
+def test_lockstep_from_its_own_state(m):
+    """Ten consecutive steps, each checked against the oracle's step from the
+    host leg's own previous state."""
+    L, n, seed = (8, 8, 8), 5120, 21
+    pos, vel = inputs.thermal_state(L, n, seed=seed)
+    box = orc.make_box(L, dt=0.1, alpha_deg=130.0, seed=seed)
+    p, v = pos.astype(np.float32), vel.astype(np.float32)
+    for k in range(10):
+        rc, gp, gv, _, _ = _host_steps(m, L, p, v, k, 1, seed=seed)
+        assert rc == m.MPCD_OK
+        st, s, cells = oracle_one_step(p, v, box, k)
+        check_against(st, s, cells, box, gp, gv)
+        p, v = gp, gv
+
+
+def test_per_particle_masses(m):
+    L, n, seed, k = (8, 6, 7), 4000, 5, 2
+    pos, vel = inputs.thermal_state(L, n, seed=seed)
+    mass = np.random.default_rng(5).uniform(0.5, 2.0, n).astype(np.float32)
+    rc, gp, gv, gm, _ = _host_steps(m, L, pos, vel, k, 1, seed=seed, mass=mass)
+    assert rc == m.MPCD_OK and np.array_equal(gm, mass.astype(np.float32))
+    box = orc.make_box(L, dt=0.1, alpha_deg=130.0, seed=seed)
+    st, s, cells = oracle_one_step(pos.astype(np.float32), vel.astype(np.float32), box, k,
+                                   mass.astype(np.float32))
+    check_against(st, s, cells, box, gp, gv)
+
+
+def test_thread_count_does_not_change_the_result(m):
+    """Exact cell sums: one thread and several give the same bits."""
+    L, n, seed = (12, 12, 12), 17280, 3
+    pos, vel = inputs.thermal_state(L, n, seed=seed)
+    r1 = _host_steps(m, L, pos, vel, 0, 5, seed=seed, threads=1)
+    r4 = _host_steps(m, L, pos, vel, 0, 5, seed=seed, threads=4)
+    assert r1[0] == r4[0] == m.MPCD_OK
+    assert np.array_equal(r1[1], r4[1]) and np.array_equal(r1[2], r4[2])
+
+
+def test_conservation_over_many_steps(m):
+    """Momentum to FP32 rounding and kinetic energy to rounding: SRD
+    conserves both exactly."""
+    L, n, seed = (10, 10, 10), 10000, 9
+    pos, vel = inputs.thermal_state(L, n, seed=seed)
+    rc, gp, gv, _, _ = _host_steps(m, L, pos, vel, 0, 200, seed=seed)
+    assert rc == m.MPCD_OK
+    v0, v1 = vel.astype(np.float32).astype(np.float64), gv.astype(np.float64)
+    assert np.all(np.abs(v1.sum(axis=1) - v0.sum(axis=1)) < 1e-3)
+    E0, E1 = np.sum(v0 * v0), np.sum(v1 * v1)
+    assert abs(E1 - E0) / E0 < 1e-5
+    assert gp.min() >= 0 and np.all(gp.max(axis=1) < np.array(L))
+
+
+def test_errors(m):
+    L, n = (4, 4, 4), 640
+    pos, vel = inputs.thermal_state(L, n, seed=1)
+    xyzv = np.ascontiguousarray(np.concatenate([pos, vel]).astype(np.float32))
+    d = m.make_desc(L, n, seed=1, init="external")
+    bad = xyzv.copy()
+    bad[0, 3] = 4.0                                         # outside the box
+    keep = bad.copy()
+    assert m.mpcd_host_step(d, bad, None, None, 0, 1, 1) == m.MPCD_EINVAL
+    assert np.array_equal(bad, keep)                        # untouched
+    bad = xyzv.copy()
+    bad[4, 7] = np.nan
+    assert m.mpcd_host_step(d, bad, None, None, 0, 1, 1) == m.MPCD_EINVAL
+    dl = m.make_desc(L, n, seed=1, init="external", conserve_l=True)
+    assert m.mpcd_host_step(dl, xyzv.copy(), None, None, 0, 1, 1) == m.MPCD_EINVAL
+    assert m.mpcd_host_step(d, xyzv.copy(), np.ones(n, np.float32), None, 0, 1, 1) == m.MPCD_EINVAL
+    dm = m.make_desc(L, n, seed=1, init="external", particle_mass=True)
+    assert m.mpcd_host_step(dm, xyzv.copy(), None, None, 0, 1, 1) == m.MPCD_EINVAL
+    fast = xyzv.copy()
+    fast[3, 0] = 300.0                                      # beyond the exact sums' range
+    assert m.mpcd_host_step(d, fast, None, None, 0, 1, 1) == m.MPCD_ESTATE
+    empty = m.make_desc(L, 0, seed=1, init="external")
+    assert m.mpcd_host_step(empty, np.zeros((6, 0), np.float32), None, None, 0, 3, 1) == m.MPCD_OK
