@@ -269,14 +269,6 @@ __device__ __forceinline__ void vacf_term(const BoxDev& b, int32_t id, float3 v,
     diag_vacf(d, v, w.x, w.y, w.z);
 }
 
-// Offset (-1, 0, 1) along one axis of the brick holding next-step cell
-// lo + d from this workgroup's brick [lo, lo + e) (the brick below spans
-// b cells, the one above bn), or 2 when it is no neighbour.
-__device__ __forceinline__ int near_rel(int d, int e, int b, int bn)
-{
-    return d < 0 ? (d >= -b ? -1 : 2) : (d < e ? 0 : (d < e + bn ? 1 : 2));
-}
-
 // One SRD step of one brick (paper Sec. 2; the shifted grid of Sec. 3.1;
 // the mass-weighted cell velocity of Sec. 3.3).  The workgroup owns every
 // particle whose collision cell lies in its brick, so the whole step is one
@@ -585,15 +577,15 @@ void k_brick_step(const Tile* __restrict__ tiles, const BoxDev* __restrict__ box
 
     // 3./4. rotate, route to the next step's buckets, store
     const float3 sh1 = grid_shift(b, k + 1);
-    // Interior bricks (a whole brick between this one and every box face):
-    // a particle that stays inside the box needs no periodic fold, and its
-    // next cell floor((x' - s1)/a) lies within one brick of this one or is
-    // farther than any wrap, so its neighbour offset follows from the cell
-    // index directly; everything else takes the exact general form.
-    const bool interior = bx >= 1 && bx + 2 <= nb0 && by >= 1 && by + 2 <= nb1 && bz >= 1 && bz + 2 <= nb2;
-    const int bbx = 1 << b.bshift[0], bby = 1 << b.bshift[1], bbz = 1 << b.bshift[2];
-    const int bnx = min(bbx, b.L[0] - (lox + ex)), bny = min(bby, b.L[1] - (loy + ey)),
-              bnz = min(bbz, b.L[2] - (loz + ez));
+    // Interior bricks (a full brick below and above this one, itself full,
+    // along every axis): a particle that stays inside the box needs no
+    // periodic fold, and the brick of its next cell c = floor((x' - s1)/a),
+    // c in [-1, L], is c >> shift, a neighbour exactly when that is within
+    // one of this brick's index (c = -1 and c = L, the images of cells L-1
+    // and 0, then fall outside the three); everything else takes the exact
+    // general form.
+    const bool interior = bx >= 1 && ((bx + 2) << b.bshift[0]) <= b.L[0] && by >= 1 &&
+                          ((by + 2) << b.bshift[1]) <= b.L[1] && bz >= 1 && ((bz + 2) << b.bshift[2]) <= b.L[2];
     MPCD_G float* const ox = ugp(b.p[dst][0]);
     MPCD_G float* const oy = ugp(b.p[dst][1]);
     MPCD_G float* const oz = ugp(b.p[dst][2]);
@@ -650,9 +642,9 @@ void k_brick_step(const Tile* __restrict__ tiles, const BoxDev* __restrict__ box
                 int rx, ry, rz;
                 if (interior && qx >= 0.0f && qx < b.len[0] && qy >= 0.0f && qy < b.len[1] && qz >= 0.0f &&
                     qz < b.len[2]) {
-                    rx = near_rel((int)floorf((qx - sh1.x) * inv_a) - lox, ex, bbx, bnx);
-                    ry = near_rel((int)floorf((qy - sh1.y) * inv_a) - loy, ey, bby, bny);
-                    rz = near_rel((int)floorf((qz - sh1.z) * inv_a) - loz, ez, bbz, bnz);
+                    rx = ((int)floorf((qx - sh1.x) * inv_a) >> b.bshift[0]) - bx;
+                    ry = ((int)floorf((qy - sh1.y) * inv_a) >> b.bshift[1]) - by;
+                    rz = ((int)floorf((qz - sh1.z) * inv_a) >> b.bshift[2]) - bz;
                 } else {
                     const int dbx = brick_of(axis_cell_raw(fold(qx, b.len[0]), sh1.x, inv_a, b.L[0]), b.bshift[0]);
                     const int dby = brick_of(axis_cell_raw(fold(qy, b.len[1]), sh1.y, inv_a, b.L[1]), b.bshift[1]);
@@ -661,7 +653,9 @@ void k_brick_step(const Tile* __restrict__ tiles, const BoxDev* __restrict__ box
                     ry = brick_rel(by, dby, nb1);
                     rz = brick_rel(bz, dbz, nb2);
                 }
-                r = (rx <= 1 && ry <= 1 && rz <= 1) ? (uint32_t)((rx + 1) + 3 * ((ry + 1) + 3 * (rz + 1))) : 27u;
+                r = ((unsigned)(rx + 1) <= 2u && (unsigned)(ry + 1) <= 2u && (unsigned)(rz + 1) <= 2u)
+                        ? (uint32_t)((rx + 1) + 3 * ((ry + 1) + 3 * (rz + 1)))
+                        : 27u;
             }
             // particles that stay in the brick (most) take consecutive ranks
             // per wave, so their stores coalesce
@@ -1085,7 +1079,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const Tile* __restrict__ til
     const MPCD_G uint32_t* __restrict__ cell = gp(b.cell);
     const MPCD_G uint32_t* __restrict__ rank = gp(b.rank);
     const MPCD_G uint32_t* __restrict__ cstart = gp(b.cstart);
-    constexpr int kU = 4;   // particles per thread in flight
+    constexpr int kU = 8;   // particles per thread in flight (the destination gathers wait on cstart)
     for (int64_t i0 = tl.begin + threadIdx.x; i0 < tl.end; i0 += (int64_t)kBlock * kU) {
         float qx[kU], qy[kU], qz[kU], ux[kU], uy[kU], uz[kU];
         int32_t id[kU];

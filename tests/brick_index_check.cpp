@@ -4,7 +4,8 @@
 // group of a destination brick (brick_rel) maps back to it (brick_nbr) and is
 // unique per source; bucket capacities with slack leave an overflow bucket
 // that can take every particle; bucket_of_slot finds the bucket of every slot
-// when some buckets are empty; the counting sort's blocked cell order
+// when some buckets are empty; interior bricks route by a shift of the next
+// cell index exactly as the general form does; the counting sort's blocked cell order
 // (sort_key) is a bijection that cell_of_key inverts.  Prints "ok" or the
 // first mismatch.  Built
 // with hipcc as host code.
@@ -123,6 +124,30 @@ int main()
                     return 1;
                 }
             }
+    }
+    // interior bricks of the brick step (a full brick below and above, itself
+    // full, along the axis): for every next-step cell index c in [-1, L] (L
+    // and -1 are the periodic images of cells 0 and L-1), a neighbour that
+    // (c >> shift) - b names is the one the exact form gives for the wrapped
+    // cell (anything else goes to the exact slow path, which is always
+    // right), and every cell of the three bricks is named
+    for (int trial = 0; trial < 2000; ++trial) {
+        const int L = rnd(1, 300), sh = rnd(1, 6);
+        const int nb = (L + (1 << sh) - 1) >> sh;
+        for (int b = 0; b < nb; ++b) {
+            if (!(b >= 1 && ((b + 2) << sh) <= L)) continue;
+            for (int c = -1; c <= L; ++c) {
+                const int fast = (c >> sh) - b;
+                const int wrapped = c < 0 ? c + L : (c >= L ? c - L : c);
+                const int exact = brick_rel(b, brick_of(wrapped, sh), nb);
+                const bool fast_nbr = fast >= -1 && fast <= 1;
+                const bool near = c >= ((b - 1) << sh) && c < ((b + 2) << sh);
+                if ((fast_nbr && fast != exact) || (near && !fast_nbr)) {
+                    printf("interior routing L=%d shift=%d brick=%d cell=%d: %d vs %d\n", L, sh, b, c, fast, exact);
+                    return 1;
+                }
+            }
+        }
     }
     // the counting sort's blocked cell order: a bijection of the cells onto
     // [0, L0 L1 L2) that cell_of_key inverts (every cell of small boxes,
