@@ -65,6 +65,31 @@ def test_lockstep_100_steps_from_gpu_state(mp, binning):
     _say("lockstep", binning, "max rel err %.2e, %d face-band particles over 100 steps" % (worst, bands))
 
 
+def test_lockstep_box_of_whole_bricks(mp):
+    """24 x 16 x 16 cells in 4^3 bricks (6 x 4 x 4 of them, every brick
+    whole): interior bricks route by the shifted next-cell index, the
+    bricks on the box faces by the exact folded form, and particles cross
+    the periodic faces into the bricks on the far side; 30 steps from the
+    GPU's own state, each against the oracle (a particle routed to a wrong
+    bucket would also mark the box)."""
+    _say("lockstep, whole bricks")
+    L, n, seed = (24, 16, 16), 61440, 51
+    pos, vel = inputs.thermal_state(L, n, seed=seed)
+    box = orc.make_box(L, dt=0.1, alpha_deg=130.0, seed=seed)
+    with mp.Context(binning=mp.MPCD_BIN_ATOMIC, brick=(4, 4, 4)) as ctx:
+        slot = ctx.admit(mp.make_desc(L, n, dt=0.1, alpha_deg=130.0, seed=seed, init="external"))
+        ctx.set_state(slot, (pos, vel))
+        p, v, _ = ctx.get_state(slot)
+        for step in range(30):
+            ctx.step(1)
+            gp, gv, k1 = ctx.get_state(slot)
+            assert k1 == step + 1
+            compare_step(p, v, gp, gv, box, step)
+            p, v = gp, gv
+        obs = ctx.observe(slot)
+    assert obs["status"] == 0 and obs["step"] == 30 and tuple(obs["brick"]) == (4, 4, 4)
+
+
 @pytest.mark.parametrize("binning", ["atomic", "sort"])
 def test_unordered_box_matches_oracle(mp, binning):
     """A box without particle ids: one step from a seeded state at k = 5,
