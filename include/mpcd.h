@@ -343,10 +343,13 @@ int mpcd_moments_noalloc(const float* vx, const float* vy, const float* vz, cons
  * mass and pid travel with their particles.  The caller owns every buffer;
  * the call allocates host memory of about 40 bytes per particle and 8 per
  * cell for its duration, and returns when the steps are done.  EINVAL for a
- * descriptor mpcd_admit refuses, MPCD_CONSERVE_L (GPU only), a position
- * outside the box or a non-finite velocity (the state is then untouched);
- * ESTATE when a velocity leaves the range of the exact sums or a cell holds
- * 4096 particles or more (the state then holds the steps' results). */
+ * descriptor mpcd_admit refuses, MPCD_CONSERVE_L or MPCD_TRACK_VACF (kept by
+ * contexts only), a position outside the box or a non-finite velocity (the
+ * state is then untouched); ESTATE when a velocity leaves the range of the
+ * exact sums or a cell holds 4096 particles or more (the state then holds
+ * the steps' results); ENOMEM when the work buffers cannot be allocated and
+ * EDEVICE when a host thread cannot start (in both cases before any step:
+ * the state is untouched). */
 int mpcd_host_step(const mpcd_box_desc* desc, float* xyzv, float* mass, int32_t* pid, int64_t step,
                    int32_t n_steps, int32_t threads);
 

@@ -17,6 +17,8 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <new>
+#include <system_error>
 #include <thread>
 #include <vector>
 
@@ -181,13 +183,16 @@ void step_part(HostBox& h, long long k, int t, int T, Barrier& bar)
 
 using namespace mpcd;
 
-extern "C" int mpcd_host_step(const mpcd_box_desc* desc, float* xyzv, float* mass, int32_t* pid, int64_t step,
-                              int32_t n_steps, int32_t threads)
+namespace {
+
+int host_step(const mpcd_box_desc* desc, float* xyzv, float* mass, int32_t* pid, int64_t step, int32_t n_steps,
+              int32_t threads)
 {
     int rc = validate_box_desc(desc);
     if (rc) return rc;
     if (step < 0 || n_steps < 0 || threads < 0) return MPCD_EINVAL;
-    if (desc->flags & MPCD_CONSERVE_L) return MPCD_EINVAL;   // the GPU's alone
+    // the angular-momentum rule and the VACF record are kept by contexts only
+    if (desc->flags & (MPCD_CONSERVE_L | MPCD_TRACK_VACF)) return MPCD_EINVAL;
     const int64_t n = desc->n_particles;
     if (n > 0 && !xyzv) return MPCD_EINVAL;
     if ((desc->flags & MPCD_PARTICLE_MASS) && n > 0 && !mass) return MPCD_EINVAL;
@@ -245,11 +250,23 @@ extern "C" int mpcd_host_step(const mpcd_box_desc* desc, float* xyzv, float* mas
     h.bad.store(out_of_range);
 
     Barrier bar(T);
+    std::atomic<int> go{0};   // the team starts together (1), or not at all (-1)
     auto work = [&](int t) {
+        int g;
+        while ((g = go.load(std::memory_order_acquire)) == 0) std::this_thread::yield();
+        if (g < 0) return;
         for (int32_t q = 0; q < n_steps; ++q) step_part(h, (long long)(step + q), t, T, bar);
     };
     std::vector<std::thread> team;
-    for (int t = 1; t < T; ++t) team.emplace_back(work, t);
+    team.reserve((size_t)T);
+    try {
+        for (int t = 1; t < T; ++t) team.emplace_back(work, t);
+    } catch (...) {   // a thread could not start: release the others, leave the state untouched
+        go.store(-1, std::memory_order_release);
+        for (auto& th : team) th.join();
+        throw;
+    }
+    go.store(1, std::memory_order_release);
     work(0);
     for (auto& th : team) th.join();
     // the state ends in the caller's arrays
@@ -259,4 +276,18 @@ extern "C" int mpcd_host_step(const mpcd_box_desc* desc, float* xyzv, float* mas
         if (pid) std::memcpy(pid, h.id_in, sizeof(int32_t) * (size_t)n);
     }
     return h.bad.load() ? MPCD_ESTATE : MPCD_OK;
+}
+
+}  // namespace
+
+extern "C" int mpcd_host_step(const mpcd_box_desc* desc, float* xyzv, float* mass, int32_t* pid, int64_t step,
+                              int32_t n_steps, int32_t threads)
+{
+    try {
+        return host_step(desc, xyzv, mass, pid, step, n_steps, threads);
+    } catch (const std::bad_alloc&) {   // work buffers
+        return MPCD_ENOMEM;
+    } catch (const std::system_error&) {   // a thread could not start
+        return MPCD_EDEVICE;
+    }
 }

@@ -111,6 +111,8 @@ def test_errors(m):
     dl = m.make_desc(L, n, seed=1, init="external", conserve_l=True)
     assert m.mpcd_host_step(dl, xyzv.copy(), None, None, 0, 1, 1) == m.MPCD_EINVAL
     assert m.mpcd_host_step(d, xyzv.copy(), np.ones(n, np.float32), None, 0, 1, 1) == m.MPCD_EINVAL
+    dv = m.make_desc(L, n, seed=1, init="external", vacf_stride=5)
+    assert m.mpcd_host_step(dv, xyzv.copy(), None, None, 0, 1, 1) == m.MPCD_EINVAL
     dm = m.make_desc(L, n, seed=1, init="external", particle_mass=True)
     assert m.mpcd_host_step(dm, xyzv.copy(), None, None, 0, 1, 1) == m.MPCD_EINVAL
     fast = xyzv.copy()
