@@ -457,7 +457,7 @@ def bench_hybrid(args, boxes, gpu_rate):
     print("[bench] hybrid: %d boxes on the host (%.3f of the particles), %d on the GPU"
           % (len(host_idx), sum(boxes[i]["n"] for i in host_idx) / total, len(ens.gpu_idx)),
           file=sys.stderr, flush=True)
-    wall, t_gpu, t_host = ens.step(args.steps)
+    wall, t_host = ens.step(args.steps)
     obs = ens.observe()
     ens.close()
     rate = total * args.steps / wall

@@ -82,7 +82,8 @@ class HybridEnsemble:
         self.pool = concurrent.futures.ThreadPoolExecutor(max_workers=self.workers)
 
     def step(self, n_steps):
-        """Advance every box by n_steps; returns (wall s, GPU-side s, host-side s)."""
+        """Advance every box by n_steps; returns (wall seconds until both
+        sides are done, seconds until the host side is done)."""
         t0 = time.perf_counter()
         if self.slots:
             self.ctx.step(n_steps)          # queued; returns at once
@@ -93,8 +94,7 @@ class HybridEnsemble:
             f.result()
         t_host = time.perf_counter() - t0
         self.ctx.synchronize()
-        t_all = time.perf_counter() - t0
-        return t_all, t_all if self.slots else 0.0, t_host
+        return time.perf_counter() - t0, t_host
 
     def observe(self):
         """Temperature and status of every box, in ensemble order."""
