@@ -1226,7 +1226,8 @@ __device__ void collide_cell_serial(const BoxDev& b, int par, long long k, uint3
 // run's velocities (and masses) in LDS with coalesced loads, one thread per
 // cell sums its particles from LDS (exact fixed point, the same terms as the
 // brick step) and builds the cell's collision map, then every thread applies
-// the maps to its particles and stores them coalesced.  A cell larger than
+// the maps to its particles and stores them coalesced.  The next run's
+// velocities are loaded into registers while a run is collided.  A cell larger than
 // the staging area is walked by one thread in global memory.  The
 // angular-momentum rule walks each cell with one thread (three passes).
 constexpr int kRotCap = 1024;
@@ -1269,35 +1270,78 @@ __global__ __launch_bounds__(kBlock) void k_cell_rotate(const Tile* __restrict__
     const int nc = (int)(tl.end - tl.begin);
     for (int i = threadIdx.x; i <= nc; i += kBlock) cs[i] = gp(b.cstart)[tl.begin + i];
     __syncthreads();
-    int c = 0;
-    while (c < nc) {
-        // the run [c, e): as many cells as fit (uniform binary search on cs)
-        int e = c + 1;
-        const uint32_t base = cs[c];
-        if (cs[e] - base <= (uint32_t)kRotCap) {
-            int lo = e, hi = min(nc, c + kRotCells);
+    // the run [c0, e): as many cells as fit (uniform binary search on cs)
+    auto run_end = [&](int c0) -> int {
+        int e1 = c0 + 1;
+        const uint32_t b0 = cs[c0];
+        if (cs[e1] - b0 <= (uint32_t)kRotCap) {
+            int lo = e1, hi = min(nc, c0 + kRotCells);
             while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (cs[mid] - base <= (uint32_t)kRotCap) lo = mid;
-                else hi = mid - 1;
+                const int m = (lo + hi + 1) >> 1;
+                if (cs[m] - b0 <= (uint32_t)kRotCap) lo = m;
+                else hi = m - 1;
             }
-            e = lo;
+            e1 = lo;
         }
-        const uint32_t np = cs[e] - base;
+        return e1;
+    };
+    constexpr int kPer = kRotCap / kBlock;
+    float qx[kPer], qy[kPer], qz[kPer], qm[kPer];
+    auto prefetch = [&](uint32_t b0, uint32_t n0) {
+#pragma unroll
+        for (int m = 0; m < kPer; ++m) {
+            const uint32_t j = (uint32_t)(m * kBlock) + threadIdx.x;
+            if (j < n0) {
+                qx[m] = vx[b0 + j];
+                qy[m] = vy[b0 + j];
+                qz[m] = vz[b0 + j];
+                qm[m] = mp ? mp[b0 + j] : 1.0f;
+            }
+        }
+    };
+    int c = 0, e = 0;
+    uint32_t base = 0, np = 0;
+    if (nc > 0) {
+        e = run_end(0);
+        base = cs[0];
+        np = cs[e] - base;
+        if (np <= (uint32_t)kRotCap) prefetch(base, np);
+    }
+    while (c < nc) {
         if (np > (uint32_t)kRotCap) {   // one cell larger than the staging area
             if (threadIdx.x == 0)
                 collide_cell_serial(b, par, k, cell_of_key(b.L, b.sshift, (uint32_t)(tl.begin + c)), base, cs[e], d,
                                     vacf);
             c = e;
+            if (c < nc) {
+                e = run_end(c);
+                base = cs[c];
+                np = cs[e] - base;
+                if (np <= (uint32_t)kRotCap) prefetch(base, np);
+            }
             continue;
         }
-        for (uint32_t j = threadIdx.x; j < np; j += kBlock) {
-            sv[0][j] = vx[base + j];
-            sv[1][j] = vy[base + j];
-            sv[2][j] = vz[base + j];
-            sm[j] = mp ? mp[base + j] : 1.0f;
+#pragma unroll
+        for (int m = 0; m < kPer; ++m) {
+            const uint32_t j = (uint32_t)(m * kBlock) + threadIdx.x;
+            if (j < np) {
+                sv[0][j] = qx[m];
+                sv[1][j] = qy[m];
+                sv[2][j] = qz[m];
+                sm[j] = qm[m];
+            }
         }
         __syncthreads();
+        // the next run's loads are in flight while this run is collided
+        const int c2 = e;
+        int e2 = c2;
+        uint32_t base2 = 0, np2 = 0;
+        if (c2 < nc) {
+            e2 = run_end(c2);
+            base2 = cs[c2];
+            np2 = cs[e2] - base2;
+            if (np2 <= (uint32_t)kRotCap) prefetch(base2, np2);
+        }
         if (threadIdx.x < e - c) {
             const int q = threadIdx.x;
             const uint32_t rb = cs[c + q] - base, re = cs[c + q + 1] - base;
@@ -1341,7 +1385,10 @@ __global__ __launch_bounds__(kBlock) void k_cell_rotate(const Tile* __restrict__
             if (vacf) vacf_term(b, pid[base + j], v, d);
         }
         __syncthreads();   // the staging area is refilled by the next run
-        c = e;
+        c = c2;
+        e = e2;
+        base = base2;
+        np = np2;
     }
     step_flush(d, vacf, dacc + (size_t)tl.box * kAccLanes * 3, blockIdx.x);
 }
