@@ -855,27 +855,29 @@ __global__ __launch_bounds__(kBlock) void k_zero_counts(const Tile* __restrict__
 // Rank of every live slot among the slots with the same key (SORT: its
 // collision cell, numbered in the blocked order of sort_key; re-bucketing:
 // the brick of that cell), and the per-key
-// counts in cstart.  The tile is taken in halves of kCountHalf slots; each
-// half gathers its keys in an LDS hash table (open addressing, load factor at
-// most 1/2), so a key takes one global atomic per half-tile, and the atomics
-// of all distinct keys are issued together rather than one after another.
-constexpr int kCountHalf = kPartTile / 2;
-constexpr int kCountPer = kCountHalf / kBlock;    // slots per thread per half
-constexpr int kHashSlots = 2 * kCountHalf;
+// counts in cstart.  The tile is taken in quarters of kCountPart slots; each
+// quarter gathers its keys in an LDS hash table (open addressing, load factor
+// at most 1/2), so a key takes one global atomic per quarter-tile, and the
+// atomics of all distinct keys are issued together rather than one after
+// another.  (Halves with a 32 KB table ran 29 % slower: fewer workgroups per
+// CU.)
+constexpr int kCountPart = kPartTile / 4;
+constexpr int kCountPer = kCountPart / kBlock;    // slots per thread per quarter
+constexpr int kHashSlots = 2 * kCountPart;
 constexpr uint32_t kHashEmpty = 0xffffffffu;
 
 __device__ __forceinline__ uint32_t hash_slot(uint32_t key)
 {
-    return (key * 0x9E3779B1u) >> (32 - 12);   // Fibonacci hashing onto kHashSlots = 4096
+    return (key * 0x9E3779B1u) >> (32 - 11);   // Fibonacci hashing onto kHashSlots = 2048
 }
-static_assert(kHashSlots == 4096, "hash_slot maps onto 4096 slots");
+static_assert(kHashSlots == 2048, "hash_slot maps onto 2048 slots");
 
 __global__ __launch_bounds__(kBlock) void k_count(const Tile* __restrict__ tiles,
                                                    const BoxDev* __restrict__ boxes,
                                                    const BoxState* __restrict__ st)
 {
     __shared__ uint32_t hkey[kHashSlots];
-    __shared__ uint32_t hval[kHashSlots];   // count of the key in this half, then its global base
+    __shared__ uint32_t hval[kHashSlots];   // count of the key in this quarter, then its global base
     const Tile tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     const BoxState s = st[uniform(tl.box)];
     const BoxDev& b = boxes[uniform(tl.box)];
@@ -894,13 +896,13 @@ __global__ __launch_bounds__(kBlock) void k_count(const Tile* __restrict__ tiles
     const bool by_brick = (b.binning == 1);
     const float3 sh = grid_shift(b, uniform(s.k));
     const float dt = b.dt;
-    for (int64_t h0 = tl.begin; h0 < tl.end; h0 += kCountHalf) {
+    for (int64_t h0 = tl.begin; h0 < tl.end; h0 += kCountPart) {
         for (int q = threadIdx.x; q < kHashSlots; q += kBlock) {
             hkey[q] = kHashEmpty;
             hval[q] = 0u;
         }
         __syncthreads();
-        uint32_t slot_rank[kCountPer];   // hash slot << 16 | rank inside the half; kHashEmpty: none
+        uint32_t slot_rank[kCountPer];   // hash slot << 16 | rank inside the quarter; kHashEmpty: none
         float qx[kCountPer], qy[kCountPer], qz[kCountPer], ux[kCountPer], uy[kCountPer], uz[kCountPer];
         bool live[kCountPer];
 #pragma unroll
@@ -934,7 +936,7 @@ __global__ __launch_bounds__(kBlock) void k_count(const Tile* __restrict__ tiles
             }
             cell[i] = key;
             uint32_t hs = hash_slot(key);
-            while (true) {   // at most kCountHalf keys in kHashSlots slots: a free slot exists
+            while (true) {   // at most kCountPart keys in kHashSlots slots: a free slot exists
                 const uint32_t old = atomicCAS(&hkey[hs], kHashEmpty, key);
                 if (old == kHashEmpty || old == key) break;
                 hs = (hs + 1u) & (kHashSlots - 1);
@@ -942,7 +944,7 @@ __global__ __launch_bounds__(kBlock) void k_count(const Tile* __restrict__ tiles
             slot_rank[u] = (hs << 16) | atomicAdd(&hval[hs], 1u);
         }
         __syncthreads();
-        // one global atomic per distinct key of the half: its base among all tiles
+        // one global atomic per distinct key of the quarter: its base among all tiles
         for (int q = threadIdx.x; q < kHashSlots; q += kBlock) {
             const uint32_t key = hkey[q];
             if (key != kHashEmpty) hval[q] = gatomic_add(counts + key, hval[q]);
@@ -954,7 +956,7 @@ __global__ __launch_bounds__(kBlock) void k_count(const Tile* __restrict__ tiles
             const int64_t i = h0 + (int64_t)u * kBlock + threadIdx.x;
             rank[i] = hval[slot_rank[u] >> 16] + (slot_rank[u] & 0xffffu);
         }
-        __syncthreads();   // the table is reset for the next half
+        __syncthreads();   // the table is reset for the next quarter
     }
 }
 
