@@ -97,6 +97,8 @@ struct BoxDev {
     float* m[2];           // per-particle masses (null: all particles equal)
     uint32_t* cell;        // sort key of each slot
     uint32_t* rank;        // rank of each slot inside its key (sort)
+    uint32_t* perm;        // SORT binning, plain rule: slot of the current buffer whose particle
+                           // goes to each slot of the next (null otherwise)
     uint32_t* cstart;      // counts, then exclusive starts, per key (C + 1)
     CellRot* un;           // brick mode: collision map of the cells of flagged bricks
     CellAm* uam;           // brick mode with conserve_l: the same for the angular-momentum rule

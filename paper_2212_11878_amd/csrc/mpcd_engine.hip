@@ -229,8 +229,8 @@ int upload(mpcd_ctx* c, void* dst, const void* src, size_t bytes)
 
 // Layout of one box's device allocation.
 struct Layout {
-    size_t off_p[2][6], off_v0, off_pid[2], off_m[2], off_cell, off_rank, off_cstart, off_un, off_uam, off_esc[2],
-        off_ecnt[2], off_eflag, off_bstart, off_bsize[2], off_vacf, off_part, total;
+    size_t off_p[2][6], off_v0, off_pid[2], off_m[2], off_cell, off_rank, off_perm, off_cstart, off_un, off_uam,
+        off_esc[2], off_ecnt[2], off_eflag, off_bstart, off_bsize[2], off_vacf, off_part, total;
 };
 
 int ntile_of(int64_t nslot) { return (int)std::max<int64_t>(1, (nslot + kPartTile - 1) / kPartTile); }
@@ -255,6 +255,7 @@ Layout box_layout(int64_t n, int64_t nslot, int64_t ncell, bool vacf, int vacf_c
     }
     L.off_cell = o; o += pf;
     L.off_rank = o; o += pf;
+    L.off_perm = o; o += (!brick && !am) ? pf : 0;
     L.off_cstart = o; o += align256((size_t)(ncell + 1) * 4);
     const size_t nbk = brick ? (size_t)g.nbrick : 0;
     L.off_un = o; o += brick ? align256((size_t)ncell * sizeof(CellRot)) : 0;
@@ -907,6 +908,7 @@ int mpcd_admit(mpcd_ctx* c, const mpcd_box_desc* d, int32_t* slot)
     b.v0 = vacf ? (float4*)(m + L.off_v0) : nullptr;
     b.cell = (uint32_t*)(m + L.off_cell);
     b.rank = (uint32_t*)(m + L.off_rank);
+    b.perm = (!brick && !am) ? (uint32_t*)(m + L.off_perm) : nullptr;
     b.cstart = (uint32_t*)(m + L.off_cstart);
     b.un = brick ? (CellRot*)(m + L.off_un) : nullptr;
     b.uam = brick && am ? (CellAm*)(m + L.off_uam) : nullptr;

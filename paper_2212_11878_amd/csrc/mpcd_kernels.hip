@@ -19,9 +19,11 @@
 //     brick, which also sets the bucket capacities
 //
 //   SORT binning (counting sort by collision cell every step)
-//     zero, k_count (streamed collision cell + rank), scan, k_scatter (streams
-//     while moving), flip, k_cell_rotate (one thread per cell over its
-//     contiguous run), k_box_finish
+//     zero, k_count (streamed collision cell + rank), scan, k_scatter (the
+//     permutation; under the angular-momentum rule the particles themselves,
+//     streamed), flip, k_cell_rotate (gathers runs of cells through the
+//     permutation and streams them, one thread per cell for the sums),
+//     k_box_finish
 //
 // Per box, outside the step: k_init_maxwell / k_init_adjust (initial state),
 // k_snapshot (exact momentum and energy on demand), k_box_stats(_tiles)
@@ -1081,6 +1083,32 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const Tile* __restrict__ til
     const MPCD_G uint32_t* __restrict__ cell = gp(b.cell);
     const MPCD_G uint32_t* __restrict__ rank = gp(b.rank);
     const MPCD_G uint32_t* __restrict__ cstart = gp(b.cstart);
+    if (b.perm) {
+        // SORT binning with the plain rule: only the permutation moves here.
+        // k_cell_rotate gathers each run of cells through it and writes the
+        // particles to the next buffer with coalesced stores; scattering
+        // 4-byte indices instead of 24-byte particles cuts the partial-line
+        // writes, which neighbouring tiles fill at different times.  A SORT
+        // box has no holes (nslot = n).
+        MPCD_G uint32_t* __restrict__ perm = gp(b.perm);
+        constexpr int kP = 16;
+        for (int64_t i0 = tl.begin + threadIdx.x; i0 < tl.end; i0 += (int64_t)kBlock * kP) {
+            uint32_t key[kP], rk[kP];
+#pragma unroll
+            for (int u = 0; u < kP; ++u) {
+                const int64_t i = i0 + (int64_t)u * kBlock;
+                const int64_t j = i < tl.end ? i : tl.begin;
+                key[u] = cell[j];
+                rk[u] = rank[j];
+            }
+#pragma unroll
+            for (int u = 0; u < kP; ++u) {
+                const int64_t i = i0 + (int64_t)u * kBlock;
+                if (i < tl.end) perm[cstart[key[u]] + rk[u]] = (uint32_t)i;
+            }
+        }
+        return;
+    }
     constexpr int kU = 8;   // particles per thread in flight (the destination gathers wait on cstart)
     for (int64_t i0 = tl.begin + threadIdx.x; i0 < tl.end; i0 += (int64_t)kBlock * kU) {
         float qx[kU], qy[kU], qz[kU], ux[kU], uy[kU], uz[kU];
@@ -1222,23 +1250,28 @@ __device__ void collide_cell_serial(const BoxDev& b, int par, long long k, uint3
     }
 }
 
-// SORT path: the particles of the cell with sort key c (sort_key) occupy
-// [cstart[c], cstart[c+1]) of the current buffer, already streamed.  A workgroup takes its cell tile in runs
-// of at most kRotCells cells holding at most kRotCap particles: it stages the
-// run's velocities (and masses) in LDS with coalesced loads, one thread per
-// cell sums its particles from LDS (exact fixed point, the same terms as the
-// brick step) and builds the cell's collision map, then every thread applies
-// the maps to its particles and stores them coalesced.  The next run's
-// velocities are loaded into registers while a run is collided.  A cell larger than
-// the staging area is walked by one thread in global memory.  The
-// angular-momentum rule walks each cell with one thread (three passes).
+// SORT path: the particles of the cell with sort key c (sort_key) go to
+// slots [cstart[c], cstart[c+1]) of the new buffer; perm names the slot of
+// the old buffer each one comes from.  A workgroup takes its cell tile in
+// runs of at most kRotCells cells holding at most kRotCap particles: it
+// gathers the run's particles through perm, writes their streamed positions
+// (and ids, masses) to the new buffer with coalesced stores and stages the
+// velocities (and masses) in LDS; one thread per cell sums its particles from
+// LDS (exact fixed point, the same terms as the brick step) and builds the
+// cell's collision map, then every thread applies the maps to its particles
+// and stores them coalesced.  The next run's gathers are in flight while a
+// run is collided.  A cell larger than the staging area is moved into place
+// and walked by one thread in global memory.  Under the angular-momentum rule
+// k_scatter has already moved the particles, and one thread walks each cell
+// (three passes).
 constexpr int kRotCap = 1024;
 constexpr int kRotCells = 128;
 
-__global__ __launch_bounds__(kBlock) void k_cell_rotate(const Tile* __restrict__ tiles,
-                                                         const BoxDev* __restrict__ boxes,
-                                                         const BoxState* __restrict__ st,
-                                                         long long* __restrict__ dacc)
+// held to 4 waves per SIMD: 128 VGPRs, no spills (unbounded it takes 147 and
+// runs 6 % slower at 3 waves)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+void k_cell_rotate(const Tile* __restrict__ tiles, const BoxDev* __restrict__ boxes, const BoxState* __restrict__ st,
+                   long long* __restrict__ dacc)
 {
     __shared__ uint32_t cs[kCellTile + 1];     // cstart of the tile's cells
     __shared__ float sv[3][kRotCap];
@@ -1264,11 +1297,28 @@ __global__ __launch_bounds__(kBlock) void k_cell_rotate(const Tile* __restrict__
         step_flush(d, vacf, dacc + (size_t)tl.box * kAccLanes * 3, blockIdx.x);
         return;
     }
+    // the particles of the next buffer's slots come from the current buffer
+    // through the counting sort's permutation
+    const int src = par ^ 1;
+    const MPCD_G uint32_t* const perm = ugp(b.perm);
+    const MPCD_G float* const ix = ugp(b.p[src][0]);
+    const MPCD_G float* const iy = ugp(b.p[src][1]);
+    const MPCD_G float* const iz = ugp(b.p[src][2]);
+    const MPCD_G float* const ivx = ugp(b.p[src][3]);
+    const MPCD_G float* const ivy = ugp(b.p[src][4]);
+    const MPCD_G float* const ivz = ugp(b.p[src][5]);
+    const MPCD_G float* const im = b.m[src] ? ugp(b.m[src]) : nullptr;
+    const MPCD_G int32_t* const iid = b.pid[src] ? ugp(b.pid[src]) : nullptr;
+    MPCD_G float* const ox = ugp(b.p[par][0]);
+    MPCD_G float* const oy = ugp(b.p[par][1]);
+    MPCD_G float* const oz = ugp(b.p[par][2]);
     MPCD_G float* const vx = ugp(b.p[par][3]);
     MPCD_G float* const vy = ugp(b.p[par][4]);
     MPCD_G float* const vz = ugp(b.p[par][5]);
-    const MPCD_G float* const mp = b.m[par] ? ugp(b.m[par]) : nullptr;
-    const MPCD_G int32_t* const pid = b.pid[par] ? ugp(b.pid[par]) : nullptr;
+    MPCD_G float* const om = b.m[par] ? ugp(b.m[par]) : nullptr;
+    MPCD_G int32_t* const pid = b.pid[par] ? ugp(b.pid[par]) : nullptr;
+    const float dt = b.dt;
+    const uint32_t last = (uint32_t)(b.n - 1);   // a slot index beyond it would be a broken permutation
     const int nc = (int)(tl.end - tl.begin);
     for (int i = threadIdx.x; i <= nc; i += kBlock) cs[i] = gp(b.cstart)[tl.begin + i];
     __syncthreads();
@@ -1288,45 +1338,91 @@ __global__ __launch_bounds__(kBlock) void k_cell_rotate(const Tile* __restrict__
         return e1;
     };
     constexpr int kPer = kRotCap / kBlock;
-    float qx[kPer], qy[kPer], qz[kPer], qm[kPer];
-    auto prefetch = [&](uint32_t b0, uint32_t n0) {
+    float gx[kPer], gy[kPer], gz[kPer], qx[kPer], qy[kPer], qz[kPer], qm[kPer];
+    int32_t qi[kPer];
+    uint32_t si[kPer];
+    // A run's loads go in two stages, one run apart: its source slots (perm),
+    // then, a run later, its particles through them; so a run's gathers never
+    // wait on its own perm loads.
+    auto load_perm = [&](uint32_t b0, uint32_t n0) {
+#pragma unroll
+        for (int m = 0; m < kPer; ++m) {
+            const uint32_t j = (uint32_t)(m * kBlock) + threadIdx.x;
+            si[m] = j < n0 ? perm[b0 + j] : 0u;
+        }
+    };
+    auto gather = [&](uint32_t n0) {
 #pragma unroll
         for (int m = 0; m < kPer; ++m) {
             const uint32_t j = (uint32_t)(m * kBlock) + threadIdx.x;
             if (j < n0) {
-                qx[m] = vx[b0 + j];
-                qy[m] = vy[b0 + j];
-                qz[m] = vz[b0 + j];
-                qm[m] = mp ? mp[b0 + j] : 1.0f;
+                const uint32_t i = min(si[m], last);
+                gx[m] = ix[i];
+                gy[m] = iy[i];
+                gz[m] = iz[i];
+                qx[m] = ivx[i];
+                qy[m] = ivy[i];
+                qz[m] = ivz[i];
+                qm[m] = im ? im[i] : 1.0f;
+                qi[m] = iid ? iid[i] : 0;
             }
         }
     };
-    int c = 0, e = 0;
-    uint32_t base = 0, np = 0;
-    if (nc > 0) {
-        e = run_end(0);
-        base = cs[0];
-        np = cs[e] - base;
-        if (np <= (uint32_t)kRotCap) prefetch(base, np);
+    struct Run {
+        int c, e;            // cells [c, e) of the tile
+        uint32_t base, np;   // their slots [base, base + np)
+    };
+    auto run_at = [&](int c0) -> Run {
+        if (c0 >= nc) return Run{c0, c0, 0u, 0u};
+        const int e0 = run_end(c0);
+        return Run{c0, e0, cs[c0], cs[e0] - cs[c0]};
+    };
+    auto fits = [&](const Run& r) { return r.c < nc && r.np <= (uint32_t)kRotCap; };
+    // r: the run being collided (gathers in flight), r2: the next (perm in flight)
+    Run r = run_at(0), r2 = run_at(r.e);
+    if (fits(r)) {
+        load_perm(r.base, r.np);
+        gather(r.np);
     }
-    while (c < nc) {
+    if (fits(r2)) load_perm(r2.base, r2.np);
+    while (r.c < nc) {
+        const int c = r.c, e = r.e;
+        const uint32_t base = r.base, np = r.np;
         if (np > (uint32_t)kRotCap) {   // one cell larger than the staging area
+            // moved into place (streamed), then walked by one thread
+            for (uint32_t j = threadIdx.x; j < np; j += kBlock) {
+                const uint32_t i = min(perm[base + j], last);
+                const float ux = ivx[i], uy = ivy[i], uz = ivz[i];
+                ox[base + j] = fold(fmaf(ux, dt, ix[i]), b.len[0]);
+                oy[base + j] = fold(fmaf(uy, dt, iy[i]), b.len[1]);
+                oz[base + j] = fold(fmaf(uz, dt, iz[i]), b.len[2]);
+                vx[base + j] = ux;
+                vy[base + j] = uy;
+                vz[base + j] = uz;
+                if (pid) pid[base + j] = iid[i];
+                if (om) om[base + j] = im[i];
+            }
+            __syncthreads();
             if (threadIdx.x == 0)
                 collide_cell_serial(b, par, k, cell_of_key(b.L, b.sshift, (uint32_t)(tl.begin + c)), base, cs[e], d,
                                     vacf);
-            c = e;
-            if (c < nc) {
-                e = run_end(c);
-                base = cs[c];
-                np = cs[e] - base;
-                if (np <= (uint32_t)kRotCap) prefetch(base, np);
-            }
+            r = r2;
+            r2 = run_at(r.e);
+            if (fits(r)) gather(r.np);
+            if (fits(r2)) load_perm(r2.base, r2.np);
             continue;
         }
+        // positions streamed (the arithmetic k_count chose the cell with),
+        // ids and masses go straight to the next buffer; velocities to LDS
 #pragma unroll
         for (int m = 0; m < kPer; ++m) {
             const uint32_t j = (uint32_t)(m * kBlock) + threadIdx.x;
             if (j < np) {
+                ox[base + j] = fold(fmaf(qx[m], dt, gx[m]), b.len[0]);
+                oy[base + j] = fold(fmaf(qy[m], dt, gy[m]), b.len[1]);
+                oz[base + j] = fold(fmaf(qz[m], dt, gz[m]), b.len[2]);
+                if (pid) pid[base + j] = qi[m];
+                if (om) om[base + j] = qm[m];
                 sv[0][j] = qx[m];
                 sv[1][j] = qy[m];
                 sv[2][j] = qz[m];
@@ -1334,16 +1430,11 @@ __global__ __launch_bounds__(kBlock) void k_cell_rotate(const Tile* __restrict__
             }
         }
         __syncthreads();
-        // the next run's loads are in flight while this run is collided
-        const int c2 = e;
-        int e2 = c2;
-        uint32_t base2 = 0, np2 = 0;
-        if (c2 < nc) {
-            e2 = run_end(c2);
-            base2 = cs[c2];
-            np2 = cs[e2] - base2;
-            if (np2 <= (uint32_t)kRotCap) prefetch(base2, np2);
-        }
+        // the next run's gathers and the one after's perm loads are in flight
+        // while this run is collided
+        const Run r3 = run_at(r2.e);
+        if (fits(r2)) gather(r2.np);
+        if (fits(r3)) load_perm(r3.base, r3.np);
         if (threadIdx.x < e - c) {
             const int q = threadIdx.x;
             const uint32_t rb = cs[c + q] - base, re = cs[c + q + 1] - base;
@@ -1387,10 +1478,8 @@ __global__ __launch_bounds__(kBlock) void k_cell_rotate(const Tile* __restrict__
             if (vacf) vacf_term(b, pid[base + j], v, d);
         }
         __syncthreads();   // the staging area is refilled by the next run
-        c = c2;
-        e = e2;
-        base = base2;
-        np = np2;
+        r = r2;
+        r2 = r3;
     }
     step_flush(d, vacf, dacc + (size_t)tl.box * kAccLanes * 3, blockIdx.x);
 }
