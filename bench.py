@@ -50,14 +50,17 @@ SERVED = "served_poisson"            # Poisson arrivals of single-box requests
 # per cell (C), independent of how the kernel is written:
 #   brick_step : the whole step of the brick boxes; read x, v (24 B) and
 #                write x, v (24 B); the cell sums live and die in LDS   -> 48 P
-#   cell_rotate: read v, write v                                      -> 24 P
-#   scatter    : read x, v (24 B), write them (24 B)                  -> 48 P
+#   cell_rotate: SORT binning, plain rule: move every particle to its
+#                slot in cell order and collide it; read x, v (24 B),
+#                write x, v (24 B)                                    -> 48 P
+#   scatter    : SORT binning, plain rule: the permutation; read the
+#                key and rank (8 B), write the source slot (4 B)      -> 12 P
 #   count      : read x, v (24 B: the key is the streamed position's
 #                cell), write the key (4 B)                           -> 28 P
 ALGO_BYTES = {
     "brick_step": (48, 0),
-    "cell_rotate": (24, 0),
-    "scatter": (48, 0),
+    "cell_rotate": (48, 0),
+    "scatter": (12, 0),
     "count": (28, 0),
 }
 # the whole step: every particle's x and v read once and written once

@@ -120,6 +120,51 @@ def test_sort_order_with_partial_blocks(mp):
     assert a["E"] == b["E"] and np.array_equal(a["P"], b["P"])
 
 
+def test_sort_cell_larger_than_the_staging_area(mp):
+    """Counting-sort binning with particle ids and per-particle masses on 6^3
+    cells: a thermal background plus 2500 particles within 0.05 of one point,
+    so that one collision cell holds more than the 1024 particles a run of
+    cells stages in LDS, and is moved into place and walked by one thread
+    instead; 4 steps from the GPU's own state, each against the oracle, with
+    the masses still on their particles at the end; then the same box on
+    bricks must hold the same momentum and energy bit for bit."""
+    _say("lockstep, sort cell larger than the staging area")
+    L, seed, ncl = (6, 6, 6), 61, 2500
+    bpos, bvel = inputs.thermal_state(L, 2160, seed=seed)
+    rng = np.random.default_rng(seed)
+    cpos = np.array([3.3, 2.6, 3.7])[:, None] + rng.uniform(-0.05, 0.05, (3, ncl))
+    cvel = rng.normal(0.0, 0.3, (3, ncl))
+    pos = np.concatenate([bpos, cpos.astype(np.float32)], axis=1)
+    vel = np.concatenate([bvel, cvel.astype(np.float32)], axis=1)
+    n = pos.shape[1]
+    mass = rng.uniform(0.5, 2.0, n).astype(np.float32)
+    box = orc.make_box(L, dt=0.1, alpha_deg=130.0, seed=seed)
+    obs, largest = {}, []
+    for binning in ("sort", "atomic"):
+        with mp.Context(binning=_mode(mp, binning)) as ctx:
+            slot = ctx.admit(mp.make_desc(L, n, dt=0.1, alpha_deg=130.0, seed=seed, init="external",
+                                          particle_mass=True))
+            ctx.set_state(slot, (pos, vel))
+            ctx.set_mass(slot, mass)
+            p, v, _ = ctx.get_state(slot)
+            for step in range(4):
+                ctx.step(1)
+                gp, gv, k1 = ctx.get_state(slot)
+                assert k1 == step + 1
+                if binning == "sort":
+                    st, s, cells = oracle_one_step(p, v, box, step, mass)
+                    largest.append(int(np.bincount(cells).max()))
+                    check_against(st, s, cells, box, gp, gv)
+                p, v = gp, gv
+            assert np.array_equal(ctx.get_mass(slot), mass)
+            obs[binning] = ctx.observe(slot)
+    _say("largest collision cell per step", largest)
+    assert min(largest) > 1024
+    a, b = obs["sort"], obs["atomic"]
+    assert a["status"] == b["status"] == 0 and a["step"] == b["step"] == 4
+    assert a["E"] == b["E"] and np.array_equal(a["P"], b["P"])
+
+
 @pytest.mark.parametrize("binning", ["atomic", "sort"])
 def test_unordered_box_matches_oracle(mp, binning):
     """A box without particle ids: one step from a seeded state at k = 5,
