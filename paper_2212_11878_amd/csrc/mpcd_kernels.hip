@@ -866,6 +866,7 @@ __global__ __launch_bounds__(kBlock) void k_zero_counts(const Tile* __restrict__
 constexpr int kCountPart = kPartTile / 4;
 constexpr int kCountPer = kCountPart / kBlock;    // slots per thread per quarter
 constexpr int kHashSlots = 2 * kCountPart;
+constexpr int kOwnSlots = kHashSlots / kBlock;   // hash slots each thread owns
 constexpr uint32_t kHashEmpty = 0xffffffffu;
 
 __device__ __forceinline__ uint32_t hash_slot(uint32_t key)
@@ -880,6 +881,7 @@ __global__ __launch_bounds__(kBlock) void k_count(const Tile* __restrict__ tiles
 {
     __shared__ uint32_t hkey[kHashSlots];
     __shared__ uint32_t hval[kHashSlots];   // count of the key in this quarter, then its global base
+    __shared__ uint16_t slots[kHashSlots];  // per wave: the occupied slots its lanes own
     const Tile tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     const BoxState s = st[uniform(tl.box)];
     const BoxDev& b = boxes[uniform(tl.box)];
@@ -946,10 +948,28 @@ __global__ __launch_bounds__(kBlock) void k_count(const Tile* __restrict__ tiles
             slot_rank[u] = (hs << 16) | atomicAdd(&hval[hs], 1u);
         }
         __syncthreads();
-        // one global atomic per distinct key of the quarter: its base among all tiles
-        for (int q = threadIdx.x; q < kHashSlots; q += kBlock) {
-            const uint32_t key = hkey[q];
-            if (key != kHashEmpty) hval[q] = gatomic_add(counts + key, hval[q]);
+        // one global atomic per distinct key of the quarter: its base among all
+        // tiles.  Each wave first lists the occupied slots among those its
+        // lanes own (ballot and popcount), so its atomics go out together,
+        // one per lane, rather than one round trip per owned slot.
+        {
+            const int lane = threadIdx.x & (kWave - 1);
+            const unsigned long long below = (1ull << lane) - 1ull;
+            uint16_t* const wl = slots + (threadIdx.x / kWave) * (kWave * kOwnSlots);
+            uint32_t nl = 0u;   // wave-uniform
+#pragma unroll
+            for (int t = 0; t < kOwnSlots; ++t) {
+                const int q = t * kBlock + threadIdx.x;
+                const bool occ = hkey[q] != kHashEmpty;
+                const unsigned long long m = __ballot(occ);
+                if (occ) wl[nl + (uint32_t)__popcll(m & below)] = (uint16_t)q;
+                nl += (uint32_t)__popcll(m);
+            }
+            __builtin_amdgcn_wave_barrier();
+            for (uint32_t e = (uint32_t)lane; e < nl; e += kWave) {
+                const int q = wl[e];
+                hval[q] = gatomic_add(counts + hkey[q], hval[q]);
+            }
         }
         __syncthreads();
 #pragma unroll
