@@ -326,6 +326,11 @@ void k_brick_step(const Tile* __restrict__ tiles, const BoxDev* __restrict__ box
     float* const fu = reinterpret_cast<float*>(lds64 + ((kAccWords * ncl + 1) & ~1));   // [ncl][kUnWords]
     for (int i = threadIdx.x; i < (am ? kAmWords : kAccWords) * ncl; i += kT) lds64[i] = 0ull;
     const uint32_t beg = (uint32_t)uniform((int)gp(b.bstart)[brick]);
+    // escape sums for this brick (overflow particles of the previous step):
+    // flagged during that step, in the half of eflag this step only reads,
+    // so the load goes out with the bucket's and is not waited for here
+    const uint32_t stamp = (uint32_t)(k + 1);
+    const uint32_t eflag_k = gp(b.eflag)[(size_t)(k & 1) * b.nbrick + brick];
     if (threadIdx.x == 0) {
         const uint32_t cap = gp(b.bstart)[brick + 1] - beg;
         s_cnt = min(gp(b.bsize[src])[brick], cap);
@@ -428,8 +433,7 @@ void k_brick_step(const Tile* __restrict__ tiles, const BoxDev* __restrict__ box
         }
     }
     __syncthreads();
-    const uint32_t stamp = (uint32_t)(k + 1);
-    const bool flagged = gp(b.eflag)[(size_t)(k & 1) * b.nbrick + brick] == stamp;
+    const bool flagged = eflag_k == stamp;
     const uint32_t L0 = (uint32_t)b.L[0], L01 = (uint32_t)b.L[0] * (uint32_t)b.L[1];
     // Angular-momentum rule, flagged brick: the particles of this step's
     // overflow bucket whose collision cell lies here are read directly (pass
