@@ -1,7 +1,7 @@
 """Parity at the benchmark's full size: 256^3 cells, 10 particles per cell
 (167,772,160 particles), in the launch configuration bench.py times (no
-particle ids, graph replay).  The box first routes itself through three
-steps; then the oracle takes step 3 from the GPU's own state and recomputes
+particle ids, graph replay), and the same with counting-sort binning every
+step.  The box first routes (or sorts) itself through three steps; then the oracle takes step 3 from the GPU's own state and recomputes
 three whole slabs of collision cells (about 2 million particles), matched
 with the GPU's particles by position."""
 import math
@@ -18,7 +18,8 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.timeout(900)
-def test_full_size_step_after_self_routing_sampled_cells():
+@pytest.mark.parametrize("binning", ["bench", "sort"])
+def test_full_size_step_after_self_routing_sampled_cells(binning):
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
@@ -26,10 +27,11 @@ def test_full_size_step_after_self_routing_sampled_cells():
     import bench
 
     L, n, seed, k = (256, 256, 256), 167772160, 3, 3
-    print("[case] full-size inputs", flush=True)
+    print("[case] full-size inputs (%s)" % binning, flush=True)
     pos, vel = inputs.thermal_state(L, n, seed)
     print("[case] full-size gpu steps", flush=True)
-    with mpcd.Context(**bench.context_options()) as ctx:
+    opts = bench.context_options() if binning == "bench" else dict(binning=mpcd.MPCD_BIN_SORT, use_graph=True)
+    with mpcd.Context(**opts) as ctx:
         slot = ctx.admit(mpcd.make_desc(L, n, dt=0.1, alpha_deg=130.0, seed=seed, init="external",
                                         unordered=True))
         ctx.set_state(slot, (pos, vel))
@@ -41,6 +43,7 @@ def test_full_size_step_after_self_routing_sampled_cells():
         gp, gv, step = ctx.get_state(slot)
         obs = ctx.observe(slot)
     assert step == k + 1 and obs["status"] == 0
+    assert obs["binning"] == (mpcd.MPCD_BIN_SORT if binning == "sort" else mpcd.MPCD_BIN_ATOMIC)
     print("[case] full-size oracle sample", flush=True)
     box = orc.make_box(L, dt=0.1, alpha_deg=130.0, seed=seed)
     st = orc.State(p3, v3)
