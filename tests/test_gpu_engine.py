@@ -220,12 +220,15 @@ def test_diagnostics_match_oracle(mp):
     assert abs(o["E"] - E) < 1e-9 * E and abs(o["T"] - T) < 1e-9 * T and o["M"] == M
 
 
-def test_vacf_samples(mp):
-    """VACF sample j = (1/N) sum v(j stride) . v(0), recorded on the device."""
-    _say("vacf")
+@pytest.mark.parametrize("binning", ["auto", "sort"])
+def test_vacf_samples(mp, binning):
+    """VACF sample j = (1/N) sum v(j stride) . v(0), recorded on the device
+    (with counting-sort binning the collision reads each particle's id from
+    the buffer it has just gathered into)."""
+    _say("vacf", binning)
     L, n = (12, 12, 12), 17280
     pos, vel = inputs.thermal_state(L, n, 8)
-    with mp.Context() as ctx:
+    with mp.Context(**({} if binning == "auto" else dict(binning=mp.MPCD_BIN_SORT))) as ctx:
         s = ctx.admit(mp.make_desc(L, n, seed=8, init="external", vacf_stride=3, n_steps=12))
         ctx.set_state(s, (pos, vel))
         ctx.step(20)                       # stops at n_steps
@@ -238,14 +241,15 @@ def test_vacf_samples(mp):
     assert abs(o["vacf"][-1] - np.sum(gv.astype(np.float64) * v0) / n) < 1e-9
 
 
-def test_one_step_vacf_closed_form_gpu(mp):
+@pytest.mark.parametrize("binning", ["auto", "sort"])
+def test_one_step_vacf_closed_form_gpu(mp, binning):
     """Same statistical pin as the oracle's, on the GPU path at 1.6e6 particles."""
-    _say("vacf-closed-form")
+    _say("vacf-closed-form", binning)
     L, n = 54, 10 * 54 ** 3
     alpha = math.radians(130.0)
     inv_n = L ** 3 / n * (1 - (1 - 1 / L ** 3) ** n)
     want = 1 - (2 / 3) * (1 - math.cos(alpha)) * (1 - inv_n)
-    with mp.Context() as ctx:
+    with mp.Context(**({} if binning == "auto" else dict(binning=mp.MPCD_BIN_SORT))) as ctx:
         s = ctx.admit(mp.make_desc(L, n, seed=31, vacf_stride=1, n_steps=1))
         ctx.step(1)
         v = ctx.observe(s)["vacf"]
