@@ -334,6 +334,7 @@ int rebuild_tables(mpcd_ctx* c)
     bool brick_am = false, brick_wide = false, brick_ids = false;
     int64_t max_bucket = 0;
     bool brick_mass = false;
+    int n_brick_boxes = 0, brick_box = -1;
     for (int s = 0; s < (int)c->slots.size(); ++s) {
         Slot& sl = c->slots[s];
         if (!sl.live) continue;
@@ -355,6 +356,8 @@ int rebuild_tables(mpcd_ctx* c)
             c->any_sort = true;
         } else {
             c->any_brick = true;
+            n_brick_boxes += 1;
+            brick_box = s;
             max_bvol = std::max(max_bvol, b.bmax[0] * b.bmax[1] * b.bmax[2]);
             // a full brick's bucket, with a 4-sigma Poisson margin, fits one chunk
             max_bucket = std::max<int64_t>(max_bucket, bucket_need((double)b.n * b.bmax[0] * b.bmax[1] * b.bmax[2] /
@@ -387,6 +390,7 @@ int rebuild_tables(mpcd_ctx* c)
     c->T.nptiles = (int)pt.size();
     c->T.nctiles = (int)ct.size();
     c->T.nbtiles = (int)bt.size();
+    c->T.brick_box = n_brick_boxes == 1 ? brick_box : -1;
     c->T.nactive = (int)active.size();
     c->T.max_bvol = max_bvol;
     c->T.brick_shape = brick_shape_for(max_bucket);

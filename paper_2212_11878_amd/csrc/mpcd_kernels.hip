@@ -292,7 +292,7 @@ __device__ __forceinline__ void vacf_term(const BoxDev& b, int32_t id, float3 v,
 template <int kT, int kS, bool kMass, bool kAM, bool kWide, bool kIds>
 __global__ __launch_bounds__(kT)
 __attribute__((amdgpu_waves_per_eu(kMass || kAM ? 1 : (kIds || kS > 6 ? 4 : 5), kMass || kAM || kIds || kS > 6 ? 8 : 5)))
-void k_brick_step(const Tile* __restrict__ tiles, const BoxDev* __restrict__ boxes,
+void k_brick_step(const Tile* __restrict__ tiles, int one_box, const BoxDev* __restrict__ boxes,
                   const BoxState* __restrict__ st, long long* __restrict__ dacc)
 {
     // LDS, per cell of the brick: exact sums of m v (3 x 64 bit) and of m (64
@@ -306,7 +306,9 @@ void k_brick_step(const Tile* __restrict__ tiles, const BoxDev* __restrict__ box
     constexpr uint32_t kChunk = (uint32_t)kT * kS;
     constexpr uint32_t kNone = 0xffffffffu;   // no particle / no cell
     const int t = xcd_tile(blockIdx.x, gridDim.x);
-    const Tile tl = tiles[t];
+    // with a single brick box the brick tiles are its bricks in order, and
+    // the tile record need not be loaded before the box's
+    const Tile tl = one_box >= 0 ? Tile{one_box, 0, t, t + 1} : tiles[t];
     const BoxState s = st[uniform(tl.box)];
     const BoxDev& b = boxes[uniform(tl.box)];
     if (box_idle(s) || b.binning != 1) return;
@@ -1884,7 +1886,7 @@ static void brick_step_run(const Tables& T, hipStream_t s)
         attr = true;
     }
     hipLaunchKernelGGL((k_brick_step<kT, kS, kMass, kAM, kWide, kIds>), dim3(T.nbtiles), dim3(kT), T.brick_lds + 16,
-                       s, T.btiles, T.boxes, T.state, T.dacc);
+                       s, T.btiles, T.brick_box, T.boxes, T.state, T.dacc);
 }
 // Instances: plain without particle ids, plain and per-particle masses with
 // 32-bit store offsets (every brick buffer below 2^30 slots), masses with

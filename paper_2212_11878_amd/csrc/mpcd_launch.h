@@ -22,6 +22,8 @@ struct Tables {
     long long* dacc = nullptr;        // per slot: kAccLanes x (VACF high, VACF low, violations)
     uint32_t* tilesum = nullptr; // per cell tile
     int nptiles = 0, nctiles = 0, nbtiles = 0, nactive = 0;
+    int32_t brick_box = -1;        // the slot of the only brick box (its bricks are the brick tiles in
+                                   // order), or -1
     int max_bvol = 0;              // largest brick of the live boxes (cells)
     int brick_shape = 0;           // launch shape of the brick step (brick_shape_for)
     bool brick_mass = false;       // some brick box carries per-particle masses
