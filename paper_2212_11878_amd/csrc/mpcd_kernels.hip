@@ -302,7 +302,6 @@ void k_brick_step(const Tile* __restrict__ tiles, int one_box, const BoxDev* __r
     // angular-momentum rule (kAM instances only) use kAmWords per cell instead.
     extern __shared__ __align__(16) unsigned long long lds64[];
     __shared__ uint32_t gcnt[27], gpos[27], gbeg[27], gcap[27];
-    __shared__ uint32_t s_cnt;
     constexpr uint32_t kChunk = (uint32_t)kT * kS;
     constexpr uint32_t kNone = 0xffffffffu;   // no particle / no cell
     const int t = xcd_tile(blockIdx.x, gridDim.x);
@@ -333,13 +332,11 @@ void k_brick_step(const Tile* __restrict__ tiles, int one_box, const BoxDev* __r
     // so the load goes out with the bucket's and is not waited for here
     const uint32_t stamp = (uint32_t)(k + 1);
     const uint32_t eflag_k = gp(b.eflag)[(size_t)(k & 1) * b.nbrick + brick];
-    if (threadIdx.x == 0) {
-        const uint32_t cap = gp(b.bstart)[brick + 1] - beg;
-        s_cnt = min(gp(b.bsize[src])[brick], cap);
-        gp(b.bsize[src])[brick] = 0u;   // this buffer is the next step's destination
-    }
+    // the bucket's fill, read by every wave (this workgroup alone reads it and
+    // clears it at the end, since this buffer is the next step's destination)
+    const uint32_t cnt = min((uint32_t)uniform((int)gp(b.bsize[src])[brick]),
+                             (uint32_t)uniform((int)gp(b.bstart)[brick + 1]) - beg);
     __syncthreads();
-    const uint32_t cnt = (uint32_t)uniform((int)s_cnt);
     const int nch = (int)((cnt + kChunk - 1) / kChunk);
 
     // bucket-relative bases (uniform): a lane's offset is its index in the bucket
@@ -742,6 +739,7 @@ void k_brick_step(const Tile* __restrict__ tiles, int one_box, const BoxDev* __r
         if (ch + 1 < nch) __syncthreads();
     }
     step_flush<kT>(d, vacf, dacc + (size_t)uniform(tl.box) * kAccLanes * 3, blockIdx.x);
+    if (threadIdx.x == 0) gp(b.bsize[src])[brick] = 0u;   // after every wave read it (step_flush's barrier)
 }
 
 // Particles of the overflow bucket of the current buffer (one workgroup per
